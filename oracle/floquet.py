@@ -1,0 +1,403 @@
+"""CPU oracle for the multimode Floquet hot path (FP64, NumPy).
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously correct
+reference that the GPU library is checked against.  Only the test suite, the
+smoke check and the benchmark's CPU-baseline leg may import it; the product
+path never does.  It shares no code with the GPU library: it imports nothing
+from it, and the GPU library imports nothing from here.
+
+Every function states the passage of the paper (G. A. Sinuco-Leon, "OPENMMF: a
+library for multimode driven quantum systems", arXiv:2005.03426) it follows.
+Units: hbar = 1.
+
+Model (Sec. 2, Eq. 1):
+    H(t) = E + sum_k [ V_k e^{+i h_k w_{l_k} t} + V_k^H e^{-i h_k w_{l_k} t} ]
+with harmonic couplings k given by (axis l_k, harmonic h_k >= 1, matrix V_k).
+
+Floquet matrix (Eq. 6 with the conjugate-term index read as U^{n-m}; block
+layout of Appendix A):
+    H_F[(i,n),(j,m)] = H^{[n-m]}_{ij} + delta_{nm} delta_{ij} (n . w)
+with H^{[0]} = E, H^{[+h e_l]} = sum of V_k with (l_k, h_k) = (l, h),
+H^{[-h e_l]} = sum of V_k^H over the same k, and zero for any other offset.
+Rows are ordered r = i + D s with the site index
+    s = sum_l (N_l - n_l) prod_{l' < l} (2 N_{l'} + 1)
+(descending n, fundamental 0 innermost), which puts H_0 + N w_1 in the top
+block and V above the block diagonal exactly as Appendix A prints it.
+
+Sign convention: the paper writes the micromotion series with e^{-i n.w t}
+and the diagonal E - n.w (Eqs. 5-6); substituting n -> -n gives the same
+matrix with E + n.w, used here, paired with U_F(t) = sum_n Phi^n e^{+i n.w t}.
+The brute-force Schroedinger integration (`rk4_evolve`) fixes this pairing.
+
+Parity status: every function below is pinned by the CPU tests (closed forms,
+invariants, brute force, the Appendix-A layout); none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+__all__ = [
+    "sites", "floquet_dim", "floquet_entry", "build_floquet", "eigh", "site_phases",
+    "evolve", "evolve_expm", "micromotion_select", "micromotion", "avg_prob",
+    "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
+    "zero_site",
+]
+
+
+# ---------------------------------------------------------------------------
+# Index set of the truncated Fourier expansion (Sec. 2 after Eq. 6; App. A)
+# ---------------------------------------------------------------------------
+def sites(N) -> np.ndarray:
+    """Fourier index vectors n (one row per site s), in site order.
+
+    Truncation n_l in [-N_l, N_l] (the "number of Floquet manifolds" of each
+    fundamental, App. A uses N_F = 3 -> 7 blocks per axis).  Site s decodes as
+    a mixed-radix number, digit q_l = (N_l - n_l) with radix 2 N_l + 1 and
+    axis 0 the least significant digit."""
+    N = [int(x) for x in N]
+    F = len(N)
+    S = 1
+    for n in N:
+        S *= 2 * n + 1
+    out = np.zeros((S, F), dtype=np.int64)
+    for s in range(S):
+        rem = s
+        for l in range(F):
+            L = 2 * N[l] + 1
+            q = rem % L
+            rem //= L
+            out[s, l] = N[l] - q
+    return out
+
+
+def zero_site(N) -> int:
+    """Site index of n = 0 (each digit q_l = N_l)."""
+    s, stride = 0, 1
+    for n in N:
+        s += int(n) * stride
+        stride *= 2 * int(n) + 1
+    return s
+
+
+def floquet_dim(p) -> int:
+    """M = D * prod_l (2 N_l + 1)."""
+    return p.D * len(sites(p.N))
+
+
+def _offset_block(p, delta):
+    """H^{[delta]} of the definition above, or None when it is zero.
+
+    delta is the integer vector n - m.  Couplings sharing (axis, h) are
+    summed in ascending k."""
+    nz = [l for l in range(len(delta)) if delta[l] != 0]
+    if not nz:
+        return p.E.copy()
+    if len(nz) != 1:
+        return None
+    l = nz[0]
+    d = int(delta[l])
+    blk = None
+    for k in range(p.K):
+        if int(p.axis[k]) != l:
+            continue
+        h = int(p.harm[k])
+        if d == h:
+            term = p.V[k]
+        elif d == -h:
+            term = p.V[k].conj().T
+        else:
+            continue
+        blk = term.copy() if blk is None else blk + term
+    return blk
+
+
+def _diag_shift(E_ii: float, n, omega) -> float:
+    """E_ii + n . w as the chain ((E_ii + n_0 w_0) + n_1 w_1) + ... in FP64,
+    each product n_l * w_l rounded once (ascending l)."""
+    x = float(E_ii)
+    for l in range(len(n)):
+        x = x + float(n[l]) * float(omega[l])
+    return x
+
+
+def floquet_entry(p, r: int, c: int) -> complex:
+    """One element H_F[r, c] straight from the definition (Eq. 6, App. A).
+
+    Used to check sampled entries of full-size matrices one by one."""
+    D = p.D
+    N = [int(x) for x in p.N]
+    i, sr = r % D, r // D
+    j, sc = c % D, c // D
+
+    def dec(s):
+        v = []
+        for n in N:
+            L = 2 * n + 1
+            v.append(n - s % L)
+            s //= L
+        return v
+    nr, nc = dec(sr), dec(sc)
+    delta = [a - b for a, b in zip(nr, nc)]
+    blk = _offset_block(p, delta)
+    if blk is None:
+        return 0j
+    val = complex(blk[i, j])
+    if all(x == 0 for x in delta) and i == j:
+        val = complex(_diag_shift(val.real, nr, p.omega), val.imag)
+    return val
+
+
+def build_floquet(p) -> np.ndarray:
+    """Dense truncated Floquet matrix H_F (M x M complex128), Eq. 6 / App. A.
+
+    Row site loop; for each row site the only nonzero column sites are the
+    site itself (block E + n.w) and its neighbours at offsets +-h e_l of the
+    couplings (blocks V, V^H), as the definition states."""
+    n = sites(p.N)
+    S, F, D = n.shape[0], n.shape[1], p.D
+    M = D * S
+    index = {tuple(v): s for s, v in enumerate(n.tolist())}
+    offsets = [tuple([0] * F)]
+    for k in range(p.K):
+        for sgn in (+1, -1):
+            o = [0] * F
+            o[int(p.axis[k])] = sgn * int(p.harm[k])
+            if tuple(o) not in offsets:
+                offsets.append(tuple(o))
+    H = np.zeros((M, M), dtype=np.complex128)
+    for sr in range(S):
+        for o in offsets:
+            m = tuple(int(a) - b for a, b in zip(n[sr], o))   # delta = n - m = o
+            sc = index.get(m)
+            if sc is None:
+                continue
+            blk = _offset_block(p, o)
+            if blk is None:
+                continue
+            blk = blk.copy()
+            if all(x == 0 for x in o):
+                for i in range(D):
+                    blk[i, i] = complex(_diag_shift(blk[i, i].real, n[sr], p.omega), blk[i, i].imag)
+            H[D * sr:D * sr + D, D * sc:D * sc + D] = blk
+    return H
+
+
+# ---------------------------------------------------------------------------
+# Dense Hermitian eigensolve (the paper delegates it to LAPACK, Sec. 3.2)
+# ---------------------------------------------------------------------------
+def eigh(H: np.ndarray):
+    """Eigenvalues (ascending) and orthonormal eigenvectors (columns) of the
+    Hermitian H_F: LAPACK zheevd through NumPy, the library routine the
+    paper's wrapper calls (Sec. 3.2)."""
+    w, Phi = np.linalg.eigh(H)
+    return w, Phi
+
+
+def jacobi_eigh(H: np.ndarray, sweeps: int = 30, tol: float = 1e-15):
+    """Cyclic complex Jacobi eigensolver (textbook method), for small matrices.
+
+    Each rotation first removes the phase of a_pq with a diagonal unitary,
+    then applies the real symmetric Jacobi rotation that zeroes the now-real
+    2x2 off-diagonal.  Used to pin `eigh` independently of LAPACK."""
+    A = np.array(H, dtype=np.complex128, copy=True)
+    n = A.shape[0]
+    V = np.eye(n, dtype=np.complex128)
+    scale = max(np.linalg.norm(A), 1e-300)
+    for _ in range(sweeps):
+        off = math.sqrt(max(np.linalg.norm(A) ** 2 - np.sum(np.abs(np.diag(A)) ** 2), 0.0))
+        if off <= tol * scale:
+            break
+        for p_ in range(n - 1):
+            for q in range(p_ + 1, n):
+                apq = A[p_, q]
+                r = abs(apq)
+                if r <= 1e-300:
+                    continue
+                ph = apq / r                            # a_pq = r e^{i phi}
+                app, aqq = A[p_, p_].real, A[q, q].real
+                theta = (aqq - app) / (2.0 * r)
+                t = (1.0 if theta >= 0 else -1.0) / (abs(theta) + math.sqrt(theta * theta + 1.0))
+                c = 1.0 / math.sqrt(t * t + 1.0)
+                s = t * c
+                # J = diag(1, conj(ph)) . [[c, s], [-s, c]] on columns p, q
+                J = np.array([[c, s], [-s * np.conj(ph), c * np.conj(ph)]], dtype=np.complex128)
+                cols = A[:, [p_, q]] @ J
+                A[:, p_], A[:, q] = cols[:, 0], cols[:, 1]
+                rows = J.conj().T @ A[[p_, q], :]
+                A[p_, :], A[q, :] = rows[0], rows[1]
+                A[p_, q] = A[q, p_] = 0.0
+                vc = V[:, [p_, q]] @ J
+                V[:, p_], V[:, q] = vc[:, 0], vc[:, 1]
+    w = np.diag(A).real.copy()
+    order = np.argsort(w, kind="stable")
+    return w[order], V[:, order]
+
+
+def householder_tridiag_apply(d, e, refl, tau):
+    """Rebuild Q from Householder reflectors and the tridiagonal T = Q^H A Q.
+
+    refl[:, i] holds v_i (v_i[i+1] = 1, zeros above), Q = H_0 H_1 ... with
+    H_i = I - tau_i v_i v_i^H.  Returns (Q, T) with T real symmetric
+    tridiagonal from d (diagonal) and e (off-diagonal).  Used to check a
+    tridiagonal reduction by its defining identity A = Q T Q^H."""
+    n = len(d)
+    Q = np.eye(n, dtype=np.complex128)
+    for i in range(n - 1):
+        v = refl[:, i]
+        Hi = np.eye(n, dtype=np.complex128) - tau[i] * np.outer(v, v.conj())
+        Q = Q @ Hi
+    T = np.diag(np.asarray(d, float)) + np.diag(np.asarray(e, float), 1) + np.diag(np.asarray(e, float), -1)
+    return Q, T
+
+
+# ---------------------------------------------------------------------------
+# Time evolution and micromotion (Eqs. 3-5)
+# ---------------------------------------------------------------------------
+def site_phases(p, t: float) -> np.ndarray:
+    """e^{+i n_s . w t} for every site s (the Fourier factors of Eq. 5 in the
+    sign convention stated in the module docstring)."""
+    n = sites(p.N).astype(np.float64)
+    return np.exp(1j * (n @ p.omega) * t)
+
+
+def evolve(p, Phi: np.ndarray, eps: np.ndarray, t0: float, ts) -> np.ndarray:
+    """Bare-basis time-evolution operators U(t, t0) for every t in ts.
+
+    Eqs. 3-5 written over all M eigenpairs of H_F (the extended-space form
+    the paper cites, Sec. 2 after Eq. 6):
+        U_ij(t, t0) = sum_n e^{i n.w t} sum_a Phi[(i,n),a] e^{-i eps_a (t-t0)} conj(Phi[(j,0),a])
+    Returns U with U[tau, i, j] (i final, j initial)."""
+    D = p.D
+    M = Phi.shape[0]
+    S = M // D
+    Phi3 = Phi.reshape(S, D, M)                 # row r = i + D s
+    Phi0 = Phi3[zero_site(p.N)]                 # (D, M): rows of the n = 0 block
+    ts = np.atleast_1d(np.asarray(ts, dtype=np.float64))
+    U = np.zeros((len(ts), D, D), dtype=np.complex128)
+    for q, t in enumerate(ts):
+        B = site_phases(p, t)                   # (S,)
+        A = np.einsum("s,sia->ia", B, Phi3)     # (D, M)
+        ph = np.exp(-1j * eps * (t - t0))       # (M,)
+        U[q] = (A * ph[None, :]) @ Phi0.conj().T
+    return U
+
+
+def evolve_expm(p, H: np.ndarray, t0: float, ts) -> np.ndarray:
+    """Same object as `evolve` with no eigendecomposition: the propagator
+    exp(-i H_F (t - t0)) applied to the n = 0 block columns, then the Fourier
+    sum over sites."""
+    from scipy.linalg import expm
+    D = p.D
+    M = H.shape[0]
+    S = M // D
+    s0 = zero_site(p.N)
+    ts = np.atleast_1d(np.asarray(ts, dtype=np.float64))
+    U = np.zeros((len(ts), D, D), dtype=np.complex128)
+    for q, t in enumerate(ts):
+        G = expm(-1j * H * (t - t0))[:, D * s0:D * s0 + D]      # (M, D)
+        B = site_phases(p, t)
+        U[q] = np.einsum("s,sij->ij", B, G.reshape(S, D, D))
+    return U
+
+
+def _round_half_away(x: np.ndarray) -> np.ndarray:
+    return np.sign(x) * np.floor(np.abs(x) + 0.5)
+
+
+def micromotion_select(p, Phi: np.ndarray, eps: np.ndarray):
+    """Pick one eigenvector per w-translation orbit (Eq. 5 needs D of them).
+
+    Fourier centre of mass c_a = sum_n n sum_i |Phi[(i,n),a]|^2 (F-vector);
+    keep the eigenvectors whose centre rounds (half away from zero) to the
+    zero vector; if more than D qualify keep the D of smallest |eps_a|, ties
+    by lower index.  Returns the selected column indices in ascending order,
+    or raises when fewer than D qualify (truncation not converged)."""
+    D = p.D
+    M = Phi.shape[0]
+    S = M // D
+    n = sites(p.N).astype(np.float64)           # (S, F)
+    w = (np.abs(Phi) ** 2).reshape(S, D, M).sum(axis=1)   # (S, M) site weights
+    c = n.T @ w                                             # (F, M)
+    ok = np.all(_round_half_away(c) == 0, axis=0) if n.shape[1] else np.ones(M, bool)
+    cand = np.nonzero(ok)[0]
+    if len(cand) < D:
+        raise ValueError(f"micromotion: only {len(cand)} orbit representatives found, need {D}")
+    if len(cand) > D:
+        key = sorted(cand.tolist(), key=lambda a: (abs(float(eps[a])), a))
+        cand = np.array(sorted(key[:D]))
+    return cand
+
+
+def micromotion(p, Phi: np.ndarray, eps: np.ndarray, ts):
+    """Micromotion operator U_F(t) (Eq. 5): U_F(t)_{i b} = sum_n Phi[(i,n),b] e^{i n.w t}
+    over the D selected representatives b; returns (UF[tau, i, b], eps_sel[b])."""
+    sel = micromotion_select(p, Phi, eps)
+    D = p.D
+    M = Phi.shape[0]
+    S = M // D
+    Phi3 = Phi[:, sel].reshape(S, D, D)
+    ts = np.atleast_1d(np.asarray(ts, dtype=np.float64))
+    UF = np.zeros((len(ts), D, D), dtype=np.complex128)
+    for q, t in enumerate(ts):
+        UF[q] = np.einsum("s,sib->ib", site_phases(p, t), Phi3)
+    return UF, eps[sel].copy()
+
+
+# ---------------------------------------------------------------------------
+# Time- and phase-averaged transition probability (MULTIMODETRANSITIONAVG)
+# ---------------------------------------------------------------------------
+def avg_prob(p, Phi: np.ndarray) -> np.ndarray:
+    """P[i, j] = long-time and drive-phase average of |U_ij(t, t0)|^2.
+
+    Averaging the eigen expansion of `evolve` over t - t0 and t0 keeps only
+    the diagonal terms of a nondegenerate spectrum:
+        P[i, j] = sum_a ( sum_n |Phi[(i,n),a]|^2 ) |Phi[(j,0),a]|^2 ."""
+    D = p.D
+    M = Phi.shape[0]
+    S = M // D
+    A2 = (np.abs(Phi) ** 2).reshape(S, D, M)
+    W = A2.sum(axis=0)                          # (D, M)
+    Z = A2[zero_site(p.N)]                      # (D, M)
+    return W @ Z.T
+
+
+# ---------------------------------------------------------------------------
+# Brute-force Schroedinger integration (independent of the Floquet matrix)
+# ---------------------------------------------------------------------------
+def hamiltonian_at(p, t: float) -> np.ndarray:
+    """H(t) of Eq. 1 in the convention of the module docstring."""
+    H = p.E.astype(np.complex128).copy()
+    for k in range(p.K):
+        ph = np.exp(1j * int(p.harm[k]) * float(p.omega[int(p.axis[k])]) * t)
+        H = H + p.V[k] * ph + p.V[k].conj().T * np.conj(ph)
+    return H
+
+
+def rk4_evolve(p, t0: float, ts, h: float = 1e-3) -> np.ndarray:
+    """U(t, t0) from classical fourth-order Runge-Kutta on i dU/dt = H(t) U,
+    U(t0) = I, with steps no longer than h (each interval [t0, t] split
+    evenly).  Returns U[tau, i, j]."""
+    D = p.D
+    ts = np.atleast_1d(np.asarray(ts, dtype=np.float64))
+    out = np.zeros((len(ts), D, D), dtype=np.complex128)
+    order = np.argsort(ts)
+    U = np.eye(D, dtype=np.complex128)
+    tc = float(t0)
+
+    def f(t, X):
+        return -1j * (hamiltonian_at(p, t) @ X)
+    for q in order:
+        T = float(ts[q])
+        nsteps = max(1, int(math.ceil(abs(T - tc) / h)))
+        dt = (T - tc) / nsteps
+        for _ in range(nsteps):
+            k1 = f(tc, U)
+            k2 = f(tc + dt / 2, U + dt / 2 * k1)
+            k3 = f(tc + dt / 2, U + dt / 2 * k2)
+            k4 = f(tc + dt, U + dt * k3)
+            U = U + (dt / 6.0) * (k1 + 2 * k2 + 2 * k3 + k4)
+            tc += dt
+        tc = T
+        out[q] = U
+    return out
