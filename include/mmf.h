@@ -1,0 +1,177 @@
+/*
+ * mmf.h -- C ABI of the MI355X multimode Floquet library (libmmf.so).
+ *
+ * Implements the computational path of G. A. Sinuco-Leon, "OPENMMF: a library
+ * for multimode driven quantum systems" (arXiv:2005.03426):
+ *   mmf_build_floquet  -- the truncated multimode Floquet matrix H_F
+ *                         (Sec. 2, Eq. 6; block layout of Appendix A)
+ *   mmf_eigh           -- its dense Hermitian eigendecomposition (Sec. 3.2,
+ *                         the diagonalisation the paper delegates to LAPACK)
+ *   mmf_evolve         -- the bare-basis time-evolution operator U(t,t0)
+ *                         (Eqs. 3-5) from the eigenpairs
+ *   mmf_micromotion    -- the micromotion operator U_F(t) (Eq. 5)
+ *   mmf_avg_prob       -- time/phase-averaged transition probabilities
+ *                         (the MULTIMODETRANSITIONAVG task of Sec. 5)
+ * plus the stages of mmf_eigh (tridiagonal reduction, tridiagonal
+ * divide-and-conquer, back-transformation) as separate calls.
+ *
+ * Conventions (all calls):
+ *   - hbar = 1.  H(t) = E + sum_k [ V_k e^{+i h_k w_{l_k} t} + V_k^H e^{-i h_k w_{l_k} t} ]
+ *     (Eq. 1 with harmonic couplings k = (axis l_k, harmonic h_k >= 1, V_k)).
+ *   - Complex numbers are interleaved (re, im) doubles (mmf_z), identical in
+ *     layout to std::complex<double> and torch.complex128.
+ *   - Matrices are column-major with an explicit leading dimension (ld >= rows).
+ *   - Floquet row index r = i + D*s, site s = sum_l (N_l - n_l) prod_{l'<l}(2N_{l'}+1):
+ *     descending Fourier index, fundamental 0 innermost (Appendix A order).
+ *   - "dev" pointers are device (HBM) memory owned by the caller; "host"
+ *     pointers are host memory read during the call only.  The library never
+ *     allocates or frees caller-visible memory and keeps no global state:
+ *     every call is reentrant.  Kernels are enqueued on `stream` (a
+ *     hipStream_t, NULL = default stream) and the call returns without
+ *     synchronising.
+ *   - Return value: 0 on success; -k when argument k (1-based) is invalid
+ *     (checked on the host before anything is enqueued); a positive MMF_ERR_*
+ *     code on a runtime failure.  Numerical failures found on the device are
+ *     reported through a device status word where a call has one.
+ */
+#ifndef MMF_H
+#define MMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } mmf_z;
+
+/* Problem statement (Eq. 1; the ATOM / MODES_NUMBER / MODE data of Sec. 3.1). */
+typedef struct {
+  int32_t D;            /* bare Hilbert-space dimension, 1 <= D <= 64                     */
+  int32_t F;            /* number of incommensurate fundamentals, 0 <= F <= 8             */
+  int32_t K;            /* number of harmonic couplings, 0 <= K <= 64                     */
+  const double  *omega; /* host [F]: fundamental angular frequencies                      */
+  const int32_t *N;     /* host [F]: truncation, n_l in [-N_l, N_l], N_l >= 0              */
+  const int32_t *axis;  /* host [K]: fundamental index l_k in [0, F)                      */
+  const int32_t *harm;  /* host [K]: harmonic order h_k >= 1                              */
+  const mmf_z   *E;     /* dev [D*D]: static Hamiltonian, column-major, Hermitian         */
+  const mmf_z   *V;     /* dev [K*D*D]: V_k column-major at offset k*D*D (any complex)    */
+} mmf_problem;
+
+/* eigensolver precision */
+enum {
+  MMF_C128 = 0,          /* complex128 throughout                                        */
+  MMF_C64_REFINED = 1,   /* complex64 reduction/back-transform + FP64 refinement          */
+  MMF_C64_RAW = 2        /* complex64 reduction/back-transform, no refinement             */
+};
+
+/* positive error codes */
+enum {
+  MMF_OK = 0,
+  MMF_ERR_HIP = 1,             /* a HIP runtime call failed                               */
+  MMF_ERR_WORKSPACE = 2,       /* workspace smaller than the size query returned         */
+  MMF_ERR_NOT_IMPLEMENTED = 3, /* option not available in this build                     */
+  MMF_ERR_NO_CONVERGENCE = 4,  /* device status: an iteration did not converge           */
+  MMF_ERR_SELECTION = 5,       /* micromotion: not exactly D orbit representatives found */
+  MMF_ERR_TOO_LARGE = 6        /* size beyond what the library supports                   */
+};
+
+/* Human-readable text for a return code (static storage). */
+const char *mmf_strerror(int code);
+
+/* Floquet dimension M = D * prod_l (2 N_l + 1) of problem p (host only).
+ * Errors: -1 p NULL or malformed, -2 M NULL, MMF_ERR_TOO_LARGE if M > 2^31-1. */
+int mmf_floquet_dim(const mmf_problem *p, int64_t *M);
+
+/* Assemble H_F (Sec. 2, Eq. 6 with the conjugate term indexed U^{n-m};
+ * Appendix A layout):
+ *   HF[(i,n),(j,m)] = H^{[n-m]}_{ij} + delta_{nm} delta_{ij} (n . w),
+ *   H^{[0]} = E, H^{[+h e_l]} = sum of V_k with (l_k,h_k) = (l,h) (ascending k),
+ *   H^{[-h e_l]} = sum of V_k^H over the same k, zero otherwise.
+ * The diagonal is evaluated as ((E_ii + n_0 w_0) + n_1 w_1) + ... in FP64.
+ * All M x M entries are written (both triangles).
+ * HF: dev, M x M, column-major, ldh >= M.
+ * Errors: -1 bad problem, -2 HF NULL, -3 ldh < M, MMF_ERR_HIP. */
+int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *stream);
+
+/* Workspace bytes that mmf_eigh needs for an M x M problem at precision prec. */
+int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
+
+/* Dense Hermitian eigendecomposition A = Phi diag(w) Phi^H (Sec. 3.2).
+ * A:   dev M x M, ld lda >= M; on entry the Hermitian matrix (only the lower
+ *      triangle is read); on exit column a holds the orthonormal eigenvector
+ *      of w[a] (the paper's U_F array).
+ * w:   dev [M], eigenvalues in ascending order.
+ * work/work_bytes: dev scratch of at least mmf_eigh_workspace() bytes.
+ * dev_info: dev int32, set to 0 or to MMF_ERR_NO_CONVERGENCE by the kernels.
+ * Method: blocked Householder reduction to a real symmetric tridiagonal
+ * matrix (trailing updates and back-transformation on FP64 matrix cores),
+ * Cuppen divide and conquer with Gu-Eisenstat eigenvector recomputation.
+ * Errors: -1 M < 0, -2 A NULL, -3 lda < M, -4 w NULL, -5 prec unknown,
+ *         -6/-7 workspace NULL or too small, -8 dev_info NULL, MMF_ERR_HIP,
+ *         MMF_ERR_NOT_IMPLEMENTED for a precision not built. */
+int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec,
+             void *work, size_t work_bytes, int32_t *dev_info, void *stream);
+
+/* Stage 1 of mmf_eigh: Householder reduction Q^H A Q = T with T real
+ * symmetric tridiagonal.  On exit d[n] (dev) is the diagonal, e[n-1] (dev) the
+ * off-diagonal, the reflector v_i (v_i[i+1] = 1, zero above) is stored in
+ * A[i+1:, i] and tau[n-1] (dev, complex) holds its scalar, so that
+ * Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H.
+ * work: at least mmf_eigh_workspace(n, MMF_C128) bytes. */
+int mmf_hetrd(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau,
+              void *work, size_t work_bytes, void *stream);
+
+/* Stage 2: eigenpairs of the real symmetric tridiagonal matrix (d, e):
+ * on exit d holds the eigenvalues ascending and Z (dev, n x n, ldz >= n,
+ * real) the orthonormal eigenvectors.  e is not modified.
+ * work: at least mmf_eigh_workspace(n, MMF_C128) bytes. */
+int mmf_stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz,
+              void *work, size_t work_bytes, int32_t *dev_info, void *stream);
+
+/* Stage 3: Phi = Q Z for the reflectors left by mmf_hetrd in V (dev, n x n,
+ * ldv) and tau; Z real n x n (ldz); Phi (dev, n x n, ldphi) must not overlap
+ * V or Z.  work: at least mmf_eigh_workspace(n, MMF_C128) bytes. */
+int mmf_unmtr(int64_t n, const mmf_z *V, int64_t ldv, const mmf_z *tau,
+              const double *Z, int64_t ldz, mmf_z *Phi, int64_t ldphi,
+              void *work, size_t work_bytes, void *stream);
+
+/* Workspace bytes for mmf_evolve / mmf_micromotion with T times. */
+int mmf_evolve_workspace(const mmf_problem *p, int32_t T, size_t *bytes);
+
+/* Bare-basis time-evolution operators (Eqs. 3-5 over all M eigenpairs):
+ *   U_ij(t,t0) = sum_n e^{i n.w t} sum_a Phi[(i,n),a] e^{-i w_a (t-t0)} conj(Phi[(j,0),a])
+ * Phi: dev M x M eigenvectors (ld), w: dev [M] eigenvalues, t: dev [T] times,
+ * U: dev [T][D*D], U[tau*D*D + i + D*j] (i final state, j initial state).
+ * Errors: -1 problem, -2 Phi, -3 ld, -4 w, -6 T < 0, -7 t, -8 U, -9/-10 workspace. */
+int mmf_evolve(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w,
+               double t0, int32_t T, const double *t, mmf_z *U,
+               void *work, size_t work_bytes, void *stream);
+
+/* Micromotion operator (Eq. 5) U_F(t)_{ib} = sum_n Phi[(i,n),b] e^{i n.w t} over
+ * one eigenvector b per w-translation orbit: the columns whose Fourier centre
+ * of mass sum_n n sum_i |Phi[(i,n),b]|^2 rounds (half away from zero) to the
+ * zero vector; if more than D qualify the D of smallest |w_b| (ties: lower b).
+ * UF: dev [T][D*D] (UF[tau*D*D + i + D*b]); eps_sel: dev [D] (ascending b);
+ * sel: dev int32 [D] selected columns; dev_info: dev int32, 0 or
+ * MMF_ERR_SELECTION when fewer than D columns qualify. */
+int mmf_micromotion(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w,
+                    int32_t T, const double *t, mmf_z *UF, double *eps_sel, int32_t *sel,
+                    void *work, size_t work_bytes, int32_t *dev_info, void *stream);
+
+/* Workspace bytes for mmf_avg_prob. */
+int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes);
+
+/* Time- and drive-phase-averaged transition probabilities:
+ *   P[i + D*j] = sum_a ( sum_n |Phi[(i,n),a]|^2 ) |Phi[(j,0),a]|^2
+ * (long-time average of |U_ij|^2 for a nondegenerate quasienergy spectrum;
+ * columns sum to one for any orthonormal Phi).  Deterministic (fixed
+ * reduction order).  P: dev [D*D] doubles, i final, j initial. */
+int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, double *P,
+                 void *work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMF_H */

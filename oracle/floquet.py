@@ -41,7 +41,7 @@ __all__ = [
     "sites", "floquet_dim", "floquet_entry", "build_floquet", "eigh", "site_phases",
     "evolve", "evolve_expm", "micromotion_select", "micromotion", "avg_prob",
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
-    "zero_site",
+    "zero_site", "tridiag_eigh",
 ]
 
 
@@ -401,3 +401,12 @@ def rk4_evolve(p, t0: float, ts, h: float = 1e-3) -> np.ndarray:
         tc = T
         out[q] = U
     return out
+
+
+def tridiag_eigh(d, e):
+    """Eigenpairs of the real symmetric tridiagonal matrix with diagonal d and
+    off-diagonal e (dense LAPACK solve of the matrix written out)."""
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    return np.linalg.eigh(T)

@@ -1,0 +1,237 @@
+"""MI355X-native multimode Floquet hot path (arXiv:2005.03426, OPENMMF).
+
+Python surface over the C ABI of libmmf.so (include/mmf.h).  Functions take
+and return torch tensors on the GPU; this layer only marshals pointers,
+sizes and streams -- every step of the computation (assembly of the Floquet
+matrix, its Hermitian eigendecomposition, U(t,t0), micromotion, averaged
+transition probabilities) runs in the library's HIP kernels.
+
+Storage conventions (the C ABI is column-major):
+  * an M x M matrix X is held in a torch tensor Xt of shape (M, M) with
+    Xt[c, r] = X[r, c]; so H_F = HFt.T and eigenvector a is the row Pt[a];
+  * U(t,t0) comes back as U[tau, i, j] (a transposed view of the raw buffer).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import numpy as np
+
+from ._lib import (lib, call, check, MMFProblem, MMFError, EXPORTED, LIB_PATH,
+                   MMF_C128, MMF_C64_REFINED, MMF_C64_RAW)
+
+__all__ = [
+    "DeviceProblem", "floquet_dim", "build_floquet", "eigh", "eigh_workspace_bytes", "hetrd",
+    "stedc", "unmtr", "evolve", "micromotion", "avg_prob", "solve", "MMFError", "lib",
+    "MMF_C128", "MMF_C64_REFINED", "MMF_C64_RAW", "EXPORTED", "LIB_PATH",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class DeviceProblem:
+    """A problem statement (see workloads.Problem) staged for the library:
+    E and V in device memory (column-major), frequencies, truncations and the
+    coupling table as host arrays kept alive for the ctypes structure."""
+
+    def __init__(self, problem, device="cuda"):
+        torch = _torch()
+        self.D = int(problem.E.shape[0])
+        self.F = int(len(problem.omega))
+        self.K = int(len(problem.axis))
+        E = np.asarray(problem.E, dtype=np.complex128)
+        if not np.allclose(E, E.conj().T, rtol=0, atol=1e-14 * max(1.0, np.abs(E).max())):
+            raise ValueError("E must be Hermitian")
+        self.omega = np.ascontiguousarray(problem.omega, dtype=np.float64)
+        self.N = np.ascontiguousarray(problem.N, dtype=np.int32)
+        self.axis = np.ascontiguousarray(problem.axis, dtype=np.int32)
+        self.harm = np.ascontiguousarray(problem.harm, dtype=np.int32)
+        self.E = torch.from_numpy(np.ascontiguousarray(E.T)).to(device)
+        if self.K:
+            V = np.asarray(problem.V, dtype=np.complex128)
+            self.V = torch.from_numpy(np.ascontiguousarray(V.transpose(0, 2, 1))).to(device)
+        else:
+            self.V = torch.zeros(1, dtype=torch.complex128, device=device)
+        self.struct = MMFProblem(
+            self.D, self.F, self.K,
+            self.omega.ctypes.data if self.F else None, self.N.ctypes.data if self.F else None,
+            self.axis.ctypes.data if self.K else None, self.harm.ctypes.data if self.K else None,
+            self.E.data_ptr(), self.V.data_ptr() if self.K else None)
+        self.M = floquet_dim(self)
+        self.device = device
+        S = self.M // self.D
+        s0, stride = 0, 1
+        for n in self.N:
+            s0 += int(n) * stride
+            stride *= 2 * int(n) + 1
+        self.S, self.s0 = S, s0
+
+    @property
+    def ref(self):
+        return C.byref(self.struct)
+
+
+def floquet_dim(dp: DeviceProblem) -> int:
+    M = C.c_int64(0)
+    call("mmf_floquet_dim", dp.ref, C.byref(M))
+    return int(M.value)
+
+
+def build_floquet(dp: DeviceProblem, out=None, stream=None):
+    """H_F in column-major storage: returns HFt with H_F = HFt.T."""
+    torch = _torch()
+    M = dp.M
+    if out is None:
+        out = torch.empty((M, M), dtype=torch.complex128, device=dp.device)
+    call("mmf_build_floquet", dp.ref, _ptr(out), C.c_int64(out.stride(0)), _stream(stream))
+    return out
+
+
+def eigh_workspace_bytes(M: int, prec: int = MMF_C128) -> int:
+    b = C.c_size_t(0)
+    call("mmf_eigh_workspace", C.c_int64(M), C.c_int(prec), C.byref(b))
+    return int(b.value)
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def eigh(At, prec: int = MMF_C128, w=None, work=None, info=None, stream=None):
+    """In-place eigendecomposition of the Hermitian matrix held (column-major)
+    in At.  Returns (w, At, info): eigenvalues ascending; At's row a is the
+    eigenvector of w[a]; info a device int32 (0 = converged)."""
+    torch = _torch()
+    M = At.shape[0]
+    dev = At.device
+    if w is None:
+        w = torch.empty(M, dtype=torch.float64, device=dev)
+    if work is None:
+        work = _workspace(eigh_workspace_bytes(M, prec), dev)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+    call("mmf_eigh", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), _ptr(w), C.c_int(prec),
+         _ptr(work), C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return w, At, info
+
+
+def hetrd(At, work=None, stream=None):
+    """Stage 1: returns (d, e, tau); At's column i (row i of the tensor) keeps
+    the reflector v_i below the diagonal."""
+    torch = _torch()
+    n = At.shape[0]
+    dev = At.device
+    d = torch.empty(n, dtype=torch.float64, device=dev)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
+    tau = torch.empty(max(n - 1, 1), dtype=torch.complex128, device=dev)
+    if work is None:
+        work = _workspace(eigh_workspace_bytes(n), dev)
+    call("mmf_hetrd", C.c_int64(n), _ptr(At), C.c_int64(At.stride(0)), _ptr(d), _ptr(e), _ptr(tau),
+         _ptr(work), C.c_size_t(work.numel()), _stream(stream))
+    return d, e, tau
+
+
+def stedc(d, e, work=None, stream=None):
+    """Stage 2: eigenpairs of the real symmetric tridiagonal (d, e).  Returns
+    (w, Zt, info) with Z = Zt.T (column a = eigenvector a); d is overwritten."""
+    torch = _torch()
+    n = d.shape[0]
+    dev = d.device
+    Zt = torch.empty((n, n), dtype=torch.float64, device=dev)
+    if work is None:
+        work = _workspace(eigh_workspace_bytes(n), dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    call("mmf_stedc", C.c_int64(n), _ptr(d), _ptr(e), _ptr(Zt), C.c_int64(n), _ptr(work),
+         C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return d, Zt, info
+
+
+def unmtr(Vt, tau, Zt, out=None, work=None, stream=None):
+    """Stage 3: Phi = Q Z (column-major tensors as elsewhere)."""
+    torch = _torch()
+    n = Vt.shape[0]
+    dev = Vt.device
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    if work is None:
+        work = _workspace(eigh_workspace_bytes(n), dev)
+    call("mmf_unmtr", C.c_int64(n), _ptr(Vt), C.c_int64(Vt.stride(0)), _ptr(tau), _ptr(Zt),
+         C.c_int64(Zt.stride(0)), _ptr(out), C.c_int64(out.stride(0)), _ptr(work),
+         C.c_size_t(work.numel()), _stream(stream))
+    return out
+
+
+def evolve(dp: DeviceProblem, Pt, w, t0: float, t, work=None, stream=None):
+    """U(t, t0) for every time in t (device float64).  Returns U[tau, i, j]."""
+    torch = _torch()
+    T = int(t.shape[0])
+    D = dp.D
+    U = torch.empty((T, D, D), dtype=torch.complex128, device=Pt.device)
+    if work is None:
+        b = C.c_size_t(0)
+        call("mmf_evolve_workspace", dp.ref, C.c_int32(T), C.byref(b))
+        work = _workspace(b.value, Pt.device)
+    call("mmf_evolve", dp.ref, _ptr(Pt), C.c_int64(Pt.stride(0)), _ptr(w), C.c_double(t0),
+         C.c_int32(T), _ptr(t), _ptr(U), _ptr(work), C.c_size_t(work.numel()), _stream(stream))
+    return U.transpose(1, 2)
+
+
+def micromotion(dp: DeviceProblem, Pt, w, t, work=None, stream=None):
+    """U_F(t) over one representative per orbit.  Returns (UF[tau, i, b],
+    eps_sel[b], sel[b], info)."""
+    torch = _torch()
+    T = int(t.shape[0])
+    D = dp.D
+    dev = Pt.device
+    UF = torch.empty((T, D, D), dtype=torch.complex128, device=dev)
+    eps = torch.empty(D, dtype=torch.float64, device=dev)
+    sel = torch.empty(D, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if work is None:
+        b = C.c_size_t(0)
+        call("mmf_evolve_workspace", dp.ref, C.c_int32(max(T, 1)), C.byref(b))
+        work = _workspace(b.value, dev)
+    call("mmf_micromotion", dp.ref, _ptr(Pt), C.c_int64(Pt.stride(0)), _ptr(w), C.c_int32(T), _ptr(t),
+         _ptr(UF), _ptr(eps), _ptr(sel), _ptr(work), C.c_size_t(work.numel()), _ptr(info),
+         _stream(stream))
+    return UF.transpose(1, 2), eps, sel, info
+
+
+def avg_prob(dp: DeviceProblem, Pt, work=None, stream=None):
+    """Averaged transition probabilities P[i, j] (i final, j initial)."""
+    torch = _torch()
+    D = dp.D
+    P = torch.empty((D, D), dtype=torch.float64, device=Pt.device)
+    if work is None:
+        b = C.c_size_t(0)
+        call("mmf_avg_prob_workspace", dp.ref, C.byref(b))
+        work = _workspace(b.value, Pt.device)
+    call("mmf_avg_prob", dp.ref, _ptr(Pt), C.c_int64(Pt.stride(0)), _ptr(P), _ptr(work),
+         C.c_size_t(work.numel()), _stream(stream))
+    return P.T
+
+
+def solve(problem, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda"):
+    """One Floquet solve: assemble -> eigh -> U at times t -> averaged P.
+    Returns a dict of device tensors (w, Pt, U, P, info)."""
+    torch = _torch()
+    dp = problem if isinstance(problem, DeviceProblem) else DeviceProblem(problem, device)
+    tt = t if torch.is_tensor(t) else torch.as_tensor(np.asarray(t, dtype=np.float64), device=dp.device)
+    HF = build_floquet(dp)
+    w, Pt, info = eigh(HF, prec)
+    U = evolve(dp, Pt, w, t0, tt)
+    P = avg_prob(dp, Pt)
+    return {"w": w, "Pt": Pt, "U": U, "P": P, "info": info, "dp": dp}

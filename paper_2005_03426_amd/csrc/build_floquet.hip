@@ -1,0 +1,125 @@
+// Assembly of the truncated multimode Floquet matrix (Sec. 2, Eq. 6;
+// block layout of Appendix A) and the small host-only entry points.
+//
+// H_F[(i,n),(j,m)] = H^{[n-m]}_{ij} + delta_{nm} delta_{ij} (n . w)
+//   H^{[0]} = E; H^{[+h e_l]} = sum_k V_k over couplings (l, h); H^{[-h e_l]}
+//   = sum_k V_k^H over the same couplings; any other offset gives a zero block.
+// Row r = i + D s, site s = sum_l (N_l - n_l) prod_{l'<l} (2 N_{l'} + 1).
+//
+// The kernel is a pure HBM store stream (16 M^2 bytes): each thread owns one
+// row and walks a strip of columns, so a wavefront writes 64 consecutive
+// complex numbers (1 KB) of one column per step.  The column site is uniform
+// across the workgroup, so its mixed-radix decode is scalar work.
+#include "common.h"
+#include "problem.h"
+
+namespace mmf {
+
+constexpr int ASM_ROWS = 256;    // rows per workgroup
+constexpr int ASM_COLS = 32;     // columns per workgroup
+
+__device__ inline void decode_site(const FloqParams &fp, int64_t s, int32_t *n) {
+  for (int l = 0; l < MAX_F; ++l) {
+    if (l >= fp.F) break;
+    const int64_t q = s % fp.radix[l];
+    s /= fp.radix[l];
+    n[l] = fp.N[l] - (int32_t)q;
+  }
+}
+
+// E_ii + n.w evaluated as ((E_ii + n_0 w_0) + n_1 w_1) + ..., one rounding per
+// product and per sum (no fused multiply-add), in the same order as the
+// CPU definition.
+__device__ __noinline__ double diag_shift(double e, const FloqParams &fp, const int32_t *n) {
+#pragma clang fp contract(off)
+  double x = e;
+  for (int l = 0; l < MAX_F; ++l) {
+    if (l >= fp.F) break;
+    const double prod = (double)n[l] * fp.omega[l];
+    x = x + prod;
+  }
+  return x;
+}
+
+__global__ void __launch_bounds__(ASM_ROWS)
+assemble_kernel(FloqParams fp, const mmf_z *__restrict__ E, const mmf_z *__restrict__ V,
+                mmf_z *__restrict__ HF, int64_t ldh) {
+  const int64_t r = (int64_t)blockIdx.x * ASM_ROWS + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * ASM_COLS;
+  if (r >= fp.M) return;
+  const int D = fp.D;
+  const int i = (int)(r % D);
+  const int64_t sr = r / D;
+  int32_t nr[MAX_F];
+  decode_site(fp, sr, nr);
+  const int64_t cend = (c0 + ASM_COLS < fp.M) ? c0 + ASM_COLS : fp.M;
+  for (int64_t c = c0; c < cend; ++c) {
+    const int j = (int)(c % D);
+    const int64_t sc = c / D;
+    int32_t nc[MAX_F];
+    decode_site(fp, sc, nc);
+    int nnz = 0, lax = -1, dval = 0;
+    for (int l = 0; l < MAX_F; ++l) {
+      if (l >= fp.F) break;
+      const int dl = nr[l] - nc[l];
+      if (dl != 0) { ++nnz; lax = l; dval = dl; }
+    }
+    cd v = cmake(0.0, 0.0);
+    if (nnz == 0) {
+      v = ldz(E + i + (int64_t)D * j);
+      if (i == j) v.re = diag_shift(v.re, fp, nr);
+    } else if (nnz == 1) {
+      bool first = true;
+      for (int k = 0; k < fp.K; ++k) {
+        if (fp.axis[k] != lax) continue;
+        cd t;
+        if (fp.harm[k] == dval) t = ldz(V + (int64_t)k * D * D + i + (int64_t)D * j);
+        else if (fp.harm[k] == -dval) t = cconj(ldz(V + (int64_t)k * D * D + j + (int64_t)D * i));
+        else continue;
+        v = first ? t : cadd(v, t);
+        first = false;
+      }
+    }
+    stz(HF + r + c * ldh, v);
+  }
+}
+
+}  // namespace mmf
+
+using namespace mmf;
+
+extern "C" int mmf_floquet_dim(const mmf_problem *p, int64_t *M) {
+  FloqParams fp;
+  const int rc = problem_params(p, 1, &fp);
+  if (rc) return rc;
+  if (!M) return -2;
+  *M = fp.M;
+  return MMF_OK;
+}
+
+extern "C" int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *stream) {
+  FloqParams fp;
+  const int rc = problem_params(p, 1, &fp);
+  if (rc) return rc;
+  if (!HF) return -2;
+  if (ldh < fp.M) return -3;
+  dim3 grid(cdiv(fp.M, ASM_ROWS), cdiv(fp.M, ASM_COLS));
+  hipLaunchKernelGGL(assemble_kernel, grid, dim3(ASM_ROWS), 0, (hipStream_t)stream, fp, p->E,
+                     p->V, HF, ldh);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+extern "C" const char *mmf_strerror(int code) {
+  if (code < 0) return "invalid argument (the negated code is the argument position)";
+  switch (code) {
+    case MMF_OK: return "success";
+    case MMF_ERR_HIP: return "HIP runtime error";
+    case MMF_ERR_WORKSPACE: return "workspace too small";
+    case MMF_ERR_NOT_IMPLEMENTED: return "option not implemented";
+    case MMF_ERR_NO_CONVERGENCE: return "iteration did not converge";
+    case MMF_ERR_SELECTION: return "micromotion: not exactly D orbit representatives";
+    case MMF_ERR_TOO_LARGE: return "problem too large";
+    default: return "unknown error";
+  }
+}

@@ -1,0 +1,73 @@
+// Shared device/host helpers of libmmf (internal header, not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "mmf.h"
+
+#define MMF_HIP_TRY(expr)                                   \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return MMF_ERR_HIP;               \
+  } while (0)
+
+#define MMF_LAUNCH_CHECK() MMF_HIP_TRY(hipGetLastError())
+
+namespace mmf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Complex arithmetic on interleaved (re, im) doubles.
+struct cd {
+  double re, im;
+};
+
+__host__ __device__ inline cd cmake(double r, double i) { cd z; z.re = r; z.im = i; return z; }
+__device__ inline cd cadd(cd a, cd b) { return cmake(a.re + b.re, a.im + b.im); }
+__device__ inline cd csub(cd a, cd b) { return cmake(a.re - b.re, a.im - b.im); }
+__device__ inline cd cmul(cd a, cd b) { return cmake(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+// conj(a) * b
+__device__ inline cd cmulc(cd a, cd b) { return cmake(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re); }
+__device__ inline cd cconj(cd a) { return cmake(a.re, -a.im); }
+__device__ inline cd cscale(cd a, double s) { return cmake(a.re * s, a.im * s); }
+__device__ inline double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+
+__device__ inline cd ldz(const mmf_z *p) {
+  const double2 v = *reinterpret_cast<const double2 *>(p);
+  return cmake(v.x, v.y);
+}
+__device__ inline void stz(mmf_z *p, cd v) {
+  double2 t; t.x = v.re; t.y = v.im;
+  *reinterpret_cast<double2 *>(p) = t;
+}
+
+// Wavefront-wide sum (64 lanes) with DPP/shuffle via __shfl_xor.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// 256-byte aligned carving of a caller workspace.
+struct Carver {
+  char *base;
+  size_t off;
+  explicit Carver(void *p) : base((char *)p), off(0) {}
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *r = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return r;
+  }
+  size_t used() const { return (off + 255) & ~(size_t)255; }
+};
+
+}  // namespace mmf

@@ -1,0 +1,391 @@
+// Blocked Householder reduction of a complex Hermitian matrix to a real
+// symmetric tridiagonal matrix (stage 1 of the dense eigensolve that the
+// paper delegates to LAPACK, Sec. 3.2).
+//
+// Q^H A Q = T,  Q = H_0 H_1 ... H_{n-2},  H_i = I - tau_i v_i v_i^H,
+// v_i = (0,..,0, 1, x/(alpha - beta)) with beta = -sign(Re alpha) ||(alpha, x)||
+// real, so T is real: d_i = Re a_ii, e_i = beta_i.
+//
+// Panels of HT_NB columns.  Inside a panel, column i = p + k is reduced
+// against the *unupdated* trailing matrix: with V, W the panel's previous
+// reflectors and their companions, the current trailing matrix is
+// A - V W^H - W V^H, so
+//   u = A v - V (W^H v) - W (V^H v),   w0 = tau u,   w = w0 - (tau/2)(w0^H v) v.
+// After the panel the trailing matrix takes one rank-2k update
+// A -= [V W] [W V]^H on the FP64 matrix cores (lower triangle only).
+//
+// Per column the row-parallel kernels are: reflector (scale x), HEMV over
+// the lower trailing triangle (64x64 tiles, each workgroup a strip of tiles
+// of one block column: the direct product goes to per-(block-column, row)
+// partials, the conjugate-transposed product accumulates in registers), the
+// panel corrections W^H v / V^H v, the reduction of the partials into w0,
+// and the final w together with the update of the next panel column.  All
+// sums are over fixed partitions in fixed order (deterministic).
+#include "common.h"
+#include "stages.h"
+#include "gemm_core.h"
+
+namespace mmf {
+
+constexpr int HV_T = 64;        // HEMV tile
+constexpr int HV_CH = 8;        // tiles per HEMV workgroup (one block column strip)
+constexpr int RW = 256;         // rows per workgroup in row-parallel kernels
+constexpr int DOT_ROWS = 1024;  // rows per workgroup of the panel dot products
+
+__device__ inline double block_sum256(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;
+}
+
+struct HtWs {
+  mmf_z *P3;       // n x 3NB (ld n): [V | W | V]
+  mmf_z *pdir;     // nbt x mpad
+  mmf_z *ptrn;     // nbt x nchmax x 64
+  mmf_z *dots;     // gdot x 2NB
+  double *norms;   // grow partials
+  mmf_z *sparts;   // grow partials
+  mmf_z *w0first;  // 1
+  int64_t nbt, mpad, nchmax;
+  size_t bytes;
+};
+
+inline HtWs hetrd_ws(int64_t n, void *base) {
+  Carver cv(base);
+  HtWs w;
+  const int64_t m = n > 1 ? n - 1 : 1;
+  w.nbt = (m + HV_T - 1) / HV_T;
+  w.mpad = w.nbt * HV_T;
+  w.nchmax = (w.nbt + HV_CH - 1) / HV_CH;
+  w.P3 = cv.take<mmf_z>((size_t)n * 3 * HT_NB);
+  w.pdir = cv.take<mmf_z>((size_t)w.nbt * w.mpad);
+  w.ptrn = cv.take<mmf_z>((size_t)w.nbt * w.nchmax * HV_T);
+  const int64_t gdot = (n + DOT_ROWS - 1) / DOT_ROWS + 1;
+  w.dots = cv.take<mmf_z>((size_t)gdot * 2 * HT_NB);
+  const int64_t grow = (n + RW - 1) / RW + 1;
+  w.norms = cv.take<double>(grow);
+  w.sparts = cv.take<mmf_z>(grow);
+  w.w0first = cv.take<mmf_z>(4);
+  w.bytes = cv.used();
+  return w;
+}
+
+size_t hetrd_ws_bytes(int64_t n) { return hetrd_ws(n, nullptr).bytes; }
+
+// ---------------------------------------------------------------- kernels
+__global__ void ht_zero_panel(mmf_z *P3, int64_t n, int64_t p) {
+  const int64_t r = p + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int c = 0; c < 3 * HT_NB; ++c) stz(P3 + r + c * n, cmake(0.0, 0.0));
+}
+
+// partial ||A[i+2:, i]||^2 (first column of a panel)
+__global__ void __launch_bounds__(RW) ht_colnorm(const mmf_z *A, int64_t lda, int64_t n, int64_t i,
+                                                double *norms) {
+  __shared__ double sh[4];
+  const int64_t r = i + 2 + (int64_t)blockIdx.x * RW + threadIdx.x;
+  double s = 0.0;
+  if (r < n) s = cabs2(ldz(A + r + i * lda));
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) norms[blockIdx.x] = s;
+}
+
+// Reflector of column i: every workgroup derives (beta, tau) from the norm
+// partials and scales its rows of x into v.
+__global__ void __launch_bounds__(RW) ht_reflector(mmf_z *A, int64_t lda, int64_t n, int64_t i, int k,
+                                                  mmf_z *P3, const double *norms, int gnorm,
+                                                  double *d, double *e, mmf_z *tau) {
+  double xn2 = 0.0;
+  for (int g = 0; g < gnorm; ++g) xn2 += norms[g];
+  const cd alpha = ldz(A + (i + 1) + i * lda);
+  double beta;
+  cd t, scale;
+  if (xn2 == 0.0 && alpha.im == 0.0) {
+    beta = alpha.re;
+    t = cmake(0.0, 0.0);
+    scale = cmake(0.0, 0.0);
+  } else {
+    const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
+    beta = alpha.re >= 0.0 ? -nrm : nrm;
+    t = cmake((beta - alpha.re) / beta, -alpha.im / beta);
+    // scale = 1 / (alpha - beta)
+    const cd den = cmake(alpha.re - beta, alpha.im);
+    const double q = den.re * den.re + den.im * den.im;
+    scale = cmake(den.re / q, -den.im / q);
+  }
+  const int64_t r = i + 2 + (int64_t)blockIdx.x * RW + threadIdx.x;
+  if (r < n) {
+    const cd v = cmul(ldz(A + r + i * lda), scale);
+    stz(A + r + i * lda, v);
+    stz(P3 + r + (int64_t)k * n, v);
+    stz(P3 + r + (int64_t)(2 * HT_NB + k) * n, v);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    stz(P3 + (i + 1) + (int64_t)k * n, cmake(1.0, 0.0));
+    stz(P3 + (i + 1) + (int64_t)(2 * HT_NB + k) * n, cmake(1.0, 0.0));
+    d[i] = ldz(A + i + i * lda).re;
+    e[i] = beta;
+    stz(tau + i, t);
+  }
+}
+
+// u = A_trail v over the lower triangle of the trailing matrix
+// A_trail = A[i+1:, i+1:] (size m).  Workgroup (bj, c): block column bj, tile
+// rows bi = bj + c*HV_CH ... ; thread (row r, wave cg) covers columns
+// cg*16 .. cg*16+15 of every tile.
+__global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int64_t n, int64_t i,
+                                               const mmf_z *P3, int k, mmf_z *pdir, mmf_z *ptrn,
+                                               int64_t mpad, int64_t nchmax) {
+  __shared__ cd vcol[HV_T];
+  __shared__ cd red[4][HV_T];
+  __shared__ cd tsh[HV_T][HV_T + 1];
+  const int64_t m = n - i - 1;
+  const int64_t nbt = (m + HV_T - 1) / HV_T;
+  const int64_t bj = blockIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t bi0 = bj + c * HV_CH;
+  if (bi0 >= nbt) return;
+  const int64_t bi1 = (bi0 + HV_CH < nbt) ? bi0 + HV_CH : nbt;
+  const int tid = threadIdx.x;
+  const int r = tid & 63, cg = tid >> 6;
+  const mmf_z *At = A + (i + 1) + (i + 1) * lda;
+  const mmf_z *v = P3 + (i + 1) + (int64_t)k * n;
+  if (tid < HV_T) {
+    const int64_t gc = bj * HV_T + tid;
+    vcol[tid] = gc < m ? ldz(v + gc) : cmake(0.0, 0.0);
+  }
+  __syncthreads();
+  cd tacc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tacc[q] = cmake(0.0, 0.0);
+  for (int64_t bi = bi0; bi < bi1; ++bi) {
+    const int64_t row = bi * HV_T + r;
+    const bool rin = row < m;
+    const cd vr = rin ? ldz(v + row) : cmake(0.0, 0.0);
+    cd av[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t gc = bj * HV_T + cg * 16 + q;
+      const bool ok = rin && gc < m && (bi > bj || row >= gc);
+      av[q] = ok ? ldz(At + row + gc * lda) : cmake(0.0, 0.0);
+    }
+    cd dacc = cmake(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t gc = bj * HV_T + cg * 16 + q;
+      cd a = av[q];
+      const bool diag = (bi == bj) && (row == gc);
+      if (diag) a.im = 0.0;
+      dacc = cadd(dacc, cmul(a, vcol[cg * 16 + q]));
+      if (!diag) tacc[q] = cadd(tacc[q], cmulc(a, vr));
+    }
+    red[cg][r] = dacc;
+    __syncthreads();
+    if (tid < HV_T) {
+      const cd s = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
+      stz(pdir + bj * mpad + bi * HV_T + tid, s);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tsh[cg * 16 + q][r] = tacc[q];
+  __syncthreads();
+  if (tid < HV_T) {
+    cd s = cmake(0.0, 0.0);
+    for (int rr = 0; rr < HV_T; ++rr) s = cadd(s, tsh[tid][rr]);
+    stz(ptrn + (bj * nchmax + c) * HV_T + tid, s);
+  }
+}
+
+// Panel corrections: dots[g*2NB + q] = sum_rows conj(W[:,q]) v (q < k) and
+// dots[g*2NB + NB + q] = sum_rows conj(V[:,q]) v over rows [i+1, n).
+__global__ void __launch_bounds__(256) ht_dots(const mmf_z *P3, int64_t n, int64_t i, int k, mmf_z *dots) {
+  __shared__ double sh[4];
+  const int g = blockIdx.x;
+  const int qq = blockIdx.y;                 // 0..2k-1
+  const int q = qq % k, which = qq / k;
+  const mmf_z *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
+  const mmf_z *v = P3 + (int64_t)k * n;
+  cd s = cmake(0.0, 0.0);
+  const int64_t r0 = i + 1 + (int64_t)g * DOT_ROWS;
+  for (int j = threadIdx.x; j < DOT_ROWS; j += 256) {
+    const int64_t r = r0 + j;
+    if (r < n) s = cadd(s, cmulc(ldz(X + r), ldz(v + r)));
+  }
+  const double sr = block_sum256(s.re, sh);
+  const double si = block_sum256(s.im, sh);
+  if (threadIdx.x == 0) stz(dots + (int64_t)g * 2 * HT_NB + which * HT_NB + q, cmake(sr, si));
+}
+
+// w0 = tau (u - V x1 - W x2), with u assembled from the HEMV partials.
+__global__ void __launch_bounds__(RW) ht_finish_u(int64_t n, int64_t i, int k, mmf_z *P3,
+                                                 const mmf_z *pdir, const mmf_z *ptrn, int64_t mpad,
+                                                 int64_t nchmax, const mmf_z *dots, int gdot,
+                                                 const mmf_z *tau, mmf_z *sparts, mmf_z *w0first) {
+  __shared__ cd x1[HT_NB], x2[HT_NB];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  if (tid < 2 * k) {
+    const int q = tid % k, which = tid / k;
+    cd s = cmake(0.0, 0.0);
+    for (int g = 0; g < gdot; ++g) s = cadd(s, ldz(dots + (int64_t)g * 2 * HT_NB + which * HT_NB + q));
+    if (which == 0) x1[q] = s; else x2[q] = s;
+  }
+  __syncthreads();
+  const int64_t m = n - i - 1;
+  const int64_t nbt = (m + HV_T - 1) / HV_T;
+  const int64_t t = (int64_t)blockIdx.x * RW + tid;
+  cd contrib = cmake(0.0, 0.0);
+  if (t < m) {
+    const int64_t bi = t / HV_T;
+    cd u = cmake(0.0, 0.0);
+    for (int64_t bj = 0; bj <= bi; ++bj) u = cadd(u, ldz(pdir + bj * mpad + t));
+    const int64_t nch = (nbt - bi + HV_CH - 1) / HV_CH;
+    for (int64_t c = 0; c < nch; ++c) u = cadd(u, ldz(ptrn + (bi * nchmax + c) * HV_T + (t % HV_T)));
+    const int64_t rho = i + 1 + t;
+    for (int q = 0; q < k; ++q) {
+      u = csub(u, cmul(ldz(P3 + rho + (int64_t)q * n), x1[q]));
+      u = csub(u, cmul(ldz(P3 + rho + (int64_t)(HT_NB + q) * n), x2[q]));
+    }
+    const cd w0 = cmul(ldz(tau + i), u);
+    stz(P3 + rho + (int64_t)(HT_NB + k) * n, w0);
+    if (t == 0) w0first[0] = *reinterpret_cast<const mmf_z *>(&w0);
+    contrib = cmulc(ldz(P3 + rho + (int64_t)k * n), w0);   // conj(v) w0
+  }
+  const double sr = block_sum256(contrib.re, sh);
+  const double si = block_sum256(contrib.im, sh);
+  if (tid == 0) stz(sparts + blockIdx.x, cmake(sr, si));
+}
+
+// w = w0 - (tau/2) conj(v^H w0) v; then, inside a panel, the update of the
+// next column i+1 by the k+1 reflectors so far and its partial norms.
+__global__ void __launch_bounds__(RW) ht_finish_w(mmf_z *A, int64_t lda, int64_t n, int64_t i, int k,
+                                                 int next, mmf_z *P3, const mmf_z *sparts, int gs,
+                                                 const mmf_z *tau, const mmf_z *w0first, double *norms) {
+  __shared__ cd cw[HT_NB], cv[HT_NB];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  cd s = cmake(0.0, 0.0);
+  for (int g = 0; g < gs; ++g) s = cadd(s, ldz(sparts + g));
+  const cd ti = ldz(tau + i);
+  const cd alpha = cscale(cmul(ti, cconj(s)), -0.5);
+  if (next && tid <= k) {
+    const int64_t rr = i + 1;
+    cd wq;
+    if (tid == k) {
+      const cd w0 = ldz(w0first);
+      wq = cadd(w0, alpha);                   // v[i+1] = 1
+    } else {
+      wq = ldz(P3 + rr + (int64_t)(HT_NB + tid) * n);
+    }
+    cw[tid] = cconj(wq);
+    cv[tid] = cconj(ldz(P3 + rr + (int64_t)tid * n));
+  }
+  __syncthreads();
+  const int64_t rho = i + 1 + (int64_t)blockIdx.x * RW + tid;
+  double nrm = 0.0;
+  if (rho < n) {
+    const cd v = ldz(P3 + rho + (int64_t)k * n);
+    const cd w = cadd(ldz(P3 + rho + (int64_t)(HT_NB + k) * n), cmul(alpha, v));
+    stz(P3 + rho + (int64_t)(HT_NB + k) * n, w);
+    if (rho == i + 1) stz(A + rho + i * lda, cmake(1.0, 0.0));
+    if (next) {
+      cd a = ldz(A + rho + (i + 1) * lda);
+      for (int q = 0; q < k; ++q) {
+        a = csub(a, cmul(ldz(P3 + rho + (int64_t)q * n), cw[q]));
+        a = csub(a, cmul(ldz(P3 + rho + (int64_t)(HT_NB + q) * n), cv[q]));
+      }
+      a = csub(a, cmul(v, cw[k]));
+      a = csub(a, cmul(w, cv[k]));
+      stz(A + rho + (i + 1) * lda, a);
+      if (rho >= i + 3) nrm = cabs2(a);
+    }
+  }
+  nrm = block_sum256(nrm, sh);
+  if (next && tid == 0) norms[blockIdx.x] = nrm;
+}
+
+__global__ void ht_last_diag(const mmf_z *A, int64_t lda, int64_t n, double *d) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) d[n - 1] = ldz(A + (n - 1) + (n - 1) * lda).re;
+}
+
+// ---------------------------------------------------------------- host
+int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau, void *work,
+              size_t bytes, hipStream_t st) {
+  if (n <= 0) return MMF_OK;
+  HtWs w = hetrd_ws(n, work);
+  if (bytes < w.bytes) return MMF_ERR_WORKSPACE;
+  for (int64_t p = 0; p < n - 1; p += HT_NB) {
+    const int kb = (int)((n - 1 - p < HT_NB) ? n - 1 - p : HT_NB);
+    hipLaunchKernelGGL(ht_zero_panel, dim3(cdiv(n - p, 256)), dim3(256), 0, st, w.P3, n, p);
+    MMF_LAUNCH_CHECK();
+    {
+      const int g = (int)cdiv(n - p - 2 > 0 ? n - p - 2 : 1, RW);
+      hipLaunchKernelGGL(ht_colnorm, dim3(g), dim3(RW), 0, st, A, lda, n, p, w.norms);
+      MMF_LAUNCH_CHECK();
+    }
+    int gnorm = (int)cdiv(n - p - 2 > 0 ? n - p - 2 : 1, RW);
+    for (int k = 0; k < kb; ++k) {
+      const int64_t i = p + k;
+      const int64_t m = n - i - 1;
+      {
+        const int g = (int)cdiv(n - i - 2 > 0 ? n - i - 2 : 1, RW);
+        hipLaunchKernelGGL(ht_reflector, dim3(g), dim3(RW), 0, st, A, lda, n, i, k, w.P3, w.norms,
+                           gnorm, d, e, tau);
+        MMF_LAUNCH_CHECK();
+      }
+      const int64_t nbt = (m + HV_T - 1) / HV_T;
+      const int64_t nch = (nbt + HV_CH - 1) / HV_CH;
+      hipLaunchKernelGGL(ht_hemv, dim3((unsigned)nbt, (unsigned)nch), dim3(256), 0, st, A, lda, n, i,
+                         w.P3, k, w.pdir, w.ptrn, w.mpad, w.nchmax);
+      MMF_LAUNCH_CHECK();
+      const int gdot = (int)cdiv(m, DOT_ROWS);
+      if (k > 0) {
+        hipLaunchKernelGGL(ht_dots, dim3(gdot, 2 * k), dim3(256), 0, st, w.P3, n, i, k, w.dots);
+        MMF_LAUNCH_CHECK();
+      }
+      const int gu = (int)cdiv(m, RW);
+      hipLaunchKernelGGL(ht_finish_u, dim3(gu), dim3(RW), 0, st, n, i, k, w.P3, w.pdir, w.ptrn, w.mpad,
+                         w.nchmax, w.dots, gdot, tau, w.sparts, w.w0first);
+      MMF_LAUNCH_CHECK();
+      const int next = (k + 1 < kb) ? 1 : 0;
+      hipLaunchKernelGGL(ht_finish_w, dim3(gu), dim3(RW), 0, st, A, lda, n, i, k, next, w.P3,
+                         w.sparts, gu, tau, w.w0first, w.norms);
+      MMF_LAUNCH_CHECK();
+      gnorm = gu;
+    }
+    // trailing update A[q:, q:] -= [V W] [W V]^H  (lower triangle)
+    const int64_t q = p + kb;
+    if (q < n) {
+      GemmArgs g = gemm_args(n - q, n - q, 2 * HT_NB, w.P3 + q, n, w.P3 + q + (int64_t)HT_NB * n, n,
+                             A + q + q * lda, lda, -1.0, 0.0, 1.0, 0.0);
+      g.lower = 1;
+      const int rc = gemm_launch<true, A_N, B_C>(g, st);
+      if (rc) return rc;
+    }
+  }
+  hipLaunchKernelGGL(ht_last_diag, dim3(1), dim3(64), 0, st, A, lda, n, d);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+}  // namespace mmf
+
+using namespace mmf;
+
+extern "C" int mmf_hetrd(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau,
+                         void *work, size_t work_bytes, void *stream) {
+  if (n < 0) return -1;
+  if (!A) return -2;
+  if (lda < n || lda < 1) return -3;
+  if (!d) return -4;
+  if (n > 1 && !e) return -5;
+  if (n > 1 && !tau) return -6;
+  if (!work) return -7;
+  if (work_bytes < hetrd_ws_bytes(n)) return -8;
+  return hetrd_run(n, A, lda, d, e, tau, work, work_bytes, (hipStream_t)stream);
+}

@@ -1,0 +1,61 @@
+// Host-side validation of mmf_problem and the small by-value kernel
+// parameter block derived from it (internal).
+#pragma once
+#include <math.h>
+#include "common.h"
+
+namespace mmf {
+
+constexpr int MAX_F = 8;
+constexpr int MAX_K = 64;
+constexpr int MAX_D = 64;
+
+struct FloqParams {
+  int32_t D, F, K;
+  int32_t N[MAX_F];
+  int32_t radix[MAX_F];        // 2 N_l + 1
+  double omega[MAX_F];
+  int32_t axis[MAX_K];
+  int32_t harm[MAX_K];
+  int64_t S;                   // number of Fourier sites
+  int64_t M;                   // D * S
+  int64_t s0;                  // site of n = 0
+};
+
+// Validates p and fills fp.  Returns 0 or a negative argument code (-argpos).
+inline int problem_params(const mmf_problem *p, int argpos, FloqParams *fp) {
+  if (!p) return -argpos;
+  if (p->D < 1 || p->D > MAX_D) return -argpos;
+  if (p->F < 0 || p->F > MAX_F) return -argpos;
+  if (p->K < 0 || p->K > MAX_K) return -argpos;
+  if (p->F > 0 && (!p->omega || !p->N)) return -argpos;
+  if (p->K > 0 && (!p->axis || !p->harm || !p->V)) return -argpos;
+  if (!p->E) return -argpos;
+  fp->D = p->D; fp->F = p->F; fp->K = p->K;
+  int64_t S = 1, s0 = 0;
+  for (int l = 0; l < MAX_F; ++l) { fp->N[l] = 0; fp->radix[l] = 1; fp->omega[l] = 0.0; }
+  for (int l = 0; l < p->F; ++l) {
+    if (p->N[l] < 0 || p->N[l] > (1 << 20)) return -argpos;
+    if (!isfinite(p->omega[l])) return -argpos;
+    fp->N[l] = p->N[l];
+    fp->radix[l] = 2 * p->N[l] + 1;
+    fp->omega[l] = p->omega[l];
+    s0 += (int64_t)p->N[l] * S;
+    S *= fp->radix[l];
+    if (S > ((int64_t)1 << 31)) return MMF_ERR_TOO_LARGE;
+  }
+  for (int k = 0; k < MAX_K; ++k) { fp->axis[k] = 0; fp->harm[k] = 0; }
+  for (int k = 0; k < p->K; ++k) {
+    if (p->axis[k] < 0 || p->axis[k] >= p->F) return -argpos;
+    if (p->harm[k] < 1) return -argpos;
+    fp->axis[k] = p->axis[k];
+    fp->harm[k] = p->harm[k];
+  }
+  fp->S = S;
+  fp->s0 = s0;
+  fp->M = S * p->D;
+  if (fp->M > (int64_t)0x7fffffff) return MMF_ERR_TOO_LARGE;
+  return 0;
+}
+
+}  // namespace mmf

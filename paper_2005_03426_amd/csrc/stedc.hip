@@ -1,0 +1,609 @@
+// Eigenpairs of a real symmetric tridiagonal matrix by Cuppen's divide and
+// conquer (stage 2 of the dense eigensolve, Sec. 3.2), with the rank-one
+// merge solved through the secular equation and Gu-Eisenstat's recomputed
+// z vector for orthogonal eigenvectors.
+//
+// Tree: L = 2^h leaves, leaf boundaries b(i) = floor(i n / L), each leaf at
+// most DC_LEAF rows.  Tearing at a boundary k subtracts |e_{k-1}| from
+// d_{k-1} and d_k, so T = diag(T1, T2) + rho u u^T with u = (.., 1 | s, ..),
+// s = sign(e_{k-1}), rho = |e_{k-1}|.
+//
+// Merge of (lam1, Q1) and (lam2, Q2) (m = n1 + n2 rows):
+//   z = (last row of Q1, s * first row of Q2) / sqrt 2, rho' = 2 rho,
+//   D + rho' z z^T with D = diag(lam1, lam2) sorted (parallel merge by binary
+//   search); deflation (sequential scan): |rho' z_j| <= tol, or a Givens
+//   rotation of a close pair (d_p, d_j) with |(d_j - d_p) c s| <= tol;
+//   secular equation f(x) = 1 + rho' sum z_i^2/(d_i - x) = 0 for the K
+//   remaining roots (one wavefront per root, origin shifted to the nearer
+//   pole, rational two-pole interpolation safeguarded by bisection);
+//   zhat_i^2 = prod_j (x_j - d_i) / (rho' prod_{j != i} (d_j - d_i));
+//   u_ij = zhat_i / (d_i - x_j) normalised; new vectors = Q_nd U (FP64 MFMA
+//   GEMM); eigenvalues merged in ascending order (rank by counting).
+// All per-merge scratch lives at the merge's own index range [s, t) of n-long
+// arrays, so every merge of a tree level runs in the same launches.
+#include <float.h>
+#include "common.h"
+#include "stages.h"
+#include "gemm_core.h"
+
+namespace mmf {
+
+constexpr int DC_LEAF = 64;
+constexpr double DC_EPS = DBL_EPSILON;
+
+struct DcWs {
+  double *dw, *lam, *T1, *T2;
+  double *ds, *zs, *dn, *zn, *ddef, *rc, *rs, *lamt, *zhat, *rho;
+  int32_t *src, *ndidx, *dfidx, *rp, *rj, *lamo, *colmap, *cnt;   // cnt: [3*n] K, R, ndef per merge
+  size_t bytes;
+};
+
+inline DcWs stedc_ws(int64_t n, void *base) {
+  Carver cv(base);
+  DcWs w;
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  w.dw = cv.take<double>(N);
+  w.lam = cv.take<double>(N);
+  w.T1 = cv.take<double>(N * N);
+  w.T2 = cv.take<double>(N * N);
+  w.ds = cv.take<double>(N);
+  w.zs = cv.take<double>(N);
+  w.dn = cv.take<double>(N);
+  w.zn = cv.take<double>(N);
+  w.ddef = cv.take<double>(N);
+  w.rc = cv.take<double>(N);
+  w.rs = cv.take<double>(N);
+  w.lamt = cv.take<double>(N);
+  w.zhat = cv.take<double>(N);
+  w.rho = cv.take<double>(N);
+  w.src = cv.take<int32_t>(N);
+  w.ndidx = cv.take<int32_t>(N);
+  w.dfidx = cv.take<int32_t>(N);
+  w.rp = cv.take<int32_t>(N);
+  w.rj = cv.take<int32_t>(N);
+  w.lamo = cv.take<int32_t>(N);
+  w.colmap = cv.take<int32_t>(N);
+  w.cnt = cv.take<int32_t>(3 * N);
+  w.bytes = cv.used();
+  return w;
+}
+
+size_t stedc_ws_bytes(int64_t n) { return stedc_ws(n, nullptr).bytes; }
+
+__device__ __host__ inline int64_t dc_b(int64_t i, int64_t n, int64_t L) { return (i * n) / L; }
+
+struct MergeGeom {
+  int64_t s, mid, t, m, n1;
+};
+__device__ inline MergeGeom dc_geom(int64_t n, int64_t L, int lev, int64_t g) {
+  MergeGeom q;
+  const int64_t span = (int64_t)1 << lev;
+  q.s = dc_b(g * span, n, L);
+  q.mid = dc_b(g * span + span / 2, n, L);
+  q.t = dc_b((g + 1) * span, n, L);
+  q.m = q.t - q.s;
+  q.n1 = q.mid - q.s;
+  return q;
+}
+
+// ------------------------------------------------------------------ tearing
+__global__ void dc_tear(int64_t n, int64_t L, const double *d, const double *e, double *dw) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int64_t i = 0; i < n; ++i) dw[i] = d[i];
+  for (int64_t i = 1; i < L; ++i) {
+    const int64_t k = dc_b(i, n, L);
+    const double r = fabs(e[k - 1]);
+    dw[k - 1] -= r;
+    dw[k] -= r;
+  }
+}
+
+// ------------------------------------------------------------------ leaves
+// One wavefront per leaf: implicit QL with Wilkinson shifts; every lane runs
+// the scalar recurrence (identical values) and rotates its own row of Z.
+__global__ void __launch_bounds__(64) dc_leaf(int64_t n, int64_t L, const double *dw, const double *e,
+                                              double *Z, int64_t ldz, double *lam, int32_t *info) {
+  __shared__ double dd[DC_LEAF], ee[DC_LEAF];
+  __shared__ double Zl[DC_LEAF * DC_LEAF];
+  __shared__ int perm[DC_LEAF];
+  const int64_t s = dc_b(blockIdx.x, n, L);
+  const int m = (int)(dc_b(blockIdx.x + 1, n, L) - s);
+  const int r = threadIdx.x;
+  if (r < m) {
+    dd[r] = dw[s + r];
+    ee[r] = (r < m - 1) ? e[s + r] : 0.0;
+  }
+  for (int c = 0; c < m; ++c) Zl[c * DC_LEAF + r] = (c == r) ? 1.0 : 0.0;
+  __syncthreads();
+  bool fail = false;
+  for (int l = 0; l < m; ++l) {
+    int iter = 0;
+    while (true) {
+      int mm = l;
+      while (mm < m - 1) {
+        const double tst = fabs(dd[mm]) + fabs(dd[mm + 1]);
+        if (fabs(ee[mm]) <= DC_EPS * tst) break;
+        ++mm;
+      }
+      if (mm == l) break;
+      if (++iter > 60) { fail = true; break; }
+      double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
+      double rr = hypot(g, 1.0);
+      g = dd[mm] - dd[l] + ee[l] / (g + copysign(rr, g));
+      double sn = 1.0, c = 1.0, p = 0.0;
+      bool restart = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const double f = sn * ee[i];
+        const double b = c * ee[i];
+        rr = hypot(f, g);
+        __syncthreads();
+        ee[i + 1] = rr;
+        __syncthreads();
+        if (rr == 0.0) {
+          const double dv = dd[i + 1] - p;
+          __syncthreads();
+          dd[i + 1] = dv;
+          ee[mm] = 0.0;
+          __syncthreads();
+          restart = true;
+          break;
+        }
+        sn = f / rr;
+        c = g / rr;
+        g = dd[i + 1] - p;
+        rr = (dd[i] - g) * sn + 2.0 * c * b;
+        p = sn * rr;
+        const double nd = g + p;
+        __syncthreads();
+        dd[i + 1] = nd;
+        __syncthreads();
+        g = c * rr - b;
+        if (r < m) {
+          const double zi1 = Zl[(i + 1) * DC_LEAF + r];
+          const double zi = Zl[i * DC_LEAF + r];
+          Zl[(i + 1) * DC_LEAF + r] = sn * zi + c * zi1;
+          Zl[i * DC_LEAF + r] = c * zi - sn * zi1;
+        }
+      }
+      if (restart) continue;
+      const double dl = dd[l] - p;
+      __syncthreads();
+      dd[l] = dl;
+      ee[l] = g;
+      ee[mm] = 0.0;
+      __syncthreads();
+    }
+    if (fail) break;
+  }
+  if (fail && r == 0) *info = MMF_ERR_NO_CONVERGENCE;
+  // ascending order (selection by rank; ties by index)
+  if (r < m) {
+    const double v = dd[r];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double u = dd[j];
+      rank += (u < v) || (u == v && j < r);
+    }
+    perm[rank] = r;
+  }
+  __syncthreads();
+  if (r < m) {
+    lam[s + r] = dd[perm[r]];
+    for (int c = 0; c < m; ++c) Z[(s + r) + (s + c) * ldz] = Zl[perm[c] * DC_LEAF + r];
+  }
+}
+
+// ------------------------------------------------------------------ merge: prepare
+__global__ void dc_prep(int64_t n, int64_t L, int lev, const double *e, const double *lam,
+                        const double *Z, int64_t ldz, double *ds, double *zs, int32_t *src, double *rho) {
+  const MergeGeom q = dc_geom(n, L, lev, blockIdx.y);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= q.m) return;
+  const double ek = e[q.mid - 1];
+  const double sg = ek >= 0.0 ? 1.0 : -1.0;
+  const double inv_sqrt2 = 0.70710678118654752440;
+  double dv, zv;
+  int64_t pos;
+  const double *L2 = lam + q.mid;
+  const int64_t n2 = q.t - q.mid;
+  if (j < q.n1) {
+    dv = lam[q.s + j];
+    zv = Z[(q.mid - 1) + (q.s + j) * ldz];
+    int64_t lo = 0, hi = n2;           // count of right values < dv
+    while (lo < hi) { const int64_t md = (lo + hi) >> 1; if (L2[md] < dv) lo = md + 1; else hi = md; }
+    pos = j + lo;
+  } else {
+    const int64_t jj = j - q.n1;
+    dv = lam[q.mid + jj];
+    zv = sg * Z[q.mid + (q.mid + jj) * ldz];
+    const double *L1 = lam + q.s;
+    int64_t lo = 0, hi = q.n1;         // count of left values <= dv
+    while (lo < hi) { const int64_t md = (lo + hi) >> 1; if (L1[md] <= dv) lo = md + 1; else hi = md; }
+    pos = jj + lo;
+  }
+  ds[q.s + pos] = dv;
+  zs[q.s + pos] = zv * inv_sqrt2;
+  src[q.s + pos] = (int32_t)j;
+  if (j == 0) rho[q.s] = 2.0 * fabs(ek);
+}
+
+// Off-diagonal blocks of the merged block start as exact zeros.
+__global__ void dc_zero_off(int64_t n, int64_t L, int lev, double *Z, int64_t ldz) {
+  const MergeGeom q = dc_geom(n, L, lev, blockIdx.z);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= q.m || c >= q.m) return;
+  const bool rl = r < q.n1, cl = c < q.n1;
+  if (rl != cl) Z[(q.s + r) + (q.s + c) * ldz] = 0.0;
+}
+
+// ------------------------------------------------------------------ merge: deflation scan
+__global__ void dc_deflate(int64_t n, int64_t L, int lev, double *ds, double *zs, const double *rho,
+                           int32_t *ndidx, int32_t *dfidx, int32_t *rp, int32_t *rj, double *rc,
+                           double *rs, int32_t *cnt) {
+  if (threadIdx.x != 0) return;
+  const int64_t g = blockIdx.x;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int64_t s = q.s, m = q.m;
+  const double rh = rho[s];
+  double dmax = fmax(fabs(ds[s]), fabs(ds[s + m - 1]));
+  const double tol = 8.0 * DC_EPS * fmax(dmax, rh);
+  int32_t K = 0, ND = 0, R = 0;
+  int64_t prev = -1;
+  for (int64_t j = 0; j < m; ++j) {
+    const double zj = zs[s + j];
+    if (rh * fabs(zj) <= tol) { dfidx[s + ND++] = (int32_t)j; continue; }
+    if (prev < 0) { prev = j; continue; }
+    double sv = zs[s + prev], cv = zj;
+    const double tt = hypot(cv, sv);
+    cv /= tt;
+    sv /= tt;
+    const double dp = ds[s + prev], dj = ds[s + j];
+    if (fabs((dj - dp) * cv * sv) <= tol) {
+      zs[s + j] = tt;
+      zs[s + prev] = 0.0;
+      ds[s + prev] = cv * cv * dp + sv * sv * dj;
+      ds[s + j] = sv * sv * dp + cv * cv * dj;
+      rp[s + R] = (int32_t)prev;
+      rj[s + R] = (int32_t)j;
+      rc[s + R] = cv;
+      rs[s + R] = sv;
+      ++R;
+      dfidx[s + ND++] = (int32_t)prev;
+      prev = j;
+    } else {
+      ndidx[s + K++] = (int32_t)prev;
+      prev = j;
+    }
+  }
+  if (prev >= 0) ndidx[s + K++] = (int32_t)prev;
+  cnt[3 * g + 0] = K;
+  cnt[3 * g + 1] = R;
+  cnt[3 * g + 2] = ND;
+}
+
+// ------------------------------------------------------------------ merge: rotate + gather
+// Thread = row of the merged block: applies the deflation rotations in order
+// to its row of Z, then gathers the non-deflated columns (in d order) into
+// T1[:, 0:K] and the deflated ones into T1[:, K:m].
+__global__ void dc_gather(int64_t n, int64_t L, int lev, double *Z, int64_t ldz, const int32_t *src,
+                          const int32_t *ndidx, const int32_t *dfidx, const int32_t *rp,
+                          const int32_t *rj, const double *rc, const double *rs, const int32_t *cnt,
+                          const double *ds, const double *zs, double *dn, double *zn, double *ddef,
+                          double *T1) {
+  const int64_t g = blockIdx.y;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= q.m) return;
+  const int64_t s = q.s;
+  const int32_t K = cnt[3 * g], R = cnt[3 * g + 1], ND = cnt[3 * g + 2];
+  double *zrow = Z + (s + r);
+  for (int32_t k = 0; k < R; ++k) {
+    const int64_t cp = s + src[s + rp[s + k]], cj = s + src[s + rj[s + k]];
+    const double c = rc[s + k], sn = rs[s + k];
+    const double zp = zrow[cp * ldz], zj = zrow[cj * ldz];
+    zrow[cp * ldz] = c * zp - sn * zj;
+    zrow[cj * ldz] = sn * zp + c * zj;
+  }
+  double *trow = T1 + (s + r);
+  for (int32_t k = 0; k < K; ++k) trow[(s + k) * n] = zrow[(s + src[s + ndidx[s + k]]) * ldz];
+  for (int32_t k = 0; k < ND; ++k) trow[(s + K + k) * n] = zrow[(s + src[s + dfidx[s + k]]) * ldz];
+  if (r < K) {
+    dn[s + r] = ds[s + ndidx[s + r]];
+    zn[s + r] = zs[s + ndidx[s + r]];
+  }
+  if (r < ND) ddef[s + r] = ds[s + dfidx[s + r]];
+}
+
+// ------------------------------------------------------------------ merge: secular equation
+// One wavefront per root k of f(x) = 1 + rho sum_i z_i^2/(d_i - x).
+__global__ void __launch_bounds__(256) dc_secular(int64_t n, int64_t L, int lev, const double *dn,
+                                                  const double *zn, const double *rho,
+                                                  const int32_t *cnt, int32_t *lamo, double *lamt,
+                                                  int32_t *info) {
+  const int64_t g = blockIdx.y;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int K = cnt[3 * g];
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= K) return;
+  const int64_t s = q.s;
+  const double *d = dn + s, *z = zn + s;
+  const double rh = rho[s];
+  if (K == 1) {
+    if (lane == 0) { lamo[s] = 0; lamt[s] = rh * z[0] * z[0]; }
+    return;
+  }
+  int o;
+  double lo, hi;
+  if (k < K - 1) {
+    const double delta = d[k + 1] - d[k];
+    const double mid = 0.5 * delta;
+    double f = 0.0;
+    for (int i = lane; i < K; i += 64) f += z[i] * z[i] / ((d[i] - d[k]) - mid);
+    f = 1.0 + rh * wave_sum(f);
+    if (f >= 0.0) { o = k; lo = 0.0; hi = mid; }
+    else { o = k + 1; lo = -mid; hi = 0.0; }
+  } else {
+    double zz = 0.0;
+    for (int i = lane; i < K; i += 64) zz += z[i] * z[i];
+    zz = wave_sum(zz);
+    o = K - 1;
+    lo = 0.0;
+    hi = rh * zz;
+  }
+  const double dorg = d[o];
+  const double pk = d[k] - dorg;                  // left pole (relative)
+  const double qk = (k < K - 1) ? d[k + 1] - dorg : 0.0;   // right pole
+  double tau = 0.5 * (lo + hi);
+  double lastw = hi - lo;
+  bool conv = false;
+  for (int it = 0; it < 200; ++it) {
+    double ps = 0.0, ph = 0.0, dps = 0.0, dph = 0.0;
+    for (int i = lane; i < K; i += 64) {
+      const double den = (d[i] - dorg) - tau;
+      const double t = z[i] * z[i] / den;
+      if (i <= k) { ps += t; dps += t / den; } else { ph += t; dph += t / den; }
+    }
+    ps = rh * wave_sum(ps);
+    ph = rh * wave_sum(ph);
+    dps = rh * wave_sum(dps);
+    dph = rh * wave_sum(dph);
+    const double f = 1.0 + ps + ph;
+    if (f < 0.0) lo = tau; else hi = tau;
+    const double errb = 8.0 * DC_EPS * (double)K * (1.0 + fabs(ps) + fabs(ph));
+    if (fabs(f) <= errb || (hi - lo) <= 4.0 * DC_EPS * fmax(fabs(lo), fabs(hi))) { conv = true; break; }
+    const double b1 = dps * (pk - tau) * (pk - tau);
+    const double a1 = ps - b1 / (pk - tau);
+    double xn;
+    if (k < K - 1) {
+      const double b2 = dph * (qk - tau) * (qk - tau);
+      const double a2 = ph - b2 / (qk - tau);
+      const double c = 1.0 + a1 + a2;
+      const double A = c, B = -(c * (pk + qk) + b1 + b2), Cc = c * pk * qk + b1 * qk + b2 * pk;
+      double x1 = NAN, x2 = NAN;
+      if (A == 0.0) {
+        x1 = -Cc / B;
+      } else {
+        double disc = B * B - 4.0 * A * Cc;
+        if (disc < 0.0) disc = 0.0;
+        const double sq = sqrt(disc);
+        const double qq = -0.5 * (B + copysign(sq, B));
+        x1 = qq / A;
+        if (qq != 0.0) x2 = Cc / qq;
+      }
+      if (x1 > lo && x1 < hi) xn = x1;
+      else if (x2 > lo && x2 < hi) xn = x2;
+      else xn = 0.5 * (lo + hi);
+    } else {
+      const double c = 1.0 + a1 + ph;
+      xn = (c != 0.0) ? pk + b1 / c : 0.5 * (lo + hi);
+      if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    }
+    const double wdt = hi - lo;
+    if (it % 3 == 2) {
+      if (wdt > 0.5 * lastw) xn = 0.5 * (lo + hi);
+      lastw = wdt;
+    }
+    tau = xn;
+  }
+  if (lane == 0) {
+    lamo[s + k] = o;
+    lamt[s + k] = tau;
+    if (!conv) *info = MMF_ERR_NO_CONVERGENCE;
+  }
+}
+
+// zhat_i^2 = (x_{K-1} - d_i)/rho * prod_{j<i} (x_j - d_i)/(d_j - d_i)
+//                                 * prod_{i<=j<K-1} (x_j - d_i)/(d_{j+1} - d_i)
+__global__ void __launch_bounds__(256) dc_lowner(int64_t n, int64_t L, int lev, const double *dn,
+                                                 const double *zn, const double *rho,
+                                                 const int32_t *cnt, const int32_t *lamo,
+                                                 const double *lamt, double *zhat) {
+  const int64_t g = blockIdx.y;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int K = cnt[3 * g];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= K) return;
+  const int64_t s = q.s;
+  const double *d = dn + s;
+  const double di = d[i];
+  double pr = 1.0;
+  for (int j = lane; j < K - 1; j += 64) {
+    const double num = (d[lamo[s + j]] - di) + lamt[s + j];
+    const double den = (j < i) ? (d[j] - di) : (d[j + 1] - di);
+    pr *= num / den;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pr *= __shfl_xor(pr, o, 64);
+  if (lane == 0) {
+    const double last = ((d[lamo[s + K - 1]] - di) + lamt[s + K - 1]) / rho[s];
+    const double v = sqrt(fmax(pr * last, 0.0));
+    zhat[s + i] = copysign(v, zn[s + i]);
+  }
+}
+
+// Column j of the rank-one eigenvector matrix U (T2 block, ld n).
+__global__ void __launch_bounds__(256) dc_vectors(int64_t n, int64_t L, int lev, const double *dn,
+                                                  const int32_t *cnt, const int32_t *lamo,
+                                                  const double *lamt, const double *zhat, double *T2) {
+  __shared__ double sh[4];
+  const int64_t g = blockIdx.y;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int K = cnt[3 * g];
+  const int j = blockIdx.x;
+  if (j >= K) return;
+  const int64_t s = q.s;
+  const double *d = dn + s;
+  const double dorg = d[lamo[s + j]], tj = lamt[s + j];
+  double *col = T2 + s + (s + j) * n;
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < K; i += 256) {
+    const double u = zhat[s + i] / ((d[i] - dorg) - tj);
+    col[i] = u;
+    ss += u * u;
+  }
+  ss = wave_sum(ss);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  const double inv = 1.0 / sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
+  for (int i = threadIdx.x; i < K; i += 256) col[i] *= inv;
+}
+
+// Final ascending position of every eigenvalue of the merge (roots first in
+// the tie order, then deflated values by index), eigenvalue output and the
+// destination column of every T1 column.
+__global__ void dc_final_pos(int64_t n, int64_t L, int lev, const double *dn, const int32_t *cnt,
+                             const int32_t *lamo, const double *lamt, const double *ddef,
+                             double *lam, int32_t *colmap) {
+  const int64_t g = blockIdx.y;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= q.m) return;
+  const int64_t s = q.s;
+  const int K = cnt[3 * g];
+  auto val = [&](int64_t x) -> double {
+    return x < K ? dn[s + lamo[s + x]] + lamt[s + x] : ddef[s + (x - K)];
+  };
+  const double v = val(e);
+  int64_t pos = 0;
+  for (int64_t x = 0; x < q.m; ++x) {
+    const double u = val(x);
+    pos += (u < v) || (u == v && x < e);
+  }
+  lam[s + pos] = v;
+  colmap[s + e] = (int32_t)(s + pos);
+}
+
+__global__ void __launch_bounds__(GEMM_THREADS) dc_gemm(int64_t n, int64_t L, int lev, const int32_t *cnt,
+                                                        const double *T1, const double *T2,
+                                                        double *Z, int64_t ldz, const int32_t *colmap) {
+  __shared__ double lds[GEMM_LDS_DOUBLES];
+  const int64_t g = blockIdx.z;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int K = cnt[3 * g];
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  if (m0 >= q.m || n0 >= K) return;
+  GemmArgs a = gemm_args(q.m, K, K, T1 + q.s + q.s * n, n, T2 + q.s + q.s * n, n, Z + q.s, ldz,
+                         1.0, 0.0, 0.0, 0.0);
+  a.colmap = colmap + q.s;
+  gemm_tile<false, A_N, B_N>(a, m0, n0, lds);
+}
+
+__global__ void dc_copy_def(int64_t n, int64_t L, int lev, const int32_t *cnt, const double *T1,
+                            double *Z, int64_t ldz, const int32_t *colmap) {
+  const int64_t g = blockIdx.y;
+  const MergeGeom q = dc_geom(n, L, lev, g);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= q.m) return;
+  const int K = cnt[3 * g];
+  for (int64_t k = K; k < q.m; ++k)
+    Z[(q.s + r) + (int64_t)colmap[q.s + k] * ldz] = T1[(q.s + r) + (q.s + k) * n];
+}
+
+__global__ void dc_copy_out(int64_t n, const double *lam, double *d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = lam[i];
+}
+
+__global__ void dc_info_init(int32_t *info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *info = 0;
+}
+
+// ------------------------------------------------------------------ host
+int stedc_run(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *work, size_t bytes,
+              int32_t *info, hipStream_t st) {
+  if (n <= 0) return MMF_OK;
+  DcWs w = stedc_ws(n, work);
+  if (bytes < w.bytes) return MMF_ERR_WORKSPACE;
+  int h = 0;
+  while (((n + ((int64_t)1 << h) - 1) >> h) > DC_LEAF) ++h;
+  const int64_t L = (int64_t)1 << h;
+  hipLaunchKernelGGL(dc_info_init, dim3(1), dim3(64), 0, st, info);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(dc_tear, dim3(1), dim3(64), 0, st, n, L, d, e, w.dw);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(dc_leaf, dim3((unsigned)L), dim3(64), 0, st, n, L, w.dw, e, Z, ldz, w.lam, info);
+  MMF_LAUNCH_CHECK();
+  for (int lev = 1; lev <= h; ++lev) {
+    const int64_t G = L >> lev;
+    const int64_t span = (int64_t)1 << lev;
+    int64_t maxm = 0;
+    for (int64_t g = 0; g < G; ++g) {
+      const int64_t m = dc_b((g + 1) * span, n, L) - dc_b(g * span, n, L);
+      if (m > maxm) maxm = m;
+    }
+    const dim3 rows(cdiv(maxm, 256), (unsigned)G);
+    hipLaunchKernelGGL(dc_prep, rows, dim3(256), 0, st, n, L, lev, e, w.lam, Z, ldz, w.ds, w.zs, w.src,
+                       w.rho);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_zero_off, dim3(cdiv(maxm, 256), (unsigned)maxm, (unsigned)G), dim3(256), 0, st,
+                       n, L, lev, Z, ldz);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_deflate, dim3((unsigned)G), dim3(64), 0, st, n, L, lev, w.ds, w.zs, w.rho,
+                       w.ndidx, w.dfidx, w.rp, w.rj, w.rc, w.rs, w.cnt);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_gather, rows, dim3(256), 0, st, n, L, lev, Z, ldz, w.src, w.ndidx, w.dfidx,
+                       w.rp, w.rj, w.rc, w.rs, w.cnt, w.ds, w.zs, w.dn, w.zn, w.ddef, w.T1);
+    MMF_LAUNCH_CHECK();
+    const dim3 roots(cdiv(maxm, 4), (unsigned)G);
+    hipLaunchKernelGGL(dc_secular, roots, dim3(256), 0, st, n, L, lev, w.dn, w.zn, w.rho, w.cnt,
+                       w.lamo, w.lamt, info);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_lowner, roots, dim3(256), 0, st, n, L, lev, w.dn, w.zn, w.rho, w.cnt, w.lamo,
+                       w.lamt, w.zhat);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_vectors, dim3((unsigned)maxm, (unsigned)G), dim3(256), 0, st, n, L, lev, w.dn,
+                       w.cnt, w.lamo, w.lamt, w.zhat, w.T2);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_final_pos, rows, dim3(256), 0, st, n, L, lev, w.dn, w.cnt, w.lamo, w.lamt,
+                       w.ddef, w.lam, w.colmap);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_gemm, dim3(cdiv(maxm, GT_M), cdiv(maxm, GT_N), (unsigned)G),
+                       dim3(GEMM_THREADS), 0, st, n, L, lev, w.cnt, w.T1, w.T2, Z, ldz, w.colmap);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_copy_def, rows, dim3(256), 0, st, n, L, lev, w.cnt, w.T1, Z, ldz, w.colmap);
+    MMF_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(dc_copy_out, dim3(cdiv(n, 256)), dim3(256), 0, st, n, w.lam, d);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+}  // namespace mmf
+
+using namespace mmf;
+
+extern "C" int mmf_stedc(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *work,
+                         size_t work_bytes, int32_t *dev_info, void *stream) {
+  if (n < 0) return -1;
+  if (!d) return -2;
+  if (n > 1 && !e) return -3;
+  if (!Z) return -4;
+  if (ldz < n || ldz < 1) return -5;
+  if (!work) return -6;
+  if (work_bytes < stedc_ws_bytes(n)) return -7;
+  if (!dev_info) return -8;
+  return stedc_run(n, d, e, Z, ldz, work, work_bytes, dev_info, (hipStream_t)stream);
+}
