@@ -1,0 +1,239 @@
+"""Benchmark of the multimode Floquet hot path on one MI355X.
+
+One step = one whole Floquet solve of the workload: assemble H_F -> dense
+Hermitian eigensolve -> U(t, t0) at the workload's times -> averaged
+transition probabilities, with every input already resident in HBM.
+
+Default workload: 8-level ladder under two incommensurate drives
+(w = 1, golden ratio), truncation +-25 on both axes, Floquet dimension
+M = 20808 (complex128), U at 256 times.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload ladder20808|tls82]
+                  [--no-cpu-baseline] [--profile-stage]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from workloads import cfg1_tls, cfg2_large
+    if name == "ladder20808":
+        p, ts, t0 = cfg2_large()
+    elif name == "tls82":
+        p, ts, t0 = cfg1_tls()
+    elif name.startswith("ladder_N"):
+        n = int(name[len("ladder_N"):])
+        p, ts, t0 = cfg2_large(N=(n, n))
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p, ts, t0
+
+
+def cpu_baseline(budget_s=30.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same system
+    (same ladder and drives, truncation +-10: M = 3528), then extrapolated to
+    the full dimension stage by stage (eigh ~ M^3, the rest ~ M^2)."""
+    import oracle
+    from workloads import cfg2_large
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    Ns = 10
+    p, ts, t0 = cfg2_large(N=(Ns, Ns))
+    t_a = time.perf_counter()
+    H = oracle.build_floquet(p)
+    t_b = time.perf_counter()
+    w, Phi = oracle.eigh(H)
+    t_c = time.perf_counter()
+    oracle.evolve(p, Phi, w, t0, ts)
+    t_d = time.perf_counter()
+    oracle.avg_prob(p, Phi)
+    t_e = time.perf_counter()
+    Ms = H.shape[0]
+    M = 8 * 51 * 51
+    r = M / Ms
+    full = (t_b - t_a) * r ** 2 + (t_c - t_b) * r ** 3 + (t_d - t_c) * r ** 2 + (t_e - t_d) * r ** 2
+    return {
+        "value": 1.0 / full, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+        "sample": (f"same ladder/drives at truncation +-{Ns} (M={Ms}, 256 times): build {t_b - t_a:.2f}s, "
+                   f"eigh {t_c - t_b:.2f}s, U {t_d - t_c:.2f}s, P {t_e - t_d:.2f}s; extrapolated to "
+                   f"M={M} with eigh ~M^3 and the other stages ~M^2"),
+        "sample_seconds": t_e - t_a,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ladder20808")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-ktimer", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2005_03426_amd as mmf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    p, ts, t0 = workload(args.workload)
+    dp = mmf.DeviceProblem(p, dev)
+    M, D, T = dp.M, dp.D, len(ts)
+    print(f"[bench] workload {args.workload}: D={D} M={M} T={T}", file=sys.stderr, flush=True)
+    tt = torch.as_tensor(np.asarray(ts), dtype=torch.float64, device=dev)
+    HF = torch.empty((M, M), dtype=torch.complex128, device=dev)
+    w = torch.empty(M, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    ework = torch.empty(mmf.eigh_workspace_bytes(M), dtype=torch.uint8, device=dev)
+    import ctypes as C
+    b = C.c_size_t(0)
+    mmf.call("mmf_evolve_workspace", dp.ref, C.c_int32(T), C.byref(b))
+    uwork = torch.empty(b.value, dtype=torch.uint8, device=dev)
+    mmf.call("mmf_avg_prob_workspace", dp.ref, C.byref(b))
+    pwork = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
+
+    stages = ("assemble", "eigh", "evolve", "avg_prob")
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        mmf.build_floquet(dp, out=HF)
+        if ev: ev[1].record()
+        mmf.eigh(HF, w=w, work=ework, info=info)
+        if ev: ev[2].record()
+        U = mmf.evolve(dp, HF, w, t0, tt, work=uwork)
+        if ev: ev[3].record()
+        P = mmf.avg_prob(dp, HF, work=pwork)
+        if ev: ev[4].record()
+        return U, P
+
+    if args.calib_copy:
+        # plain copy of a known size: calibrates the HBM byte counters of a
+        # --pmc run (FETCH_SIZE / WRITE_SIZE of this kernel vs 1 GiB each way)
+        src = torch.ones(1 << 26, dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    L = mmf.lib()
+    torch.cuda.synchronize()
+    if not args.no_ktimer:
+        mmf.call("mmf_ktimer_arm", b"hemv")
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        U, P = step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kt = None
+    if not args.no_ktimer:
+        nl, tms, wb = C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
+        mmf.call("mmf_ktimer_read", C.byref(nl), C.byref(tms), C.byref(wb))
+        kt = {"launches": int(nl.value), "total_ms": tms.value, "bytes": wb.value}
+    per_stage = {s: [] for s in stages}
+    step_ms = []
+    for ev in evs:
+        for j, s in enumerate(stages):
+            per_stage[s].append(ev[j].elapsed_time(ev[j + 1]))
+        step_ms.append(ev[0].elapsed_time(ev[4]))
+    med = {s: float(np.median(v)) for s, v in per_stage.items()}
+    print(f"[bench] timed {args.steps} steps: {elapsed:.3f}s; stages(ms) {med}", file=sys.stderr, flush=True)
+
+    eigh_flops = (40.0 / 3.0) * M ** 3
+    t_eigh = med["eigh"] / 1e3
+    eigh_tflops = eigh_flops / t_eigh / 1e12
+
+    check = {}
+    if not args.no_check:
+        assert int(info.item()) == 0, "eigensolver reported non-convergence"
+        g = torch.Generator(device="cpu").manual_seed(0)
+        idx = torch.randperm(M, generator=g)[:64].to(dev)
+        H = mmf.build_floquet(dp)                       # H_F again (storage = H^T)
+        Hm = H.T                                        # logical H_F (view)
+        Phi_s = HF[idx].T.contiguous()                  # columns of sampled eigenvectors (M x 64)
+        R = Hm @ Phi_s - Phi_s * w[idx][None, :]
+        hn = torch.linalg.matrix_norm(Hm, ord=1).item()
+        check["eig_residual_rel"] = float(R.abs().max().item() / hn)
+        G = HF.conj() @ Phi_s                           # rows a: <phi_a | phi_idx>
+        G[idx, torch.arange(64, device=dev)] -= 1.0
+        check["orth_max"] = float(G.abs().max().item())
+        check["trace_rel"] = float(abs(w.sum().item() - torch.diagonal(Hm).real.sum().item()) / hn)
+        check["colsum_P_max_dev"] = float((P.sum(dim=0) - 1.0).abs().max().item())
+        Ud = U.conj().transpose(1, 2) @ U - torch.eye(D, dtype=U.dtype, device=dev)
+        check["unitarity_U_max_dev"] = float(Ud.abs().max().item())
+        del H, R, G
+
+    value = args.steps / elapsed
+    out = {
+        "metric": "Floquet eigensolves/s",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "D": D, "M": M, "times": T,
+                   "drives": [float(x) for x in p.omega], "truncation": [int(x) for x in p.N]},
+        "eigh_tflops": eigh_tflops,
+        "eigh_frac_fp64_peak": eigh_tflops / FP64_MFMA_PEAK_TFLOPS,
+        "stage_ms": med,
+        "step_ms_p50": float(np.percentile(step_ms, 50)),
+        "step_ms_p99": float(np.percentile(step_ms, 99)),
+        "check": check,
+    }
+    if kt and kt["launches"]:
+        per_launch_bytes = kt["bytes"] / kt["launches"]
+        avg_ms = kt["total_ms"] / kt["launches"]
+        gbs = per_launch_bytes / (avg_ms / 1e3) / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "ht_hemv (Hermitian matrix-vector product of the tridiagonal reduction)",
+            "launches": kt["launches"], "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": per_launch_bytes,
+            "share_of_step": kt["total_ms"] / (elapsed * 1e3),
+        }
+    out["eigh_roofline"] = {
+        "bound": "mfma", "achieved": eigh_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": eigh_tflops / FP64_MFMA_PEAK_TFLOPS,
+        "note": "whole mmf_eigh call at the nominal (40/3) M^3 flops of reduction + back-transformation",
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

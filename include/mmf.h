@@ -25,7 +25,8 @@
  *     descending Fourier index, fundamental 0 innermost (Appendix A order).
  *   - "dev" pointers are device (HBM) memory owned by the caller; "host"
  *     pointers are host memory read during the call only.  The library never
- *     allocates or frees caller-visible memory and keeps no global state:
+ *     allocates or frees caller-visible memory and keeps no global state
+ *     (apart from the opt-in benchmark timer at the end of this header):
  *     every call is reentrant.  Kernels are enqueued on `stream` (a
  *     hipStream_t, NULL = default stream) and the call returns without
  *     synchronising.
@@ -170,6 +171,19 @@ int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes);
  * reduction order).  P: dev [D*D] doubles, i final, j initial. */
 int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, double *P,
                  void *work, size_t work_bytes, void *stream);
+
+/* Benchmark instrumentation (not needed for computation).  mmf_ktimer_arm
+ * starts recording HIP events around every launch of one kernel class
+ * ("hemv": the Hermitian matrix-vector product of the tridiagonal
+ * reduction) on the stream it is launched on, together with the algorithmic
+ * bytes of each launch; mmf_ktimer_read disarms, waits for the events and
+ * returns the launch count, the summed kernel time in ms and the summed
+ * bytes.  Process-wide state: use from one host thread, never concurrently
+ * with other library calls on other threads.
+ * Errors: arm: -1 name NULL or longer than 63 chars; read: -k pointer k NULL,
+ * MMF_ERR_HIP. */
+int mmf_ktimer_arm(const char *kernel);
+int mmf_ktimer_read(int64_t *launches, double *total_ms, double *work);
 
 #ifdef __cplusplus
 }

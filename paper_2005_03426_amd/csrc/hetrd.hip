@@ -24,11 +24,12 @@
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
+#include "ktimer.h"
 
 namespace mmf {
 
 constexpr int HV_T = 64;        // HEMV tile
-constexpr int HV_CH = 8;        // tiles per HEMV workgroup (one block column strip)
+constexpr int HV_CH = 16;       // tiles per HEMV workgroup (one block column strip)
 constexpr int RW = 256;         // rows per workgroup in row-parallel kernels
 constexpr int DOT_ROWS = 1024;  // rows per workgroup of the panel dot products
 
@@ -68,7 +69,7 @@ inline HtWs hetrd_ws(int64_t n, void *base) {
   w.dots = cv.take<mmf_z>((size_t)gdot * 2 * HT_NB);
   const int64_t grow = (n + RW - 1) / RW + 1;
   w.norms = cv.take<double>(grow);
-  w.sparts = cv.take<mmf_z>(grow);
+  w.sparts = cv.take<mmf_z>(w.nbt + 1);
   w.w0first = cv.take<mmf_z>(4);
   w.bytes = cv.used();
   return w;
@@ -99,8 +100,10 @@ __global__ void __launch_bounds__(RW) ht_colnorm(const mmf_z *A, int64_t lda, in
 __global__ void __launch_bounds__(RW) ht_reflector(mmf_z *A, int64_t lda, int64_t n, int64_t i, int k,
                                                   mmf_z *P3, const double *norms, int gnorm,
                                                   double *d, double *e, mmf_z *tau) {
-  double xn2 = 0.0;
-  for (int g = 0; g < gnorm; ++g) xn2 += norms[g];
+  __shared__ double sh[4];
+  double xp = 0.0;
+  for (int g = threadIdx.x; g < gnorm; g += RW) xp += norms[g];
+  const double xn2 = block_sum256(xp, sh);
   const cd alpha = ldz(A + (i + 1) + i * lda);
   double beta;
   cd t, scale;
@@ -134,15 +137,20 @@ __global__ void __launch_bounds__(RW) ht_reflector(mmf_z *A, int64_t lda, int64_
 }
 
 // u = A_trail v over the lower triangle of the trailing matrix
-// A_trail = A[i+1:, i+1:] (size m).  Workgroup (bj, c): block column bj, tile
-// rows bi = bj + c*HV_CH ... ; thread (row r, wave cg) covers columns
-// cg*16 .. cg*16+15 of every tile.
+// A_trail = A[i+1:, i+1:] (size m).  Workgroup (bj, c) covers the tile strip
+// bi = bj + c*HV_CH ... of block column bj; each wavefront owns whole tiles
+// (bi = bi0 + wave, bi0 + wave + 4, ...), so no workgroup barrier sits in the
+// streaming loop.  Lane l covers rows rg + 16 q (rg = l % 16, q = 0..3) and
+// columns 16 cg + j (cg = l / 16, j = 0..15): every load instruction reads four
+// 256-byte column segments.  The direct product of a tile is folded across
+// the four column groups with shuffles and written as one partial per
+// (block column, row); the conjugate-transposed product accumulates in
+// registers over the strip and is folded once at the end.
 __global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int64_t n, int64_t i,
                                                const mmf_z *P3, int k, mmf_z *pdir, mmf_z *ptrn,
                                                int64_t mpad, int64_t nchmax) {
   __shared__ cd vcol[HV_T];
-  __shared__ cd red[4][HV_T];
-  __shared__ cd tsh[HV_T][HV_T + 1];
+  __shared__ cd tsum[4][HV_T];
   const int64_t m = n - i - 1;
   const int64_t nbt = (m + HV_T - 1) / HV_T;
   const int64_t bj = blockIdx.x;
@@ -151,7 +159,8 @@ __global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int6
   if (bi0 >= nbt) return;
   const int64_t bi1 = (bi0 + HV_CH < nbt) ? bi0 + HV_CH : nbt;
   const int tid = threadIdx.x;
-  const int r = tid & 63, cg = tid >> 6;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rg = lane & 15, cg = lane >> 4;
   const mmf_z *At = A + (i + 1) + (i + 1) * lda;
   const mmf_z *v = P3 + (i + 1) + (int64_t)k * n;
   if (tid < HV_T) {
@@ -161,42 +170,62 @@ __global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int6
   __syncthreads();
   cd tacc[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) tacc[q] = cmake(0.0, 0.0);
-  for (int64_t bi = bi0; bi < bi1; ++bi) {
-    const int64_t row = bi * HV_T + r;
-    const bool rin = row < m;
-    const cd vr = rin ? ldz(v + row) : cmake(0.0, 0.0);
-    cd av[16];
+  for (int j = 0; j < 16; ++j) tacc[j] = cmake(0.0, 0.0);
+  const int64_t col0 = bj * HV_T + cg * 16;
+  for (int64_t bi = bi0 + wave; bi < bi1; bi += 4) {
+    const bool diagt = (bi == bj);
+    cd vr[4], dacc[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t gc = bj * HV_T + cg * 16 + q;
-      const bool ok = rin && gc < m && (bi > bj || row >= gc);
-      av[q] = ok ? ldz(At + row + gc * lda) : cmake(0.0, 0.0);
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = bi * HV_T + rg + 16 * q;
+      vr[q] = row < m ? ldz(v + row) : cmake(0.0, 0.0);
+      dacc[q] = cmake(0.0, 0.0);
     }
-    cd dacc = cmake(0.0, 0.0);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t gc = bj * HV_T + cg * 16 + q;
-      cd a = av[q];
-      const bool diag = (bi == bj) && (row == gc);
-      if (diag) a.im = 0.0;
-      dacc = cadd(dacc, cmul(a, vcol[cg * 16 + q]));
-      if (!diag) tacc[q] = cadd(tacc[q], cmulc(a, vr));
+    for (int jb = 0; jb < 16; jb += 4) {
+      cd av[4][4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t row = bi * HV_T + rg + 16 * q;
+          const int64_t gc = col0 + jb + jj;
+          const bool ok = row < m && gc < m && (!diagt || row >= gc);
+          av[jj][q] = ok ? ldz(At + row + gc * lda) : cmake(0.0, 0.0);
+        }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const cd vc = vcol[cg * 16 + jb + jj];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cd a = av[jj][q];
+          const bool dg = diagt && (rg + 16 * q == cg * 16 + jb + jj);
+          if (dg) a.im = 0.0;
+          dacc[q] = cadd(dacc[q], cmul(a, vc));
+          if (!dg) tacc[jb + jj] = cadd(tacc[jb + jj], cmulc(a, vr[q]));
+        }
+      }
     }
-    red[cg][r] = dacc;
-    __syncthreads();
-    if (tid < HV_T) {
-      const cd s = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
-      stz(pdir + bj * mpad + bi * HV_T + tid, s);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double re = dacc[q].re, im = dacc[q].im;
+      re += __shfl_xor(re, 16, 64); im += __shfl_xor(im, 16, 64);
+      re += __shfl_xor(re, 32, 64); im += __shfl_xor(im, 32, 64);
+      if (cg == 0) stz(pdir + bj * mpad + bi * HV_T + rg + 16 * q, cmake(re, im));
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) tsh[cg * 16 + q][r] = tacc[q];
+  for (int j = 0; j < 16; ++j) {
+    double re = tacc[j].re, im = tacc[j].im;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
+    if (rg == 0) tsum[wave][cg * 16 + j] = cmake(re, im);
+  }
   __syncthreads();
   if (tid < HV_T) {
+    const int nw = (int)((bi1 - bi0 < 4) ? bi1 - bi0 : 4);
     cd s = cmake(0.0, 0.0);
-    for (int rr = 0; rr < HV_T; ++rr) s = cadd(s, tsh[tid][rr]);
+    for (int w2 = 0; w2 < nw; ++w2) s = cadd(s, tsum[w2][tid]);
     stz(ptrn + (bj * nchmax + c) * HV_T + tid, s);
   }
 }
@@ -222,13 +251,17 @@ __global__ void __launch_bounds__(256) ht_dots(const mmf_z *P3, int64_t n, int64
 }
 
 // w0 = tau (u - V x1 - W x2), with u assembled from the HEMV partials.
-__global__ void __launch_bounds__(RW) ht_finish_u(int64_t n, int64_t i, int k, mmf_z *P3,
-                                                 const mmf_z *pdir, const mmf_z *ptrn, int64_t mpad,
-                                                 int64_t nchmax, const mmf_z *dots, int gdot,
-                                                 const mmf_z *tau, mmf_z *sparts, mmf_z *w0first) {
+// One workgroup per 64-row block; its four wavefronts split the partial
+// sums and the panel corrections, combined in LDS in fixed order.
+__global__ void __launch_bounds__(256) ht_finish_u(int64_t n, int64_t i, int k, mmf_z *P3,
+                                                  const mmf_z *pdir, const mmf_z *ptrn, int64_t mpad,
+                                                  int64_t nchmax, const mmf_z *dots, int gdot,
+                                                  const mmf_z *tau, mmf_z *sparts, mmf_z *w0first) {
   __shared__ cd x1[HT_NB], x2[HT_NB];
+  __shared__ cd part[4][HV_T];
   __shared__ double sh[4];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   if (tid < 2 * k) {
     const int q = tid % k, which = tid / k;
     cd s = cmake(0.0, 0.0);
@@ -238,20 +271,25 @@ __global__ void __launch_bounds__(RW) ht_finish_u(int64_t n, int64_t i, int k, m
   __syncthreads();
   const int64_t m = n - i - 1;
   const int64_t nbt = (m + HV_T - 1) / HV_T;
-  const int64_t t = (int64_t)blockIdx.x * RW + tid;
-  cd contrib = cmake(0.0, 0.0);
+  const int64_t bi = blockIdx.x;
+  const int64_t t = bi * HV_T + lane;
+  const int64_t rho = i + 1 + t;
+  cd u = cmake(0.0, 0.0);
   if (t < m) {
-    const int64_t bi = t / HV_T;
-    cd u = cmake(0.0, 0.0);
-    for (int64_t bj = 0; bj <= bi; ++bj) u = cadd(u, ldz(pdir + bj * mpad + t));
+    for (int64_t bj = wave; bj <= bi; bj += 4) u = cadd(u, ldz(pdir + bj * mpad + t));
     const int64_t nch = (nbt - bi + HV_CH - 1) / HV_CH;
-    for (int64_t c = 0; c < nch; ++c) u = cadd(u, ldz(ptrn + (bi * nchmax + c) * HV_T + (t % HV_T)));
-    const int64_t rho = i + 1 + t;
-    for (int q = 0; q < k; ++q) {
+    for (int64_t c = wave; c < nch; c += 4) u = cadd(u, ldz(ptrn + (bi * nchmax + c) * HV_T + lane));
+    for (int q = wave; q < k; q += 4) {
       u = csub(u, cmul(ldz(P3 + rho + (int64_t)q * n), x1[q]));
       u = csub(u, cmul(ldz(P3 + rho + (int64_t)(HT_NB + q) * n), x2[q]));
     }
-    const cd w0 = cmul(ldz(tau + i), u);
+  }
+  part[wave][lane] = u;
+  __syncthreads();
+  cd contrib = cmake(0.0, 0.0);
+  if (wave == 0 && t < m) {
+    const cd us = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
+    const cd w0 = cmul(ldz(tau + i), us);
     stz(P3 + rho + (int64_t)(HT_NB + k) * n, w0);
     if (t == 0) w0first[0] = *reinterpret_cast<const mmf_z *>(&w0);
     contrib = cmulc(ldz(P3 + rho + (int64_t)k * n), w0);   // conj(v) w0
@@ -270,7 +308,12 @@ __global__ void __launch_bounds__(RW) ht_finish_w(mmf_z *A, int64_t lda, int64_t
   __shared__ double sh[4];
   const int tid = threadIdx.x;
   cd s = cmake(0.0, 0.0);
-  for (int g = 0; g < gs; ++g) s = cadd(s, ldz(sparts + g));
+  {
+    cd ps = cmake(0.0, 0.0);
+    for (int g = tid; g < gs; g += RW) ps = cadd(ps, ldz(sparts + g));
+    s.re = block_sum256(ps.re, sh);
+    s.im = block_sum256(ps.im, sh);
+  }
   const cd ti = ldz(tau + i);
   const cd alpha = cscale(cmul(ti, cconj(s)), -0.5);
   if (next && tid <= k) {
@@ -340,21 +383,24 @@ int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau
       }
       const int64_t nbt = (m + HV_T - 1) / HV_T;
       const int64_t nch = (nbt + HV_CH - 1) / HV_CH;
+      const int ks = ktimer_begin("hemv", st);
       hipLaunchKernelGGL(ht_hemv, dim3((unsigned)nbt, (unsigned)nch), dim3(256), 0, st, A, lda, n, i,
                          w.P3, k, w.pdir, w.ptrn, w.mpad, w.nchmax);
       MMF_LAUNCH_CHECK();
+      // algorithmic bytes: the lower triangle of the trailing matrix, read once
+      ktimer_end(ks, st, 16.0 * (double)m * (double)(m + 1) / 2.0);
       const int gdot = (int)cdiv(m, DOT_ROWS);
       if (k > 0) {
         hipLaunchKernelGGL(ht_dots, dim3(gdot, 2 * k), dim3(256), 0, st, w.P3, n, i, k, w.dots);
         MMF_LAUNCH_CHECK();
       }
-      const int gu = (int)cdiv(m, RW);
-      hipLaunchKernelGGL(ht_finish_u, dim3(gu), dim3(RW), 0, st, n, i, k, w.P3, w.pdir, w.ptrn, w.mpad,
-                         w.nchmax, w.dots, gdot, tau, w.sparts, w.w0first);
+      hipLaunchKernelGGL(ht_finish_u, dim3((unsigned)nbt), dim3(256), 0, st, n, i, k, w.P3, w.pdir, w.ptrn,
+                         w.mpad, w.nchmax, w.dots, gdot, tau, w.sparts, w.w0first);
       MMF_LAUNCH_CHECK();
+      const int gu = (int)cdiv(m, RW);
       const int next = (k + 1 < kb) ? 1 : 0;
       hipLaunchKernelGGL(ht_finish_w, dim3(gu), dim3(RW), 0, st, A, lda, n, i, k, next, w.P3,
-                         w.sparts, gu, tau, w.w0first, w.norms);
+                         w.sparts, (int)nbt, tau, w.w0first, w.norms);
       MMF_LAUNCH_CHECK();
       gnorm = gu;
     }
