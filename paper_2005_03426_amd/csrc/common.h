@@ -16,21 +16,38 @@
 namespace mmf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
-// Complex arithmetic on interleaved (re, im) doubles.
-struct cd {
-  double re, im;
+// Complex arithmetic on interleaved (re, im) pairs of R = double or float.
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+  R re, im;
 };
+typedef cx<double> cd;
+typedef cx<float> cf;
 
-__host__ __device__ inline cd cmake(double r, double i) { cd z; z.re = r; z.im = i; return z; }
-__device__ inline cd cadd(cd a, cd b) { return cmake(a.re + b.re, a.im + b.im); }
-__device__ inline cd csub(cd a, cd b) { return cmake(a.re - b.re, a.im - b.im); }
-__device__ inline cd cmul(cd a, cd b) { return cmake(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+template <typename R>
+__host__ __device__ inline cx<R> cmk(R r, R i) { cx<R> z; z.re = r; z.im = i; return z; }
+__host__ __device__ inline cd cmake(double r, double i) { return cmk<double>(r, i); }
+template <typename R>
+__device__ inline cx<R> cadd(cx<R> a, cx<R> b) { return cmk<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+__device__ inline cx<R> csub(cx<R> a, cx<R> b) { return cmk<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+__device__ inline cx<R> cmul(cx<R> a, cx<R> b) {
+  return cmk<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
 // conj(a) * b
-__device__ inline cd cmulc(cd a, cd b) { return cmake(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re); }
-__device__ inline cd cconj(cd a) { return cmake(a.re, -a.im); }
-__device__ inline cd cscale(cd a, double s) { return cmake(a.re * s, a.im * s); }
-__device__ inline double cabs2(cd a) { return a.re * a.re + a.im * a.im; }
+template <typename R>
+__device__ inline cx<R> cmulc(cx<R> a, cx<R> b) {
+  return cmk<R>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename R>
+__device__ inline cx<R> cconj(cx<R> a) { return cmk<R>(a.re, -a.im); }
+template <typename R>
+__device__ inline cx<R> cscale(cx<R> a, R s) { return cmk<R>(a.re * s, a.im * s); }
+template <typename R>
+__device__ inline R cabs2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 
 __device__ inline cd ldz(const mmf_z *p) {
   const double2 v = *reinterpret_cast<const double2 *>(p);
@@ -40,6 +57,11 @@ __device__ inline void stz(mmf_z *p, cd v) {
   double2 t; t.x = v.re; t.y = v.im;
   *reinterpret_cast<double2 *>(p) = t;
 }
+// generic complex load/store on cx<R> storage (16 B for double, 8 B for float)
+template <typename R>
+__device__ inline cx<R> ldc(const cx<R> *p) { return *p; }
+template <typename R>
+__device__ inline void stc(cx<R> *p, cx<R> v) { *p = v; }
 
 // Wavefront-wide sum (64 lanes) with DPP/shuffle via __shfl_xor.
 __device__ inline double wave_sum(double v) {

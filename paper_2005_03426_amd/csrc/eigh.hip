@@ -41,7 +41,8 @@ extern "C" int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes) {
   if (M < 0) return -1;
   if (prec != MMF_C128 && prec != MMF_C64_REFINED && prec != MMF_C64_RAW) return -2;
   if (!bytes) return -3;
-  size_t b = eigh_ws(M, nullptr, 0).bytes;
+  size_t b = (prec == MMF_C128) ? eigh_ws(M, nullptr, 0).bytes
+                                 : eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED);
   // every stage entry point accepts a workspace of this size
   const size_t s1 = hetrd_ws_bytes(M), s2 = stedc_ws_bytes(M), s3 = unmtr_ws_bytes(M);
   if (s1 > b) b = s1;
@@ -59,11 +60,14 @@ extern "C" int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, v
   if (!w && M > 0) return -4;
   if (prec != MMF_C128 && prec != MMF_C64_REFINED && prec != MMF_C64_RAW) return -5;
   if (!work) return -6;
+  if (!dev_info) return -8;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec != MMF_C128) {
+    if (work_bytes < eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED)) return -7;
+    return eigh_c64_run(M, A, lda, w, prec == MMF_C64_REFINED, work, work_bytes, dev_info, st);
+  }
   EighWs ws = eigh_ws(M, work, work_bytes);
   if (work_bytes < ws.bytes) return -7;
-  if (!dev_info) return -8;
-  if (prec != MMF_C128) return MMF_ERR_NOT_IMPLEMENTED;
-  hipStream_t st = (hipStream_t)stream;
   if (M == 0) return MMF_OK;
   int rc = hetrd_run(M, A, lda, w, ws.e, ws.tau, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;

@@ -12,15 +12,18 @@
 // A - V W^H - W V^H, so
 //   u = A v - V (W^H v) - W (V^H v),   w0 = tau u,   w = w0 - (tau/2)(w0^H v) v.
 // After the panel the trailing matrix takes one rank-2k update
-// A -= [V W] [W V]^H on the FP64 matrix cores (lower triangle only).
+// A -= [V W] [W V]^H on the matrix cores (lower triangle only).
 //
 // Per column the row-parallel kernels are: reflector (scale x), HEMV over
-// the lower trailing triangle (64x64 tiles, each workgroup a strip of tiles
-// of one block column: the direct product goes to per-(block-column, row)
-// partials, the conjugate-transposed product accumulates in registers), the
-// panel corrections W^H v / V^H v, the reduction of the partials into w0,
-// and the final w together with the update of the next panel column.  All
-// sums are over fixed partitions in fixed order (deterministic).
+// the lower trailing triangle, the panel corrections W^H v / V^H v, the
+// reduction of the partials into w0, and the final w together with the
+// update of the next panel column.  All sums are over fixed partitions in
+// fixed order (deterministic).
+//
+// Every kernel is a template over the scalar type R: R = double is the
+// complex128 path; R = float is the complex64 reduction of the precision
+// layer (FP32 storage, FP32 accumulation, FP32 matrix cores), whose d and e
+// are still returned in FP64.
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
@@ -29,112 +32,124 @@
 namespace mmf {
 
 constexpr int HV_T = 64;        // HEMV tile
-constexpr int HV_CH = 16;       // tiles per HEMV workgroup (one block column strip)
+constexpr int HV_CH = 32;       // tiles per HEMV workgroup (one block column strip)
 constexpr int RW = 256;         // rows per workgroup in row-parallel kernels
 constexpr int DOT_ROWS = 1024;  // rows per workgroup of the panel dot products
 
-__device__ inline double block_sum256(double v, double *sh) {
-  v = wave_sum(v);
+template <typename R>
+__device__ inline R block_sum256(R v, R *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wv] = v;
   __syncthreads();
-  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  return r;
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+template <typename R>
 struct HtWs {
-  mmf_z *P3;       // n x 3NB (ld n): [V | W | V]
-  mmf_z *pdir;     // nbt x mpad
-  mmf_z *ptrn;     // nbt x nchmax x 64
-  mmf_z *dots;     // gdot x 2NB
-  double *norms;   // grow partials
-  mmf_z *sparts;   // grow partials
-  mmf_z *w0first;  // 1
+  cx<R> *P3;       // n x 3NB (ld n): [V | W | V]
+  cx<R> *pdir;     // nbt x mpad
+  cx<R> *ptrn;     // nbt x nchmax x 64
+  cx<R> *dots;     // gdot x 2NB
+  R *norms;        // grow partials
+  cx<R> *sparts;   // nbt partials
+  cx<R> *w0first;  // 1
   int64_t nbt, mpad, nchmax;
   size_t bytes;
 };
 
-inline HtWs hetrd_ws(int64_t n, void *base) {
+template <typename R>
+inline HtWs<R> hetrd_ws(int64_t n, void *base) {
   Carver cv(base);
-  HtWs w;
+  HtWs<R> w;
   const int64_t m = n > 1 ? n - 1 : 1;
   w.nbt = (m + HV_T - 1) / HV_T;
   w.mpad = w.nbt * HV_T;
   w.nchmax = (w.nbt + HV_CH - 1) / HV_CH;
-  w.P3 = cv.take<mmf_z>((size_t)n * 3 * HT_NB);
-  w.pdir = cv.take<mmf_z>((size_t)w.nbt * w.mpad);
-  w.ptrn = cv.take<mmf_z>((size_t)w.nbt * w.nchmax * HV_T);
+  w.P3 = cv.take<cx<R>>((size_t)n * 3 * HT_NB);
+  w.pdir = cv.take<cx<R>>((size_t)w.nbt * w.mpad);
+  w.ptrn = cv.take<cx<R>>((size_t)w.nbt * w.nchmax * HV_T);
   const int64_t gdot = (n + DOT_ROWS - 1) / DOT_ROWS + 1;
-  w.dots = cv.take<mmf_z>((size_t)gdot * 2 * HT_NB);
+  w.dots = cv.take<cx<R>>((size_t)gdot * 2 * HT_NB);
   const int64_t grow = (n + RW - 1) / RW + 1;
-  w.norms = cv.take<double>(grow);
-  w.sparts = cv.take<mmf_z>(w.nbt + 1);
-  w.w0first = cv.take<mmf_z>(4);
+  w.norms = cv.take<R>(grow);
+  w.sparts = cv.take<cx<R>>(w.nbt + 1);
+  w.w0first = cv.take<cx<R>>(4);
   w.bytes = cv.used();
   return w;
 }
 
-size_t hetrd_ws_bytes(int64_t n) { return hetrd_ws(n, nullptr).bytes; }
+template <typename R>
+size_t hetrd_ws_bytes_t(int64_t n) { return hetrd_ws<R>(n, nullptr).bytes; }
+size_t hetrd_ws_bytes(int64_t n) { return hetrd_ws_bytes_t<double>(n); }
 
 // ---------------------------------------------------------------- kernels
-__global__ void ht_zero_panel(mmf_z *P3, int64_t n, int64_t p) {
+template <typename R>
+__global__ void ht_zero_panel(cx<R> *P3, int64_t n, int64_t p) {
   const int64_t r = p + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  for (int c = 0; c < 3 * HT_NB; ++c) stz(P3 + r + c * n, cmake(0.0, 0.0));
+  for (int c = 0; c < 3 * HT_NB; ++c) P3[r + c * n] = cmk<R>(0, 0);
 }
 
 // partial ||A[i+2:, i]||^2 (first column of a panel)
-__global__ void __launch_bounds__(RW) ht_colnorm(const mmf_z *A, int64_t lda, int64_t n, int64_t i,
-                                                double *norms) {
-  __shared__ double sh[4];
+template <typename R>
+__global__ void __launch_bounds__(RW) ht_colnorm(const cx<R> *A, int64_t lda, int64_t n, int64_t i,
+                                                R *norms) {
+  __shared__ R sh[4];
   const int64_t r = i + 2 + (int64_t)blockIdx.x * RW + threadIdx.x;
-  double s = 0.0;
-  if (r < n) s = cabs2(ldz(A + r + i * lda));
+  R s = 0;
+  if (r < n) s = cabs2(A[r + i * lda]);
   s = block_sum256(s, sh);
   if (threadIdx.x == 0) norms[blockIdx.x] = s;
 }
 
 // Reflector of column i: every workgroup derives (beta, tau) from the norm
 // partials and scales its rows of x into v.
-__global__ void __launch_bounds__(RW) ht_reflector(mmf_z *A, int64_t lda, int64_t n, int64_t i, int k,
-                                                  mmf_z *P3, const double *norms, int gnorm,
-                                                  double *d, double *e, mmf_z *tau) {
-  __shared__ double sh[4];
-  double xp = 0.0;
+template <typename R>
+__global__ void __launch_bounds__(RW) ht_reflector(cx<R> *A, int64_t lda, int64_t n, int64_t i, int k,
+                                                  cx<R> *P3, const R *norms, int gnorm,
+                                                  double *d, double *e, cx<R> *tau) {
+  __shared__ R sh[4];
+  R xp = 0;
   for (int g = threadIdx.x; g < gnorm; g += RW) xp += norms[g];
-  const double xn2 = block_sum256(xp, sh);
-  const cd alpha = ldz(A + (i + 1) + i * lda);
-  double beta;
-  cd t, scale;
-  if (xn2 == 0.0 && alpha.im == 0.0) {
+  const R xn2 = block_sum256(xp, sh);
+  const cx<R> alpha = A[(i + 1) + i * lda];
+  R beta;
+  cx<R> t, scale;
+  if (xn2 == R(0) && alpha.im == R(0)) {
     beta = alpha.re;
-    t = cmake(0.0, 0.0);
-    scale = cmake(0.0, 0.0);
+    t = cmk<R>(0, 0);
+    scale = cmk<R>(0, 0);
   } else {
-    const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
-    beta = alpha.re >= 0.0 ? -nrm : nrm;
-    t = cmake((beta - alpha.re) / beta, -alpha.im / beta);
+    const R nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
+    beta = alpha.re >= R(0) ? -nrm : nrm;
+    t = cmk<R>((beta - alpha.re) / beta, -alpha.im / beta);
     // scale = 1 / (alpha - beta)
-    const cd den = cmake(alpha.re - beta, alpha.im);
-    const double q = den.re * den.re + den.im * den.im;
-    scale = cmake(den.re / q, -den.im / q);
+    const cx<R> den = cmk<R>(alpha.re - beta, alpha.im);
+    const R q = den.re * den.re + den.im * den.im;
+    scale = cmk<R>(den.re / q, -den.im / q);
   }
   const int64_t r = i + 2 + (int64_t)blockIdx.x * RW + threadIdx.x;
   if (r < n) {
-    const cd v = cmul(ldz(A + r + i * lda), scale);
-    stz(A + r + i * lda, v);
-    stz(P3 + r + (int64_t)k * n, v);
-    stz(P3 + r + (int64_t)(2 * HT_NB + k) * n, v);
+    const cx<R> v = cmul(A[r + i * lda], scale);
+    A[r + i * lda] = v;
+    P3[r + (int64_t)k * n] = v;
+    P3[r + (int64_t)(2 * HT_NB + k) * n] = v;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    stz(P3 + (i + 1) + (int64_t)k * n, cmake(1.0, 0.0));
-    stz(P3 + (i + 1) + (int64_t)(2 * HT_NB + k) * n, cmake(1.0, 0.0));
-    d[i] = ldz(A + i + i * lda).re;
-    e[i] = beta;
-    stz(tau + i, t);
+    P3[(i + 1) + (int64_t)k * n] = cmk<R>(1, 0);
+    P3[(i + 1) + (int64_t)(2 * HT_NB + k) * n] = cmk<R>(1, 0);
+    d[i] = (double)A[i + i * lda].re;
+    e[i] = (double)beta;
+    tau[i] = t;
   }
 }
+
+template <typename R> struct NtVec;
+template <> struct NtVec<double> { typedef double v __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<float> { typedef float v __attribute__((ext_vector_type(2))); };
 
 // u = A_trail v over the lower triangle of the trailing matrix
 // A_trail = A[i+1:, i+1:] (size m).  Workgroup (bj, c) covers the tile strip
@@ -142,15 +157,19 @@ __global__ void __launch_bounds__(RW) ht_reflector(mmf_z *A, int64_t lda, int64_
 // (bi = bi0 + wave, bi0 + wave + 4, ...), so no workgroup barrier sits in the
 // streaming loop.  Lane l covers rows rg + 16 q (rg = l % 16, q = 0..3) and
 // columns 16 cg + j (cg = l / 16, j = 0..15): every load instruction reads four
-// 256-byte column segments.  The direct product of a tile is folded across
-// the four column groups with shuffles and written as one partial per
+// contiguous column segments.  Interior tiles are read with non-temporal
+// loads and no per-element guards.  The direct product of a tile is folded
+// across the four column groups with shuffles and written as one partial per
 // (block column, row); the conjugate-transposed product accumulates in
 // registers over the strip and is folded once at the end.
-__global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int64_t n, int64_t i,
-                                               const mmf_z *P3, int k, mmf_z *pdir, mmf_z *ptrn,
+template <typename R>
+__global__ void __launch_bounds__(256) ht_hemv(const cx<R> *A, int64_t lda, int64_t n, int64_t i,
+                                               const cx<R> *P3, int k, cx<R> *pdir, cx<R> *ptrn,
                                                int64_t mpad, int64_t nchmax) {
-  __shared__ cd vcol[HV_T];
-  __shared__ cd tsum[4][HV_T];
+  typedef cx<R> C;
+  typedef typename NtVec<R>::v nv;
+  __shared__ C vcol[HV_T];
+  __shared__ C tsum[4][HV_T];
   const int64_t m = n - i - 1;
   const int64_t nbt = (m + HV_T - 1) / HV_T;
   const int64_t bj = blockIdx.x;
@@ -161,46 +180,61 @@ __global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int6
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int rg = lane & 15, cg = lane >> 4;
-  const mmf_z *At = A + (i + 1) + (i + 1) * lda;
-  const mmf_z *v = P3 + (i + 1) + (int64_t)k * n;
+  const C *At = A + (i + 1) + (i + 1) * lda;
+  const C *v = P3 + (i + 1) + (int64_t)k * n;
   if (tid < HV_T) {
     const int64_t gc = bj * HV_T + tid;
-    vcol[tid] = gc < m ? ldz(v + gc) : cmake(0.0, 0.0);
+    vcol[tid] = gc < m ? v[gc] : cmk<R>(0, 0);
   }
   __syncthreads();
-  cd tacc[16];
+  C tacc[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) tacc[j] = cmake(0.0, 0.0);
+  for (int j = 0; j < 16; ++j) tacc[j] = cmk<R>(0, 0);
   const int64_t col0 = bj * HV_T + cg * 16;
   for (int64_t bi = bi0 + wave; bi < bi1; bi += 4) {
     const bool diagt = (bi == bj);
-    cd vr[4], dacc[4];
+    // interior tile: every element is in range and below the diagonal
+    const bool full = !diagt && (bi + 1) * HV_T <= m;
+    C vr[4], dacc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t row = bi * HV_T + rg + 16 * q;
-      vr[q] = row < m ? ldz(v + row) : cmake(0.0, 0.0);
-      dacc[q] = cmake(0.0, 0.0);
+      vr[q] = row < m ? v[row] : cmk<R>(0, 0);
+      dacc[q] = cmk<R>(0, 0);
     }
+    const C *tb = At + bi * HV_T + rg + col0 * lda;
 #pragma unroll
     for (int jb = 0; jb < 16; jb += 4) {
-      cd av[4][4];
+      C av[4][4];
+      if (full) {
+        // streaming data read exactly once: non-temporal loads, no per-element guards
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj)
+        for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t row = bi * HV_T + rg + 16 * q;
-          const int64_t gc = col0 + jb + jj;
-          const bool ok = row < m && gc < m && (!diagt || row >= gc);
-          av[jj][q] = ok ? ldz(At + row + gc * lda) : cmake(0.0, 0.0);
-        }
+          for (int q = 0; q < 4; ++q) {
+            const nv x = __builtin_nontemporal_load(
+                reinterpret_cast<const nv *>(tb + 16 * q + (int64_t)(jb + jj) * lda));
+            av[jj][q] = cmk<R>(x[0], x[1]);
+          }
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t row = bi * HV_T + rg + 16 * q;
+            const int64_t gc = col0 + jb + jj;
+            const bool ok = row < m && gc < m && (!diagt || row >= gc);
+            av[jj][q] = ok ? At[row + gc * lda] : cmk<R>(0, 0);
+          }
+      }
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const cd vc = vcol[cg * 16 + jb + jj];
+        const C vc = vcol[cg * 16 + jb + jj];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          cd a = av[jj][q];
+          C a = av[jj][q];
           const bool dg = diagt && (rg + 16 * q == cg * 16 + jb + jj);
-          if (dg) a.im = 0.0;
+          if (dg) a.im = R(0);
           dacc[q] = cadd(dacc[q], cmul(a, vc));
           if (!dg) tacc[jb + jj] = cadd(tacc[jb + jj], cmulc(a, vr[q]));
         }
@@ -208,64 +242,67 @@ __global__ void __launch_bounds__(256) ht_hemv(const mmf_z *A, int64_t lda, int6
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double re = dacc[q].re, im = dacc[q].im;
+      R re = dacc[q].re, im = dacc[q].im;
       re += __shfl_xor(re, 16, 64); im += __shfl_xor(im, 16, 64);
       re += __shfl_xor(re, 32, 64); im += __shfl_xor(im, 32, 64);
-      if (cg == 0) stz(pdir + bj * mpad + bi * HV_T + rg + 16 * q, cmake(re, im));
+      if (cg == 0) pdir[bj * mpad + bi * HV_T + rg + 16 * q] = cmk<R>(re, im);
     }
   }
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    double re = tacc[j].re, im = tacc[j].im;
+    R re = tacc[j].re, im = tacc[j].im;
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
-    if (rg == 0) tsum[wave][cg * 16 + j] = cmake(re, im);
+    if (rg == 0) tsum[wave][cg * 16 + j] = cmk<R>(re, im);
   }
   __syncthreads();
   if (tid < HV_T) {
     const int nw = (int)((bi1 - bi0 < 4) ? bi1 - bi0 : 4);
-    cd s = cmake(0.0, 0.0);
+    C s = cmk<R>(0, 0);
     for (int w2 = 0; w2 < nw; ++w2) s = cadd(s, tsum[w2][tid]);
-    stz(ptrn + (bj * nchmax + c) * HV_T + tid, s);
+    ptrn[(bj * nchmax + c) * HV_T + tid] = s;
   }
 }
 
 // Panel corrections: dots[g*2NB + q] = sum_rows conj(W[:,q]) v (q < k) and
 // dots[g*2NB + NB + q] = sum_rows conj(V[:,q]) v over rows [i+1, n).
-__global__ void __launch_bounds__(256) ht_dots(const mmf_z *P3, int64_t n, int64_t i, int k, mmf_z *dots) {
-  __shared__ double sh[4];
+template <typename R>
+__global__ void __launch_bounds__(256) ht_dots(const cx<R> *P3, int64_t n, int64_t i, int k, cx<R> *dots) {
+  __shared__ R sh[4];
   const int g = blockIdx.x;
   const int qq = blockIdx.y;                 // 0..2k-1
   const int q = qq % k, which = qq / k;
-  const mmf_z *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
-  const mmf_z *v = P3 + (int64_t)k * n;
-  cd s = cmake(0.0, 0.0);
+  const cx<R> *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
+  const cx<R> *v = P3 + (int64_t)k * n;
+  cx<R> s = cmk<R>(0, 0);
   const int64_t r0 = i + 1 + (int64_t)g * DOT_ROWS;
   for (int j = threadIdx.x; j < DOT_ROWS; j += 256) {
     const int64_t r = r0 + j;
-    if (r < n) s = cadd(s, cmulc(ldz(X + r), ldz(v + r)));
+    if (r < n) s = cadd(s, cmulc(X[r], v[r]));
   }
-  const double sr = block_sum256(s.re, sh);
-  const double si = block_sum256(s.im, sh);
-  if (threadIdx.x == 0) stz(dots + (int64_t)g * 2 * HT_NB + which * HT_NB + q, cmake(sr, si));
+  const R sr = block_sum256(s.re, sh);
+  const R si = block_sum256(s.im, sh);
+  if (threadIdx.x == 0) dots[(int64_t)g * 2 * HT_NB + which * HT_NB + q] = cmk<R>(sr, si);
 }
 
 // w0 = tau (u - V x1 - W x2), with u assembled from the HEMV partials.
 // One workgroup per 64-row block; its four wavefronts split the partial
 // sums and the panel corrections, combined in LDS in fixed order.
-__global__ void __launch_bounds__(256) ht_finish_u(int64_t n, int64_t i, int k, mmf_z *P3,
-                                                  const mmf_z *pdir, const mmf_z *ptrn, int64_t mpad,
-                                                  int64_t nchmax, const mmf_z *dots, int gdot,
-                                                  const mmf_z *tau, mmf_z *sparts, mmf_z *w0first) {
-  __shared__ cd x1[HT_NB], x2[HT_NB];
-  __shared__ cd part[4][HV_T];
-  __shared__ double sh[4];
+template <typename R>
+__global__ void __launch_bounds__(256) ht_finish_u(int64_t n, int64_t i, int k, cx<R> *P3,
+                                                  const cx<R> *pdir, const cx<R> *ptrn, int64_t mpad,
+                                                  int64_t nchmax, const cx<R> *dots, int gdot,
+                                                  const cx<R> *tau, cx<R> *sparts, cx<R> *w0first) {
+  typedef cx<R> C;
+  __shared__ C x1[HT_NB], x2[HT_NB];
+  __shared__ C part[4][HV_T];
+  __shared__ R sh[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   if (tid < 2 * k) {
     const int q = tid % k, which = tid / k;
-    cd s = cmake(0.0, 0.0);
-    for (int g = 0; g < gdot; ++g) s = cadd(s, ldz(dots + (int64_t)g * 2 * HT_NB + which * HT_NB + q));
+    C s = cmk<R>(0, 0);
+    for (int g = 0; g < gdot; ++g) s = cadd(s, dots[(int64_t)g * 2 * HT_NB + which * HT_NB + q]);
     if (which == 0) x1[q] = s; else x2[q] = s;
   }
   __syncthreads();
@@ -274,77 +311,75 @@ __global__ void __launch_bounds__(256) ht_finish_u(int64_t n, int64_t i, int k, 
   const int64_t bi = blockIdx.x;
   const int64_t t = bi * HV_T + lane;
   const int64_t rho = i + 1 + t;
-  cd u = cmake(0.0, 0.0);
+  C u = cmk<R>(0, 0);
   if (t < m) {
-    for (int64_t bj = wave; bj <= bi; bj += 4) u = cadd(u, ldz(pdir + bj * mpad + t));
+    for (int64_t bj = wave; bj <= bi; bj += 4) u = cadd(u, pdir[bj * mpad + t]);
     const int64_t nch = (nbt - bi + HV_CH - 1) / HV_CH;
-    for (int64_t c = wave; c < nch; c += 4) u = cadd(u, ldz(ptrn + (bi * nchmax + c) * HV_T + lane));
+    for (int64_t c = wave; c < nch; c += 4) u = cadd(u, ptrn[(bi * nchmax + c) * HV_T + lane]);
     for (int q = wave; q < k; q += 4) {
-      u = csub(u, cmul(ldz(P3 + rho + (int64_t)q * n), x1[q]));
-      u = csub(u, cmul(ldz(P3 + rho + (int64_t)(HT_NB + q) * n), x2[q]));
+      u = csub(u, cmul(P3[rho + (int64_t)q * n], x1[q]));
+      u = csub(u, cmul(P3[rho + (int64_t)(HT_NB + q) * n], x2[q]));
     }
   }
   part[wave][lane] = u;
   __syncthreads();
-  cd contrib = cmake(0.0, 0.0);
+  C contrib = cmk<R>(0, 0);
   if (wave == 0 && t < m) {
-    const cd us = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
-    const cd w0 = cmul(ldz(tau + i), us);
-    stz(P3 + rho + (int64_t)(HT_NB + k) * n, w0);
-    if (t == 0) w0first[0] = *reinterpret_cast<const mmf_z *>(&w0);
-    contrib = cmulc(ldz(P3 + rho + (int64_t)k * n), w0);   // conj(v) w0
+    const C us = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
+    const C w0 = cmul(tau[i], us);
+    P3[rho + (int64_t)(HT_NB + k) * n] = w0;
+    if (t == 0) w0first[0] = w0;
+    contrib = cmulc(P3[rho + (int64_t)k * n], w0);   // conj(v) w0
   }
-  const double sr = block_sum256(contrib.re, sh);
-  const double si = block_sum256(contrib.im, sh);
-  if (tid == 0) stz(sparts + blockIdx.x, cmake(sr, si));
+  const R sr = block_sum256(contrib.re, sh);
+  const R si = block_sum256(contrib.im, sh);
+  if (tid == 0) sparts[blockIdx.x] = cmk<R>(sr, si);
 }
 
 // w = w0 - (tau/2) conj(v^H w0) v; then, inside a panel, the update of the
 // next column i+1 by the k+1 reflectors so far and its partial norms.
-__global__ void __launch_bounds__(RW) ht_finish_w(mmf_z *A, int64_t lda, int64_t n, int64_t i, int k,
-                                                 int next, mmf_z *P3, const mmf_z *sparts, int gs,
-                                                 const mmf_z *tau, const mmf_z *w0first, double *norms) {
-  __shared__ cd cw[HT_NB], cv[HT_NB];
-  __shared__ double sh[4];
+template <typename R>
+__global__ void __launch_bounds__(RW) ht_finish_w(cx<R> *A, int64_t lda, int64_t n, int64_t i, int k,
+                                                 int next, cx<R> *P3, const cx<R> *sparts, int gs,
+                                                 const cx<R> *tau, const cx<R> *w0first, R *norms) {
+  typedef cx<R> C;
+  __shared__ C cw[HT_NB], cv[HT_NB];
+  __shared__ R sh[4];
   const int tid = threadIdx.x;
-  cd s = cmake(0.0, 0.0);
+  C s;
   {
-    cd ps = cmake(0.0, 0.0);
-    for (int g = tid; g < gs; g += RW) ps = cadd(ps, ldz(sparts + g));
+    C ps = cmk<R>(0, 0);
+    for (int g = tid; g < gs; g += RW) ps = cadd(ps, sparts[g]);
     s.re = block_sum256(ps.re, sh);
     s.im = block_sum256(ps.im, sh);
   }
-  const cd ti = ldz(tau + i);
-  const cd alpha = cscale(cmul(ti, cconj(s)), -0.5);
+  const C ti = tau[i];
+  const C alpha = cscale(cmul(ti, cconj(s)), R(-0.5));
   if (next && tid <= k) {
     const int64_t rr = i + 1;
-    cd wq;
-    if (tid == k) {
-      const cd w0 = ldz(w0first);
-      wq = cadd(w0, alpha);                   // v[i+1] = 1
-    } else {
-      wq = ldz(P3 + rr + (int64_t)(HT_NB + tid) * n);
-    }
+    C wq;
+    if (tid == k) wq = cadd(w0first[0], alpha);                   // v[i+1] = 1
+    else wq = P3[rr + (int64_t)(HT_NB + tid) * n];
     cw[tid] = cconj(wq);
-    cv[tid] = cconj(ldz(P3 + rr + (int64_t)tid * n));
+    cv[tid] = cconj(P3[rr + (int64_t)tid * n]);
   }
   __syncthreads();
   const int64_t rho = i + 1 + (int64_t)blockIdx.x * RW + tid;
-  double nrm = 0.0;
+  R nrm = 0;
   if (rho < n) {
-    const cd v = ldz(P3 + rho + (int64_t)k * n);
-    const cd w = cadd(ldz(P3 + rho + (int64_t)(HT_NB + k) * n), cmul(alpha, v));
-    stz(P3 + rho + (int64_t)(HT_NB + k) * n, w);
-    if (rho == i + 1) stz(A + rho + i * lda, cmake(1.0, 0.0));
+    const C v = P3[rho + (int64_t)k * n];
+    const C w = cadd(P3[rho + (int64_t)(HT_NB + k) * n], cmul(alpha, v));
+    P3[rho + (int64_t)(HT_NB + k) * n] = w;
+    if (rho == i + 1) A[rho + i * lda] = cmk<R>(1, 0);
     if (next) {
-      cd a = ldz(A + rho + (i + 1) * lda);
+      C a = A[rho + (i + 1) * lda];
       for (int q = 0; q < k; ++q) {
-        a = csub(a, cmul(ldz(P3 + rho + (int64_t)q * n), cw[q]));
-        a = csub(a, cmul(ldz(P3 + rho + (int64_t)(HT_NB + q) * n), cv[q]));
+        a = csub(a, cmul(P3[rho + (int64_t)q * n], cw[q]));
+        a = csub(a, cmul(P3[rho + (int64_t)(HT_NB + q) * n], cv[q]));
       }
       a = csub(a, cmul(v, cw[k]));
       a = csub(a, cmul(w, cv[k]));
-      stz(A + rho + (i + 1) * lda, a);
+      A[rho + (i + 1) * lda] = a;
       if (rho >= i + 3) nrm = cabs2(a);
     }
   }
@@ -352,54 +387,54 @@ __global__ void __launch_bounds__(RW) ht_finish_w(mmf_z *A, int64_t lda, int64_t
   if (next && tid == 0) norms[blockIdx.x] = nrm;
 }
 
-__global__ void ht_last_diag(const mmf_z *A, int64_t lda, int64_t n, double *d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) d[n - 1] = ldz(A + (n - 1) + (n - 1) * lda).re;
+template <typename R>
+__global__ void ht_last_diag(const cx<R> *A, int64_t lda, int64_t n, double *d) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) d[n - 1] = (double)A[(n - 1) + (n - 1) * lda].re;
 }
 
 // ---------------------------------------------------------------- host
-int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau, void *work,
-              size_t bytes, hipStream_t st) {
+template <typename R>
+int hetrd_run_t(int64_t n, cx<R> *A, int64_t lda, double *d, double *e, cx<R> *tau, void *work,
+                size_t bytes, hipStream_t st) {
   if (n <= 0) return MMF_OK;
-  HtWs w = hetrd_ws(n, work);
+  HtWs<R> w = hetrd_ws<R>(n, work);
   if (bytes < w.bytes) return MMF_ERR_WORKSPACE;
   for (int64_t p = 0; p < n - 1; p += HT_NB) {
     const int kb = (int)((n - 1 - p < HT_NB) ? n - 1 - p : HT_NB);
-    hipLaunchKernelGGL(ht_zero_panel, dim3(cdiv(n - p, 256)), dim3(256), 0, st, w.P3, n, p);
+    hipLaunchKernelGGL(ht_zero_panel<R>, dim3(cdiv(n - p, 256)), dim3(256), 0, st, w.P3, n, p);
     MMF_LAUNCH_CHECK();
-    {
-      const int g = (int)cdiv(n - p - 2 > 0 ? n - p - 2 : 1, RW);
-      hipLaunchKernelGGL(ht_colnorm, dim3(g), dim3(RW), 0, st, A, lda, n, p, w.norms);
-      MMF_LAUNCH_CHECK();
-    }
-    int gnorm = (int)cdiv(n - p - 2 > 0 ? n - p - 2 : 1, RW);
+    const int g0 = (int)cdiv(n - p - 2 > 0 ? n - p - 2 : 1, RW);
+    hipLaunchKernelGGL(ht_colnorm<R>, dim3(g0), dim3(RW), 0, st, A, lda, n, p, w.norms);
+    MMF_LAUNCH_CHECK();
+    int gnorm = g0;
     for (int k = 0; k < kb; ++k) {
       const int64_t i = p + k;
       const int64_t m = n - i - 1;
       {
         const int g = (int)cdiv(n - i - 2 > 0 ? n - i - 2 : 1, RW);
-        hipLaunchKernelGGL(ht_reflector, dim3(g), dim3(RW), 0, st, A, lda, n, i, k, w.P3, w.norms,
+        hipLaunchKernelGGL(ht_reflector<R>, dim3(g), dim3(RW), 0, st, A, lda, n, i, k, w.P3, w.norms,
                            gnorm, d, e, tau);
         MMF_LAUNCH_CHECK();
       }
       const int64_t nbt = (m + HV_T - 1) / HV_T;
       const int64_t nch = (nbt + HV_CH - 1) / HV_CH;
-      const int ks = ktimer_begin("hemv", st);
-      hipLaunchKernelGGL(ht_hemv, dim3((unsigned)nbt, (unsigned)nch), dim3(256), 0, st, A, lda, n, i,
+      const int ks = ktimer_begin(sizeof(R) == 8 ? "hemv" : "hemv_c64", st);
+      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbt, (unsigned)nch), dim3(256), 0, st, A, lda, n, i,
                          w.P3, k, w.pdir, w.ptrn, w.mpad, w.nchmax);
       MMF_LAUNCH_CHECK();
       // algorithmic bytes: the lower triangle of the trailing matrix, read once
-      ktimer_end(ks, st, 16.0 * (double)m * (double)(m + 1) / 2.0);
+      ktimer_end(ks, st, 2.0 * sizeof(R) * (double)m * (double)(m + 1) / 2.0);
       const int gdot = (int)cdiv(m, DOT_ROWS);
       if (k > 0) {
-        hipLaunchKernelGGL(ht_dots, dim3(gdot, 2 * k), dim3(256), 0, st, w.P3, n, i, k, w.dots);
+        hipLaunchKernelGGL(ht_dots<R>, dim3(gdot, 2 * k), dim3(256), 0, st, w.P3, n, i, k, w.dots);
         MMF_LAUNCH_CHECK();
       }
-      hipLaunchKernelGGL(ht_finish_u, dim3((unsigned)nbt), dim3(256), 0, st, n, i, k, w.P3, w.pdir, w.ptrn,
-                         w.mpad, w.nchmax, w.dots, gdot, tau, w.sparts, w.w0first);
+      hipLaunchKernelGGL(ht_finish_u<R>, dim3((unsigned)nbt), dim3(256), 0, st, n, i, k, w.P3, w.pdir,
+                         w.ptrn, w.mpad, w.nchmax, w.dots, gdot, tau, w.sparts, w.w0first);
       MMF_LAUNCH_CHECK();
       const int gu = (int)cdiv(m, RW);
       const int next = (k + 1 < kb) ? 1 : 0;
-      hipLaunchKernelGGL(ht_finish_w, dim3(gu), dim3(RW), 0, st, A, lda, n, i, k, next, w.P3,
+      hipLaunchKernelGGL(ht_finish_w<R>, dim3(gu), dim3(RW), 0, st, A, lda, n, i, k, next, w.P3,
                          w.sparts, (int)nbt, tau, w.w0first, w.norms);
       MMF_LAUNCH_CHECK();
       gnorm = gu;
@@ -410,13 +445,26 @@ int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau
       GemmArgs g = gemm_args(n - q, n - q, 2 * HT_NB, w.P3 + q, n, w.P3 + q + (int64_t)HT_NB * n, n,
                              A + q + q * lda, lda, -1.0, 0.0, 1.0, 0.0);
       g.lower = 1;
-      const int rc = gemm_launch<true, A_N, B_C>(g, st);
+      const int rc = gemm_launch_t<R, true, A_N, B_C>(g, st);
       if (rc) return rc;
     }
   }
-  hipLaunchKernelGGL(ht_last_diag, dim3(1), dim3(64), 0, st, A, lda, n, d);
+  hipLaunchKernelGGL(ht_last_diag<R>, dim3(1), dim3(64), 0, st, A, lda, n, d);
   MMF_LAUNCH_CHECK();
   return MMF_OK;
+}
+
+int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau, void *work,
+              size_t bytes, hipStream_t st) {
+  return hetrd_run_t<double>(n, reinterpret_cast<cd *>(A), lda, d, e, reinterpret_cast<cd *>(tau), work,
+                             bytes, st);
+}
+
+size_t hetrd_ws_bytes_c64(int64_t n) { return hetrd_ws_bytes_t<float>(n); }
+int hetrd_run_c64(int64_t n, void *A, int64_t lda, double *d, double *e, void *tau, void *work,
+                  size_t bytes, hipStream_t st) {
+  return hetrd_run_t<float>(n, reinterpret_cast<cf *>(A), lda, d, e, reinterpret_cast<cf *>(tau), work,
+                            bytes, st);
 }
 
 }  // namespace mmf

@@ -1,0 +1,393 @@
+// Precision layer of the eigensolver (not part of the paper, whose
+// diagonalisation is a plain FP64 LAPACK call): complex64 reduction and
+// back-transformation on the FP32 matrix cores with FP32 accumulation, FP64
+// divide and conquer in between, then FP64 refinement of the eigenpairs.
+//
+// Refinement (Ogita and Aishima's iteration for symmetric/Hermitian
+// eigenproblems, with their treatment of clustered eigenvalues):
+//   G = X^H X,  S = X^H (A X),  lam_i = s_ii / g_ii,  R = I - G,
+//   for i != j outside a common cluster
+//       e_ij = (s_ij + lam_j r_ij) / (lam_j - lam_i),
+//   e_ii = r_ii / 2, and inside a cluster e_ij = r_ij / 2 followed by the
+//   Rayleigh-Ritz rotation that diagonalises the cluster block of
+//   T = S - (R S + S R)/2 (first-order projection onto the orthonormalised
+//   cluster basis);  X <- X (I + E).
+// Clusters are runs of consecutive eigenvalues closer than
+//   delta = CL_FACTOR * max( max_{i!=j} |s_ij|, max|lam| max_{i!=j} |g_ij| ),
+// the level at which the first-order correction would stop being small.
+// All products are FP64 complex GEMMs on the matrix cores; A X is clipped to
+// the bandwidth of A, detected on the device (the Floquet matrix is banded).
+#include <float.h>
+#include "common.h"
+#include "stages.h"
+#include "gemm_core.h"
+
+namespace mmf {
+
+constexpr int REF_ITERS = 2;
+constexpr double CL_FACTOR = 10.0;
+constexpr int CL_MAX = 32;          // clusters are split into chunks of at most CL_MAX
+
+// ---------------------------------------------------------------- conversions
+__global__ void rf_to_c64(int64_t n, const cd *A, int64_t lda, cf *Ac, int64_t ldc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n) return;
+  const cd a = A[r + c * lda];
+  Ac[r + c * ldc] = cmk<float>((float)a.re, (float)a.im);
+}
+
+__global__ void rf_to_c128(int64_t n, const cf *Xc, int64_t ldc, cd *X, int64_t ldx) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n) return;
+  const cf a = Xc[r + c * ldc];
+  X[r + c * ldx] = cmake((double)a.re, (double)a.im);
+}
+
+// Full Hermitian matrix from its lower triangle.
+__global__ void rf_hermitize(int64_t n, const cd *A, int64_t lda, cd *H) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n) return;
+  cd v;
+  if (r > c) v = A[r + c * lda];
+  else if (r == c) v = cmake(A[r + c * lda].re, 0.0);
+  else v = cconj(A[c + r * lda]);
+  H[r + c * n] = v;
+}
+
+// Half-bandwidth of the lower triangle: max over columns of (last nonzero row - column).
+__global__ void rf_band(int64_t n, const cd *A, int64_t lda, int32_t *band) {
+  __shared__ int32_t sh[4];
+  const int64_t c = blockIdx.x;
+  int32_t b = 0;
+  for (int64_t r = c + threadIdx.x; r < n; r += 256) {
+    const cd a = A[r + c * lda];
+    if (a.re != 0.0 || a.im != 0.0) b = (int32_t)(r - c);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(band, max(max(sh[0], sh[1]), max(sh[2], sh[3])));
+}
+
+__global__ void rf_zero_int(int32_t *p) { if (threadIdx.x == 0) *p = 0; }
+
+// ---------------------------------------------------------------- per-iteration scalars
+// lam_i = Re s_ii / Re g_ii; per-column maxima of the off-diagonal |s_ij|, |g_ij|.
+__global__ void __launch_bounds__(256) rf_lambda(int64_t n, const cd *S, const cd *G, double *lam,
+                                                 double *colmax) {
+  __shared__ double sh[2][4];
+  const int64_t j = blockIdx.x;
+  double ms = 0.0, mg = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    if (i == j) continue;
+    const cd s = S[i + j * n], g = G[i + j * n];
+    ms = fmax(ms, sqrt(cabs2(s)));
+    mg = fmax(mg, sqrt(cabs2(g)));
+  }
+  ms = wave_max(ms);
+  mg = wave_max(mg);
+  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ms; sh[1][threadIdx.x >> 6] = mg; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    lam[j] = S[j + j * n].re / G[j + j * n].re;
+    colmax[2 * j] = fmax(fmax(sh[0][0], sh[0][1]), fmax(sh[0][2], sh[0][3]));
+    colmax[2 * j + 1] = fmax(fmax(sh[1][0], sh[1][1]), fmax(sh[1][2], sh[1][3]));
+  }
+}
+
+// Cluster scan (one thread): cid[i] = first index of i's cluster chunk;
+// clist holds (start, size) of every chunk with size >= 2; ncl its count.
+__global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, int32_t *cid,
+                            int32_t *clist, int32_t *ncl, double *delta_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double ms = 0.0, mg = 0.0, ml = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    ms = fmax(ms, colmax[2 * j]);
+    mg = fmax(mg, colmax[2 * j + 1]);
+    ml = fmax(ml, fabs(lam[j]));
+  }
+  const double delta = CL_FACTOR * fmax(ms, ml * mg);
+  *delta_out = delta;
+  int32_t nc = 0;
+  int64_t start = 0;
+  for (int64_t i = 1; i <= n; ++i) {
+    const bool brk = (i == n) || (fabs(lam[i] - lam[i - 1]) > delta) || (i - start >= CL_MAX);
+    if (brk) {
+      for (int64_t q = start; q < i; ++q) cid[q] = (int32_t)start;
+      if (i - start >= 2) {
+        clist[2 * nc] = (int32_t)start;
+        clist[2 * nc + 1] = (int32_t)(i - start);
+        ++nc;
+      }
+      start = i;
+    }
+  }
+  *ncl = nc;
+}
+
+// F = I + E, written over S.
+__global__ void rf_build_f(int64_t n, cd *S, const cd *G, const double *lam, const int32_t *cid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= n) return;
+  const cd s = S[i + j * n], g = G[i + j * n];
+  cd f;
+  if (i == j) {
+    f = cmake(1.0 + 0.5 * (1.0 - g.re), 0.0);
+  } else if (cid[i] == cid[j]) {
+    f = cscale(g, -0.5);                         // r_ij / 2
+  } else {
+    const double den = lam[j] - lam[i];
+    // (s_ij + lam_j r_ij) / (lam_j - lam_i), r_ij = -g_ij
+    f = cscale(csub(s, cscale(g, lam[j])), 1.0 / den);
+  }
+  S[i + j * n] = f;
+}
+
+// Cluster blocks: T = S_CC - (R S + S R)/2 with R = I - G (first order),
+// Jacobi-diagonalised by one thread per cluster; Q (size x size) and the
+// Ritz values are stored for the rotation kernel.
+__global__ void rf_cluster_rr(int64_t n, const cd *S, const cd *G, const int32_t *clist,
+                              const int32_t *ncl, cd *Qbuf, double *lam) {
+  __shared__ cd T[CL_MAX][CL_MAX], Q[CL_MAX][CL_MAX];
+  const int c = blockIdx.x;
+  if (c >= *ncl || threadIdx.x != 0) return;
+  const int st = clist[2 * c], sz = clist[2 * c + 1];
+  for (int a = 0; a < sz; ++a)
+    for (int b = 0; b < sz; ++b) {
+      cd acc = S[(st + a) + (int64_t)(st + b) * n];
+      for (int k = 0; k < sz; ++k) {
+        const cd rak = cmake((a == k ? 1.0 : 0.0) - G[(st + a) + (int64_t)(st + k) * n].re,
+                             -G[(st + a) + (int64_t)(st + k) * n].im);
+        const cd rkb = cmake((k == b ? 1.0 : 0.0) - G[(st + k) + (int64_t)(st + b) * n].re,
+                             -G[(st + k) + (int64_t)(st + b) * n].im);
+        acc = csub(acc, cscale(cadd(cmul(rak, S[(st + k) + (int64_t)(st + b) * n]),
+                                    cmul(S[(st + a) + (int64_t)(st + k) * n], rkb)), 0.5));
+      }
+      T[a][b] = acc;
+      Q[a][b] = cmake(a == b ? 1.0 : 0.0, 0.0);
+    }
+  // make T exactly Hermitian
+  for (int a = 0; a < sz; ++a) {
+    T[a][a].im = 0.0;
+    for (int b = a + 1; b < sz; ++b) {
+      const cd h = cscale(cadd(T[a][b], cconj(T[b][a])), 0.5);
+      T[a][b] = h;
+      T[b][a] = cconj(h);
+    }
+  }
+  // cyclic complex Jacobi
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int a = 0; a < sz; ++a)
+      for (int b = 0; b < sz; ++b) {
+        const double v = cabs2(T[a][b]);
+        tot += v;
+        if (a != b) off += v;
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < sz - 1; ++p)
+      for (int q = p + 1; q < sz; ++q) {
+        const double r = sqrt(cabs2(T[p][q]));
+        if (r == 0.0) continue;
+        const cd ph = cscale(T[p][q], 1.0 / r);     // a_pq = r e^{i phi}
+        const double theta = (T[q][q].re - T[p][p].re) / (2.0 * r);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        // J = [[c, s], [-s conj(ph), c conj(ph)]] on columns p, q
+        const cd j00 = cmake(cs, 0.0), j01 = cmake(sn, 0.0);
+        const cd j10 = cscale(cconj(ph), -sn), j11 = cscale(cconj(ph), cs);
+        for (int k = 0; k < sz; ++k) {               // T <- T J
+          const cd tp = T[k][p], tq = T[k][q];
+          T[k][p] = cadd(cmul(tp, j00), cmul(tq, j10));
+          T[k][q] = cadd(cmul(tp, j01), cmul(tq, j11));
+        }
+        for (int k = 0; k < sz; ++k) {               // T <- J^H T
+          const cd tp = T[p][k], tq = T[q][k];
+          T[p][k] = cadd(cmulc(j00, tp), cmulc(j10, tq));
+          T[q][k] = cadd(cmulc(j01, tp), cmulc(j11, tq));
+        }
+        T[p][q] = cmake(0.0, 0.0);
+        T[q][p] = cmake(0.0, 0.0);
+        for (int k = 0; k < sz; ++k) {               // Q <- Q J
+          const cd qp = Q[k][p], qq = Q[k][q];
+          Q[k][p] = cadd(cmul(qp, j00), cmul(qq, j10));
+          Q[k][q] = cadd(cmul(qp, j01), cmul(qq, j11));
+        }
+      }
+  }
+  cd *Qo = Qbuf + (int64_t)c * CL_MAX * CL_MAX;
+  for (int a = 0; a < sz; ++a) {
+    lam[st + a] = T[a][a].re;
+    for (int b = 0; b < sz; ++b) Qo[a + b * CL_MAX] = Q[a][b];
+  }
+}
+
+// F[:, C] <- F[:, C] Q_C for every cluster chunk C (thread = row).
+__global__ void rf_cluster_rotate(int64_t n, cd *F, const int32_t *clist, const int32_t *ncl,
+                                  const cd *Qbuf) {
+  const int c = blockIdx.y;
+  if (c >= *ncl) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int st = clist[2 * c], sz = clist[2 * c + 1];
+  const cd *Q = Qbuf + (int64_t)c * CL_MAX * CL_MAX;
+  cd row[CL_MAX];
+#pragma unroll
+  for (int a = 0; a < CL_MAX; ++a) row[a] = (a < sz) ? F[r + (int64_t)(st + a) * n] : cmake(0.0, 0.0);
+  for (int b = 0; b < sz; ++b) {
+    cd s = cmake(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < CL_MAX; ++a)
+      if (a < sz) s = cadd(s, cmul(row[a], Q[a + b * CL_MAX]));
+    F[r + (int64_t)(st + b) * n] = s;
+  }
+}
+
+// Ascending order of the refined eigenvalues (rank by counting, ties by index).
+__global__ void rf_rank(int64_t n, const double *lam, int32_t *dest) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = lam[i];
+  int64_t pos = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double u = lam[k];
+    pos += (u < v) || (u == v && k < i);
+  }
+  dest[i] = (int32_t)pos;
+}
+
+__global__ void rf_scatter(int64_t n, const cd *X, const double *lam, const int32_t *dest, cd *A,
+                           int64_t lda, double *w) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n) return;
+  const int64_t dc = dest[c];
+  A[r + dc * lda] = X[r + c * n];
+  if (r == 0) w[dc] = lam[c];
+}
+
+// ---------------------------------------------------------------- workspace
+struct RefWs {
+  cf *Ac;          // complex64 copy of A; reflectors, then the complex64 eigenvectors
+  cf *tauc;
+  double *e;
+  double *Z;
+  void *stage;
+  size_t stage_bytes;
+  cd *X, *B1, *B2;
+  double *lam, *colmax, *delta;
+  int32_t *cid, *clist, *ncl, *band, *dest;
+  cd *Qbuf;
+  size_t bytes;
+};
+
+inline RefWs ref_ws(int64_t M, bool refine, void *base) {
+  Carver cv(base);
+  RefWs w;
+  const size_t n = (size_t)(M > 0 ? M : 1);
+  w.Ac = cv.take<cf>(n * n);
+  w.tauc = cv.take<cf>(n);
+  w.e = cv.take<double>(n);
+  w.Z = cv.take<double>(n * n);
+  size_t st = hetrd_ws_bytes_c64(M);
+  const size_t s2 = stedc_ws_bytes(M), s3 = unmtr_ws_bytes_c64(M);
+  if (s2 > st) st = s2;
+  if (s3 > st) st = s3;
+  w.stage = cv.take<char>(st);
+  w.stage_bytes = st;
+  if (refine) {
+    w.X = cv.take<cd>(n * n);
+    w.B1 = cv.take<cd>(n * n);
+    w.B2 = cv.take<cd>(n * n);
+  } else {
+    w.X = w.B1 = w.B2 = nullptr;
+  }
+  w.lam = cv.take<double>(n);
+  w.colmax = cv.take<double>(2 * n);
+  w.delta = cv.take<double>(1);
+  w.cid = cv.take<int32_t>(n);
+  w.clist = cv.take<int32_t>(2 * n);
+  w.ncl = cv.take<int32_t>(1);
+  w.band = cv.take<int32_t>(1);
+  w.dest = cv.take<int32_t>(n);
+  w.Qbuf = cv.take<cd>((n / 2 + 1) * CL_MAX * CL_MAX);
+  w.bytes = cv.used();
+  return w;
+}
+
+size_t eigh_c64_ws_bytes(int64_t M, bool refine) { return ref_ws(M, refine, nullptr).bytes; }
+
+int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void *work, size_t bytes,
+                 int32_t *info, hipStream_t st) {
+  if (M <= 0) return MMF_OK;
+  RefWs ws = ref_ws(M, refine, work);
+  if (bytes < ws.bytes) return MMF_ERR_WORKSPACE;
+  cd *A = reinterpret_cast<cd *>(Az);
+  const int64_t n = M;
+  const dim3 g2(cdiv(n, 256), (unsigned)n);
+  // complex64 eigensolve: reduction and back-transformation in FP32, D&C in FP64
+  hipLaunchKernelGGL(rf_to_c64, g2, dim3(256), 0, st, n, A, lda, ws.Ac, n);
+  MMF_LAUNCH_CHECK();
+  int rc = hetrd_run_c64(n, ws.Ac, n, w, ws.e, ws.tauc, ws.stage, ws.stage_bytes, st);
+  if (rc) return rc;
+  rc = stedc_run(n, w, ws.e, ws.Z, n, ws.stage, ws.stage_bytes, info, st);
+  if (rc) return rc;
+  rc = unmtr_run_c64(n, ws.Ac, n, ws.tauc, ws.Z, n, ws.Ac, n, ws.stage, ws.stage_bytes, st);
+  if (rc) return rc;
+  if (!refine) {
+    hipLaunchKernelGGL(rf_to_c128, g2, dim3(256), 0, st, n, ws.Ac, n, A, lda);
+    MMF_LAUNCH_CHECK();
+    return MMF_OK;
+  }
+  hipLaunchKernelGGL(rf_to_c128, g2, dim3(256), 0, st, n, ws.Ac, n, ws.X, n);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.band);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(rf_band, dim3((unsigned)n), dim3(256), 0, st, n, A, lda, ws.band);
+  MMF_LAUNCH_CHECK();
+  cd *X = ws.X, *B1 = ws.B1, *B2 = ws.B2;
+  for (int it = 0; it < REF_ITERS; ++it) {
+    // B1 = A X (A Hermitian from its lower triangle, banded)
+    hipLaunchKernelGGL(rf_hermitize, g2, dim3(256), 0, st, n, A, lda, B2);
+    MMF_LAUNCH_CHECK();
+    GemmArgs ga = gemm_args(n, n, n, B2, n, X, n, B1, n, 1.0, 0.0, 0.0, 0.0);
+    ga.band_ptr = ws.band;
+    rc = gemm_launch<true, A_N, B_N>(ga, st);
+    if (rc) return rc;
+    // B2 = S = X^H (A X);  B1 = G = X^H X
+    rc = gemm_launch<true, A_C, B_N>(gemm_args(n, n, n, X, n, B1, n, B2, n, 1.0, 0.0, 0.0, 0.0), st);
+    if (rc) return rc;
+    rc = gemm_launch<true, A_C, B_N>(gemm_args(n, n, n, X, n, X, n, B1, n, 1.0, 0.0, 0.0, 0.0), st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, B2, B1, ws.lam, ws.colmax);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_clusters, dim3(1), dim3(64), 0, st, n, ws.lam, ws.colmax, ws.cid, ws.clist,
+                       ws.ncl, ws.delta);
+    MMF_LAUNCH_CHECK();
+    const unsigned maxcl = (unsigned)(n / 2 + 1);
+    hipLaunchKernelGGL(rf_cluster_rr, dim3(maxcl), dim3(64), 0, st, n, B2, B1, ws.clist, ws.ncl, ws.Qbuf,
+                       ws.lam);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_build_f, g2, dim3(256), 0, st, n, B2, B1, ws.lam, ws.cid);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_cluster_rotate, dim3(cdiv(n, 256), maxcl), dim3(256), 0, st, n, B2, ws.clist,
+                       ws.ncl, ws.Qbuf);
+    MMF_LAUNCH_CHECK();
+    // X <- X F  (into B1, then swap)
+    rc = gemm_launch<true, A_N, B_N>(gemm_args(n, n, n, X, n, B2, n, B1, n, 1.0, 0.0, 0.0, 0.0), st);
+    if (rc) return rc;
+    cd *t = X; X = B1; B1 = t;
+  }
+  hipLaunchKernelGGL(rf_rank, dim3(cdiv(n, 256)), dim3(256), 0, st, n, ws.lam, ws.dest);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(rf_scatter, g2, dim3(256), 0, st, n, X, ws.lam, ws.dest, A, lda, w);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+}  // namespace mmf

@@ -298,3 +298,66 @@ def test_argument_errors():
                       0, C.c_void_p(small.data_ptr()), C.c_size_t(16), C.c_void_p(info.data_ptr()), None) == -7
     assert L.mmf_eigh(C.c_int64(dp.M), C.c_void_p(buf.data_ptr()), C.c_int64(dp.M), C.c_void_p(w.data_ptr()),
                       9, C.c_void_p(small.data_ptr()), C.c_size_t(16), C.c_void_p(info.data_ptr()), None) == -5
+
+
+# --------------------------------------------------------------- precision layer
+def _eigh_prec(H, prec):
+    torch, mmf = require_gpu()
+    At = to_dev_cm(torch, H)
+    w, Pt, info = mmf.eigh(At, prec=prec)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    return w.cpu().numpy(), from_dev_cm(Pt)
+
+
+@pytest.mark.parametrize("n", [5, 64, 129, 400])
+def test_eigh_c64_raw_is_single_precision(n):
+    """Unrefined complex64 path: error reported, only sanity-bounded."""
+    torch, mmf = require_gpu()
+    rng = np.random.default_rng(2000 + n)
+    A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    H = (A + A.conj().T) / 2
+    w, Phi = _eigh_prec(H, mmf.MMF_C64_RAW)
+    wo, _ = oracle.eigh(H)
+    err = np.abs(w - wo).max() / max(1.0, np.abs(wo).max())
+    log(f"c64 raw n={n}: eigenvalue error {err:.2e}")
+    assert err < 1e-4
+    assert np.abs(Phi.conj().T @ Phi - np.eye(n)).max() < 1e-3
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 129, 400])
+def test_eigh_c64_refined_random(n):
+    """Refined mixed path: eigenvalues within 1e-9, eigenpairs at FP64 level."""
+    torch, mmf = require_gpu()
+    rng = np.random.default_rng(3000 + n)
+    A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    H = (A + A.conj().T) / 2
+    w, Phi = _eigh_prec(H, mmf.MMF_C64_REFINED)
+    wo, _ = oracle.eigh(H)
+    scale = max(1.0, np.abs(wo).max())
+    log(f"c64 refined n={n}: eig err {np.abs(w - wo).max() / scale:.2e}")
+    assert np.abs(w - wo).max() <= 1e-9 * scale
+    assert np.linalg.norm(H @ Phi - Phi * w) / max(1.0, np.linalg.norm(H)) < 1e-11
+    assert np.abs(Phi.conj().T @ Phi - np.eye(n)).max() < 1e-11
+
+
+@pytest.mark.parametrize("name,mk", [
+    ("tls_cfg", lambda: cfg1_tls()),
+    ("ladder_small", lambda: cfg2_large(N=(5, 5))),
+])
+def test_refined_pipeline_against_oracle(name, mk):
+    """Precision-layer solve: eigenvalues, U(t,t0) and P within 1e-9 of the FP64 oracle."""
+    torch, mmf = require_gpu()
+    p, ts, t0 = mk()
+    ts = ts[:40]
+    out = mmf.solve(p, ts, t0, prec=mmf.MMF_C64_REFINED)
+    torch.cuda.synchronize()
+    assert int(out["info"].item()) == 0
+    H, wo, Phio = _oracle_solve(p)
+    w = out["w"].cpu().numpy()
+    ew = np.abs(w - wo).max() / max(1.0, np.abs(wo).max())
+    Uo = oracle.evolve(p, Phio, wo, t0, ts)
+    eu = np.abs(out["U"].cpu().numpy() - Uo).max()
+    ep = np.abs(out["P"].cpu().numpy() - oracle.avg_prob(p, Phio)).max()
+    log(f"refined pipeline {name}: eps {ew:.2e} U {eu:.2e} P {ep:.2e}")
+    assert ew <= 1e-9 and eu <= 1e-9 and ep <= 1e-9
