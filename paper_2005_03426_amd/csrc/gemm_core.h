@@ -53,6 +53,7 @@ struct GemmArgs {
   int lower;                         // 1: only elements with row >= col are written (tiles above skipped)
   int64_t band;                      // >= 0: op(A)[m,k] = 0 for |m-k| > band
   const int32_t *band_ptr;           // optional device copy of the band (overrides band when set)
+  const int32_t *skip;               // optional device flag: when nonzero the launch does nothing
 };
 
 template <typename R> struct MfmaT;
@@ -288,6 +289,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel_t(GemmArgs g) {
   const int64_t m0 = (int64_t)blockIdx.x * GT_M;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   if (g.lower && m0 + GT_M <= n0) return;     // tile entirely above the diagonal
+  if (g.skip && *g.skip) return;
   gemm_tile_t<R, CPLX, OA, OB>(g, m0, n0, lds);
 }
 
@@ -319,6 +321,7 @@ __host__ __device__ inline GemmArgs gemm_args(int64_t M, int64_t N, int64_t K, c
   g.lower = 0;
   g.band = -1;
   g.band_ptr = nullptr;
+  g.skip = nullptr;
   return g;
 }
 

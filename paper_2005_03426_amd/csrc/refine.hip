@@ -8,13 +8,18 @@
 //   G = X^H X,  S = X^H (A X),  lam_i = s_ii / g_ii,  R = I - G,
 //   for i != j outside a common cluster
 //       e_ij = (s_ij + lam_j r_ij) / (lam_j - lam_i),
-//   e_ii = r_ii / 2, and inside a cluster e_ij = r_ij / 2 followed by the
-//   Rayleigh-Ritz rotation that diagonalises the cluster block of
-//   T = S - (R S + S R)/2 (first-order projection onto the orthonormalised
-//   cluster basis);  X <- X (I + E).
+//   e_ii = r_ii / 2, and inside a cluster e_ij = r_ij / 2;  X <- X (I + E).
+//   Before the correction, every cluster is moved to its Rayleigh-Ritz
+//   basis: Q_C diagonalises the cluster block of T = S - (R S + S R)/2 (the
+//   first-order projection onto the orthonormalised cluster basis) and
+//   X <- X Q, S <- Q^H S Q, G <- Q^H G Q, so that the corrections coupling a
+//   cluster to the rest use the Ritz values of its rotated vectors.
 // Clusters are runs of consecutive eigenvalues closer than
-//   delta = CL_FACTOR * max( max_{i!=j} |s_ij|, max|lam| max_{i!=j} |g_ij| ),
-// the level at which the first-order correction would stop being small.
+//   delta = CL_FACTOR * max_{i!=j} |s_ij - lam_j g_ij|,
+// so that every first-order correction outside a cluster is below 1/CL_FACTOR:
+// from complex64 eigenvectors (error ~ eps32 ||A|| / gap) a pair closer than
+// that cannot be separated by the first-order step and is rotated inside its
+// cluster instead; the threshold collapses after the first iteration.
 // All products are FP64 complex GEMMs on the matrix cores; A X is clipped to
 // the bandwidth of A, detected on the device (the Floquet matrix is banded).
 #include <float.h>
@@ -24,8 +29,9 @@
 
 namespace mmf {
 
-constexpr int REF_ITERS = 2;
-constexpr double CL_FACTOR = 10.0;
+constexpr int REF_ITERS = 6;      // upper bound; converged iterations are skipped on the device
+constexpr double CONV_TOL = 1e-13; // stop once max |s_ij - lam_j g_ij| <= CONV_TOL max(1, max|lam|)
+constexpr double CL_FACTOR = 100.0;
 constexpr int CL_MAX = 32;          // clusters are split into chunks of at most CL_MAX
 
 // ---------------------------------------------------------------- conversions
@@ -46,7 +52,8 @@ __global__ void rf_to_c128(int64_t n, const cf *Xc, int64_t ldc, cd *X, int64_t 
 }
 
 // Full Hermitian matrix from its lower triangle.
-__global__ void rf_hermitize(int64_t n, const cd *A, int64_t lda, cd *H) {
+__global__ void rf_hermitize(int64_t n, const cd *A, int64_t lda, cd *H, const int32_t *skip) {
+  if (*skip) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = blockIdx.y;
   if (r >= n) return;
@@ -74,43 +81,46 @@ __global__ void rf_band(int64_t n, const cd *A, int64_t lda, int32_t *band) {
 }
 
 __global__ void rf_zero_int(int32_t *p) { if (threadIdx.x == 0) *p = 0; }
+// skip <- stop_next at the start of an iteration (both flags live on the device)
+__global__ void rf_latch(int32_t *skip, const int32_t *stop_next) { if (threadIdx.x == 0) *skip = *stop_next; }
 
 // ---------------------------------------------------------------- per-iteration scalars
-// lam_i = Re s_ii / Re g_ii; per-column maxima of the off-diagonal |s_ij|, |g_ij|.
+// lam_j = Re s_jj / Re g_jj and, per column, max_{i != j} |s_ij - lam_j g_ij|
+// (the numerator of the first-order correction).
 __global__ void __launch_bounds__(256) rf_lambda(int64_t n, const cd *S, const cd *G, double *lam,
-                                                 double *colmax) {
-  __shared__ double sh[2][4];
+                                                 double *colmax, const int32_t *skip) {
+  __shared__ double sh[4];
+  if (*skip) return;
   const int64_t j = blockIdx.x;
-  double ms = 0.0, mg = 0.0;
+  const double lj = S[j + j * n].re / G[j + j * n].re;
+  double ms = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     if (i == j) continue;
-    const cd s = S[i + j * n], g = G[i + j * n];
-    ms = fmax(ms, sqrt(cabs2(s)));
-    mg = fmax(mg, sqrt(cabs2(g)));
+    const cd v = csub(S[i + j * n], cscale(G[i + j * n], lj));
+    ms = fmax(ms, sqrt(cabs2(v)));
   }
   ms = wave_max(ms);
-  mg = wave_max(mg);
-  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ms; sh[1][threadIdx.x >> 6] = mg; }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ms;
   __syncthreads();
   if (threadIdx.x == 0) {
-    lam[j] = S[j + j * n].re / G[j + j * n].re;
-    colmax[2 * j] = fmax(fmax(sh[0][0], sh[0][1]), fmax(sh[0][2], sh[0][3]));
-    colmax[2 * j + 1] = fmax(fmax(sh[1][0], sh[1][1]), fmax(sh[1][2], sh[1][3]));
+    lam[j] = lj;
+    colmax[j] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
   }
 }
 
 // Cluster scan (one thread): cid[i] = first index of i's cluster chunk;
 // clist holds (start, size) of every chunk with size >= 2; ncl its count.
 __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, int32_t *cid,
-                            int32_t *clist, int32_t *ncl, double *delta_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double ms = 0.0, mg = 0.0, ml = 0.0;
+                            int32_t *clist, int32_t *ncl, double *delta_out, const int32_t *skip,
+                            int32_t *stop_next) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *skip) return;
+  double ms = 0.0, ml = 1.0;
   for (int64_t j = 0; j < n; ++j) {
-    ms = fmax(ms, colmax[2 * j]);
-    mg = fmax(mg, colmax[2 * j + 1]);
+    ms = fmax(ms, colmax[j]);
     ml = fmax(ml, fabs(lam[j]));
   }
-  const double delta = CL_FACTOR * fmax(ms, ml * mg);
+  if (ms <= CONV_TOL * ml) *stop_next = 1;     // this iteration's update is the last one
+  const double delta = CL_FACTOR * ms;
   *delta_out = delta;
   int32_t nc = 0;
   int64_t start = 0;
@@ -130,7 +140,9 @@ __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, 
 }
 
 // F = I + E, written over S.
-__global__ void rf_build_f(int64_t n, cd *S, const cd *G, const double *lam, const int32_t *cid) {
+__global__ void rf_build_f(int64_t n, cd *S, const cd *G, const double *lam, const int32_t *cid,
+                           const int32_t *skip) {
+  if (*skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= n) return;
@@ -152,10 +164,10 @@ __global__ void rf_build_f(int64_t n, cd *S, const cd *G, const double *lam, con
 // Jacobi-diagonalised by one thread per cluster; Q (size x size) and the
 // Ritz values are stored for the rotation kernel.
 __global__ void rf_cluster_rr(int64_t n, const cd *S, const cd *G, const int32_t *clist,
-                              const int32_t *ncl, cd *Qbuf, double *lam) {
+                              const int32_t *ncl, cd *Qbuf, double *lam, const int32_t *skip) {
   __shared__ cd T[CL_MAX][CL_MAX], Q[CL_MAX][CL_MAX];
   const int c = blockIdx.x;
-  if (c >= *ncl || threadIdx.x != 0) return;
+  if (*skip || c >= *ncl || threadIdx.x != 0) return;
   const int st = clist[2 * c], sz = clist[2 * c + 1];
   for (int a = 0; a < sz; ++a)
     for (int b = 0; b < sz; ++b) {
@@ -229,9 +241,9 @@ __global__ void rf_cluster_rr(int64_t n, const cd *S, const cd *G, const int32_t
 
 // F[:, C] <- F[:, C] Q_C for every cluster chunk C (thread = row).
 __global__ void rf_cluster_rotate(int64_t n, cd *F, const int32_t *clist, const int32_t *ncl,
-                                  const cd *Qbuf) {
+                                  const cd *Qbuf, const int32_t *skip) {
   const int c = blockIdx.y;
-  if (c >= *ncl) return;
+  if (*skip || c >= *ncl) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int st = clist[2 * c], sz = clist[2 * c + 1];
@@ -246,6 +258,36 @@ __global__ void rf_cluster_rotate(int64_t n, cd *F, const int32_t *clist, const 
       if (a < sz) s = cadd(s, cmul(row[a], Q[a + b * CL_MAX]));
     F[r + (int64_t)(st + b) * n] = s;
   }
+}
+
+// S[C, :] <- Q_C^H S[C, :] for every cluster chunk C (thread = column).
+__global__ void rf_cluster_rotate_rows(int64_t n, cd *S, const int32_t *clist, const int32_t *ncl,
+                                       const cd *Qbuf, const int32_t *skip) {
+  const int c = blockIdx.y;
+  if (*skip || c >= *ncl) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int st = clist[2 * c], sz = clist[2 * c + 1];
+  const cd *Q = Qbuf + (int64_t)c * CL_MAX * CL_MAX;
+  cd col[CL_MAX];
+#pragma unroll
+  for (int a = 0; a < CL_MAX; ++a) col[a] = (a < sz) ? S[(st + a) + j * n] : cmake(0.0, 0.0);
+  for (int b = 0; b < sz; ++b) {
+    cd s = cmake(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < CL_MAX; ++a)
+      if (a < sz) s = cadd(s, cmulc(Q[a + b * CL_MAX], col[a]));     // (Q^H)_{ba} = conj(Q_ab)
+    S[(st + b) + j * n] = s;
+  }
+}
+
+// In a skipped iteration the vectors are carried over unchanged.
+__global__ void rf_carry(int64_t n, const cd *X, cd *Xo, const int32_t *skip) {
+  if (!*skip) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n) return;
+  Xo[r + c * n] = X[r + c * n];
 }
 
 // Ascending order of the refined eigenvalues (rank by counting, ties by index).
@@ -281,7 +323,7 @@ struct RefWs {
   size_t stage_bytes;
   cd *X, *B1, *B2;
   double *lam, *colmax, *delta;
-  int32_t *cid, *clist, *ncl, *band, *dest;
+  int32_t *cid, *clist, *ncl, *band, *dest, *skip, *stop;
   cd *Qbuf;
   size_t bytes;
 };
@@ -315,6 +357,8 @@ inline RefWs ref_ws(int64_t M, bool refine, void *base) {
   w.ncl = cv.take<int32_t>(1);
   w.band = cv.take<int32_t>(1);
   w.dest = cv.take<int32_t>(n);
+  w.skip = cv.take<int32_t>(1);
+  w.stop = cv.take<int32_t>(1);
   w.Qbuf = cv.take<cd>((n / 2 + 1) * CL_MAX * CL_MAX);
   w.bytes = cv.used();
   return w;
@@ -350,39 +394,74 @@ int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void
   MMF_LAUNCH_CHECK();
   hipLaunchKernelGGL(rf_band, dim3((unsigned)n), dim3(256), 0, st, n, A, lda, ws.band);
   MMF_LAUNCH_CHECK();
-  cd *X = ws.X, *B1 = ws.B1, *B2 = ws.B2;
+  hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.stop);
+  MMF_LAUNCH_CHECK();
+  // X alternates between two buffers; a skipped iteration must not swap, so
+  // the product X F is always written and read back through fixed roles:
+  // iteration it reads Xin = bufs[it % 2] and writes Xout = bufs[(it+1) % 2];
+  // when it is skipped, a copy kernel carries Xin over to Xout.
+  cd *bufs[2] = {ws.X, ws.B1};
+  cd *B2 = ws.B2, *B3 = nullptr;
+  (void)B3;
   for (int it = 0; it < REF_ITERS; ++it) {
-    // B1 = A X (A Hermitian from its lower triangle, banded)
-    hipLaunchKernelGGL(rf_hermitize, g2, dim3(256), 0, st, n, A, lda, B2);
+    cd *X = bufs[it % 2], *Xo = bufs[(it + 1) % 2];
+    hipLaunchKernelGGL(rf_latch, dim3(1), dim3(64), 0, st, ws.skip, ws.stop);
     MMF_LAUNCH_CHECK();
-    GemmArgs ga = gemm_args(n, n, n, B2, n, X, n, B1, n, 1.0, 0.0, 0.0, 0.0);
+    // Xo = A X (A Hermitian from its lower triangle, banded); Xo is free here
+    hipLaunchKernelGGL(rf_hermitize, g2, dim3(256), 0, st, n, A, lda, B2, ws.skip);
+    MMF_LAUNCH_CHECK();
+    GemmArgs ga = gemm_args(n, n, n, B2, n, X, n, Xo, n, 1.0, 0.0, 0.0, 0.0);
     ga.band_ptr = ws.band;
+    ga.skip = ws.skip;
     rc = gemm_launch<true, A_N, B_N>(ga, st);
     if (rc) return rc;
-    // B2 = S = X^H (A X);  B1 = G = X^H X
-    rc = gemm_launch<true, A_C, B_N>(gemm_args(n, n, n, X, n, B1, n, B2, n, 1.0, 0.0, 0.0, 0.0), st);
+    // B2 = S = X^H (A X);  Xo = G = X^H X
+    GemmArgs gs = gemm_args(n, n, n, X, n, Xo, n, B2, n, 1.0, 0.0, 0.0, 0.0);
+    gs.skip = ws.skip;
+    rc = gemm_launch<true, A_C, B_N>(gs, st);
     if (rc) return rc;
-    rc = gemm_launch<true, A_C, B_N>(gemm_args(n, n, n, X, n, X, n, B1, n, 1.0, 0.0, 0.0, 0.0), st);
+    GemmArgs gg = gemm_args(n, n, n, X, n, X, n, Xo, n, 1.0, 0.0, 0.0, 0.0);
+    gg.skip = ws.skip;
+    rc = gemm_launch<true, A_C, B_N>(gg, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, B2, B1, ws.lam, ws.colmax);
+    cd *S = B2, *G = Xo;
+    hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, S, G, ws.lam, ws.colmax, ws.skip);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_clusters, dim3(1), dim3(64), 0, st, n, ws.lam, ws.colmax, ws.cid, ws.clist,
-                       ws.ncl, ws.delta);
+                       ws.ncl, ws.delta, ws.skip, ws.stop);
     MMF_LAUNCH_CHECK();
     const unsigned maxcl = (unsigned)(n / 2 + 1);
-    hipLaunchKernelGGL(rf_cluster_rr, dim3(maxcl), dim3(64), 0, st, n, B2, B1, ws.clist, ws.ncl, ws.Qbuf,
-                       ws.lam);
+    hipLaunchKernelGGL(rf_cluster_rr, dim3(maxcl), dim3(64), 0, st, n, S, G, ws.clist, ws.ncl, ws.Qbuf,
+                       ws.lam, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_build_f, g2, dim3(256), 0, st, n, B2, B1, ws.lam, ws.cid);
+    // move X, S and G into the Rayleigh-Ritz basis of every cluster:
+    // X <- X Q, S <- Q^H S Q, G <- Q^H G Q (Q block diagonal, identity outside clusters)
+    const dim3 gcl(cdiv(n, 256), maxcl);
+    hipLaunchKernelGGL(rf_cluster_rotate, gcl, dim3(256), 0, st, n, X, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_cluster_rotate, dim3(cdiv(n, 256), maxcl), dim3(256), 0, st, n, B2, ws.clist,
-                       ws.ncl, ws.Qbuf);
+    hipLaunchKernelGGL(rf_cluster_rotate, gcl, dim3(256), 0, st, n, S, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
     MMF_LAUNCH_CHECK();
-    // X <- X F  (into B1, then swap)
-    rc = gemm_launch<true, A_N, B_N>(gemm_args(n, n, n, X, n, B2, n, B1, n, 1.0, 0.0, 0.0, 0.0), st);
+    hipLaunchKernelGGL(rf_cluster_rotate_rows, gcl, dim3(256), 0, st, n, S, ws.clist, ws.ncl, ws.Qbuf,
+                       ws.skip);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_cluster_rotate, gcl, dim3(256), 0, st, n, G, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_cluster_rotate_rows, gcl, dim3(256), 0, st, n, G, ws.clist, ws.ncl, ws.Qbuf,
+                       ws.skip);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, S, G, ws.lam, ws.colmax, ws.skip);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_build_f, g2, dim3(256), 0, st, n, S, G, ws.lam, ws.cid, ws.skip);
+    MMF_LAUNCH_CHECK();
+    // Xo = X F  (G in Xo is no longer needed); a skipped iteration copies X into Xo
+    GemmArgs gf = gemm_args(n, n, n, X, n, S, n, Xo, n, 1.0, 0.0, 0.0, 0.0);
+    gf.skip = ws.skip;
+    rc = gemm_launch<true, A_N, B_N>(gf, st);
     if (rc) return rc;
-    cd *t = X; X = B1; B1 = t;
+    hipLaunchKernelGGL(rf_carry, g2, dim3(256), 0, st, n, X, Xo, ws.skip);
+    MMF_LAUNCH_CHECK();
   }
+  cd *X = bufs[REF_ITERS % 2];
   hipLaunchKernelGGL(rf_rank, dim3(cdiv(n, 256)), dim3(256), 0, st, n, ws.lam, ws.dest);
   MMF_LAUNCH_CHECK();
   hipLaunchKernelGGL(rf_scatter, g2, dim3(256), 0, st, n, X, ws.lam, ws.dest, A, lda, w);

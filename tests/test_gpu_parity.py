@@ -361,3 +361,22 @@ def test_refined_pipeline_against_oracle(name, mk):
     ep = np.abs(out["P"].cpu().numpy() - oracle.avg_prob(p, Phio)).max()
     log(f"refined pipeline {name}: eps {ew:.2e} U {eu:.2e} P {ep:.2e}")
     assert ew <= 1e-9 and eu <= 1e-9 and ep <= 1e-9
+
+
+def test_refined_ladder_medium_against_oracle():
+    """Refined mixed path on a 3528-dimensional two-drive ladder (dense
+    quasienergy spectrum with close pairs): eigenvalues and U within 1e-9."""
+    torch, mmf = require_gpu()
+    p, ts, t0 = cfg2_large(N=(10, 10))
+    ts = ts[::32]
+    out = mmf.solve(p, ts, t0, prec=mmf.MMF_C64_REFINED)
+    torch.cuda.synchronize()
+    assert int(out["info"].item()) == 0
+    H, wo, Phio = _oracle_solve(p)
+    w = out["w"].cpu().numpy()
+    ew = np.abs(w - wo).max() / max(1.0, np.abs(wo).max())
+    Uo = oracle.evolve(p, Phio, wo, t0, ts)
+    eu = np.abs(out["U"].cpu().numpy() - Uo).max()
+    ep = np.abs(out["P"].cpu().numpy() - oracle.avg_prob(p, Phio)).max()
+    log(f"refined ladder M=3528: eps {ew:.2e} U {eu:.2e} P {ep:.2e}")
+    assert ew <= 1e-9 and eu <= 1e-9

@@ -1,0 +1,55 @@
+"""Continuous-batching executor: every result is the same alone and in the
+mix (bitwise: the kernels are deterministic and solves share nothing), and
+admission respects the HBM budget."""
+import numpy as np
+import pytest
+
+from workloads import random_problem, cfg1_tls, cfg5_serving, cfg3_batch
+from gpu_util import require_gpu, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _reqs(serve, problems, arrivals, prec=0):
+    return [serve.Request(rid=k, arrival=a, problem=p, times=np.linspace(0, 10, 8), t0=0.3, prec=prec)
+            for k, (p, a) in enumerate(zip(problems, arrivals))]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_result_same_alone_and_in_mix(prec):
+    torch, mmf = require_gpu()
+    from paper_2005_03426_amd import serve
+    probe = [random_problem(3, (4, 2), seed=s) for s in range(3)]
+    filler = [random_problem(2 + s % 3, (6, 1 + s % 2), seed=100 + s) for s in range(9)]
+    alone = []
+    for p in probe:
+        ex = serve.Executor(slots=1)
+        alone.append(ex.run(_reqs(serve, [p], [0.0], prec))[0].result)
+    mix = probe + filler
+    order = np.random.default_rng(0).permutation(len(mix))
+    arrivals = np.linspace(0.0, 0.02, len(mix))
+    reqs = _reqs(serve, [mix[i] for i in order], arrivals, prec)
+    ex = serve.Executor(slots=4)
+    done = ex.run(reqs)
+    assert len(done) == len(mix)
+    by_problem = {id(r.problem): r for r in done}
+    for p, a in zip(probe, alone):
+        r = by_problem[id(p)].result
+        for k in ("w", "U", "P"):
+            assert torch.equal(a[k], r[k]), k
+    stats = serve.latency_stats(done)
+    log(f"mix prec={prec}: {stats}")
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_admission_rejects_oversized_and_respects_budget():
+    torch, mmf = require_gpu()
+    from paper_2005_03426_amd import serve
+    small = random_problem(2, (3,), seed=1)
+    big = random_problem(8, (20, 20), seed=2)        # M = 13448: > 2 GB footprint
+    fp_small = serve.footprint_bytes(14, 2, 8)
+    ex = serve.Executor(slots=2, hbm_budget=int(1.5 * fp_small) + (1 << 20))
+    done = ex.run(_reqs(serve, [small, big, small, small], [0.0, 0.0, 0.0, 0.0]))
+    assert len(done) == 3 and len(ex.rejected) == 1 and ex.rejected[0].problem is big
+    for r in done:
+        assert int(r.result["info"].item()) == 0
