@@ -24,10 +24,17 @@
 // complex128 path; R = float is the complex64 reduction of the precision
 // layer (FP32 storage, FP32 accumulation, FP32 matrix cores), whose d and e
 // are still returned in FP64.
+//
+// Grouped execution: every kernel takes a device table of problems (HtProb)
+// and works on problem blockIdx.z, so one launch advances column i of every
+// matrix of a batch; a matrix whose reduction has finished (i >= n - 1) simply
+// exits.  Grids are sized for the largest matrix.  A single reduction is the
+// one-entry case.
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
 #include "ktimer.h"
+#include "table.h"
 
 namespace mmf {
 
@@ -83,21 +90,52 @@ inline HtWs<R> hetrd_ws(int64_t n, void *base) {
 
 template <typename R>
 size_t hetrd_ws_bytes_t(int64_t n) { return hetrd_ws<R>(n, nullptr).bytes; }
-size_t hetrd_ws_bytes(int64_t n) { return hetrd_ws_bytes_t<double>(n); }
+size_t hetrd_ws_bytes(int64_t n) { return hetrd_ws_bytes_t<double>(n) + 256; }
+
+// one row of the problem table
+template <typename R>
+struct HtProb {
+  int64_t n, lda, mpad, nchmax;
+  cx<R> *A;
+  double *d, *e;
+  cx<R> *tau;
+  cx<R> *P3, *pdir, *ptrn, *dots;
+  R *norms;
+  cx<R> *sparts, *w0first;
+};
+
+template <typename R>
+inline HtProb<R> ht_prob(int64_t n, cx<R> *A, int64_t lda, double *d, double *e, cx<R> *tau,
+                         const HtWs<R> &w) {
+  HtProb<R> q;
+  q.n = n; q.lda = lda; q.mpad = w.mpad; q.nchmax = w.nchmax;
+  q.A = A; q.d = d; q.e = e; q.tau = tau;
+  q.P3 = w.P3; q.pdir = w.pdir; q.ptrn = w.ptrn; q.dots = w.dots;
+  q.norms = w.norms; q.sparts = w.sparts; q.w0first = w.w0first;
+  return q;
+}
 
 // ---------------------------------------------------------------- kernels
 template <typename R>
-__global__ void ht_zero_panel(cx<R> *P3, int64_t n, int64_t p) {
+__global__ void ht_zero_panel(const HtProb<R> *pr, int64_t p) {
+  const HtProb<R> &q = pr[blockIdx.z];
+  const int64_t n = q.n;
   const int64_t r = p + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  for (int c = 0; c < 3 * HT_NB; ++c) P3[r + c * n] = cmk<R>(0, 0);
+  for (int c = 0; c < 3 * HT_NB; ++c) q.P3[r + c * n] = cmk<R>(0, 0);
 }
 
 // partial ||A[i+2:, i]||^2 (first column of a panel)
 template <typename R>
-__global__ void __launch_bounds__(RW) ht_colnorm(const cx<R> *A, int64_t lda, int64_t n, int64_t i,
-                                                R *norms) {
+__global__ void __launch_bounds__(RW) ht_colnorm(const HtProb<R> *pr, int64_t i) {
   __shared__ R sh[4];
+  const HtProb<R> &q = pr[blockIdx.z];
+  const int64_t n = q.n, lda = q.lda;
+  const cx<R> *A = q.A;
+  R *norms = q.norms;
+  if (i >= n - 1) return;
+  // only this matrix's partials (its norms buffer has that many entries)
+  if ((int64_t)blockIdx.x >= ((n - i - 2 > 0 ? n - i - 2 : 1) + RW - 1) / RW) return;
   const int64_t r = i + 2 + (int64_t)blockIdx.x * RW + threadIdx.x;
   R s = 0;
   if (r < n) s = cabs2(A[r + i * lda]);
@@ -108,10 +146,18 @@ __global__ void __launch_bounds__(RW) ht_colnorm(const cx<R> *A, int64_t lda, in
 // Reflector of column i: every workgroup derives (beta, tau) from the norm
 // partials and scales its rows of x into v.
 template <typename R>
-__global__ void __launch_bounds__(RW) ht_reflector(cx<R> *A, int64_t lda, int64_t n, int64_t i, int k,
-                                                  cx<R> *P3, const R *norms, int gnorm,
-                                                  double *d, double *e, cx<R> *tau) {
+__global__ void __launch_bounds__(RW) ht_reflector(const HtProb<R> *pr, int64_t p, int k) {
   __shared__ R sh[4];
+  const HtProb<R> &q = pr[blockIdx.z];
+  const int64_t n = q.n, lda = q.lda, i = p + k;
+  if (i >= n - 1) return;
+  cx<R> *A = q.A;
+  cx<R> *P3 = q.P3;
+  const R *norms = q.norms;
+  double *d = q.d, *e = q.e;
+  cx<R> *tau = q.tau;
+  // norm partials come from ht_colnorm (first panel column) or ht_finish_w
+  const int gnorm = (int)((k == 0) ? (((n - p - 2 > 0 ? n - p - 2 : 1) + RW - 1) / RW) : ((n - i + RW - 1) / RW));
   R xp = 0;
   for (int g = threadIdx.x; g < gnorm; g += RW) xp += norms[g];
   const R xn2 = block_sum256(xp, sh);
@@ -163,19 +209,23 @@ template <> struct NtVec<float> { typedef float v __attribute__((ext_vector_type
 // (block column, row); the conjugate-transposed product accumulates in
 // registers over the strip and is folded once at the end.
 template <typename R>
-__global__ void __launch_bounds__(256) ht_hemv(const cx<R> *A, int64_t lda, int64_t n, int64_t i,
-                                               const cx<R> *P3, int k, cx<R> *pdir, cx<R> *ptrn,
-                                               int64_t mpad, int64_t nchmax) {
+__global__ void __launch_bounds__(256) ht_hemv(const HtProb<R> *pr, int64_t i, int k) {
   typedef cx<R> C;
   typedef typename NtVec<R>::v nv;
   __shared__ C vcol[HV_T];
   __shared__ C tsum[4][HV_T];
+  const HtProb<R> &q = pr[blockIdx.z];
+  const int64_t n = q.n, lda = q.lda, mpad = q.mpad, nchmax = q.nchmax;
+  if (i >= n - 1) return;
+  const C *A = q.A;
+  const C *P3 = q.P3;
+  C *pdir = q.pdir, *ptrn = q.ptrn;
   const int64_t m = n - i - 1;
   const int64_t nbt = (m + HV_T - 1) / HV_T;
   const int64_t bj = blockIdx.x;
   const int64_t c = blockIdx.y;
   const int64_t bi0 = bj + c * HV_CH;
-  if (bi0 >= nbt) return;
+  if (bj >= nbt || bi0 >= nbt) return;
   const int64_t bi1 = (bi0 + HV_CH < nbt) ? bi0 + HV_CH : nbt;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -267,8 +317,14 @@ __global__ void __launch_bounds__(256) ht_hemv(const cx<R> *A, int64_t lda, int6
 // Panel corrections: dots[g*2NB + q] = sum_rows conj(W[:,q]) v (q < k) and
 // dots[g*2NB + NB + q] = sum_rows conj(V[:,q]) v over rows [i+1, n).
 template <typename R>
-__global__ void __launch_bounds__(256) ht_dots(const cx<R> *P3, int64_t n, int64_t i, int k, cx<R> *dots) {
+__global__ void __launch_bounds__(256) ht_dots(const HtProb<R> *pr, int64_t i, int k) {
   __shared__ R sh[4];
+  const HtProb<R> &pq = pr[blockIdx.z];
+  const int64_t n = pq.n;
+  if (i >= n - 1) return;
+  if ((int64_t)blockIdx.x >= (n - i - 1 + DOT_ROWS - 1) / DOT_ROWS) return;   // this matrix's partials only
+  const cx<R> *P3 = pq.P3;
+  cx<R> *dots = pq.dots;
   const int g = blockIdx.x;
   const int qq = blockIdx.y;                 // 0..2k-1
   const int q = qq % k, which = qq / k;
@@ -289,14 +345,19 @@ __global__ void __launch_bounds__(256) ht_dots(const cx<R> *P3, int64_t n, int64
 // One workgroup per 64-row block; its four wavefronts split the partial
 // sums and the panel corrections, combined in LDS in fixed order.
 template <typename R>
-__global__ void __launch_bounds__(256) ht_finish_u(int64_t n, int64_t i, int k, cx<R> *P3,
-                                                  const cx<R> *pdir, const cx<R> *ptrn, int64_t mpad,
-                                                  int64_t nchmax, const cx<R> *dots, int gdot,
-                                                  const cx<R> *tau, cx<R> *sparts, cx<R> *w0first) {
+__global__ void __launch_bounds__(256) ht_finish_u(const HtProb<R> *pr, int64_t i, int k) {
   typedef cx<R> C;
   __shared__ C x1[HT_NB], x2[HT_NB];
   __shared__ C part[4][HV_T];
   __shared__ R sh[4];
+  const HtProb<R> &pq = pr[blockIdx.z];
+  const int64_t n = pq.n, mpad = pq.mpad, nchmax = pq.nchmax;
+  if (i >= n - 1) return;
+  if ((int64_t)blockIdx.x * HV_T >= n - i - 1) return;          // beyond this matrix's row blocks
+  C *P3 = pq.P3;
+  const C *pdir = pq.pdir, *ptrn = pq.ptrn, *dots = pq.dots, *tau = pq.tau;
+  C *sparts = pq.sparts, *w0first = pq.w0first;
+  const int gdot = (int)((n - i - 1 + DOT_ROWS - 1) / DOT_ROWS);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   if (tid < 2 * k) {
@@ -339,12 +400,20 @@ __global__ void __launch_bounds__(256) ht_finish_u(int64_t n, int64_t i, int k, 
 // w = w0 - (tau/2) conj(v^H w0) v; then, inside a panel, the update of the
 // next column i+1 by the k+1 reflectors so far and its partial norms.
 template <typename R>
-__global__ void __launch_bounds__(RW) ht_finish_w(cx<R> *A, int64_t lda, int64_t n, int64_t i, int k,
-                                                 int next, cx<R> *P3, const cx<R> *sparts, int gs,
-                                                 const cx<R> *tau, const cx<R> *w0first, R *norms) {
+__global__ void __launch_bounds__(RW) ht_finish_w(const HtProb<R> *pr, int64_t p, int k) {
   typedef cx<R> C;
   __shared__ C cw[HT_NB], cv[HT_NB];
   __shared__ R sh[4];
+  const HtProb<R> &pq = pr[blockIdx.z];
+  const int64_t n = pq.n, lda = pq.lda, i = p + k;
+  if (i >= n - 1) return;
+  if ((int64_t)blockIdx.x * RW >= n - i - 1) return;              // beyond this matrix's rows
+  const int kb = (int)((n - 1 - p < HT_NB) ? n - 1 - p : HT_NB);
+  const int next = (k + 1 < kb) ? 1 : 0;
+  const int gs = (int)((n - i - 1 + HV_T - 1) / HV_T);
+  C *A = pq.A, *P3 = pq.P3;
+  const C *sparts = pq.sparts, *tau = pq.tau, *w0first = pq.w0first;
+  R *norms = pq.norms;
   const int tid = threadIdx.x;
   C s;
   {
@@ -388,70 +457,102 @@ __global__ void __launch_bounds__(RW) ht_finish_w(cx<R> *A, int64_t lda, int64_t
 }
 
 template <typename R>
-__global__ void ht_last_diag(const cx<R> *A, int64_t lda, int64_t n, double *d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) d[n - 1] = (double)A[(n - 1) + (n - 1) * lda].re;
+__global__ void ht_last_diag(const HtProb<R> *pr) {
+  const HtProb<R> &q = pr[blockIdx.z];
+  if (threadIdx.x == 0 && blockIdx.x == 0 && q.n > 0) q.d[q.n - 1] = (double)q.A[(q.n - 1) + (q.n - 1) * q.lda].re;
+}
+
+// Trailing update A[q0:, q0:] -= [V W] [W V]^H (lower tiles) after the panel
+// starting at column p, for every matrix of the table.
+template <typename R>
+__global__ void __launch_bounds__(GEMM_THREADS) ht_her2k(const HtProb<R> *pr, int64_t p) {
+  __shared__ R lds[GEMM_LDS_ELEMS];
+  const HtProb<R> &q = pr[blockIdx.z];
+  const int64_t n = q.n;
+  if (p >= n - 1) return;
+  const int kb = (int)((n - 1 - p < HT_NB) ? n - 1 - p : HT_NB);
+  const int64_t q0 = p + kb;
+  const int64_t M = n - q0;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  if (M <= 0 || m0 >= M || n0 >= M || m0 + GT_M <= n0) return;
+  GemmArgs g = gemm_args(M, M, 2 * HT_NB, q.P3 + q0, n, q.P3 + q0 + (int64_t)HT_NB * n, n,
+                         q.A + q0 + q0 * q.lda, q.lda, -1.0, 0.0, 1.0, 0.0);
+  g.lower = 1;
+  gemm_tile_t<R, true, A_N, B_C>(g, m0, n0, lds);
 }
 
 // ---------------------------------------------------------------- host
+// Grouped reduction of `count` matrices described by the device table pr
+// (orders nh[0..count) on the host, largest nmax).
+template <typename R>
+int hetrd_grouped(const HtProb<R> *pr, const int64_t *nh, int64_t count, hipStream_t st) {
+  int64_t nmax = 0;
+  for (int64_t c = 0; c < count; ++c) nmax = nh[c] > nmax ? nh[c] : nmax;
+  if (nmax <= 0 || count <= 0) return MMF_OK;
+  const unsigned Z = (unsigned)count;
+  for (int64_t p = 0; p < nmax - 1; p += HT_NB) {
+    const int kb = (int)((nmax - 1 - p < HT_NB) ? nmax - 1 - p : HT_NB);
+    hipLaunchKernelGGL(ht_zero_panel<R>, dim3(cdiv(nmax - p, 256), 1, Z), dim3(256), 0, st, pr, p);
+    MMF_LAUNCH_CHECK();
+    const unsigned g0 = cdiv(nmax - p - 2 > 0 ? nmax - p - 2 : 1, RW);
+    hipLaunchKernelGGL(ht_colnorm<R>, dim3(g0, 1, Z), dim3(RW), 0, st, pr, p);
+    MMF_LAUNCH_CHECK();
+    for (int k = 0; k < kb; ++k) {
+      const int64_t i = p + k;
+      const int64_t m = nmax - i - 1;
+      const unsigned gr = cdiv(nmax - i - 2 > 0 ? nmax - i - 2 : 1, RW);
+      hipLaunchKernelGGL(ht_reflector<R>, dim3(gr, 1, Z), dim3(RW), 0, st, pr, p, k);
+      MMF_LAUNCH_CHECK();
+      const int64_t nbt = (m + HV_T - 1) / HV_T;
+      const int64_t nch = (nbt + HV_CH - 1) / HV_CH;
+      const int ks = ktimer_begin(sizeof(R) == 8 ? "hemv" : "hemv_c64", st);
+      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbt, (unsigned)nch, Z), dim3(256), 0, st, pr, i, k);
+      MMF_LAUNCH_CHECK();
+      if (ks >= 0) {
+        // algorithmic bytes: the lower triangle of every trailing matrix, read once
+        double bytes = 0.0;
+        for (int64_t c = 0; c < count; ++c) {
+          const double mc = (double)(nh[c] - i - 1);
+          if (mc > 0) bytes += 2.0 * sizeof(R) * mc * (mc + 1.0) / 2.0;
+        }
+        ktimer_end(ks, st, bytes);
+      }
+      if (k > 0) {
+        hipLaunchKernelGGL(ht_dots<R>, dim3(cdiv(m, DOT_ROWS), 2 * k, Z), dim3(256), 0, st, pr, i, k);
+        MMF_LAUNCH_CHECK();
+      }
+      hipLaunchKernelGGL(ht_finish_u<R>, dim3((unsigned)nbt, 1, Z), dim3(256), 0, st, pr, i, k);
+      MMF_LAUNCH_CHECK();
+      hipLaunchKernelGGL(ht_finish_w<R>, dim3(cdiv(m, RW), 1, Z), dim3(RW), 0, st, pr, p, k);
+      MMF_LAUNCH_CHECK();
+    }
+    const int64_t q0 = p + kb;
+    if (q0 < nmax) {
+      const unsigned t = cdiv(nmax - q0, GT_M);
+      hipLaunchKernelGGL(ht_her2k<R>, dim3(t, t, Z), dim3(GEMM_THREADS), 0, st, pr, p);
+      MMF_LAUNCH_CHECK();
+    }
+  }
+  hipLaunchKernelGGL(ht_last_diag<R>, dim3(1, 1, Z), dim3(64), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+// bytes of the one-entry table placed in front of a single reduction's workspace
+constexpr size_t HT_TABLE_BYTES = 256;
+
 template <typename R>
 int hetrd_run_t(int64_t n, cx<R> *A, int64_t lda, double *d, double *e, cx<R> *tau, void *work,
                 size_t bytes, hipStream_t st) {
   if (n <= 0) return MMF_OK;
-  HtWs<R> w = hetrd_ws<R>(n, work);
-  if (bytes < w.bytes) return MMF_ERR_WORKSPACE;
-  for (int64_t p = 0; p < n - 1; p += HT_NB) {
-    const int kb = (int)((n - 1 - p < HT_NB) ? n - 1 - p : HT_NB);
-    hipLaunchKernelGGL(ht_zero_panel<R>, dim3(cdiv(n - p, 256)), dim3(256), 0, st, w.P3, n, p);
-    MMF_LAUNCH_CHECK();
-    const int g0 = (int)cdiv(n - p - 2 > 0 ? n - p - 2 : 1, RW);
-    hipLaunchKernelGGL(ht_colnorm<R>, dim3(g0), dim3(RW), 0, st, A, lda, n, p, w.norms);
-    MMF_LAUNCH_CHECK();
-    int gnorm = g0;
-    for (int k = 0; k < kb; ++k) {
-      const int64_t i = p + k;
-      const int64_t m = n - i - 1;
-      {
-        const int g = (int)cdiv(n - i - 2 > 0 ? n - i - 2 : 1, RW);
-        hipLaunchKernelGGL(ht_reflector<R>, dim3(g), dim3(RW), 0, st, A, lda, n, i, k, w.P3, w.norms,
-                           gnorm, d, e, tau);
-        MMF_LAUNCH_CHECK();
-      }
-      const int64_t nbt = (m + HV_T - 1) / HV_T;
-      const int64_t nch = (nbt + HV_CH - 1) / HV_CH;
-      const int ks = ktimer_begin(sizeof(R) == 8 ? "hemv" : "hemv_c64", st);
-      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbt, (unsigned)nch), dim3(256), 0, st, A, lda, n, i,
-                         w.P3, k, w.pdir, w.ptrn, w.mpad, w.nchmax);
-      MMF_LAUNCH_CHECK();
-      // algorithmic bytes: the lower triangle of the trailing matrix, read once
-      ktimer_end(ks, st, 2.0 * sizeof(R) * (double)m * (double)(m + 1) / 2.0);
-      const int gdot = (int)cdiv(m, DOT_ROWS);
-      if (k > 0) {
-        hipLaunchKernelGGL(ht_dots<R>, dim3(gdot, 2 * k), dim3(256), 0, st, w.P3, n, i, k, w.dots);
-        MMF_LAUNCH_CHECK();
-      }
-      hipLaunchKernelGGL(ht_finish_u<R>, dim3((unsigned)nbt), dim3(256), 0, st, n, i, k, w.P3, w.pdir,
-                         w.ptrn, w.mpad, w.nchmax, w.dots, gdot, tau, w.sparts, w.w0first);
-      MMF_LAUNCH_CHECK();
-      const int gu = (int)cdiv(m, RW);
-      const int next = (k + 1 < kb) ? 1 : 0;
-      hipLaunchKernelGGL(ht_finish_w<R>, dim3(gu), dim3(RW), 0, st, A, lda, n, i, k, next, w.P3,
-                         w.sparts, (int)nbt, tau, w.w0first, w.norms);
-      MMF_LAUNCH_CHECK();
-      gnorm = gu;
-    }
-    // trailing update A[q:, q:] -= [V W] [W V]^H  (lower triangle)
-    const int64_t q = p + kb;
-    if (q < n) {
-      GemmArgs g = gemm_args(n - q, n - q, 2 * HT_NB, w.P3 + q, n, w.P3 + q + (int64_t)HT_NB * n, n,
-                             A + q + q * lda, lda, -1.0, 0.0, 1.0, 0.0);
-      g.lower = 1;
-      const int rc = gemm_launch_t<R, true, A_N, B_C>(g, st);
-      if (rc) return rc;
-    }
-  }
-  hipLaunchKernelGGL(ht_last_diag<R>, dim3(1), dim3(64), 0, st, A, lda, n, d);
-  MMF_LAUNCH_CHECK();
-  return MMF_OK;
+  static_assert(sizeof(HtProb<R>) <= HT_TABLE_BYTES, "table entry");
+  HtWs<R> w = hetrd_ws<R>(n, (char *)work + HT_TABLE_BYTES);
+  if (bytes < w.bytes + HT_TABLE_BYTES) return MMF_ERR_WORKSPACE;
+  HtProb<R> *pr = reinterpret_cast<HtProb<R> *>(work);
+  const HtProb<R> q = ht_prob<R>(n, A, lda, d, e, tau, w);
+  int rc = table_write(pr, &q, 1, st);
+  if (rc) return rc;
+  return hetrd_grouped<R>(pr, &n, 1, st);
 }
 
 int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau, void *work,
@@ -460,7 +561,7 @@ int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau
                              bytes, st);
 }
 
-size_t hetrd_ws_bytes_c64(int64_t n) { return hetrd_ws_bytes_t<float>(n); }
+size_t hetrd_ws_bytes_c64(int64_t n) { return hetrd_ws_bytes_t<float>(n) + 256; }
 int hetrd_run_c64(int64_t n, void *A, int64_t lda, double *d, double *e, void *tau, void *work,
                   size_t bytes, hipStream_t st) {
   return hetrd_run_t<float>(n, reinterpret_cast<cf *>(A), lda, d, e, reinterpret_cast<cf *>(tau), work,

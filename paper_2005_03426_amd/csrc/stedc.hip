@@ -21,10 +21,16 @@
 //   GEMM); eigenvalues merged in ascending order (rank by counting).
 // All per-merge scratch lives at the merge's own index range [s, t) of n-long
 // arrays, so every merge of a tree level runs in the same launches.
+//
+// Grouped execution: the kernels read each problem's tree and buffers from a
+// device table (DcProb); the grid's z (or y) dimension enumerates
+// (problem, merge) pairs, so one launch serves a tree level of every matrix
+// of a batch.  A single tridiagonal problem is the one-entry case.
 #include <float.h>
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
+#include "table.h"
 
 namespace mmf {
 
@@ -68,7 +74,23 @@ inline DcWs stedc_ws(int64_t n, void *base) {
   return w;
 }
 
-size_t stedc_ws_bytes(int64_t n) { return stedc_ws(n, nullptr).bytes; }
+size_t stedc_ws_bytes(int64_t n) { return stedc_ws(n, nullptr).bytes + 512; }
+
+struct DcProb {
+  int64_t n, ldz, L;
+  int32_t h;
+  double *d;
+  const double *e;
+  double *Z;
+  int32_t *info;
+  DcWs w;
+};
+
+inline int dc_depth(int64_t n) {
+  int h = 0;
+  while (((n + ((int64_t)1 << h) - 1) >> h) > DC_LEAF) ++h;
+  return h;
+}
 
 __device__ __host__ inline int64_t dc_b(int64_t i, int64_t n, int64_t L) { return (i * n) / L; }
 
@@ -87,8 +109,13 @@ __device__ inline MergeGeom dc_geom(int64_t n, int64_t L, int lev, int64_t g) {
 }
 
 // ------------------------------------------------------------------ tearing
-__global__ void dc_tear(int64_t n, int64_t L, const double *d, const double *e, double *dw) {
+__global__ void dc_tear(const DcProb *pr) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const DcProb &q = pr[blockIdx.z];
+  const int64_t n = q.n, L = q.L;
+  const double *d = q.d, *e = q.e;
+  double *dw = q.w.dw;
+  if (n <= 0) return;
   for (int64_t i = 0; i < n; ++i) dw[i] = d[i];
   for (int64_t i = 1; i < L; ++i) {
     const int64_t k = dc_b(i, n, L);
@@ -101,11 +128,16 @@ __global__ void dc_tear(int64_t n, int64_t L, const double *d, const double *e, 
 // ------------------------------------------------------------------ leaves
 // One wavefront per leaf: implicit QL with Wilkinson shifts; every lane runs
 // the scalar recurrence (identical values) and rotates its own row of Z.
-__global__ void __launch_bounds__(64) dc_leaf(int64_t n, int64_t L, const double *dw, const double *e,
-                                              double *Z, int64_t ldz, double *lam, int32_t *info) {
+__global__ void __launch_bounds__(64) dc_leaf(const DcProb *pr) {
   __shared__ double dd[DC_LEAF], ee[DC_LEAF];
   __shared__ double Zl[DC_LEAF * DC_LEAF];
   __shared__ int perm[DC_LEAF];
+  const DcProb &q = pr[blockIdx.z];
+  const int64_t n = q.n, L = q.L, ldz = q.ldz;
+  if ((int64_t)blockIdx.x >= L || n <= 0) return;
+  const double *dw = q.w.dw, *e = q.e;
+  double *Z = q.Z, *lam = q.w.lam;
+  int32_t *info = q.info;
   const int64_t s = dc_b(blockIdx.x, n, L);
   const int m = (int)(dc_b(blockIdx.x + 1, n, L) - s);
   const int r = threadIdx.x;
@@ -194,8 +226,13 @@ __global__ void __launch_bounds__(64) dc_leaf(int64_t n, int64_t L, const double
 }
 
 // ------------------------------------------------------------------ merge: prepare
-__global__ void dc_prep(int64_t n, int64_t L, int lev, const double *e, const double *lam,
-                        const double *Z, int64_t ldz, double *ds, double *zs, int32_t *src, double *rho) {
+__global__ void dc_prep(const DcProb *pr, int lev) {
+  const DcProb &P = pr[blockIdx.z];
+  if (lev > P.h || (int64_t)blockIdx.y >= (P.L >> lev)) return;
+  const int64_t n = P.n, L = P.L, ldz = P.ldz;
+  const double *e = P.e, *lam = P.w.lam, *Z = P.Z;
+  double *ds = P.w.ds, *zs = P.w.zs, *rho = P.w.rho;
+  int32_t *src = P.w.src;
   const MergeGeom q = dc_geom(n, L, lev, blockIdx.y);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= q.m) return;
@@ -228,22 +265,33 @@ __global__ void dc_prep(int64_t n, int64_t L, int lev, const double *e, const do
 }
 
 // Off-diagonal blocks of the merged block start as exact zeros.
-__global__ void dc_zero_off(int64_t n, int64_t L, int lev, double *Z, int64_t ldz) {
-  const MergeGeom q = dc_geom(n, L, lev, blockIdx.z);
+// grid: x = row block, y = chunk of 64 columns, z = merge + Gmax * problem
+__global__ void dc_zero_off(const DcProb *pr, int lev, int64_t Gmax) {
+  const DcProb &P = pr[blockIdx.z / Gmax];
+  const int64_t g = blockIdx.z % Gmax;
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  if (r >= q.m || c >= q.m) return;
-  const bool rl = r < q.n1, cl = c < q.n1;
-  if (rl != cl) Z[(q.s + r) + (q.s + c) * ldz] = 0.0;
+  if (r >= q.m) return;
+  const bool rl = r < q.n1;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const int64_t c1 = (c0 + 64 < q.m) ? c0 + 64 : q.m;
+  for (int64_t c = c0; c < c1; ++c) {
+    const bool cl = c < q.n1;
+    if (rl != cl) P.Z[(q.s + r) + (q.s + c) * P.ldz] = 0.0;
+  }
 }
 
 // ------------------------------------------------------------------ merge: deflation scan
-__global__ void dc_deflate(int64_t n, int64_t L, int lev, double *ds, double *zs, const double *rho,
-                           int32_t *ndidx, int32_t *dfidx, int32_t *rp, int32_t *rj, double *rc,
-                           double *rs, int32_t *cnt) {
+__global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
   if (threadIdx.x != 0) return;
-  const int64_t g = blockIdx.x;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  const DcProb &P = pr[blockIdx.x / Gmax];
+  const int64_t g = blockIdx.x % Gmax;
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  double *ds = P.w.ds, *zs = P.w.zs, *rc = P.w.rc, *rs = P.w.rs;
+  const double *rho = P.w.rho;
+  int32_t *ndidx = P.w.ndidx, *dfidx = P.w.dfidx, *rp = P.w.rp, *rj = P.w.rj, *cnt = P.w.cnt;
+  const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t s = q.s, m = q.m;
   const double rh = rho[s];
   double dmax = fmax(fabs(ds[s]), fabs(ds[s + m - 1]));
@@ -286,13 +334,17 @@ __global__ void dc_deflate(int64_t n, int64_t L, int lev, double *ds, double *zs
 // Thread = row of the merged block: applies the deflation rotations in order
 // to its row of Z, then gathers the non-deflated columns (in d order) into
 // T1[:, 0:K] and the deflated ones into T1[:, K:m].
-__global__ void dc_gather(int64_t n, int64_t L, int lev, double *Z, int64_t ldz, const int32_t *src,
-                          const int32_t *ndidx, const int32_t *dfidx, const int32_t *rp,
-                          const int32_t *rj, const double *rc, const double *rs, const int32_t *cnt,
-                          const double *ds, const double *zs, double *dn, double *zn, double *ddef,
-                          double *T1) {
+__global__ void dc_gather(const DcProb *pr, int lev) {
+  const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const int64_t n = P.n, ldz = P.ldz;
+  double *Z = P.Z;
+  const int32_t *src = P.w.src, *ndidx = P.w.ndidx, *dfidx = P.w.dfidx, *rp = P.w.rp, *rj = P.w.rj;
+  const int32_t *cnt = P.w.cnt;
+  const double *rc = P.w.rc, *rs = P.w.rs, *ds = P.w.ds, *zs = P.w.zs;
+  double *dn = P.w.dn, *zn = P.w.zn, *ddef = P.w.ddef, *T1 = P.w.T1;
+  const MergeGeom q = dc_geom(n, P.L, lev, g);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= q.m) return;
   const int64_t s = q.s;
@@ -317,12 +369,15 @@ __global__ void dc_gather(int64_t n, int64_t L, int lev, double *Z, int64_t ldz,
 
 // ------------------------------------------------------------------ merge: secular equation
 // One wavefront per root k of f(x) = 1 + rho sum_i z_i^2/(d_i - x).
-__global__ void __launch_bounds__(256) dc_secular(int64_t n, int64_t L, int lev, const double *dn,
-                                                  const double *zn, const double *rho,
-                                                  const int32_t *cnt, int32_t *lamo, double *lamt,
-                                                  int32_t *info) {
+__global__ void __launch_bounds__(256) dc_secular(const DcProb *pr, int lev) {
+  const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const double *dn = P.w.dn, *zn = P.w.zn, *rho = P.w.rho;
+  const int32_t *cnt = P.w.cnt;
+  int32_t *lamo = P.w.lamo, *info = P.info;
+  double *lamt = P.w.lamt;
+  const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int K = cnt[3 * g];
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -416,12 +471,14 @@ __global__ void __launch_bounds__(256) dc_secular(int64_t n, int64_t L, int lev,
 
 // zhat_i^2 = (x_{K-1} - d_i)/rho * prod_{j<i} (x_j - d_i)/(d_j - d_i)
 //                                 * prod_{i<=j<K-1} (x_j - d_i)/(d_{j+1} - d_i)
-__global__ void __launch_bounds__(256) dc_lowner(int64_t n, int64_t L, int lev, const double *dn,
-                                                 const double *zn, const double *rho,
-                                                 const int32_t *cnt, const int32_t *lamo,
-                                                 const double *lamt, double *zhat) {
+__global__ void __launch_bounds__(256) dc_lowner(const DcProb *pr, int lev) {
+  const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const double *dn = P.w.dn, *zn = P.w.zn, *rho = P.w.rho, *lamt = P.w.lamt;
+  const int32_t *cnt = P.w.cnt, *lamo = P.w.lamo;
+  double *zhat = P.w.zhat;
+  const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int K = cnt[3 * g];
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -429,28 +486,32 @@ __global__ void __launch_bounds__(256) dc_lowner(int64_t n, int64_t L, int lev, 
   const int64_t s = q.s;
   const double *d = dn + s;
   const double di = d[i];
-  double pr = 1.0;
+  double prod = 1.0;
   for (int j = lane; j < K - 1; j += 64) {
     const double num = (d[lamo[s + j]] - di) + lamt[s + j];
     const double den = (j < i) ? (d[j] - di) : (d[j + 1] - di);
-    pr *= num / den;
+    prod *= num / den;
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) pr *= __shfl_xor(pr, o, 64);
+  for (int o = 32; o > 0; o >>= 1) prod *= __shfl_xor(prod, o, 64);
   if (lane == 0) {
     const double last = ((d[lamo[s + K - 1]] - di) + lamt[s + K - 1]) / rho[s];
-    const double v = sqrt(fmax(pr * last, 0.0));
+    const double v = sqrt(fmax(prod * last, 0.0));
     zhat[s + i] = copysign(v, zn[s + i]);
   }
 }
 
 // Column j of the rank-one eigenvector matrix U (T2 block, ld n).
-__global__ void __launch_bounds__(256) dc_vectors(int64_t n, int64_t L, int lev, const double *dn,
-                                                  const int32_t *cnt, const int32_t *lamo,
-                                                  const double *lamt, const double *zhat, double *T2) {
+__global__ void __launch_bounds__(256) dc_vectors(const DcProb *pr, int lev) {
   __shared__ double sh[4];
+  const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const int64_t n = P.n;
+  const double *dn = P.w.dn, *lamt = P.w.lamt, *zhat = P.w.zhat;
+  const int32_t *cnt = P.w.cnt, *lamo = P.w.lamo;
+  double *T2 = P.w.T2;
+  const MergeGeom q = dc_geom(n, P.L, lev, g);
   const int K = cnt[3 * g];
   const int j = blockIdx.x;
   if (j >= K) return;
@@ -474,11 +535,15 @@ __global__ void __launch_bounds__(256) dc_vectors(int64_t n, int64_t L, int lev,
 // Final ascending position of every eigenvalue of the merge (roots first in
 // the tie order, then deflated values by index), eigenvalue output and the
 // destination column of every T1 column.
-__global__ void dc_final_pos(int64_t n, int64_t L, int lev, const double *dn, const int32_t *cnt,
-                             const int32_t *lamo, const double *lamt, const double *ddef,
-                             double *lam, int32_t *colmap) {
+__global__ void dc_final_pos(const DcProb *pr, int lev) {
+  const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const double *dn = P.w.dn, *lamt = P.w.lamt, *ddef = P.w.ddef;
+  const int32_t *cnt = P.w.cnt, *lamo = P.w.lamo;
+  double *lam = P.w.lam;
+  int32_t *colmap = P.w.colmap;
+  const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= q.m) return;
   const int64_t s = q.s;
@@ -496,12 +561,16 @@ __global__ void dc_final_pos(int64_t n, int64_t L, int lev, const double *dn, co
   colmap[s + e] = (int32_t)(s + pos);
 }
 
-__global__ void __launch_bounds__(GEMM_THREADS) dc_gemm(int64_t n, int64_t L, int lev, const int32_t *cnt,
-                                                        const double *T1, const double *T2,
-                                                        double *Z, int64_t ldz, const int32_t *colmap) {
+__global__ void __launch_bounds__(GEMM_THREADS) dc_gemm(const DcProb *pr, int lev, int64_t Gmax) {
   __shared__ double lds[GEMM_LDS_DOUBLES];
-  const int64_t g = blockIdx.z;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  const DcProb &P = pr[blockIdx.z / Gmax];
+  const int64_t g = blockIdx.z % Gmax;
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const int64_t n = P.n, ldz = P.ldz;
+  const int32_t *cnt = P.w.cnt, *colmap = P.w.colmap;
+  const double *T1 = P.w.T1, *T2 = P.w.T2;
+  double *Z = P.Z;
+  const MergeGeom q = dc_geom(n, P.L, lev, g);
   const int K = cnt[3 * g];
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
   if (m0 >= q.m || n0 >= K) return;
@@ -511,10 +580,15 @@ __global__ void __launch_bounds__(GEMM_THREADS) dc_gemm(int64_t n, int64_t L, in
   gemm_tile<false, A_N, B_N>(a, m0, n0, lds);
 }
 
-__global__ void dc_copy_def(int64_t n, int64_t L, int lev, const int32_t *cnt, const double *T1,
-                            double *Z, int64_t ldz, const int32_t *colmap) {
+__global__ void dc_copy_def(const DcProb *pr, int lev) {
+  const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
-  const MergeGeom q = dc_geom(n, L, lev, g);
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const int64_t n = P.n, ldz = P.ldz;
+  const int32_t *cnt = P.w.cnt, *colmap = P.w.colmap;
+  const double *T1 = P.w.T1;
+  double *Z = P.Z;
+  const MergeGeom q = dc_geom(n, P.L, lev, g);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= q.m) return;
   const int K = cnt[3 * g];
@@ -522,73 +596,125 @@ __global__ void dc_copy_def(int64_t n, int64_t L, int lev, const int32_t *cnt, c
     Z[(q.s + r) + (int64_t)colmap[q.s + k] * ldz] = T1[(q.s + r) + (q.s + k) * n];
 }
 
-__global__ void dc_copy_out(int64_t n, const double *lam, double *d) {
+__global__ void dc_copy_out(const DcProb *pr) {
+  const DcProb &P = pr[blockIdx.z];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = lam[i];
+  if (i < P.n) P.d[i] = P.w.lam[i];
 }
 
-__global__ void dc_info_init(int32_t *info) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *info = 0;
+__global__ void dc_info_init(const DcProb *pr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *pr[blockIdx.z].info = 0;
 }
 
 // ------------------------------------------------------------------ host
+// Grouped divide and conquer over the table pr of `count` problems with
+// orders nh[] (host copy).
+int stedc_grouped(const DcProb *pr, const int64_t *nh, int64_t count, hipStream_t st) {
+  if (count <= 0) return MMF_OK;
+  int64_t nmax = 0;
+  int hmax = 0;
+  for (int64_t c = 0; c < count; ++c) {
+    nmax = nh[c] > nmax ? nh[c] : nmax;
+    const int h = dc_depth(nh[c]);
+    hmax = h > hmax ? h : hmax;
+  }
+  if (nmax <= 0) return MMF_OK;
+  {
+    // grid z holds (merge, problem) pairs: split the batch so it stays within 65535
+    int64_t Lall = 1;
+    for (int64_t c = 0; c < count; ++c) {
+      const int64_t L = (int64_t)1 << dc_depth(nh[c]);
+      Lall = L > Lall ? L : Lall;
+    }
+    const int64_t Gmax1 = Lall / 2 > 1 ? Lall / 2 : 1;
+    const int64_t limit = 65535 / Gmax1;
+    if (count > limit) {
+      for (int64_t b = 0; b < count; b += limit) {
+        const int rc = stedc_grouped(pr + b, nh + b, count - b < limit ? count - b : limit, st);
+        if (rc) return rc;
+      }
+      return MMF_OK;
+    }
+  }
+  const unsigned Z = (unsigned)count;
+  hipLaunchKernelGGL(dc_info_init, dim3(1, 1, Z), dim3(64), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(dc_tear, dim3(1, 1, Z), dim3(64), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  int64_t Lall = 0;
+  for (int64_t c = 0; c < count; ++c) {
+    const int64_t L = (int64_t)1 << dc_depth(nh[c]);
+    Lall = L > Lall ? L : Lall;
+  }
+  hipLaunchKernelGGL(dc_leaf, dim3((unsigned)Lall, 1, Z), dim3(64), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  for (int lev = 1; lev <= hmax; ++lev) {
+    int64_t Gmax = 0, maxm = 0;
+    for (int64_t c = 0; c < count; ++c) {
+      const int h = dc_depth(nh[c]);
+      if (lev > h) continue;
+      const int64_t L = (int64_t)1 << h;
+      const int64_t G = L >> lev;
+      const int64_t span = (int64_t)1 << lev;
+      Gmax = G > Gmax ? G : Gmax;
+      for (int64_t g = 0; g < G; ++g) {
+        const int64_t m = dc_b((g + 1) * span, nh[c], L) - dc_b(g * span, nh[c], L);
+        maxm = m > maxm ? m : maxm;
+      }
+    }
+    if (Gmax == 0) continue;
+    const dim3 rows(cdiv(maxm, 256), (unsigned)Gmax, Z);
+    hipLaunchKernelGGL(dc_prep, rows, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_zero_off, dim3(cdiv(maxm, 256), cdiv(maxm, 64), (unsigned)(Gmax * count)), dim3(256),
+                       0, st, pr, lev, Gmax);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_deflate, dim3((unsigned)(Gmax * count)), dim3(64), 0, st, pr, lev, Gmax);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_gather, rows, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    const dim3 roots(cdiv(maxm, 4), (unsigned)Gmax, Z);
+    hipLaunchKernelGGL(dc_secular, roots, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_lowner, roots, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_vectors, dim3((unsigned)maxm, (unsigned)Gmax, Z), dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_final_pos, rows, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_gemm, dim3(cdiv(maxm, GT_M), cdiv(maxm, GT_N), (unsigned)(Gmax * count)),
+                       dim3(GEMM_THREADS), 0, st, pr, lev, Gmax);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(dc_copy_def, rows, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(dc_copy_out, dim3(cdiv(nmax, 256), 1, Z), dim3(256), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+inline DcProb dc_prob(int64_t n, double *d, const double *e, double *Z, int64_t ldz, int32_t *info,
+                      const DcWs &w) {
+  DcProb q;
+  q.n = n; q.ldz = ldz;
+  q.h = dc_depth(n);
+  q.L = (int64_t)1 << q.h;
+  q.d = d; q.e = e; q.Z = Z; q.info = info;
+  q.w = w;
+  return q;
+}
+
 int stedc_run(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *work, size_t bytes,
               int32_t *info, hipStream_t st) {
   if (n <= 0) return MMF_OK;
-  DcWs w = stedc_ws(n, work);
-  if (bytes < w.bytes) return MMF_ERR_WORKSPACE;
-  int h = 0;
-  while (((n + ((int64_t)1 << h) - 1) >> h) > DC_LEAF) ++h;
-  const int64_t L = (int64_t)1 << h;
-  hipLaunchKernelGGL(dc_info_init, dim3(1), dim3(64), 0, st, info);
-  MMF_LAUNCH_CHECK();
-  hipLaunchKernelGGL(dc_tear, dim3(1), dim3(64), 0, st, n, L, d, e, w.dw);
-  MMF_LAUNCH_CHECK();
-  hipLaunchKernelGGL(dc_leaf, dim3((unsigned)L), dim3(64), 0, st, n, L, w.dw, e, Z, ldz, w.lam, info);
-  MMF_LAUNCH_CHECK();
-  for (int lev = 1; lev <= h; ++lev) {
-    const int64_t G = L >> lev;
-    const int64_t span = (int64_t)1 << lev;
-    int64_t maxm = 0;
-    for (int64_t g = 0; g < G; ++g) {
-      const int64_t m = dc_b((g + 1) * span, n, L) - dc_b(g * span, n, L);
-      if (m > maxm) maxm = m;
-    }
-    const dim3 rows(cdiv(maxm, 256), (unsigned)G);
-    hipLaunchKernelGGL(dc_prep, rows, dim3(256), 0, st, n, L, lev, e, w.lam, Z, ldz, w.ds, w.zs, w.src,
-                       w.rho);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_zero_off, dim3(cdiv(maxm, 256), (unsigned)maxm, (unsigned)G), dim3(256), 0, st,
-                       n, L, lev, Z, ldz);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_deflate, dim3((unsigned)G), dim3(64), 0, st, n, L, lev, w.ds, w.zs, w.rho,
-                       w.ndidx, w.dfidx, w.rp, w.rj, w.rc, w.rs, w.cnt);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_gather, rows, dim3(256), 0, st, n, L, lev, Z, ldz, w.src, w.ndidx, w.dfidx,
-                       w.rp, w.rj, w.rc, w.rs, w.cnt, w.ds, w.zs, w.dn, w.zn, w.ddef, w.T1);
-    MMF_LAUNCH_CHECK();
-    const dim3 roots(cdiv(maxm, 4), (unsigned)G);
-    hipLaunchKernelGGL(dc_secular, roots, dim3(256), 0, st, n, L, lev, w.dn, w.zn, w.rho, w.cnt,
-                       w.lamo, w.lamt, info);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_lowner, roots, dim3(256), 0, st, n, L, lev, w.dn, w.zn, w.rho, w.cnt, w.lamo,
-                       w.lamt, w.zhat);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_vectors, dim3((unsigned)maxm, (unsigned)G), dim3(256), 0, st, n, L, lev, w.dn,
-                       w.cnt, w.lamo, w.lamt, w.zhat, w.T2);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_final_pos, rows, dim3(256), 0, st, n, L, lev, w.dn, w.cnt, w.lamo, w.lamt,
-                       w.ddef, w.lam, w.colmap);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_gemm, dim3(cdiv(maxm, GT_M), cdiv(maxm, GT_N), (unsigned)G),
-                       dim3(GEMM_THREADS), 0, st, n, L, lev, w.cnt, w.T1, w.T2, Z, ldz, w.colmap);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_copy_def, rows, dim3(256), 0, st, n, L, lev, w.cnt, w.T1, Z, ldz, w.colmap);
-    MMF_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL(dc_copy_out, dim3(cdiv(n, 256)), dim3(256), 0, st, n, w.lam, d);
-  MMF_LAUNCH_CHECK();
-  return MMF_OK;
+  static_assert(sizeof(DcProb) <= 512, "table entry");
+  DcWs w = stedc_ws(n, (char *)work + 512);
+  if (bytes < w.bytes + 512) return MMF_ERR_WORKSPACE;
+  DcProb *pr = reinterpret_cast<DcProb *>(work);
+  const DcProb q = dc_prob(n, d, e, Z, ldz, info, w);
+  const int rc = table_write(pr, &q, 1, st);
+  if (rc) return rc;
+  return stedc_grouped(pr, &n, 1, st);
 }
 
 }  // namespace mmf

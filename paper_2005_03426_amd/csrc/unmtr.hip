@@ -13,9 +13,12 @@
 // the rank-BT_NB update is a plain MFMA GEMM.  8 n^3 real flops in total.
 // Templated over the scalar type (complex128, or complex64 with FP32
 // accumulation for the precision layer; Z is read in FP64 and rounded).
+// Grouped: every kernel reads its problem from a device table (BtProb) at
+// grid index z, so one launch applies block b of every matrix of a batch.
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
+#include "table.h"
 
 namespace mmf {
 
@@ -32,11 +35,9 @@ struct BtWs {
   size_t bytes;
 };
 
-inline int64_t bt_off(int64_t n, int64_t b) {
-  // sum over blocks b' < b of (n - p_b' - 1) * NB
-  int64_t off = 0;
-  for (int64_t q = 0; q < b; ++q) off += (n - q * BT_NB - 1) * BT_NB;
-  return off;
+__host__ __device__ inline int64_t bt_off(int64_t n, int64_t b) {
+  // sum over blocks b' < b of (n - b' NB - 1) NB
+  return BT_NB * (b * (n - 1) - (int64_t)BT_NB * (b * (b - 1) / 2));
 }
 
 template <typename R>
@@ -55,70 +56,90 @@ inline BtWs<R> unmtr_ws(int64_t n, void *base) {
   return w;
 }
 
-size_t unmtr_ws_bytes(int64_t n) { return unmtr_ws<double>(n, nullptr).bytes; }
-size_t unmtr_ws_bytes_c64(int64_t n) { return unmtr_ws<float>(n, nullptr).bytes; }
+constexpr size_t BT_TABLE_BYTES = 256;
+size_t unmtr_ws_bytes(int64_t n) { return unmtr_ws<double>(n, nullptr).bytes + BT_TABLE_BYTES; }
+size_t unmtr_ws_bytes_c64(int64_t n) { return unmtr_ws<float>(n, nullptr).bytes + BT_TABLE_BYTES; }
 
-// Clean copy of block b: Vb[r', q] (r' = 0..mb-1 is row p+1+r'), reflector p+q.
+// One problem of a grouped back-transformation.
 template <typename R>
-__global__ void bt_pack(int64_t n, const cx<R> *V, int64_t ldv, cx<R> *Vb, int64_t p, int kb) {
+struct BtProb {
+  int64_t n, ldv, ldz, ldphi, nblk, nsplit;
+  const cx<R> *V, *tau;
+  const double *Z;
+  cx<R> *Phi;
+  cx<R> *Vp, *Tm, *Wpart, *W2, *Gpart;
+};
+
+// Clean copy of block b = blockIdx.y: Vb[r', q] (r' = 0..mb-1 is row p+1+r'),
+// reflector p+q; one thread per row writes all BT_NB columns.
+template <typename R>
+__global__ void bt_pack(const BtProb<R> *pr) {
+  const BtProb<R> &P = pr[blockIdx.z];
+  const int64_t b = blockIdx.y;
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, p = b * BT_NB;
+  const int kb = (int)((n - 1 - p < BT_NB) ? n - 1 - p : BT_NB);
   const int64_t mb = n - p - 1;
   const int64_t rr = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
   if (rr >= mb) return;
-  const int64_t row = p + 1 + rr, i = p + q;
-  cx<R> v = cmk<R>(0, 0);
-  if (q < kb) {
-    if (row == i + 1) v = cmk<R>(1, 0);
-    else if (row > i + 1) v = V[row + i * ldv];
+  const int64_t row = p + 1 + rr;
+  cx<R> *Vb = P.Vp + bt_off(n, b);
+  for (int q = 0; q < BT_NB; ++q) {
+    const int64_t i = p + q;
+    cx<R> v = cmk<R>(0, 0);
+    if (q < kb) {
+      if (row == i + 1) v = cmk<R>(1, 0);
+      else if (row > i + 1) v = P.V[row + i * P.ldv];
+    }
+    Vb[rr + (int64_t)q * mb] = v;
   }
-  Vb[rr + (int64_t)q * mb] = v;
 }
 
-// Split-K slices of C = op(A) op(B) with A_C / B_N: slice z covers
-// k in [z*kc, min((z+1)*kc, K)); result to part + z*pstride (ld = M).
+// Split-K slices of W1 = Vb^H Phi[p+1:, :] for block b: slice z = blockIdx.x
+// covers rows [z*BT_KCHUNK, ...) of the block; result to Wpart + z*NB*n.
 template <typename R>
-__global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(GemmArgs g, int64_t kc, cx<R> *part,
-                                                          int64_t pstride) {
+__global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, int64_t b) {
   __shared__ R lds[GEMM_LDS_ELEMS];
-  const int64_t z = blockIdx.z;
-  const int64_t k0 = z * kc;
-  if (k0 >= g.K) return;
-  GemmArgs s = g;
-  s.K = (g.K - k0 < kc) ? g.K - k0 : kc;
-  s.A = reinterpret_cast<const cx<R> *>(g.A) + k0;   // A_C: op(A)[m,k] = conj(A[k + m lda])
-  s.B = reinterpret_cast<const cx<R> *>(g.B) + k0;   // B_N: op(B)[k,n] = B[k + n ldb]
-  s.C = part + z * pstride;
-  s.ldc = g.M;
-  s.alpha_re = 1.0; s.alpha_im = 0.0; s.beta_re = 0.0; s.beta_im = 0.0;
-  gemm_tile_t<R, true, A_C, B_N>(s, (int64_t)blockIdx.x * GT_M, (int64_t)blockIdx.y * GT_N, lds);
+  const BtProb<R> &P = pr[blockIdx.z];
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
+  const int64_t z = blockIdx.x;
+  const int64_t k0 = z * BT_KCHUNK;
+  const int64_t n0 = (int64_t)blockIdx.y * GT_N;
+  if (k0 >= mb || n0 >= n) return;
+  const cx<R> *Vb = P.Vp + bt_off(n, b);
+  // A_C: op(A)[m,k] = conj(A[k + m lda]);  B_N: op(B)[k,n] = B[k + n ldb]
+  GemmArgs s = gemm_args(BT_NB, n, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb,
+                         P.Phi + (p + 1) + k0, P.ldphi, P.Wpart + z * BT_NB * n, BT_NB, 1.0, 0.0, 0.0, 0.0);
+  gemm_tile_t<R, true, A_C, B_N>(s, 0, n0, lds);
 }
 
 // Gram partials of every block at once: Gpart[b][z] = Vb^H Vb over slice z.
 template <typename R>
-__global__ void __launch_bounds__(GEMM_THREADS) bt_gram(int64_t n, const cx<R> *Vp, int64_t nsplit,
-                                                        cx<R> *Gpart) {
+__global__ void __launch_bounds__(GEMM_THREADS) bt_gram(const BtProb<R> *pr) {
   __shared__ R lds[GEMM_LDS_ELEMS];
+  const BtProb<R> &P = pr[blockIdx.z];
   const int64_t b = blockIdx.x;
   const int64_t z = blockIdx.y;
-  const int64_t p = b * BT_NB;
-  const int64_t mb = n - p - 1;
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
   const int64_t k0 = z * BT_KCHUNK;
   if (k0 >= mb) return;
-  int64_t off = 0;
-  for (int64_t q = 0; q < b; ++q) off += (n - q * BT_NB - 1) * BT_NB;
-  const cx<R> *Vb = Vp + off;
+  const cx<R> *Vb = P.Vp + bt_off(n, b);
   GemmArgs s = gemm_args(BT_NB, BT_NB, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb, Vb + k0,
-                         mb, Gpart + (b * nsplit + z) * BT_NB * BT_NB, BT_NB, 1.0, 0.0, 0.0, 0.0);
+                         mb, P.Gpart + (b * P.nsplit + z) * BT_NB * BT_NB, BT_NB, 1.0, 0.0, 0.0, 0.0);
   gemm_tile_t<R, true, A_C, B_N>(s, 0, 0, lds);
 }
 
 // T of block b from its Gram matrix (one wavefront; thread = row of T).
 template <typename R>
-__global__ void __launch_bounds__(64) bt_tmat(int64_t n, const cx<R> *tau, const cx<R> *Gpart,
-                                              int64_t nsplit, cx<R> *Tm) {
+__global__ void __launch_bounds__(64) bt_tmat(const BtProb<R> *pr) {
   __shared__ cx<R> G[BT_NB][BT_NB];
   __shared__ cx<R> T[BT_NB][BT_NB];
+  const BtProb<R> &P = pr[blockIdx.z];
   const int64_t b = blockIdx.x;
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, nsplit = P.nsplit;
   const int64_t p = b * BT_NB;
   const int64_t mb = n - p - 1;
   const int kb = (int)((n - 1 - p < BT_NB) ? n - 1 - p : BT_NB);
@@ -126,13 +147,13 @@ __global__ void __launch_bounds__(64) bt_tmat(int64_t n, const cx<R> *tau, const
   const int64_t ns = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
   for (int c = 0; c < BT_NB; ++c) {
     cx<R> s = cmk<R>(0, 0);
-    for (int64_t z = 0; z < ns; ++z) s = cadd(s, Gpart[(b * nsplit + z) * BT_NB * BT_NB + r + c * BT_NB]);
+    for (int64_t z = 0; z < ns; ++z) s = cadd(s, P.Gpart[(b * nsplit + z) * BT_NB * BT_NB + r + c * BT_NB]);
     G[r][c] = s;
     T[r][c] = cmk<R>(0, 0);
   }
   __syncthreads();
   for (int k = 0; k < kb; ++k) {
-    const cx<R> tk = tau[p + k];
+    const cx<R> tk = P.tau[p + k];
     // T[r,k] = -tau_k sum_{j<k} T[r,j] G[j,k]   (r < k)
     cx<R> s = cmk<R>(0, 0);
     if (r < k)
@@ -142,78 +163,122 @@ __global__ void __launch_bounds__(64) bt_tmat(int64_t n, const cx<R> *tau, const
     if (r == k) T[r][k] = tk;
     __syncthreads();
   }
-  for (int c = 0; c < BT_NB; ++c) Tm[b * BT_NB * BT_NB + r + c * BT_NB] = T[r][c];
+  for (int c = 0; c < BT_NB; ++c) P.Tm[b * BT_NB * BT_NB + r + c * BT_NB] = T[r][c];
 }
 
-// W2[:, c] = T (sum_z Wpart[z][:, c]) for every column c (one wavefront per column).
+// W2[:, c] = T_b (sum_z Wpart[z][:, c]) for every column c (one wavefront per column).
 template <typename R>
-__global__ void __launch_bounds__(64) bt_reduce_t(int64_t n, const cx<R> *Wpart, int64_t nsl,
-                                                  const cx<R> *Tb, cx<R> *W2) {
+__global__ void __launch_bounds__(64) bt_reduce_t(const BtProb<R> *pr, int64_t b) {
   __shared__ cx<R> w1[BT_NB];
+  const BtProb<R> &P = pr[blockIdx.z];
   const int64_t c = blockIdx.x;
+  if (b >= P.nblk || c >= P.n) return;
+  const int64_t n = P.n, mb = n - b * BT_NB - 1;
+  const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
+  const cx<R> *Tb = P.Tm + b * BT_NB * BT_NB;
   const int r = threadIdx.x;
   cx<R> s = cmk<R>(0, 0);
-  for (int64_t z = 0; z < nsl; ++z) s = cadd(s, Wpart[z * BT_NB * n + r + c * BT_NB]);
+  for (int64_t z = 0; z < nsl; ++z) s = cadd(s, P.Wpart[z * BT_NB * n + r + c * BT_NB]);
   w1[r] = s;
   __syncthreads();
   cx<R> o = cmk<R>(0, 0);
   for (int j = r; j < BT_NB; ++j) o = cadd(o, cmul(Tb[r + j * BT_NB], w1[j]));
-  W2[r + c * BT_NB] = o;
+  P.W2[r + c * BT_NB] = o;
+}
+
+// Rank-BT_NB update Phi[p+1:, :] -= Vb W2 of block b.
+template <typename R>
+__global__ void __launch_bounds__(GEMM_THREADS) bt_update(const BtProb<R> *pr, int64_t b) {
+  __shared__ R lds[GEMM_LDS_ELEMS];
+  const BtProb<R> &P = pr[blockIdx.z];
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  if (m0 >= mb || n0 >= n) return;
+  GemmArgs u = gemm_args(mb, n, BT_NB, P.Vp + bt_off(n, b), mb, P.W2, BT_NB, P.Phi + (p + 1), P.ldphi, -1.0,
+                         0.0, 1.0, 0.0);
+  gemm_tile_t<R, true, A_N, B_N>(u, m0, n0, lds);
+}
+
+// Phi = Z (complex); grid y walks 64-column chunks.
+template <typename R>
+__global__ void bt_init_phi(const BtProb<R> *pr) {
+  const BtProb<R> &P = pr[blockIdx.z];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = P.n;
+  if (r >= n) return;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const int64_t c1 = c0 + 64 < n ? c0 + 64 : n;
+  for (int64_t c = c0; c < c1; ++c) P.Phi[r + c * P.ldphi] = cmk<R>((R)P.Z[r + c * P.ldz], R(0));
+}
+
+// Grouped back-transformation of `count` problems (orders nh[], host copy).
+template <typename R>
+int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStream_t st) {
+  if (count <= 0) return MMF_OK;
+  if (count > 65535) {
+    for (int64_t b = 0; b < count; b += 65535) {
+      const int rc = unmtr_grouped<R>(pr + b, nh + b, count - b < 65535 ? count - b : 65535, st);
+      if (rc) return rc;
+    }
+    return MMF_OK;
+  }
+  int64_t nmax = 0;
+  for (int64_t c = 0; c < count; ++c) nmax = nh[c] > nmax ? nh[c] : nmax;
+  if (nmax <= 0) return MMF_OK;
+  const unsigned Z = (unsigned)count;
+  const int64_t nblk = nmax > 1 ? (nmax - 1 + BT_NB - 1) / BT_NB : 0;
+  const int64_t nsplit = (nmax + BT_KCHUNK - 1) / BT_KCHUNK;
+  // 1. clean copies of every reflector block (Phi may alias V)
+  if (nblk > 0) {
+    hipLaunchKernelGGL(bt_pack<R>, dim3(cdiv(nmax - 1, 256), (unsigned)nblk, Z), dim3(256), 0, st, pr);
+    MMF_LAUNCH_CHECK();
+    // 2. T factors
+    hipLaunchKernelGGL(bt_gram<R>, dim3((unsigned)nblk, (unsigned)nsplit, Z), dim3(GEMM_THREADS), 0, st, pr);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bt_tmat<R>, dim3((unsigned)nblk, 1, Z), dim3(64), 0, st, pr);
+    MMF_LAUNCH_CHECK();
+  }
+  // 3. Phi = Z (complex)
+  hipLaunchKernelGGL(bt_init_phi<R>, dim3(cdiv(nmax, 256), cdiv(nmax, 64), Z), dim3(256), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  // 4. apply blocks last to first (a problem with fewer blocks idles until its last one)
+  for (int64_t b = nblk - 1; b >= 0; --b) {
+    const int64_t mb = nmax - b * BT_NB - 1;
+    const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
+    hipLaunchKernelGGL(bt_splitk<R>, dim3((unsigned)nsl, cdiv(nmax, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr, b);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)nmax, 1, Z), dim3(64), 0, st, pr, b);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bt_update<R>, dim3(cdiv(mb, GT_M), cdiv(nmax, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr,
+                       b);
+    MMF_LAUNCH_CHECK();
+  }
+  return MMF_OK;
 }
 
 template <typename R>
-__global__ void bt_init_phi(int64_t n, const double *Z, int64_t ldz, cx<R> *Phi, int64_t ldphi) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  if (r >= n) return;
-  Phi[r + c * ldphi] = cmk<R>((R)Z[r + c * ldz], R(0));
+inline BtProb<R> bt_prob(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *tau, const double *Z,
+                         int64_t ldz, cx<R> *Phi, int64_t ldphi, void *ws) {
+  const BtWs<R> w = unmtr_ws<R>(n, ws);
+  BtProb<R> q;
+  q.n = n; q.ldv = ldv; q.ldz = ldz; q.ldphi = ldphi; q.nblk = w.nblk; q.nsplit = w.nsplit;
+  q.V = V; q.tau = tau; q.Z = Z; q.Phi = Phi;
+  q.Vp = w.Vp; q.Tm = w.Tm; q.Wpart = w.Wpart; q.W2 = w.W2; q.Gpart = w.Gpart;
+  return q;
 }
 
 template <typename R>
 int unmtr_run_t(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *tau, const double *Z, int64_t ldz,
                 cx<R> *Phi, int64_t ldphi, void *work, size_t bytes, hipStream_t st) {
   if (n <= 0) return MMF_OK;
-  BtWs<R> w = unmtr_ws<R>(n, work);
-  if (bytes < w.bytes) return MMF_ERR_WORKSPACE;
-  // 1. clean copies of every reflector block (Phi may alias V)
-  for (int64_t b = 0; b < w.nblk; ++b) {
-    const int64_t p = b * BT_NB;
-    const int kb = (int)((n - 1 - p < BT_NB) ? n - 1 - p : BT_NB);
-    hipLaunchKernelGGL(bt_pack<R>, dim3(cdiv(n - p - 1, 256), BT_NB), dim3(256), 0, st, n, V, ldv,
-                       w.Vp + bt_off(n, b), p, kb);
-    MMF_LAUNCH_CHECK();
-  }
-  // 2. T factors
-  if (w.nblk > 0) {
-    hipLaunchKernelGGL(bt_gram<R>, dim3((unsigned)w.nblk, (unsigned)w.nsplit), dim3(GEMM_THREADS), 0, st,
-                       n, w.Vp, w.nsplit, w.Gpart);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_tmat<R>, dim3((unsigned)w.nblk), dim3(64), 0, st, n, tau, w.Gpart, w.nsplit, w.Tm);
-    MMF_LAUNCH_CHECK();
-  }
-  // 3. Phi = Z (complex)
-  hipLaunchKernelGGL(bt_init_phi<R>, dim3(cdiv(n, 256), (unsigned)n), dim3(256), 0, st, n, Z, ldz, Phi,
-                     ldphi);
-  MMF_LAUNCH_CHECK();
-  // 4. apply blocks last to first
-  for (int64_t b = w.nblk - 1; b >= 0; --b) {
-    const int64_t p = b * BT_NB;
-    const int64_t mb = n - p - 1;
-    const cx<R> *Vb = w.Vp + bt_off(n, b);
-    cx<R> *Ph = Phi + (p + 1);
-    const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
-    GemmArgs g = gemm_args(BT_NB, n, mb, Vb, mb, Ph, ldphi, nullptr, BT_NB, 1.0, 0.0, 0.0, 0.0);
-    hipLaunchKernelGGL(bt_splitk<R>, dim3(1, cdiv(n, GT_N), (unsigned)nsl), dim3(GEMM_THREADS), 0, st, g,
-                       (int64_t)BT_KCHUNK, w.Wpart, (int64_t)BT_NB * n);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)n), dim3(64), 0, st, n, w.Wpart, nsl,
-                       w.Tm + b * BT_NB * BT_NB, w.W2);
-    MMF_LAUNCH_CHECK();
-    GemmArgs u = gemm_args(mb, n, BT_NB, Vb, mb, w.W2, BT_NB, Ph, ldphi, -1.0, 0.0, 1.0, 0.0);
-    const int rc = gemm_launch_t<R, true, A_N, B_N>(u, st);
-    if (rc) return rc;
-  }
-  return MMF_OK;
+  static_assert(sizeof(BtProb<R>) <= BT_TABLE_BYTES, "table entry");
+  if (bytes < unmtr_ws<R>(n, nullptr).bytes + BT_TABLE_BYTES) return MMF_ERR_WORKSPACE;
+  BtProb<R> *pr = reinterpret_cast<BtProb<R> *>(work);
+  const BtProb<R> q = bt_prob<R>(n, V, ldv, tau, Z, ldz, Phi, ldphi, (char *)work + BT_TABLE_BYTES);
+  const int rc = table_write(pr, &q, 1, st);
+  if (rc) return rc;
+  return unmtr_grouped<R>(pr, &n, 1, st);
 }
 
 int unmtr_run(int64_t n, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z, int64_t ldz,
