@@ -115,6 +115,29 @@ int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
 int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec,
              void *work, size_t work_bytes, int32_t *dev_info, void *stream);
 
+/* Workspace bytes that mmf_eigh_batched needs for `count` problems of orders
+ * n[0..count) (host array) at precision prec.
+ * Errors: -1 count < 0, -2 n NULL or an n[c] < 0, -3 prec unknown, -4 bytes NULL. */
+int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t *bytes);
+
+/* Many independent eigendecompositions (Sec. 3.2) in one call, e.g. the
+ * Floquet matrices of a parameter scan.  Problem c is exactly the mmf_eigh
+ * problem (n[c], A[c], lda[c], w[c]) and gets the same result; the stages
+ * run grouped, so each kernel launch advances every matrix of the batch
+ * (sizes may differ; launches cover the largest).
+ * n, lda: host arrays [count]; A, w: host arrays [count] of device pointers
+ *   (A[c] n[c] x n[c] column-major, lower triangle read, eigenvectors on
+ *   exit; w[c] eigenvalues ascending).  Problems with n[c] = 0 are skipped.
+ * work/work_bytes: dev scratch of at least mmf_eigh_batched_workspace().
+ * dev_info: dev int32 [count]; entry c set to 0 or MMF_ERR_NO_CONVERGENCE.
+ * The host arrays are read during the call only.
+ * Errors: -1 count < 0, -2 n NULL or n[c] < 0, -3 A NULL or A[c] NULL,
+ *   -4 lda NULL or lda[c] < max(1, n[c]), -5 w NULL or w[c] NULL, -6 prec
+ *   unknown, -7/-8 workspace NULL or too small, -9 dev_info NULL, MMF_ERR_HIP. */
+int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                     double *const *w, int prec, void *work, size_t work_bytes,
+                     int32_t *dev_info, void *stream);
+
 /* Stage 1 of mmf_eigh: Householder reduction Q^H A Q = T with T real
  * symmetric tridiagonal.  On exit d[n] (dev) is the diagonal, e[n-1] (dev) the
  * off-diagonal, the reflector v_i (v_i[i+1] = 1, zero above) is stored in

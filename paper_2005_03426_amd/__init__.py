@@ -128,6 +128,39 @@ def eigh(At, prec: int = MMF_C128, w=None, work=None, info=None, stream=None):
     return w, At, info
 
 
+def eigh_batched_workspace_bytes(sizes, prec: int = MMF_C128) -> int:
+    n = (C.c_int64 * max(len(sizes), 1))(*[int(m) for m in sizes])
+    b = C.c_size_t(0)
+    call("mmf_eigh_batched_workspace", C.c_int64(len(sizes)), n, C.c_int(prec), C.byref(b))
+    return int(b.value)
+
+
+def eigh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stream=None):
+    """In-place eigendecomposition of every Hermitian matrix of the list
+    `mats` (column-major like eigh's argument) in one grouped call.  Returns
+    (ws, mats, info): eigenvalue tensors, the matrices now holding the
+    eigenvectors (row a = eigenvector a), and a device int32 [count]."""
+    torch = _torch()
+    count = len(mats)
+    if count == 0:
+        return [], mats, None
+    dev = mats[0].device
+    sizes = [int(A.shape[0]) for A in mats]
+    if ws is None:
+        ws = [torch.empty(m, dtype=torch.float64, device=dev) for m in sizes]
+    if work is None:
+        work = _workspace(eigh_batched_workspace_bytes(sizes, prec), dev)
+    if info is None:
+        info = torch.zeros(count, dtype=torch.int32, device=dev)
+    n = (C.c_int64 * count)(*sizes)
+    ld = (C.c_int64 * count)(*[int(A.stride(0)) if m else 1 for A, m in zip(mats, sizes)])
+    Ap = (C.c_void_p * count)(*[A.data_ptr() for A in mats])
+    wp = (C.c_void_p * count)(*[w.data_ptr() for w in ws])
+    call("mmf_eigh_batched", C.c_int64(count), n, Ap, ld, wp, C.c_int(prec), _ptr(work),
+         C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return ws, mats, info
+
+
 def hetrd(At, work=None, stream=None):
     """Stage 1: returns (d, e, tau); At's column i (row i of the tensor) keeps
     the reflector v_i below the diagonal."""
@@ -235,3 +268,26 @@ def solve(problem, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda"):
     U = evolve(dp, Pt, w, t0, tt)
     P = avg_prob(dp, Pt)
     return {"w": w, "Pt": Pt, "U": U, "P": P, "info": info, "dp": dp}
+
+
+def solve_batched(problems, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda", stream=None):
+    """Many Floquet solves with one grouped eigensolve: assemble each H_F,
+    diagonalise them all together, then U(t) and averaged P per problem.
+    Returns a list of dicts like solve()."""
+    torch = _torch()
+    import contextlib
+    ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+    with ctx:          # temporaries are then allocated and freed in the order of `stream`
+        dps = [p if isinstance(p, DeviceProblem) else DeviceProblem(p, device) for p in problems]
+        if not dps:
+            return []
+        dev = dps[0].device
+        tt = t if torch.is_tensor(t) else torch.as_tensor(np.asarray(t, dtype=np.float64), device=dev)
+        HFs = [build_floquet(dp, stream=stream) for dp in dps]
+        ws, Pts, info = eigh_batched(HFs, prec, stream=stream)
+        out = []
+        for k, (dp, w, Pt) in enumerate(zip(dps, ws, Pts)):
+            U = evolve(dp, Pt, w, t0, tt, stream=stream)
+            P = avg_prob(dp, Pt, stream=stream)
+            out.append({"w": w, "Pt": Pt, "U": U, "P": P, "info": info[k:k + 1], "dp": dp})
+    return out

@@ -1,6 +1,7 @@
 // Dense Hermitian eigendecomposition H_F = Phi diag(w) Phi^H (the
 // diagonalisation step of Sec. 3.2): reduction to a real tridiagonal matrix,
 // divide and conquer on it, back-transformation, all on the caller's stream.
+#include <vector>
 #include "common.h"
 #include "stages.h"
 
@@ -31,6 +32,20 @@ inline EighWs eigh_ws(int64_t M, void *base, size_t have) {
   w.bytes = cv.used();
   (void)have;
   return w;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline size_t eigh_one_bytes(int64_t M, int prec) {
+  return prec == MMF_C128 ? eigh_ws(M, nullptr, 0).bytes : eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED);
+}
+
+// largest number of problems one grouped launch takes (grid z dimension)
+constexpr int64_t EIGH_GROUP_MAX = 65535;
+
+__global__ void eigh_zero_info(int32_t *info, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) info[i] = 0;
 }
 
 }  // namespace mmf
@@ -74,4 +89,96 @@ extern "C" int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, v
   rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st);
   if (rc) return rc;
   return unmtr_run(M, A, lda, ws.tau, ws.Z, M, A, lda, ws.rest, ws.rest_bytes, st);
+}
+
+extern "C" int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t *bytes) {
+  if (count < 0) return -1;
+  if (count > 0 && !n) return -2;
+  if (prec != MMF_C128 && prec != MMF_C64_REFINED && prec != MMF_C64_RAW) return -3;
+  if (!bytes) return -4;
+  const int64_t group = count < EIGH_GROUP_MAX ? count : EIGH_GROUP_MAX;
+  size_t b = align256((size_t)(group > 0 ? group : 1) * STAGE_TABLE_BYTES);
+  for (int64_t c = 0; c < count; ++c) {
+    if (n[c] < 0) return -2;
+    if (n[c] > 0) b += align256(eigh_one_bytes(n[c], prec));
+  }
+  *bytes = b;
+  return MMF_OK;
+}
+
+extern "C" int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                                double *const *w, int prec, void *work, size_t work_bytes, int32_t *dev_info,
+                                void *stream) {
+  if (count < 0) return -1;
+  if (count == 0) return MMF_OK;
+  if (!n) return -2;
+  if (!A) return -3;
+  if (!lda) return -4;
+  if (!w) return -5;
+  for (int64_t c = 0; c < count; ++c) {
+    if (n[c] < 0) return -2;
+    if (n[c] > 0 && !A[c]) return -3;
+    if (lda[c] < n[c] || lda[c] < 1) return -4;
+    if (n[c] > 0 && !w[c]) return -5;
+  }
+  if (prec != MMF_C128 && prec != MMF_C64_REFINED && prec != MMF_C64_RAW) return -6;
+  if (!work) return -7;
+  size_t need = 0;
+  mmf_eigh_batched_workspace(count, n, prec, &need);
+  if (work_bytes < need) return -8;
+  if (!dev_info) return -9;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(eigh_zero_info, dim3(cdiv(count, 256)), dim3(256), 0, st, dev_info, count);
+  MMF_LAUNCH_CHECK();
+  // carve: [table | problem 0 | problem 1 | ...] (empty problems take nothing)
+  const int64_t group = count < EIGH_GROUP_MAX ? count : EIGH_GROUP_MAX;
+  char *table = (char *)work;
+  char *cur = table + align256((size_t)group * STAGE_TABLE_BYTES);
+  std::vector<int64_t> nn, ld;
+  std::vector<mmf_z *> Av;
+  std::vector<double *> wv;
+  std::vector<void *> base;
+  std::vector<int32_t *> info;
+  for (int64_t c = 0; c < count; ++c) {
+    if (n[c] == 0) continue;
+    nn.push_back(n[c]);
+    ld.push_back(lda[c]);
+    Av.push_back(A[c]);
+    wv.push_back(w[c]);
+    base.push_back(cur);
+    info.push_back(dev_info + c);
+    cur += align256(eigh_one_bytes(n[c], prec));
+  }
+  const int64_t live = (int64_t)nn.size();
+  for (int64_t g0 = 0; g0 < live; g0 += EIGH_GROUP_MAX) {
+    const int64_t gc = (live - g0 < EIGH_GROUP_MAX) ? live - g0 : EIGH_GROUP_MAX;
+    const int64_t *gn = nn.data() + g0;
+    int rc;
+    if (prec != MMF_C128) {
+      rc = eigh_c64_batched(gc, gn, Av.data() + g0, ld.data() + g0, wv.data() + g0, prec == MMF_C64_REFINED,
+                            base.data() + g0, info.data() + g0, table, st);
+      if (rc) return rc;
+      continue;
+    }
+    std::vector<double *> e((size_t)gc), Z((size_t)gc);
+    std::vector<mmf_z *> tau((size_t)gc);
+    std::vector<void *> stage((size_t)gc);
+    for (int64_t c = 0; c < gc; ++c) {
+      const EighWs ws = eigh_ws(gn[c], base[g0 + c], 0);
+      e[c] = ws.e; Z[c] = ws.Z; tau[c] = ws.tau; stage[c] = ws.rest;
+    }
+    rc = hetrd_batched(gc, gn, Av.data() + g0, ld.data() + g0, wv.data() + g0, e.data(), tau.data(),
+                       stage.data(), table, st);
+    if (rc) return rc;
+    rc = stedc_batched(gc, gn, wv.data() + g0, e.data(), Z.data(), gn, stage.data(), info.data() + g0, table,
+                       st);
+    if (rc) return rc;
+    std::vector<const mmf_z *> Vc(Av.begin() + g0, Av.begin() + g0 + gc);
+    std::vector<const mmf_z *> tc(tau.begin(), tau.end());
+    std::vector<const double *> Zc(Z.begin(), Z.end());
+    rc = unmtr_batched(gc, gn, Vc.data(), ld.data() + g0, tc.data(), Zc.data(), gn, Av.data() + g0,
+                       ld.data() + g0, stage.data(), table, st);
+    if (rc) return rc;
+  }
+  return MMF_OK;
 }

@@ -30,6 +30,7 @@
 // matrix of a batch; a matrix whose reduction has finished (i >= n - 1) simply
 // exits.  Grids are sized for the largest matrix.  A single reduction is the
 // one-entry case.
+#include <vector>
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
@@ -553,6 +554,35 @@ int hetrd_run_t(int64_t n, cx<R> *A, int64_t lda, double *d, double *e, cx<R> *t
   int rc = table_write(pr, &q, 1, st);
   if (rc) return rc;
   return hetrd_grouped<R>(pr, &n, 1, st);
+}
+
+// Batch: entry c reduces A[c] (order n[c] >= 1) using the stage workspace
+// stage[c] (laid out as for a single reduction); the problem table goes to
+// `table` (count * STAGE_TABLE_BYTES device bytes).
+template <typename R>
+int hetrd_batched_t(int64_t count, const int64_t *n, cx<R> *const *A, const int64_t *lda, double *const *d,
+                    double *const *e, cx<R> *const *tau, void *const *stage, void *table, hipStream_t st) {
+  static_assert(sizeof(HtProb<R>) <= STAGE_TABLE_BYTES, "table entry");
+  std::vector<HtProb<R>> h((size_t)count);
+  for (int64_t c = 0; c < count; ++c)
+    h[c] = ht_prob<R>(n[c], A[c], lda[c], d[c], e[c], tau[c],
+                      hetrd_ws<R>(n[c], (char *)stage[c] + HT_TABLE_BYTES));
+  HtProb<R> *pr = reinterpret_cast<HtProb<R> *>(table);
+  const int rc = table_write(pr, h.data(), count, st);
+  if (rc) return rc;
+  return hetrd_grouped<R>(pr, n, count, st);
+}
+
+int hetrd_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda, double *const *d,
+                  double *const *e, mmf_z *const *tau, void *const *stage, void *table, hipStream_t st) {
+  return hetrd_batched_t<double>(count, n, reinterpret_cast<cd *const *>(A), lda, d, e,
+                                 reinterpret_cast<cd *const *>(tau), stage, table, st);
+}
+
+int hetrd_batched_c64(int64_t count, const int64_t *n, void *const *A, const int64_t *lda, double *const *d,
+                      double *const *e, void *const *tau, void *const *stage, void *table, hipStream_t st) {
+  return hetrd_batched_t<float>(count, n, reinterpret_cast<cf *const *>(A), lda, d, e,
+                                reinterpret_cast<cf *const *>(tau), stage, table, st);
 }
 
 int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau, void *work,

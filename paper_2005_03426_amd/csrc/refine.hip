@@ -23,6 +23,7 @@
 // All products are FP64 complex GEMMs on the matrix cores; A X is clipped to
 // the bandwidth of A, detected on the device (the Floquet matrix is banded).
 #include <float.h>
+#include <vector>
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
@@ -366,23 +367,11 @@ inline RefWs ref_ws(int64_t M, bool refine, void *base) {
 
 size_t eigh_c64_ws_bytes(int64_t M, bool refine) { return ref_ws(M, refine, nullptr).bytes; }
 
-int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void *work, size_t bytes,
-                 int32_t *info, hipStream_t st) {
-  if (M <= 0) return MMF_OK;
-  RefWs ws = ref_ws(M, refine, work);
-  if (bytes < ws.bytes) return MMF_ERR_WORKSPACE;
-  cd *A = reinterpret_cast<cd *>(Az);
-  const int64_t n = M;
+// After the complex64 eigensolve (eigenvectors in ws.Ac): widen them into A
+// (raw), or refine them in FP64 against A and write the refined pairs.
+static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, const RefWs &ws, hipStream_t st) {
   const dim3 g2(cdiv(n, 256), (unsigned)n);
-  // complex64 eigensolve: reduction and back-transformation in FP32, D&C in FP64
-  hipLaunchKernelGGL(rf_to_c64, g2, dim3(256), 0, st, n, A, lda, ws.Ac, n);
-  MMF_LAUNCH_CHECK();
-  int rc = hetrd_run_c64(n, ws.Ac, n, w, ws.e, ws.tauc, ws.stage, ws.stage_bytes, st);
-  if (rc) return rc;
-  rc = stedc_run(n, w, ws.e, ws.Z, n, ws.stage, ws.stage_bytes, info, st);
-  if (rc) return rc;
-  rc = unmtr_run_c64(n, ws.Ac, n, ws.tauc, ws.Z, n, ws.Ac, n, ws.stage, ws.stage_bytes, st);
-  if (rc) return rc;
+  int rc = MMF_OK;
   if (!refine) {
     hipLaunchKernelGGL(rf_to_c128, g2, dim3(256), 0, st, n, ws.Ac, n, A, lda);
     MMF_LAUNCH_CHECK();
@@ -466,6 +455,53 @@ int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void
   MMF_LAUNCH_CHECK();
   hipLaunchKernelGGL(rf_scatter, g2, dim3(256), 0, st, n, X, ws.lam, ws.dest, A, lda, w);
   MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void *work, size_t bytes,
+                 int32_t *info, hipStream_t st) {
+  if (M <= 0) return MMF_OK;
+  RefWs ws = ref_ws(M, refine, work);
+  if (bytes < ws.bytes) return MMF_ERR_WORKSPACE;
+  cd *A = reinterpret_cast<cd *>(Az);
+  const int64_t n = M;
+  // complex64 eigensolve: reduction and back-transformation in FP32, D&C in FP64
+  hipLaunchKernelGGL(rf_to_c64, dim3(cdiv(n, 256), (unsigned)n), dim3(256), 0, st, n, A, lda, ws.Ac, n);
+  MMF_LAUNCH_CHECK();
+  int rc = hetrd_run_c64(n, ws.Ac, n, w, ws.e, ws.tauc, ws.stage, ws.stage_bytes, st);
+  if (rc) return rc;
+  rc = stedc_run(n, w, ws.e, ws.Z, n, ws.stage, ws.stage_bytes, info, st);
+  if (rc) return rc;
+  rc = unmtr_run_c64(n, ws.Ac, n, ws.tauc, ws.Z, n, ws.Ac, n, ws.stage, ws.stage_bytes, st);
+  if (rc) return rc;
+  return c64_finish(n, A, lda, w, refine, ws, st);
+}
+
+int eigh_c64_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda, double *const *w,
+                     bool refine, void *const *base, int32_t *const *info, void *table, hipStream_t st) {
+  if (count <= 0) return MMF_OK;
+  std::vector<RefWs> ws((size_t)count);
+  std::vector<void *> Ac((size_t)count), tauc((size_t)count), stage((size_t)count);
+  std::vector<double *> e((size_t)count), Z((size_t)count);
+  for (int64_t c = 0; c < count; ++c) {
+    ws[c] = ref_ws(n[c], refine, base[c]);
+    Ac[c] = ws[c].Ac; tauc[c] = ws[c].tauc; stage[c] = ws[c].stage;
+    e[c] = ws[c].e; Z[c] = ws[c].Z;
+    hipLaunchKernelGGL(rf_to_c64, dim3(cdiv(n[c], 256), (unsigned)n[c]), dim3(256), 0, st, n[c],
+                       reinterpret_cast<const cd *>(A[c]), lda[c], ws[c].Ac, n[c]);
+    MMF_LAUNCH_CHECK();
+  }
+  int rc = hetrd_batched_c64(count, n, Ac.data(), n, w, e.data(), tauc.data(), stage.data(), table, st);
+  if (rc) return rc;
+  rc = stedc_batched(count, n, w, e.data(), Z.data(), n, stage.data(), info, table, st);
+  if (rc) return rc;
+  rc = unmtr_batched_c64(count, n, Ac.data(), n, tauc.data(), Z.data(), n, Ac.data(), n, stage.data(), table,
+                         st);
+  if (rc) return rc;
+  for (int64_t c = 0; c < count; ++c) {
+    rc = c64_finish(n[c], reinterpret_cast<cd *>(A[c]), lda[c], w[c], refine, ws[c], st);
+    if (rc) return rc;
+  }
   return MMF_OK;
 }
 

@@ -27,6 +27,7 @@
 // (problem, merge) pairs, so one launch serves a tree level of every matrix
 // of a batch.  A single tridiagonal problem is the one-entry case.
 #include <float.h>
+#include <vector>
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
@@ -702,6 +703,18 @@ inline DcProb dc_prob(int64_t n, double *d, const double *e, double *Z, int64_t 
   q.d = d; q.e = e; q.Z = Z; q.info = info;
   q.w = w;
   return q;
+}
+
+int stedc_batched(int64_t count, const int64_t *n, double *const *d, double *const *e, double *const *Z,
+                  const int64_t *ldz, void *const *stage, int32_t *const *info, void *table, hipStream_t st) {
+  static_assert(sizeof(DcProb) <= STAGE_TABLE_BYTES, "table entry");
+  std::vector<DcProb> h((size_t)count);
+  for (int64_t c = 0; c < count; ++c)
+    h[c] = dc_prob(n[c], d[c], e[c], Z[c], ldz[c], info[c], stedc_ws(n[c], (char *)stage[c] + 512));
+  DcProb *pr = reinterpret_cast<DcProb *>(table);
+  const int rc = table_write(pr, h.data(), count, st);
+  if (rc) return rc;
+  return stedc_grouped(pr, n, count, st);
 }
 
 int stedc_run(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *work, size_t bytes,

@@ -15,6 +15,7 @@
 // accumulation for the precision layer; Z is read in FP64 and rounded).
 // Grouped: every kernel reads its problem from a device table (BtProb) at
 // grid index z, so one launch applies block b of every matrix of a batch.
+#include <vector>
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
@@ -279,6 +280,37 @@ int unmtr_run_t(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *tau, const 
   const int rc = table_write(pr, &q, 1, st);
   if (rc) return rc;
   return unmtr_grouped<R>(pr, &n, 1, st);
+}
+
+template <typename R>
+int unmtr_batched_t(int64_t count, const int64_t *n, const cx<R> *const *V, const int64_t *ldv,
+                    const cx<R> *const *tau, const double *const *Z, const int64_t *ldz, cx<R> *const *Phi,
+                    const int64_t *ldphi, void *const *stage, void *table, hipStream_t st) {
+  static_assert(sizeof(BtProb<R>) <= STAGE_TABLE_BYTES, "table entry");
+  std::vector<BtProb<R>> h((size_t)count);
+  for (int64_t c = 0; c < count; ++c)
+    h[c] = bt_prob<R>(n[c], V[c], ldv[c], tau[c], Z[c], ldz[c], Phi[c], ldphi[c],
+                      (char *)stage[c] + BT_TABLE_BYTES);
+  BtProb<R> *pr = reinterpret_cast<BtProb<R> *>(table);
+  const int rc = table_write(pr, h.data(), count, st);
+  if (rc) return rc;
+  return unmtr_grouped<R>(pr, n, count, st);
+}
+
+int unmtr_batched(int64_t count, const int64_t *n, const mmf_z *const *V, const int64_t *ldv,
+                  const mmf_z *const *tau, const double *const *Z, const int64_t *ldz, mmf_z *const *Phi,
+                  const int64_t *ldphi, void *const *stage, void *table, hipStream_t st) {
+  return unmtr_batched_t<double>(count, n, reinterpret_cast<const cd *const *>(V), ldv,
+                                 reinterpret_cast<const cd *const *>(tau), Z, ldz,
+                                 reinterpret_cast<cd *const *>(Phi), ldphi, stage, table, st);
+}
+
+int unmtr_batched_c64(int64_t count, const int64_t *n, const void *const *V, const int64_t *ldv,
+                      const void *const *tau, const double *const *Z, const int64_t *ldz, void *const *Phi,
+                      const int64_t *ldphi, void *const *stage, void *table, hipStream_t st) {
+  return unmtr_batched_t<float>(count, n, reinterpret_cast<const cf *const *>(V), ldv,
+                                reinterpret_cast<const cf *const *>(tau), Z, ldz,
+                                reinterpret_cast<cf *const *>(Phi), ldphi, stage, table, st);
 }
 
 int unmtr_run(int64_t n, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z, int64_t ldz,

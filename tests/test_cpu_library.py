@@ -54,3 +54,44 @@ def test_floquet_dim_and_argument_checks_host_only():
     assert L.mmf_eigh_workspace(C.c_int64(-1), 0, C.byref(b)) == -1
     assert L.mmf_eigh_workspace(C.c_int64(10), 7, C.byref(b)) == -2
     assert L.mmf_strerror(4).decode().startswith("iteration")
+
+
+def test_batched_argument_checks_host_only():
+    """Every argument error of mmf_eigh_batched is found before any device work."""
+    import paper_2005_03426_amd as mmf
+    L = mmf.lib()
+    dummy = 16                                  # never dereferenced on these paths
+    n = (C.c_int64 * 2)(4, 5)
+    bad = (C.c_int64 * 2)(4, -1)
+    Ap = (C.c_void_p * 2)(dummy, dummy)
+    Anull = (C.c_void_p * 2)(dummy, None)
+    wp = (C.c_void_p * 2)(dummy, dummy)
+    ld = (C.c_int64 * 2)(5, 5)
+    ld_bad = (C.c_int64 * 2)(5, 4)
+    b = C.c_size_t(0)
+    assert L.mmf_eigh_batched_workspace(C.c_int64(2), n, 0, C.byref(b)) == 0
+    one = C.c_size_t(0)
+    assert L.mmf_eigh_workspace(C.c_int64(5), 0, C.byref(one)) == 0
+    assert b.value > one.value
+    assert L.mmf_eigh_batched_workspace(C.c_int64(-1), n, 0, C.byref(b)) == -1
+    assert L.mmf_eigh_batched_workspace(C.c_int64(2), bad, 0, C.byref(b)) == -2
+    assert L.mmf_eigh_batched_workspace(C.c_int64(2), n, 5, C.byref(b)) == -3
+    assert L.mmf_eigh_batched_workspace(C.c_int64(2), n, 0, None) == -4
+    assert L.mmf_eigh_batched_workspace(C.c_int64(2), n, 0, C.byref(b)) == 0
+
+    def call(count=2, nn=n, A=Ap, lda=ld, w=wp, prec=0, work=dummy, nbytes=None, info=dummy):
+        nb = b.value if nbytes is None else nbytes
+        return L.mmf_eigh_batched(C.c_int64(count), nn, A, lda, w, prec, C.c_void_p(work), C.c_size_t(nb),
+                                  C.c_void_p(info), None)
+    assert call(count=-1) == -1
+    assert call(count=0) == 0
+    assert call(nn=None) == -2
+    assert call(nn=bad) == -2
+    assert call(A=None) == -3
+    assert call(A=Anull) == -3
+    assert call(lda=ld_bad) == -4
+    assert call(w=None) == -5
+    assert call(prec=9) == -6
+    assert call(work=0) == -7
+    assert call(nbytes=b.value - 1) == -8
+    assert call(info=0) == -9
