@@ -40,7 +40,7 @@
 namespace mmf {
 
 constexpr int HV_T = 64;        // HEMV tile
-constexpr int HV_CH = 32;       // tiles per HEMV workgroup (one block column strip)
+constexpr int HV_CH = 8;        // interior tiles per HEMV workgroup (one block column strip)
 constexpr int RW = 256;         // rows per workgroup in row-parallel kernels
 constexpr int DOT_ROWS = 1024;  // rows per workgroup of the panel dot products
 
@@ -58,8 +58,8 @@ __device__ inline R block_sum256(R v, R *sh) {
 template <typename R>
 struct HtWs {
   cx<R> *P3;       // n x 3NB (ld n): [V | W | V]
-  cx<R> *pdir;     // nbt x mpad
-  cx<R> *ptrn;     // nbt x nchmax x 64
+  cx<R> *pdir;     // nbt x mpad: direct partial of block column lb for local row
+  cx<R> *ptrn;     // nbt x nchmax x 64: transposed partials (slot 0 diagonal/edge tiles)
   cx<R> *dots;     // gdot x 2NB
   R *norms;        // grow partials
   cx<R> *sparts;   // nbt partials
@@ -72,10 +72,12 @@ template <typename R>
 inline HtWs<R> hetrd_ws(int64_t n, void *base) {
   Carver cv(base);
   HtWs<R> w;
-  const int64_t m = n > 1 ? n - 1 : 1;
-  w.nbt = (m + HV_T - 1) / HV_T;
+  // HEMV tiles sit on the absolute 64-row grid of A: block columns of the
+  // trailing matrix number at most ceil(n / 64)
+  w.nbt = (n + HV_T - 1) / HV_T;
+  if (w.nbt < 1) w.nbt = 1;
   w.mpad = w.nbt * HV_T;
-  w.nchmax = (w.nbt + HV_CH - 1) / HV_CH;
+  w.nchmax = (w.nbt + HV_CH - 1) / HV_CH + 1;    // slot 0: diagonal/edge tiles
   w.P3 = cv.take<cx<R>>((size_t)n * 3 * HT_NB);
   w.pdir = cv.take<cx<R>>((size_t)w.nbt * w.mpad);
   w.ptrn = cv.take<cx<R>>((size_t)w.nbt * w.nchmax * HV_T);
@@ -199,119 +201,155 @@ template <> struct NtVec<double> { typedef double v __attribute__((ext_vector_ty
 template <> struct NtVec<float> { typedef float v __attribute__((ext_vector_type(2))); };
 
 // u = A_trail v over the lower triangle of the trailing matrix
-// A_trail = A[i+1:, i+1:] (size m).  Workgroup (bj, c) covers the tile strip
-// bi = bj + c*HV_CH ... of block column bj; each wavefront owns whole tiles
-// (bi = bi0 + wave, bi0 + wave + 4, ...), so no workgroup barrier sits in the
-// streaming loop.  Lane l covers rows rg + 16 q (rg = l % 16, q = 0..3) and
-// columns 16 cg + j (cg = l / 16, j = 0..15): every load instruction reads four
-// contiguous column segments.  Interior tiles are read with non-temporal
-// loads and no per-element guards.  The direct product of a tile is folded
-// across the four column groups with shuffles and written as one partial per
-// (block column, row); the conjugate-transposed product accumulates in
-// registers over the strip and is folded once at the end.
+// A_trail = A[i+1:, i+1:].  Tiles lie on the absolute 64 x 64 grid of A
+// (block b covers rows 64b .. 64b+63), so on a leading dimension divisible by
+// 8 every column segment a load touches starts on a 128-byte line; b0 is the
+// block holding row i+1 and local block lb = b - b0.
+//   blockIdx.y >= 1: interior tiles (block row > block column, all rows
+//     < n): chunk y-1 of HV_CH tiles of block column b0 + blockIdx.x.  The
+//     four wavefronts share every tile, wave w taking its columns
+//     16w .. 16w+15 (lane: rows rg + 16q, columns 16w + 4cg + j), so a lane
+//     holds 16 elements per tile; the next tile is loaded (non-temporal, no
+//     guards) while the current one is multiplied.  The direct product is
+//     summed over the waves through LDS once per tile and written as the
+//     partial of (block column, row); the conjugate-transposed product stays
+//     in registers over the strip.  Columns left of i+1 carry v = 0.
+//   blockIdx.y == 0: the diagonal tile of the block column and, when n is
+//     not a multiple of 64, its tile in the last (partial) block row, with
+//     every element masked (rows/columns in [i+1, n), lower triangle, real
+//     diagonal); lane = row, wave w = columns 16w .. 16w+15.
 template <typename R>
-__global__ void __launch_bounds__(256) ht_hemv(const HtProb<R> *pr, int64_t i, int k) {
+__global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i, int k) {
   typedef cx<R> C;
   typedef typename NtVec<R>::v nv;
   __shared__ C vcol[HV_T];
-  __shared__ C tsum[4][HV_T];
+  __shared__ C red[2][4][HV_T];
   const HtProb<R> &q = pr[blockIdx.z];
   const int64_t n = q.n, lda = q.lda, mpad = q.mpad, nchmax = q.nchmax;
   if (i >= n - 1) return;
+  const int64_t b0 = (i + 1) / HV_T;
+  const int64_t nb = (n + HV_T - 1) / HV_T;        // absolute blocks
+  const int64_t nfull = n / HV_T;                   // blocks entirely inside the matrix
+  const int64_t lb = blockIdx.x;
+  const int64_t bj = b0 + lb;
+  if (bj >= nb) return;
+  const int64_t slot = blockIdx.y;
+  const int64_t first = bj + 1 + (slot - 1) * HV_CH;   // interior chunk's first block row
+  if (slot > 0 && first >= nfull) return;
   const C *A = q.A;
-  const C *P3 = q.P3;
+  const C *v = q.P3 + (int64_t)k * n;               // v[row], zero outside [i+1, n)
   C *pdir = q.pdir, *ptrn = q.ptrn;
-  const int64_t m = n - i - 1;
-  const int64_t nbt = (m + HV_T - 1) / HV_T;
-  const int64_t bj = blockIdx.x;
-  const int64_t c = blockIdx.y;
-  const int64_t bi0 = bj + c * HV_CH;
-  if (bj >= nbt || bi0 >= nbt) return;
-  const int64_t bi1 = (bi0 + HV_CH < nbt) ? bi0 + HV_CH : nbt;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int rg = lane & 15, cg = lane >> 4;
-  const C *At = A + (i + 1) + (i + 1) * lda;
-  const C *v = P3 + (i + 1) + (int64_t)k * n;
   if (tid < HV_T) {
     const int64_t gc = bj * HV_T + tid;
-    vcol[tid] = gc < m ? v[gc] : cmk<R>(0, 0);
+    vcol[tid] = (gc > i && gc < n) ? v[gc] : cmk<R>(0, 0);
   }
   __syncthreads();
-  C tacc[16];
+  if (slot == 0) {
+    // ------------------------------------------------ guarded tiles
+    C tacc[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) tacc[j] = cmk<R>(0, 0);
-  const int64_t col0 = bj * HV_T + cg * 16;
-  for (int64_t bi = bi0 + wave; bi < bi1; bi += 4) {
-    const bool diagt = (bi == bj);
-    // interior tile: every element is in range and below the diagonal
-    const bool full = !diagt && (bi + 1) * HV_T <= m;
+    for (int j = 0; j < 16; ++j) tacc[j] = cmk<R>(0, 0);
+    const int ntile = (nb != nfull && bj < nb - 1) ? 2 : 1;
+    for (int tt = 0; tt < ntile; ++tt) {
+      const int64_t bi = (tt == 0) ? bj : nb - 1;
+      const int64_t row = bi * HV_T + lane;
+      const bool rok = row > i && row < n;
+      const C vr = rok ? v[row] : cmk<R>(0, 0);
+      C d = cmk<R>(0, 0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t col = bj * HV_T + 16 * wave + j;
+        const bool ok = rok && col > i && row >= col;     // col < n follows from row < n
+        C a = ok ? A[row + col * lda] : cmk<R>(0, 0);
+        const bool dg = (row == col);
+        if (dg) a.im = R(0);
+        d = cadd(d, cmul(a, vcol[16 * wave + j]));
+        if (!dg) tacc[j] = cadd(tacc[j], cmulc(a, vr));
+      }
+      red[0][wave][lane] = d;
+      __syncthreads();
+      if (tid < HV_T) {
+        const C s = cadd(cadd(red[0][0][tid], red[0][1][tid]), cadd(red[0][2][tid], red[0][3][tid]));
+        pdir[lb * mpad + (bi - b0) * HV_T + tid] = s;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      R re = tacc[j].re, im = tacc[j].im;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
+      if (lane == 0) ptrn[(lb * nchmax + 0) * HV_T + 16 * wave + j] = cmk<R>(re, im);
+    }
+    return;
+  }
+  // -------------------------------------------------- interior strip
+  const int64_t bi1 = (first + HV_CH < nfull) ? first + HV_CH : nfull;
+  const int rg = lane & 15, cg = lane >> 4;
+  const int cb = 16 * wave + 4 * cg;
+  C vc[4], tacc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) { vc[j] = vcol[cb + j]; tacc[j] = cmk<R>(0, 0); }
+  const C *colp = A + (bj * HV_T + cb) * lda + rg;
+  C b0t[4][4], b1t[4][4];
+  auto load = [&](C (&b)[4][4], int64_t bi) {
+    const C *p = colp + bi * HV_T;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const nv x = __builtin_nontemporal_load(reinterpret_cast<const nv *>(p + 16 * qq + (int64_t)j * lda));
+        b[j][qq] = cmk<R>(x[0], x[1]);
+      }
+  };
+  auto step = [&](C (&b)[4][4], C (&nxt)[4][4], int64_t bi, int t) {
+    if (bi + 1 < bi1) load(nxt, bi + 1);
+    __builtin_amdgcn_sched_barrier(0);
     C vr[4], dacc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t row = bi * HV_T + rg + 16 * q;
-      vr[q] = row < m ? v[row] : cmk<R>(0, 0);
-      dacc[q] = cmk<R>(0, 0);
-    }
-    const C *tb = At + bi * HV_T + rg + col0 * lda;
+    for (int qq = 0; qq < 4; ++qq) { vr[qq] = v[bi * HV_T + rg + 16 * qq]; dacc[qq] = cmk<R>(0, 0); }
 #pragma unroll
-    for (int jb = 0; jb < 16; jb += 4) {
-      C av[4][4];
-      if (full) {
-        // streaming data read exactly once: non-temporal loads, no per-element guards
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const nv x = __builtin_nontemporal_load(
-                reinterpret_cast<const nv *>(tb + 16 * q + (int64_t)(jb + jj) * lda));
-            av[jj][q] = cmk<R>(x[0], x[1]);
-          }
-      } else {
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int64_t row = bi * HV_T + rg + 16 * q;
-            const int64_t gc = col0 + jb + jj;
-            const bool ok = row < m && gc < m && (!diagt || row >= gc);
-            av[jj][q] = ok ? At[row + gc * lda] : cmk<R>(0, 0);
-          }
+      for (int qq = 0; qq < 4; ++qq) {
+        const C a = b[j][qq];
+        // dacc += a vc ;  tacc += conj(a) vr
+        dacc[qq].re = fma(a.re, vc[j].re, dacc[qq].re);
+        dacc[qq].re = fma(-a.im, vc[j].im, dacc[qq].re);
+        dacc[qq].im = fma(a.re, vc[j].im, dacc[qq].im);
+        dacc[qq].im = fma(a.im, vc[j].re, dacc[qq].im);
+        tacc[j].re = fma(a.re, vr[qq].re, tacc[j].re);
+        tacc[j].re = fma(a.im, vr[qq].im, tacc[j].re);
+        tacc[j].im = fma(a.re, vr[qq].im, tacc[j].im);
+        tacc[j].im = fma(-a.im, vr[qq].re, tacc[j].im);
       }
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const C vc = vcol[cg * 16 + jb + jj];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          C a = av[jj][q];
-          const bool dg = diagt && (rg + 16 * q == cg * 16 + jb + jj);
-          if (dg) a.im = R(0);
-          dacc[q] = cadd(dacc[q], cmul(a, vc));
-          if (!dg) tacc[jb + jj] = cadd(tacc[jb + jj], cmulc(a, vr[q]));
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      R re = dacc[q].re, im = dacc[q].im;
+    for (int qq = 0; qq < 4; ++qq) {
+      R re = dacc[qq].re, im = dacc[qq].im;
       re += __shfl_xor(re, 16, 64); im += __shfl_xor(im, 16, 64);
       re += __shfl_xor(re, 32, 64); im += __shfl_xor(im, 32, 64);
-      if (cg == 0) pdir[bj * mpad + bi * HV_T + rg + 16 * q] = cmk<R>(re, im);
+      if (cg == 0) red[t & 1][wave][rg + 16 * qq] = cmk<R>(re, im);
     }
+    __syncthreads();
+    if (tid < HV_T) {
+      const C s = cadd(cadd(red[t & 1][0][tid], red[t & 1][1][tid]), cadd(red[t & 1][2][tid], red[t & 1][3][tid]));
+      pdir[lb * mpad + (bi - b0) * HV_T + tid] = s;
+    }
+  };
+  load(b0t, first);
+  int t = 0;
+  for (int64_t bi = first; bi < bi1; bi += 2, t += 2) {
+    step(b0t, b1t, bi, t);
+    if (bi + 1 < bi1) step(b1t, b0t, bi + 1, t + 1);
   }
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < 4; ++j) {
     R re = tacc[j].re, im = tacc[j].im;
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
-    if (rg == 0) tsum[wave][cg * 16 + j] = cmk<R>(re, im);
-  }
-  __syncthreads();
-  if (tid < HV_T) {
-    const int nw = (int)((bi1 - bi0 < 4) ? bi1 - bi0 : 4);
-    C s = cmk<R>(0, 0);
-    for (int w2 = 0; w2 < nw; ++w2) s = cadd(s, tsum[w2][tid]);
-    ptrn[(bj * nchmax + c) * HV_T + tid] = s;
+    if (rg == 0) ptrn[(lb * nchmax + slot) * HV_T + cb + j] = cmk<R>(re, im);
   }
 }
 
@@ -354,7 +392,7 @@ __global__ void __launch_bounds__(256) ht_finish_u(const HtProb<R> *pr, int64_t 
   const HtProb<R> &pq = pr[blockIdx.z];
   const int64_t n = pq.n, mpad = pq.mpad, nchmax = pq.nchmax;
   if (i >= n - 1) return;
-  if ((int64_t)blockIdx.x * HV_T >= n - i - 1) return;          // beyond this matrix's row blocks
+  if ((int64_t)blockIdx.x >= (n + HV_T - 1) / HV_T - (i + 1) / HV_T) return;   // beyond this matrix's blocks
   C *P3 = pq.P3;
   const C *pdir = pq.pdir, *ptrn = pq.ptrn, *dots = pq.dots, *tau = pq.tau;
   C *sparts = pq.sparts, *w0first = pq.w0first;
@@ -368,16 +406,17 @@ __global__ void __launch_bounds__(256) ht_finish_u(const HtProb<R> *pr, int64_t 
     if (which == 0) x1[q] = s; else x2[q] = s;
   }
   __syncthreads();
-  const int64_t m = n - i - 1;
-  const int64_t nbt = (m + HV_T - 1) / HV_T;
-  const int64_t bi = blockIdx.x;
-  const int64_t t = bi * HV_T + lane;
-  const int64_t rho = i + 1 + t;
+  const int64_t b0 = (i + 1) / HV_T;
+  const int64_t nfull = n / HV_T;
+  const int64_t lbi = blockIdx.x;                   // local block of these rows
+  const int64_t rho = (b0 + lbi) * HV_T + lane;     // absolute row
+  const bool live = rho > i && rho < n;
   C u = cmk<R>(0, 0);
-  if (t < m) {
-    for (int64_t bj = wave; bj <= bi; bj += 4) u = cadd(u, pdir[bj * mpad + t]);
-    const int64_t nch = (nbt - bi + HV_CH - 1) / HV_CH;
-    for (int64_t c = wave; c < nch; c += 4) u = cadd(u, ptrn[(bi * nchmax + c) * HV_T + lane]);
+  if (live) {
+    for (int64_t lb = wave; lb <= lbi; lb += 4) u = cadd(u, pdir[lb * mpad + lbi * HV_T + lane]);
+    const int64_t inner = nfull - (b0 + lbi) - 1;   // interior tiles below this block's diagonal
+    const int64_t nslot = 1 + (inner > 0 ? (inner + HV_CH - 1) / HV_CH : 0);
+    for (int64_t c = wave; c < nslot; c += 4) u = cadd(u, ptrn[(lbi * nchmax + c) * HV_T + lane]);
     for (int q = wave; q < k; q += 4) {
       u = csub(u, cmul(P3[rho + (int64_t)q * n], x1[q]));
       u = csub(u, cmul(P3[rho + (int64_t)(HT_NB + q) * n], x2[q]));
@@ -386,11 +425,11 @@ __global__ void __launch_bounds__(256) ht_finish_u(const HtProb<R> *pr, int64_t 
   part[wave][lane] = u;
   __syncthreads();
   C contrib = cmk<R>(0, 0);
-  if (wave == 0 && t < m) {
+  if (wave == 0 && live) {
     const C us = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
     const C w0 = cmul(tau[i], us);
     P3[rho + (int64_t)(HT_NB + k) * n] = w0;
-    if (t == 0) w0first[0] = w0;
+    if (rho == i + 1) w0first[0] = w0;
     contrib = cmulc(P3[rho + (int64_t)k * n], w0);   // conj(v) w0
   }
   const R sr = block_sum256(contrib.re, sh);
@@ -411,7 +450,7 @@ __global__ void __launch_bounds__(RW) ht_finish_w(const HtProb<R> *pr, int64_t p
   if ((int64_t)blockIdx.x * RW >= n - i - 1) return;              // beyond this matrix's rows
   const int kb = (int)((n - 1 - p < HT_NB) ? n - 1 - p : HT_NB);
   const int next = (k + 1 < kb) ? 1 : 0;
-  const int gs = (int)((n - i - 1 + HV_T - 1) / HV_T);
+  const int gs = (int)((n + HV_T - 1) / HV_T - (i + 1) / HV_T);   // finish_u workgroups
   C *A = pq.A, *P3 = pq.P3;
   const C *sparts = pq.sparts, *tau = pq.tau, *w0first = pq.w0first;
   R *norms = pq.norms;
@@ -504,10 +543,14 @@ int hetrd_grouped(const HtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
       const unsigned gr = cdiv(nmax - i - 2 > 0 ? nmax - i - 2 : 1, RW);
       hipLaunchKernelGGL(ht_reflector<R>, dim3(gr, 1, Z), dim3(RW), 0, st, pr, p, k);
       MMF_LAUNCH_CHECK();
-      const int64_t nbt = (m + HV_T - 1) / HV_T;
-      const int64_t nch = (nbt + HV_CH - 1) / HV_CH;
+      // anchored 64-blocks of the largest matrix: block columns b0 .. nb-1,
+      // slot 0 for the guarded tiles plus the interior chunks of column b0
+      const int64_t b0 = (i + 1) / HV_T;
+      const int64_t nbl = (nmax + HV_T - 1) / HV_T - b0;
+      const int64_t inner = nmax / HV_T - b0 - 1;
+      const int64_t nslot = 1 + (inner > 0 ? (inner + HV_CH - 1) / HV_CH : 0);
       const int ks = ktimer_begin(sizeof(R) == 8 ? "hemv" : "hemv_c64", st);
-      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbt, (unsigned)nch, Z), dim3(256), 0, st, pr, i, k);
+      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbl, (unsigned)nslot, Z), dim3(256), 0, st, pr, i, k);
       MMF_LAUNCH_CHECK();
       if (ks >= 0) {
         // algorithmic bytes: the lower triangle of every trailing matrix, read once
@@ -522,7 +565,7 @@ int hetrd_grouped(const HtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
         hipLaunchKernelGGL(ht_dots<R>, dim3(cdiv(m, DOT_ROWS), 2 * k, Z), dim3(256), 0, st, pr, i, k);
         MMF_LAUNCH_CHECK();
       }
-      hipLaunchKernelGGL(ht_finish_u<R>, dim3((unsigned)nbt, 1, Z), dim3(256), 0, st, pr, i, k);
+      hipLaunchKernelGGL(ht_finish_u<R>, dim3((unsigned)nbl, 1, Z), dim3(256), 0, st, pr, i, k);
       MMF_LAUNCH_CHECK();
       hipLaunchKernelGGL(ht_finish_w<R>, dim3(cdiv(m, RW), 1, Z), dim3(RW), 0, st, pr, p, k);
       MMF_LAUNCH_CHECK();
