@@ -98,11 +98,11 @@ def run_executor_bench(args, torch, mmf):
         if args.prec_only and prec_name != args.prec_only:
             continue
         if args.warmup:
-            ex = serve.Executor(slots=args.slots)
+            ex = serve.Executor(slots=args.slots, max_batch=args.max_batch)
             ex.run([serve.Request(rid=-1, arrival=0.0, problem=items[0][1], times=items[0][2], prec=prec)])
         reqs = [serve.Request(rid=k, arrival=a, problem=p, times=ts, t0=t0, prec=prec)
                 for k, (a, p, ts, t0) in enumerate(items)]
-        ex = serve.Executor(slots=args.slots)
+        ex = serve.Executor(slots=args.slots, max_batch=args.max_batch)
         torch.cuda.synchronize()
         t_a = time.perf_counter()
         done = ex.run(reqs)
@@ -112,7 +112,8 @@ def run_executor_bench(args, torch, mmf):
         bad = sum(int(r.result["info"].item()) != 0 for r in done)
         flops = sum((40.0 / 3.0) * float(r.result["M"]) ** 3 for r in done)
         st.update({"wall_s": wall, "eigh_tflops": flops / wall / 1e12, "failed": bad,
-                   "rejected": len(ex.rejected)})
+                   "rejected": len(ex.rejected), "batches": len(ex.batches),
+                   "mean_batch": float(np.mean(ex.batches)) if ex.batches else 0.0})
         print(f"[bench] {args.workload} {prec_name}: {st}", file=sys.stderr, flush=True)
         out_runs[prec_name] = st
     main_run = out_runs.get("c128") or next(iter(out_runs.values()))
@@ -120,7 +121,7 @@ def run_executor_bench(args, torch, mmf):
         "metric": "Floquet eigensolves/s", "value": main_run["solves_per_s"], "unit": "solves/s",
         "n_gpus": 1, "steps": 1, "warmup": args.warmup, "ms_per_step": main_run["makespan_s"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
-        "data": "synthetic", "config": dict(cfg, slots=args.slots),
+        "data": "synthetic", "config": dict(cfg, slots=args.slots, max_batch=args.max_batch),
         "p50_ms": main_run["p50_ms"], "p99_ms": main_run["p99_ms"], "runs": out_runs,
     }
     print(json.dumps(out), flush=True)
@@ -215,9 +216,10 @@ def main():
     ap.add_argument("--no-ktimer", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--prec-only", default="")
-    ap.add_argument("--batch-mode", default="grouped", choices=["grouped", "executor"])
+    ap.add_argument("--batch-mode", default="executor", choices=["grouped", "executor"])
     ap.add_argument("--prec", default="c128", choices=["c128", "c64_refined", "c64_raw"])
     args = ap.parse_args()
     if args.gpus != 1:

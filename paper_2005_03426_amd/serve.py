@@ -2,15 +2,20 @@
 
 Requests (a problem, its times, t0) arrive over time.  The executor keeps a
 fixed number of slots; each slot owns a HIP stream (default priority) and a
-worker thread.  A request is admitted when it has arrived, a slot is free
-and its HBM footprint (Floquet matrix, eigensolver and evolution
-workspaces) fits in the budget next to the requests already on the device;
-its whole solve (assemble -> eigh -> U(t) -> P) is then enqueued on the
-slot's stream, so solves of different slots overlap on the GPU.  Results
-(eigenvalues, P, U) stay on the device until the caller reads them.
-Latency is measured from a request's arrival to the moment its stream has
-finished.  Every step runs in the library's kernels (libmmf.so); this
-module only schedules.
+worker thread.  A free slot takes the oldest arrived request and, with it,
+every other arrived request of the same size class and precision (classes
+are octaves of the Floquet dimension M, so a batch's largest solve costs at
+most eight times its smallest), up to `max_batch` requests and as long as
+their HBM footprints (Floquet matrix, eigensolver and evolution workspaces)
+fit in the budget next to the work already on the device.  The batch is
+solved with one grouped eigensolve (each kernel launch advances every matrix
+of the batch), then U(t) and the averaged P per request, all on the slot's
+stream; batches of different slots overlap on the GPU.  A request's result
+does not depend on the batch it joined (the grouped kernels do the same
+arithmetic per matrix as a single solve).  Results stay on the device until
+the caller reads them.  Latency runs from a request's arrival to the moment
+its batch's stream has finished.  Every step runs in the library's kernels
+(libmmf.so); this module only schedules.
 """
 from __future__ import annotations
 
@@ -21,8 +26,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (DeviceProblem, build_floquet, eigh, evolve, avg_prob, eigh_workspace_bytes, call,
-               MMF_C128)
+from . import (DeviceProblem, build_floquet, eigh, eigh_batched, evolve, avg_prob, eigh_workspace_bytes,
+               call, MMF_C128)
 
 
 def footprint_bytes(M: int, D: int, T: int, prec: int = MMF_C128) -> int:
@@ -52,11 +57,12 @@ class Request:
 
 class Executor:
     def __init__(self, slots: int = 4, hbm_budget: int | None = None, device: str = "cuda",
-                 keep_eigenvectors: bool = False):
+                 keep_eigenvectors: bool = False, max_batch: int = 64):
         import torch
         self.torch = torch
         self.device = device
         self.slots = slots
+        self.max_batch = max(1, int(max_batch))
         if hbm_budget is None:
             free, _total = torch.cuda.mem_get_info()
             hbm_budget = int(0.8 * free)
@@ -74,22 +80,61 @@ class Executor:
         self._streams = [torch.cuda.Stream(device=self._dev_index) for _ in range(slots)]
         self._threads = [threading.Thread(target=self._worker, args=(k,), daemon=True) for k in range(slots)]
         self.rejected: list[Request] = []
+        self.batches: list[int] = []
 
     # ------------------------------------------------------------------ worker
-    def _solve(self, req: Request, stream):
+    def _solve(self, reqs: list[Request], stream):
         torch = self.torch
         with torch.cuda.stream(stream):
-            dp = DeviceProblem(req.problem, self.device)
-            tt = torch.as_tensor(np.asarray(req.times, dtype=np.float64), device=self.device)
-            HF = build_floquet(dp, stream=stream)
-            w, Pt, info = eigh(HF, prec=req.prec, stream=stream)
-            U = evolve(dp, Pt, w, req.t0, tt, stream=stream)
-            P = avg_prob(dp, Pt, stream=stream)
+            dps = [DeviceProblem(r.problem, self.device) for r in reqs]
+            HFs = [build_floquet(dp, stream=stream) for dp in dps]
+            if len(reqs) == 1:
+                w, Pt, info = eigh(HFs[0], prec=reqs[0].prec, stream=stream)
+                ws, Pts, infos = [w], [Pt], [info]
+            else:
+                ws, Pts, info = eigh_batched(HFs, prec=reqs[0].prec, stream=stream)
+                infos = [info[k:k + 1] for k in range(len(reqs))]
+            out = []
+            for r, dp, w, Pt, inf in zip(reqs, dps, ws, Pts, infos):
+                tt = torch.as_tensor(np.asarray(r.times, dtype=np.float64), device=self.device)
+                U = evolve(dp, Pt, w, r.t0, tt, stream=stream)
+                P = avg_prob(dp, Pt, stream=stream)
+                res = {"w": w, "U": U, "P": P, "info": inf, "M": dp.M}
+                if self.keep_vectors:
+                    res["Pt"] = Pt
+                out.append(res)
         stream.synchronize()
-        res = {"w": w, "U": U, "P": P, "info": info, "M": dp.M}
-        if self.keep_vectors:
-            res["Pt"] = Pt
-        return res
+        return out
+
+    def _take(self, now: float) -> list[Request]:
+        """Oldest arrived request plus arrived requests of its class (lock held)."""
+        if not self._pending or self._pending[0].arrival > now:
+            return []
+        head = None
+        for idx, r in enumerate(self._pending):
+            if r.arrival > now:
+                break                                  # pending is sorted by arrival
+            if self._in_use + r._fp <= self.budget:
+                head = idx
+                break
+        if head is None:
+            return []
+        first = self._pending[head]
+        batch, room = [head], self.budget - self._in_use - first._fp
+        for idx in range(head + 1, len(self._pending)):
+            if len(batch) >= self.max_batch:
+                break
+            r = self._pending[idx]
+            if r.arrival > now:
+                break
+            if r._cls == first._cls and r.prec == first.prec and r._fp <= room:
+                batch.append(idx)
+                room -= r._fp
+        taken = [self._pending[i] for i in batch]
+        for i in reversed(batch):
+            self._pending.pop(i)
+        self._in_use += sum(r._fp for r in taken)
+        return taken
 
     def _worker(self, k: int):
         torch = self.torch
@@ -97,24 +142,21 @@ class Executor:
         torch.cuda.set_device(self._dev_index)
         while True:
             with self._lock:
-                req = None
-                while req is None:
+                reqs = []
+                while not reqs:
                     if self._closed and not self._pending:
                         return
-                    now = self._now()
-                    for idx, r in enumerate(self._pending):
-                        if r.arrival > now:
-                            break                       # pending is sorted by arrival
-                        need = r._fp
-                        if self._in_use + need <= self.budget:
-                            req = self._pending.pop(idx)
-                            self._in_use += need
-                            break
-                    if req is None:
+                    reqs = self._take(self._now())
+                    if not reqs:
                         self._lock.wait(timeout=0.0005)
-                req.admitted = self._now()
+                t_adm = self._now()
+                for r in reqs:
+                    r.admitted = t_adm
+                self.batches.append(len(reqs))
             try:
-                req.result = self._solve(req, stream)
+                results = self._solve(reqs, stream)
+                for r, res in zip(reqs, results):
+                    r.result = res
             except BaseException as exc:          # surfaced by run()
                 with self._lock:
                     self._errors.append(exc)
@@ -122,9 +164,11 @@ class Executor:
                     self._pending.clear()
             finally:
                 with self._lock:
-                    req.done = self._now()
-                    self._in_use -= req._fp
-                    self._finished.append(req)
+                    t_done = self._now()
+                    for r in reqs:
+                        r.done = t_done
+                        self._in_use -= r._fp
+                        self._finished.append(r)
                     self._lock.notify_all()
 
     def _now(self) -> float:
@@ -141,6 +185,7 @@ class Executor:
             for n in r.problem.N:
                 M *= 2 * int(n) + 1
             r._fp = footprint_bytes(M, D, len(r.times), r.prec)
+            r._cls = int(M).bit_length()                 # octave of M
             if r._fp > self.budget:
                 self.rejected.append(r)
         reqs = [r for r in reqs if r._fp <= self.budget]

@@ -1,6 +1,7 @@
 """Continuous-batching executor: every result is the same alone and in the
-mix (bitwise: the kernels are deterministic and solves share nothing), and
-admission respects the HBM budget."""
+mix (bitwise: the kernels are deterministic, and a grouped solve does the
+same arithmetic per matrix as a single one), and admission respects the HBM
+budget."""
 import numpy as np
 import pytest
 
@@ -15,8 +16,8 @@ def _reqs(serve, problems, arrivals, prec=0):
             for k, (p, a) in enumerate(zip(problems, arrivals))]
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_result_same_alone_and_in_mix(prec):
+@pytest.mark.parametrize("prec,burst", [(0, False), (1, False), (0, True)])
+def test_result_same_alone_and_in_mix(prec, burst):
     torch, mmf = require_gpu()
     from paper_2005_03426_amd import serve
     probe = [random_problem(3, (4, 2), seed=s) for s in range(3)]
@@ -27,11 +28,14 @@ def test_result_same_alone_and_in_mix(prec):
         alone.append(ex.run(_reqs(serve, [p], [0.0], prec))[0].result)
     mix = probe + filler
     order = np.random.default_rng(0).permutation(len(mix))
-    arrivals = np.linspace(0.0, 0.02, len(mix))
+    # burst: everything arrives at once, so requests of one size class share a grouped solve
+    arrivals = np.zeros(len(mix)) if burst else np.linspace(0.0, 0.02, len(mix))
     reqs = _reqs(serve, [mix[i] for i in order], arrivals, prec)
     ex = serve.Executor(slots=4)
     done = ex.run(reqs)
     assert len(done) == len(mix)
+    if burst:
+        assert max(ex.batches) > 1
     by_problem = {id(r.problem): r for r in done}
     for p, a in zip(probe, alone):
         r = by_problem[id(p)].result
