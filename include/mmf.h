@@ -49,7 +49,8 @@ typedef struct { double re, im; } mmf_z;
 
 /* Problem statement (Eq. 1; the ATOM / MODES_NUMBER / MODE data of Sec. 3.1). */
 typedef struct {
-  int32_t D;            /* bare Hilbert-space dimension, 1 <= D <= 64                     */
+  int32_t D;            /* bare Hilbert-space dimension, 1 <= D <= 4096 (<= 64 for
+                           mmf_evolve, mmf_micromotion, mmf_avg_prob: MMF_ERR_TOO_LARGE) */
   int32_t F;            /* number of incommensurate fundamentals, 0 <= F <= 8             */
   int32_t K;            /* number of harmonic couplings, 0 <= K <= 64                     */
   const double  *omega; /* host [F]: fundamental angular frequencies                      */
@@ -137,6 +138,24 @@ int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t
 int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
                      double *const *w, int prec, void *work, size_t work_bytes,
                      int32_t *dev_info, void *stream);
+
+/* Workspace bytes that mmf_eigvalsh_batched needs (count, n as for
+ * mmf_eigh_batched_workspace; prec MMF_C128 or MMF_C64_RAW).
+ * Errors: -1 count < 0, -2 n NULL or an n[c] < 0, -3 prec unsupported, -4 bytes NULL. */
+int mmf_eigvalsh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t *bytes);
+
+/* Eigenvalues only of many Hermitian matrices (Sec. 3.2 without the
+ * eigenvectors; the quasienergy scans of Sec. 4.2): each A[c] (n[c] x n[c],
+ * lower triangle read, destroyed) is reduced to a real tridiagonal matrix by
+ * the grouped Householder reduction (complex128, or complex64 for
+ * MMF_C64_RAW, from a complex64 copy; A[c] then stays intact), and all
+ * eigenvalues are found by bisection on Sturm counts in FP64; w[c] receives
+ * them in ascending order.  Arguments, ownership and errors as for
+ * mmf_eigh_batched (-6: prec not MMF_C128 / MMF_C64_RAW); dev_info[c] is set
+ * to 0. */
+int mmf_eigvalsh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                         double *const *w, int prec, void *work, size_t work_bytes,
+                         int32_t *dev_info, void *stream);
 
 /* Stage 1 of mmf_eigh: Householder reduction Q^H A Q = T with T real
  * symmetric tridiagonal.  On exit d[n] (dev) is the diagonal, e[n-1] (dev) the

@@ -41,7 +41,7 @@ __all__ = [
     "sites", "floquet_dim", "floquet_entry", "build_floquet", "eigh", "site_phases",
     "evolve", "evolve_expm", "micromotion_select", "micromotion", "avg_prob",
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
-    "zero_site", "tridiag_eigh",
+    "zero_site", "tridiag_eigh", "quasienergies",
 ]
 
 
@@ -192,6 +192,13 @@ def eigh(H: np.ndarray):
     paper's wrapper calls (Sec. 3.2)."""
     w, Phi = np.linalg.eigh(H)
     return w, Phi
+
+
+def quasienergies(p) -> np.ndarray:
+    """All eigenvalues (ascending) of the truncated H_F, without eigenvectors:
+    LAPACK's eigenvalue-only Hermitian solver through NumPy (the paper's
+    LAPACK_FULLEIGENVALUES call on the Floquet matrix, Sec. 4.2)."""
+    return np.linalg.eigvalsh(build_floquet(p))
 
 
 def jacobi_eigh(H: np.ndarray, sweeps: int = 30, tol: float = 1e-15):

@@ -161,6 +161,52 @@ def eigh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stre
     return ws, mats, info
 
 
+def eigvalsh_batched_workspace_bytes(sizes, prec: int = MMF_C128) -> int:
+    n = (C.c_int64 * max(len(sizes), 1))(*[int(m) for m in sizes])
+    b = C.c_size_t(0)
+    call("mmf_eigvalsh_batched_workspace", C.c_int64(len(sizes)), n, C.c_int(prec), C.byref(b))
+    return int(b.value)
+
+
+def eigvalsh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stream=None):
+    """Eigenvalues (ascending) of every Hermitian matrix of `mats` (column-
+    major like eigh's argument; destroyed for complex128, kept for
+    MMF_C64_RAW).  Returns (ws, info)."""
+    torch = _torch()
+    count = len(mats)
+    if count == 0:
+        return [], None
+    dev = mats[0].device
+    sizes = [int(A.shape[0]) for A in mats]
+    if ws is None:
+        ws = [torch.empty(m, dtype=torch.float64, device=dev) for m in sizes]
+    if work is None:
+        work = _workspace(eigvalsh_batched_workspace_bytes(sizes, prec), dev)
+    if info is None:
+        info = torch.zeros(count, dtype=torch.int32, device=dev)
+    n = (C.c_int64 * count)(*sizes)
+    ld = (C.c_int64 * count)(*[int(A.stride(0)) if m else 1 for A, m in zip(mats, sizes)])
+    Ap = (C.c_void_p * count)(*[A.data_ptr() for A in mats])
+    wp = (C.c_void_p * count)(*[w.data_ptr() for w in ws])
+    call("mmf_eigvalsh_batched", C.c_int64(count), n, Ap, ld, wp, C.c_int(prec), _ptr(work),
+         C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return ws, info
+
+
+def quasienergy_scan(problems, prec: int = MMF_C128, device="cuda", stream=None):
+    """Quasienergy spectra of many Floquet problems (e.g. a frequency scan):
+    assemble every H_F, then one grouped eigenvalue-only solve.  Returns the
+    list of eigenvalue tensors."""
+    torch = _torch()
+    import contextlib
+    ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+    with ctx:
+        dps = [p if isinstance(p, DeviceProblem) else DeviceProblem(p, device) for p in problems]
+        HFs = [build_floquet(dp, stream=stream) for dp in dps]
+        ws, info = eigvalsh_batched(HFs, prec, stream=stream)
+    return ws
+
+
 def hetrd(At, work=None, stream=None):
     """Stage 1: returns (d, e, tau); At's column i (row i of the tensor) keeps
     the reflector v_i below the diagonal."""

@@ -44,6 +44,9 @@ _SIGS = {
     "mmf_eigh_batched_workspace": (C.c_int, [C.c_int64, C.c_void_p, C.c_int, C.c_void_p]),
     "mmf_eigh_batched": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "mmf_eigvalsh_batched_workspace": (C.c_int, [C.c_int64, C.c_void_p, C.c_int, C.c_void_p]),
+    "mmf_eigvalsh_batched": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                       C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "mmf_hetrd": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_size_t, C.c_void_p]),
     "mmf_stedc": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,

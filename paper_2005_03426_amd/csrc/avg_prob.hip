@@ -67,12 +67,22 @@ avgprob_partial(int64_t M, int D, int64_t s0, const mmf_z *__restrict__ Phi, int
   }
 }
 
-__global__ void avgprob_reduce(int DD, int G, const double *__restrict__ part, double *__restrict__ P) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= DD) return;
+// P[e] = sum_g part[g][e]: one workgroup per element e; thread t sums the
+// partials g = t, t + 256, ... and a fixed tree combines the 256 sums.
+__global__ void __launch_bounds__(AP_THREADS) avgprob_reduce(int DD, int G, const double *__restrict__ part,
+                                                            double *__restrict__ P) {
+  __shared__ double red[AP_THREADS];
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x;
   double s = 0.0;
-  for (int g = 0; g < G; ++g) s += part[(int64_t)g * DD + e];
-  P[e] = s;
+  for (int g = tid; g < G; g += AP_THREADS) s += part[(int64_t)g * DD + e];
+  red[tid] = s;
+  __syncthreads();
+  for (int h = AP_THREADS / 2; h >= 1; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) P[e] = red[0];
 }
 
 inline int avgprob_groups(int64_t M) { return (int)(M < AP_MAX_WG ? M : AP_MAX_WG); }
@@ -83,7 +93,7 @@ using namespace mmf;
 
 extern "C" int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes) {
   FloqParams fp;
-  const int rc = problem_params(p, 1, &fp);
+  const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (!bytes) return -2;
   *bytes = (size_t)avgprob_groups(fp.M) * fp.D * fp.D * sizeof(double) + 256;
@@ -93,7 +103,7 @@ extern "C" int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes) {
 extern "C" int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, double *P,
                             void *work, size_t work_bytes, void *stream) {
   FloqParams fp;
-  const int rc = problem_params(p, 1, &fp);
+  const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (!Phi) return -2;
   if (ld < fp.M) return -3;
@@ -108,7 +118,7 @@ extern "C" int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, 
                      part, G);
   MMF_LAUNCH_CHECK();
   const int DD = fp.D * fp.D;
-  hipLaunchKernelGGL(avgprob_reduce, dim3(cdiv(DD, 256)), dim3(256), 0, st, DD, G, part, P);
+  hipLaunchKernelGGL(avgprob_reduce, dim3((unsigned)DD), dim3(AP_THREADS), 0, st, DD, G, part, P);
   MMF_LAUNCH_CHECK();
   return MMF_OK;
 }

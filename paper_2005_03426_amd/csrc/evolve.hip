@@ -124,7 +124,7 @@ using namespace mmf;
 
 extern "C" int mmf_evolve_workspace(const mmf_problem *p, int32_t T, size_t *bytes) {
   FloqParams fp;
-  const int rc = problem_params(p, 1, &fp);
+  const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (T < 0) return -2;
   if (!bytes) return -3;
@@ -136,7 +136,7 @@ extern "C" int mmf_evolve(const mmf_problem *p, const mmf_z *Phi, int64_t ld, co
                           double t0, int32_t T, const double *t, mmf_z *U, void *work,
                           size_t work_bytes, void *stream) {
   FloqParams fp;
-  const int rc = problem_params(p, 1, &fp);
+  const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (!Phi) return -2;
   if (ld < fp.M) return -3;
@@ -293,7 +293,7 @@ extern "C" int mmf_micromotion(const mmf_problem *p, const mmf_z *Phi, int64_t l
                                int32_t T, const double *t, mmf_z *UF, double *eps_sel, int32_t *sel,
                                void *work, size_t work_bytes, int32_t *dev_info, void *stream) {
   FloqParams fp;
-  const int rc = problem_params(p, 1, &fp);
+  const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (!Phi) return -2;
   if (ld < fp.M) return -3;

@@ -8,7 +8,8 @@ namespace mmf {
 
 constexpr int MAX_F = 8;
 constexpr int MAX_K = 64;
-constexpr int MAX_D = 64;
+constexpr int MAX_D = 64;          // bare dimension of U(t), micromotion and P (D x D register/LDS tiles)
+constexpr int MAX_D_BUILD = 4096;   // bare dimension accepted for assembly and eigensolves
 
 struct FloqParams {
   int32_t D, F, K;
@@ -25,7 +26,7 @@ struct FloqParams {
 // Validates p and fills fp.  Returns 0 or a negative argument code (-argpos).
 inline int problem_params(const mmf_problem *p, int argpos, FloqParams *fp) {
   if (!p) return -argpos;
-  if (p->D < 1 || p->D > MAX_D) return -argpos;
+  if (p->D < 1 || p->D > MAX_D_BUILD) return -argpos;
   if (p->F < 0 || p->F > MAX_F) return -argpos;
   if (p->K < 0 || p->K > MAX_K) return -argpos;
   if (p->F > 0 && (!p->omega || !p->N)) return -argpos;
@@ -56,6 +57,14 @@ inline int problem_params(const mmf_problem *p, int argpos, FloqParams *fp) {
   fp->M = S * p->D;
   if (fp->M > (int64_t)0x7fffffff) return MMF_ERR_TOO_LARGE;
   return 0;
+}
+
+// As problem_params, for the calls that keep D x D blocks on chip (U(t),
+// micromotion, P): D above MAX_D is MMF_ERR_TOO_LARGE.
+inline int problem_params_small_d(const mmf_problem *p, int argpos, FloqParams *fp) {
+  const int rc = problem_params(p, argpos, fp);
+  if (rc) return rc;
+  return fp->D > MAX_D ? MMF_ERR_TOO_LARGE : 0;
 }
 
 }  // namespace mmf

@@ -95,3 +95,49 @@ def test_batched_argument_checks_host_only():
     assert call(work=0) == -7
     assert call(nbytes=b.value - 1) == -8
     assert call(info=0) == -9
+
+
+def test_eigvalsh_batched_argument_checks_host_only():
+    import paper_2005_03426_amd as mmf
+    L = mmf.lib()
+    dummy = 16
+    n = (C.c_int64 * 2)(4, 5)
+    Ap = (C.c_void_p * 2)(dummy, dummy)
+    wp = (C.c_void_p * 2)(dummy, dummy)
+    ld = (C.c_int64 * 2)(5, 5)
+    b = C.c_size_t(0)
+    assert L.mmf_eigvalsh_batched_workspace(C.c_int64(2), n, 0, C.byref(b)) == 0 and b.value > 0
+    assert L.mmf_eigvalsh_batched_workspace(C.c_int64(2), n, 1, C.byref(b)) == -3     # refined: no
+    assert L.mmf_eigvalsh_batched_workspace(C.c_int64(2), n, 2, C.byref(b)) == 0
+    assert L.mmf_eigvalsh_batched_workspace(C.c_int64(2), n, 0, C.byref(b)) == 0
+
+    def call(count=2, A=Ap, lda=ld, prec=0, nbytes=None, info=dummy):
+        nb = b.value if nbytes is None else nbytes
+        return L.mmf_eigvalsh_batched(C.c_int64(count), n, A, lda, wp, prec, C.c_void_p(dummy),
+                                      C.c_size_t(nb), C.c_void_p(info), None)
+    assert call(count=-1) == -1
+    assert call(A=None) == -3
+    assert call(lda=(C.c_int64 * 2)(3, 5)) == -4
+    assert call(prec=1) == -6
+    assert call(nbytes=b.value - 1) == -8
+    assert call(info=0) == -9
+
+
+def test_large_bare_dimension_limits_host_only():
+    """D up to 4096 assembles and diagonalises; the D x D on-chip calls stop at 64."""
+    import paper_2005_03426_amd as mmf
+    from paper_2005_03426_amd._lib import MMFProblem
+    L = mmf.lib()
+    omega = np.array([0.5]); N = np.array([2], np.int32)
+    axis = np.array([0], np.int32); harm = np.array([1], np.int32)
+    dummy = C.c_void_p(16)
+    M = C.c_int64(0)
+    b = C.c_size_t(0)
+    big = MMFProblem(256, 1, 1, omega.ctypes.data, N.ctypes.data, axis.ctypes.data, harm.ctypes.data,
+                     dummy, dummy)
+    assert L.mmf_floquet_dim(C.byref(big), C.byref(M)) == 0 and M.value == 256 * 5
+    assert L.mmf_avg_prob_workspace(C.byref(big), C.byref(b)) == 6          # MMF_ERR_TOO_LARGE
+    assert L.mmf_evolve_workspace(C.byref(big), 4, C.byref(b)) == 6
+    huge = MMFProblem(5000, 1, 1, omega.ctypes.data, N.ctypes.data, axis.ctypes.data, harm.ctypes.data,
+                      dummy, dummy)
+    assert L.mmf_floquet_dim(C.byref(huge), C.byref(M)) == -1

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Problem", "gue", "tls_problem", "cfg1_tls", "cfg2_large", "cfg3_batch",
     "cfg3_uniform_sweep", "cfg4_precision", "cfg5_serving", "random_problem",
-    "time_grid", "floquet_dim_of",
+    "time_grid", "floquet_dim_of", "lattice_problem", "lattice_sweep",
 ]
 
 
@@ -98,6 +98,35 @@ def tls_problem(w0: float, Omega: float, w: float, N: int) -> Problem:
     E = np.diag([w0 / 2.0, -w0 / 2.0]).astype(np.complex128)
     return Problem(E=E, omega=[w], N=[N], axis=[0], harm=[1],
                    V=[(Omega / 4.0) * sx], name=f"tls_w{w}_N{N}")
+
+
+def lattice_problem(omega: float, D: int = 256, V0: float = 0.25, t: float = 0.125, V: float = 0.0625,
+                    phi: float = 0.0, N: int = 10) -> Problem:
+    """Driven 1-D lattice of Sec. 4.2 (Eq. 8): D sites (D/2 two-site cells)
+    with on-site energies (-1)^m V0 (m = 1..D), static hopping
+    t exp(i cos(2 pi m / D)) from site m+1 to site m, and a uniform hopping
+    modulation V cos(omega t + phi) on every bond.  The drive's Fourier
+    coefficient is (V/2) e^{i phi} times the bond matrix.  Defaults: the
+    figure's parameters D = 256, V0 = 0.25, t = 0.125, V = 0.0625, phi = 0,
+    truncation +-10 (Floquet dimension 5376)."""
+    m = np.arange(1, D + 1)
+    E = np.diag(((-1.0) ** m) * V0).astype(np.complex128)
+    B = np.zeros((D, D), np.complex128)
+    for k in range(1, D):                      # bond between sites k and k+1 (1-based)
+        h = t * np.exp(1j * np.cos(2.0 * np.pi * k / D))
+        E[k - 1, k] = h
+        E[k, k - 1] = np.conj(h)
+        B[k - 1, k] = 1.0
+        B[k, k - 1] = 1.0
+    Vk = (V / 2.0) * np.exp(1j * phi) * B
+    return Problem(E=E, omega=[omega], N=[N], axis=[0], harm=[1], V=[Vk],
+                   name=f"lattice_D{D}_w{omega:.4f}_N{N}")
+
+
+def lattice_sweep(count: int = 64, lo: float = 0.2, hi: float = 1.0, D: int = 256, N: int = 10):
+    """Frequency scan of the driven lattice: `count` drive frequencies
+    uniform in [lo, hi] (the quasienergy-versus-frequency plot of Sec. 4.2)."""
+    return [lattice_problem(float(w), D=D, N=N) for w in np.linspace(lo, hi, count)]
 
 
 def cfg1_tls() -> tuple[Problem, np.ndarray, float]:
