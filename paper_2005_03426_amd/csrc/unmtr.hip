@@ -1,11 +1,14 @@
 // Back-transformation Phi = Q Z of the tridiagonal eigenvectors (stage 3 of
 // the dense eigensolve, Sec. 3.2), Q = H_0 H_1 ... H_{n-2}.
 //
-// Reflectors are grouped in blocks of BT_NB; a block is applied as
+// Reflectors are grouped in blocks of BT_NB = 128; a block is applied as
 //   Q_b = H_p ... H_{p+nb-1} = I - V T V^H        (compact WY)
-// with T upper triangular from the recurrence T[k,k] = tau_k,
-// T[0:k,k] = -tau_k T[0:k,0:k] (V^H V)[0:k,k].  Blocks are applied from the
-// last to the first:  Phi[p+1:, :] -= V (T (V^H Phi[p+1:, :])).
+// with T upper triangular.  Each 64-wide half of a block gets its T_h from
+// the recurrence T[k,k] = tau_k, T[0:k,k] = -tau_k T[0:k,0:k] (V^H V)[0:k,k];
+// the halves are joined by T_12 = -T_1 (V_1^H V_2) T_2 (the product of two
+// compact-WY factors).  Blocks are applied from the last to the first:
+//   Phi[p+1:, :] -= V (T (V^H Phi[p+1:, :])),
+// a rank-128 update, which keeps the update GEMM near the matrix-core rate.
 // The reflectors are first copied into clean dense blocks (explicit unit and
 // zeros), which also lets Phi overwrite the matrix that held them.  V^H Phi
 // and V^H V are long-K contractions, computed split-K on the matrix cores
@@ -96,15 +99,17 @@ __global__ void bt_pack(const BtProb<R> *pr) {
   }
 }
 
-// Split-K slices of W1 = Vb^H Phi[p+1:, :] for block b: slice z = blockIdx.x
-// covers rows [z*BT_KCHUNK, ...) of the block; result to Wpart + z*NB*n.
+// Split-K slices of W1 = Vb^H Phi[p+1:, :] for block b: blockIdx.x = slice z
+// times the two 64-row tiles of W1; slice z covers rows [z*BT_KCHUNK, ...) of
+// the block; result to Wpart + z*NB*n.
 template <typename R>
 __global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, int64_t b) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const BtProb<R> &P = pr[blockIdx.z];
   if (b >= P.nblk) return;
   const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
-  const int64_t z = blockIdx.x;
+  const int64_t z = blockIdx.x / (BT_NB / GT_M);              // slice
+  const int64_t m0 = (blockIdx.x % (BT_NB / GT_M)) * GT_M;     // row tile of W1
   const int64_t k0 = z * BT_KCHUNK;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   if (k0 >= mb || n0 >= n) return;
@@ -112,49 +117,62 @@ __global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, i
   // A_C: op(A)[m,k] = conj(A[k + m lda]);  B_N: op(B)[k,n] = B[k + n ldb]
   GemmArgs s = gemm_args(BT_NB, n, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb,
                          P.Phi + (p + 1) + k0, P.ldphi, P.Wpart + z * BT_NB * n, BT_NB, 1.0, 0.0, 0.0, 0.0);
-  gemm_tile_t<R, true, A_C, B_N>(s, 0, n0, lds);
+  gemm_tile_t<R, true, A_C, B_N>(s, m0, n0, lds);
 }
 
-// Gram partials of every block at once: Gpart[b][z] = Vb^H Vb over slice z.
+// Gram partials of every block at once: Gpart[b][z] = Vb^H Vb over slice z
+// (BT_NB x BT_NB, four 64 x 64 tiles: blockIdx.x = 4 b + tile).
 template <typename R>
 __global__ void __launch_bounds__(GEMM_THREADS) bt_gram(const BtProb<R> *pr) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const BtProb<R> &P = pr[blockIdx.z];
-  const int64_t b = blockIdx.x;
+  const int64_t b = blockIdx.x >> 2;
+  const int tile = blockIdx.x & 3;
   const int64_t z = blockIdx.y;
-  if (b >= P.nblk) return;
+  if (b >= P.nblk || tile == 1) return;           // the lower-left block V_2^H V_1 is not needed
   const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
   const int64_t k0 = z * BT_KCHUNK;
   if (k0 >= mb) return;
   const cx<R> *Vb = P.Vp + bt_off(n, b);
   GemmArgs s = gemm_args(BT_NB, BT_NB, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb, Vb + k0,
                          mb, P.Gpart + (b * P.nsplit + z) * BT_NB * BT_NB, BT_NB, 1.0, 0.0, 0.0, 0.0);
-  gemm_tile_t<R, true, A_C, B_N>(s, 0, 0, lds);
+  gemm_tile_t<R, true, A_C, B_N>(s, (int64_t)(tile & 1) * GT_M, (int64_t)(tile >> 1) * GT_N, lds);
 }
 
-// T of block b from its Gram matrix (one wavefront; thread = row of T).
+// Summed Gram element G[r, c] of block b (over its split-K slices).
+template <typename R>
+__device__ inline cx<R> bt_gram_at(const BtProb<R> &P, int64_t b, int64_t ns, int r, int c) {
+  cx<R> s = cmk<R>(0, 0);
+  for (int64_t z = 0; z < ns; ++z) s = cadd(s, P.Gpart[(b * P.nsplit + z) * BT_NB * BT_NB + r + c * BT_NB]);
+  return s;
+}
+
+// T of one 64-wide half h of block b (blockIdx.x = 2 b + h) from the diagonal
+// block of its Gram matrix (one wavefront; thread = row of T).
 template <typename R>
 __global__ void __launch_bounds__(64) bt_tmat(const BtProb<R> *pr) {
-  __shared__ cx<R> G[BT_NB][BT_NB];
-  __shared__ cx<R> T[BT_NB][BT_NB];
+  constexpr int H = BT_NB / 2;
+  __shared__ cx<R> G[H][H];
+  __shared__ cx<R> T[H][H];
   const BtProb<R> &P = pr[blockIdx.z];
-  const int64_t b = blockIdx.x;
+  const int64_t b = blockIdx.x >> 1;
+  const int h = blockIdx.x & 1;
   if (b >= P.nblk) return;
-  const int64_t n = P.n, nsplit = P.nsplit;
+  const int64_t n = P.n;
   const int64_t p = b * BT_NB;
   const int64_t mb = n - p - 1;
   const int kb = (int)((n - 1 - p < BT_NB) ? n - 1 - p : BT_NB);
+  int kh = kb - h * H;
+  kh = kh < 0 ? 0 : (kh > H ? H : kh);
   const int r = threadIdx.x;
   const int64_t ns = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
-  for (int c = 0; c < BT_NB; ++c) {
-    cx<R> s = cmk<R>(0, 0);
-    for (int64_t z = 0; z < ns; ++z) s = cadd(s, P.Gpart[(b * nsplit + z) * BT_NB * BT_NB + r + c * BT_NB]);
-    G[r][c] = s;
+  for (int c = 0; c < H; ++c) {
+    G[r][c] = bt_gram_at(P, b, ns, h * H + r, h * H + c);
     T[r][c] = cmk<R>(0, 0);
   }
   __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    const cx<R> tk = P.tau[p + k];
+  for (int k = 0; k < kh; ++k) {
+    const cx<R> tk = P.tau[p + h * H + k];
     // T[r,k] = -tau_k sum_{j<k} T[r,j] G[j,k]   (r < k)
     cx<R> s = cmk<R>(0, 0);
     if (r < k)
@@ -164,12 +182,42 @@ __global__ void __launch_bounds__(64) bt_tmat(const BtProb<R> *pr) {
     if (r == k) T[r][k] = tk;
     __syncthreads();
   }
-  for (int c = 0; c < BT_NB; ++c) P.Tm[b * BT_NB * BT_NB + r + c * BT_NB] = T[r][c];
+  cx<R> *Tb = P.Tm + b * BT_NB * BT_NB;
+  for (int c = 0; c < H; ++c) Tb[(h * H + r) + (h * H + c) * BT_NB] = T[r][c];
+  if (h == 0)
+    for (int c = 0; c < H; ++c) Tb[(H + r) + c * BT_NB] = cmk<R>(0, 0);     // lower-left block
 }
 
-// W2[:, c] = T_b (sum_z Wpart[z][:, c]) for every column c (one wavefront per column).
+// T_12 = -T_1 (V_1^H V_2) T_2 of block b (after bt_tmat): X = G_12 T_2 in
+// LDS (thread = element of X), then T_12 = -T_1 X.
 template <typename R>
-__global__ void __launch_bounds__(64) bt_reduce_t(const BtProb<R> *pr, int64_t b) {
+__global__ void __launch_bounds__(256) bt_tcross(const BtProb<R> *pr) {
+  constexpr int H = BT_NB / 2;
+  __shared__ cx<R> X[H][H + 1];
+  const BtProb<R> &P = pr[blockIdx.z];
+  const int64_t b = blockIdx.x;
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
+  const int64_t ns = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
+  cx<R> *Tb = P.Tm + b * BT_NB * BT_NB;
+  for (int e = threadIdx.x; e < H * H; e += 256) {
+    const int i = e % H, j = e / H;
+    cx<R> s = cmk<R>(0, 0);
+    for (int k = 0; k <= j; ++k) s = cadd(s, cmul(bt_gram_at(P, b, ns, i, H + k), Tb[(H + k) + (H + j) * BT_NB]));
+    X[i][j] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < H * H; e += 256) {
+    const int i = e % H, j = e / H;
+    cx<R> s = cmk<R>(0, 0);
+    for (int k = i; k < H; ++k) s = cadd(s, cmul(Tb[i + k * BT_NB], X[k][j]));
+    Tb[i + (H + j) * BT_NB] = cscale(s, R(-1));
+  }
+}
+
+// W2[:, c] = T_b (sum_z Wpart[z][:, c]) for every column c (BT_NB threads per column).
+template <typename R>
+__global__ void __launch_bounds__(BT_NB) bt_reduce_t(const BtProb<R> *pr, int64_t b) {
   __shared__ cx<R> w1[BT_NB];
   const BtProb<R> &P = pr[blockIdx.z];
   const int64_t c = blockIdx.x;
@@ -235,9 +283,12 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
     hipLaunchKernelGGL(bt_pack<R>, dim3(cdiv(nmax - 1, 256), (unsigned)nblk, Z), dim3(256), 0, st, pr);
     MMF_LAUNCH_CHECK();
     // 2. T factors
-    hipLaunchKernelGGL(bt_gram<R>, dim3((unsigned)nblk, (unsigned)nsplit, Z), dim3(GEMM_THREADS), 0, st, pr);
+    hipLaunchKernelGGL(bt_gram<R>, dim3((unsigned)(4 * nblk), (unsigned)nsplit, Z), dim3(GEMM_THREADS), 0, st,
+                       pr);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_tmat<R>, dim3((unsigned)nblk, 1, Z), dim3(64), 0, st, pr);
+    hipLaunchKernelGGL(bt_tmat<R>, dim3((unsigned)(2 * nblk), 1, Z), dim3(BT_NB / 2), 0, st, pr);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bt_tcross<R>, dim3((unsigned)nblk, 1, Z), dim3(256), 0, st, pr);
     MMF_LAUNCH_CHECK();
   }
   // 3. Phi = Z (complex)
@@ -247,9 +298,10 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t mb = nmax - b * BT_NB - 1;
     const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
-    hipLaunchKernelGGL(bt_splitk<R>, dim3((unsigned)nsl, cdiv(nmax, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr, b);
+    hipLaunchKernelGGL(bt_splitk<R>, dim3((unsigned)(nsl * (BT_NB / GT_M)), cdiv(nmax, GT_N), Z),
+                       dim3(GEMM_THREADS), 0, st, pr, b);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)nmax, 1, Z), dim3(64), 0, st, pr, b);
+    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)nmax, 1, Z), dim3(BT_NB), 0, st, pr, b);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(bt_update<R>, dim3(cdiv(mb, GT_M), cdiv(nmax, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr,
                        b);

@@ -186,7 +186,7 @@ def test_hetrd_defining_identity(n):
     assert np.abs(Q @ T @ Q.conj().T - A).max() < 1e-13 * scale * max(1, n / 10)
 
 
-@pytest.mark.parametrize("n", [2, 5, 64, 65, 130, 300])
+@pytest.mark.parametrize("n", [2, 5, 64, 65, 129, 130, 200, 257, 300])
 def test_unmtr_against_oracle_reflectors(n):
     torch, mmf = require_gpu()
     rng = np.random.default_rng(7 + n)
