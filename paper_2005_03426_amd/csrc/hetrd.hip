@@ -413,7 +413,21 @@ __global__ void __launch_bounds__(256) ht_finish_u(const HtProb<R> *pr, int64_t 
   const bool live = rho > i && rho < n;
   C u = cmk<R>(0, 0);
   if (live) {
-    for (int64_t lb = wave; lb <= lbi; lb += 4) u = cadd(u, pdir[lb * mpad + lbi * HV_T + lane]);
+    {
+      // direct partials of block columns wave, wave + 4, ...: four independent
+      // accumulators keep four loads in flight, combined in fixed order
+      const C *pc = pdir + lbi * HV_T + lane;
+      C u0 = cmk<R>(0, 0), u1 = u0, u2 = u0, u3 = u0;
+      int64_t lb = wave;
+      for (; lb + 12 <= lbi; lb += 16) {
+        u0 = cadd(u0, pc[lb * mpad]);
+        u1 = cadd(u1, pc[(lb + 4) * mpad]);
+        u2 = cadd(u2, pc[(lb + 8) * mpad]);
+        u3 = cadd(u3, pc[(lb + 12) * mpad]);
+      }
+      for (; lb <= lbi; lb += 4) u0 = cadd(u0, pc[lb * mpad]);
+      u = cadd(cadd(u0, u1), cadd(u2, u3));
+    }
     const int64_t inner = nfull - (b0 + lbi) - 1;   // interior tiles below this block's diagonal
     const int64_t nslot = 1 + (inner > 0 ? (inner + HV_CH - 1) / HV_CH : 0);
     for (int64_t c = wave; c < nslot; c += 4) u = cadd(u, ptrn[(lbi * nchmax + c) * HV_T + lane]);

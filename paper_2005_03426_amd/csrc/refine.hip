@@ -19,7 +19,9 @@
 // so that every first-order correction outside a cluster is below 1/CL_FACTOR:
 // from complex64 eigenvectors (error ~ eps32 ||A|| / gap) a pair closer than
 // that cannot be separated by the first-order step and is rotated inside its
-// cluster instead; the threshold collapses after the first iteration.
+// cluster instead; the threshold shrinks with the residual (on dense
+// quasienergy spectra, where many gaps are below it at first, this takes a
+// few iterations).
 // All products are FP64 complex GEMMs on the matrix cores; A X is clipped to
 // the bandwidth of A, detected on the device (the Floquet matrix is banded).
 #include <float.h>
@@ -34,6 +36,13 @@ constexpr int REF_ITERS = 6;      // upper bound; converged iterations are skipp
 constexpr double CONV_TOL = 1e-13; // stop once max |s_ij - lam_j g_ij| <= CONV_TOL max(1, max|lam|)
 constexpr double CL_FACTOR = 100.0;
 constexpr int CL_MAX = 32;          // clusters are split into chunks of at most CL_MAX
+// Predictive stop: once the corrections are small (off-cluster max |e_ij|
+// <= REF_QUAD, second-order regime), the next measured residual is about
+// ms * max|e_ij|; when REF_SAFETY times that is already below the
+// convergence bound the next iteration (whose only effect would be to
+// confirm convergence) is skipped.
+constexpr double REF_QUAD = 1e-3;
+constexpr double REF_SAFETY = 100.0;
 
 // ---------------------------------------------------------------- conversions
 __global__ void rf_to_c64(int64_t n, const cd *A, int64_t lda, cf *Ac, int64_t ldc) {
@@ -85,6 +94,33 @@ __global__ void rf_zero_int(int32_t *p) { if (threadIdx.x == 0) *p = 0; }
 // skip <- stop_next at the start of an iteration (both flags live on the device)
 __global__ void rf_latch(int32_t *skip, const int32_t *stop_next) { if (threadIdx.x == 0) *skip = *stop_next; }
 
+// S and G are computed on their lower triangle only (Hermitian products);
+// the upper triangle is filled with the conjugates and the diagonal made real.
+__global__ void rf_mirror(int64_t n, cd *S, cd *G, const int32_t *skip) {
+  if (*skip) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= n || r > c) return;
+  if (r == c) {
+    S[r + c * n].im = 0.0;
+    G[r + c * n].im = 0.0;
+  } else {
+    S[r + c * n] = cconj(S[c + r * n]);
+    G[r + c * n] = cconj(G[c + r * n]);
+  }
+}
+
+__global__ void rf_zero_u64(unsigned long long *p) { if (threadIdx.x == 0) *p = 0ull; }
+
+// stop_next <- 1 when the predicted next residual is converged (msml: this
+// iteration's max |s_ij - lam_j g_ij| and max(1, max |lam|)).
+__global__ void rf_predict(const unsigned long long *emax_bits, const double *msml, int32_t *stop_next,
+                           const int32_t *skip) {
+  if (threadIdx.x != 0 || *skip) return;
+  const double e = __longlong_as_double((long long)*emax_bits);
+  if (e <= REF_QUAD && REF_SAFETY * msml[0] * e <= CONV_TOL * msml[1]) *stop_next = 1;
+}
+
 // ---------------------------------------------------------------- per-iteration scalars
 // lam_j = Re s_jj / Re g_jj and, per column, max_{i != j} |s_ij - lam_j g_ij|
 // (the numerator of the first-order correction).
@@ -112,8 +148,8 @@ __global__ void __launch_bounds__(256) rf_lambda(int64_t n, const cd *S, const c
 // Cluster scan (one thread): cid[i] = first index of i's cluster chunk;
 // clist holds (start, size) of every chunk with size >= 2; ncl its count.
 __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, int32_t *cid,
-                            int32_t *clist, int32_t *ncl, double *delta_out, const int32_t *skip,
-                            int32_t *stop_next) {
+                            int32_t *clist, int32_t *ncl, double *delta_out, double *msml,
+                            const int32_t *skip, int32_t *stop_next) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || *skip) return;
   double ms = 0.0, ml = 1.0;
   for (int64_t j = 0; j < n; ++j) {
@@ -121,6 +157,8 @@ __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, 
     ml = fmax(ml, fabs(lam[j]));
   }
   if (ms <= CONV_TOL * ml) *stop_next = 1;     // this iteration's update is the last one
+  msml[0] = ms;
+  msml[1] = ml;
   const double delta = CL_FACTOR * ms;
   *delta_out = delta;
   int32_t nc = 0;
@@ -140,25 +178,38 @@ __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, 
   *ncl = nc;
 }
 
-// F = I + E, written over S.
-__global__ void rf_build_f(int64_t n, cd *S, const cd *G, const double *lam, const int32_t *cid,
-                           const int32_t *skip) {
+// F = I + E, written over S; emax_bits collects max |e_ij| outside clusters
+// (non-negative doubles order like their bit patterns).
+__global__ void __launch_bounds__(256) rf_build_f(int64_t n, cd *S, const cd *G, const double *lam,
+                                                 const int32_t *cid, unsigned long long *emax_bits,
+                                                 const int32_t *skip) {
+  __shared__ double sh[4];
   if (*skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
-  if (i >= n) return;
-  const cd s = S[i + j * n], g = G[i + j * n];
-  cd f;
-  if (i == j) {
-    f = cmake(1.0 + 0.5 * (1.0 - g.re), 0.0);
-  } else if (cid[i] == cid[j]) {
-    f = cscale(g, -0.5);                         // r_ij / 2
-  } else {
-    const double den = lam[j] - lam[i];
-    // (s_ij + lam_j r_ij) / (lam_j - lam_i), r_ij = -g_ij
-    f = cscale(csub(s, cscale(g, lam[j])), 1.0 / den);
+  double e = 0.0;
+  if (i < n) {
+    const cd s = S[i + j * n], g = G[i + j * n];
+    cd f;
+    if (i == j) {
+      f = cmake(1.0 + 0.5 * (1.0 - g.re), 0.0);
+    } else if (cid[i] == cid[j]) {
+      f = cscale(g, -0.5);                         // r_ij / 2
+    } else {
+      const double den = lam[j] - lam[i];
+      // (s_ij + lam_j r_ij) / (lam_j - lam_i), r_ij = -g_ij
+      f = cscale(csub(s, cscale(g, lam[j])), 1.0 / den);
+      e = sqrt(cabs2(f));
+    }
+    S[i + j * n] = f;
   }
-  S[i + j * n] = f;
+  e = wave_max(e);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    e = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    atomicMax(emax_bits, (unsigned long long)__double_as_longlong(e));
+  }
 }
 
 // Cluster blocks: T = S_CC - (R S + S R)/2 with R = I - G (first order),
@@ -325,6 +376,8 @@ struct RefWs {
   cd *X, *B1, *B2;
   double *lam, *colmax, *delta;
   int32_t *cid, *clist, *ncl, *band, *dest, *skip, *stop;
+  unsigned long long *emax;
+  double *msml;
   cd *Qbuf;
   size_t bytes;
 };
@@ -360,6 +413,8 @@ inline RefWs ref_ws(int64_t M, bool refine, void *base) {
   w.dest = cv.take<int32_t>(n);
   w.skip = cv.take<int32_t>(1);
   w.stop = cv.take<int32_t>(1);
+  w.emax = cv.take<unsigned long long>(1);
+  w.msml = cv.take<double>(2);
   w.Qbuf = cv.take<cd>((n / 2 + 1) * CL_MAX * CL_MAX);
   w.bytes = cv.used();
   return w;
@@ -404,20 +459,24 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     ga.skip = ws.skip;
     rc = gemm_launch<true, A_N, B_N>(ga, st);
     if (rc) return rc;
-    // B2 = S = X^H (A X);  Xo = G = X^H X
+    // B2 = S = X^H (A X);  Xo = G = X^H X  (Hermitian: lower triangles, then mirrored)
     GemmArgs gs = gemm_args(n, n, n, X, n, Xo, n, B2, n, 1.0, 0.0, 0.0, 0.0);
     gs.skip = ws.skip;
+    gs.lower = 1;
     rc = gemm_launch<true, A_C, B_N>(gs, st);
     if (rc) return rc;
     GemmArgs gg = gemm_args(n, n, n, X, n, X, n, Xo, n, 1.0, 0.0, 0.0, 0.0);
     gg.skip = ws.skip;
+    gg.lower = 1;
     rc = gemm_launch<true, A_C, B_N>(gg, st);
     if (rc) return rc;
     cd *S = B2, *G = Xo;
+    hipLaunchKernelGGL(rf_mirror, g2, dim3(256), 0, st, n, S, G, ws.skip);
+    MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, S, G, ws.lam, ws.colmax, ws.skip);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_clusters, dim3(1), dim3(64), 0, st, n, ws.lam, ws.colmax, ws.cid, ws.clist,
-                       ws.ncl, ws.delta, ws.skip, ws.stop);
+                       ws.ncl, ws.delta, ws.msml, ws.skip, ws.stop);
     MMF_LAUNCH_CHECK();
     const unsigned maxcl = (unsigned)(n / 2 + 1);
     hipLaunchKernelGGL(rf_cluster_rr, dim3(maxcl), dim3(64), 0, st, n, S, G, ws.clist, ws.ncl, ws.Qbuf,
@@ -440,7 +499,11 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, S, G, ws.lam, ws.colmax, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_build_f, g2, dim3(256), 0, st, n, S, G, ws.lam, ws.cid, ws.skip);
+    hipLaunchKernelGGL(rf_zero_u64, dim3(1), dim3(64), 0, st, ws.emax);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_build_f, g2, dim3(256), 0, st, n, S, G, ws.lam, ws.cid, ws.emax, ws.skip);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rf_predict, dim3(1), dim3(64), 0, st, ws.emax, ws.msml, ws.stop, ws.skip);
     MMF_LAUNCH_CHECK();
     // Xo = X F  (G in Xo is no longer needed); a skipped iteration copies X into Xo
     GemmArgs gf = gemm_args(n, n, n, X, n, S, n, Xo, n, 1.0, 0.0, 0.0, 0.0);
