@@ -203,6 +203,18 @@ int mmf_micromotion(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const do
                     int32_t T, const double *t, mmf_z *UF, double *eps_sel, int32_t *sel,
                     void *work, size_t work_bytes, int32_t *dev_info, void *stream);
 
+/* Evolution in a dressed basis (Sec. 4.1: the basis of a subset of the modes,
+ * Eq. 4 with that subset's micromotion operator):
+ *   Ud[q] = UF2[q]^H  U[q]  UF1,   q = 0 .. T-1,
+ * UF2: dev [T][D*D] micromotion operator of the dressing subset at the times
+ *      t_q (mmf_micromotion of the subset problem, same layout);
+ * U:   dev [T][D*D] bare evolution U(t_q, t1) of the full problem (mmf_evolve);
+ * UF1: dev [D*D]    micromotion operator of the dressing subset at t1;
+ * Ud:  dev [T][D*D] output (Ud[q*D*D + i + D*j], i final, j initial dressed state).
+ * Errors: -1 D outside [1, 64], -2 T < 0, -3..-6 a NULL pointer, MMF_ERR_HIP. */
+int mmf_dressed_evolution(int32_t D, int32_t T, const mmf_z *UF2, const mmf_z *U,
+                          const mmf_z *UF1, mmf_z *Ud, void *stream);
+
 /* Workspace bytes for mmf_avg_prob. */
 int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes);
 

@@ -41,7 +41,7 @@ __all__ = [
     "sites", "floquet_dim", "floquet_entry", "build_floquet", "eigh", "site_phases",
     "evolve", "evolve_expm", "micromotion_select", "micromotion", "avg_prob",
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
-    "zero_site", "tridiag_eigh", "quasienergies",
+    "zero_site", "tridiag_eigh", "quasienergies", "restrict_modes", "dressed_evolution",
 ]
 
 
@@ -349,6 +349,55 @@ def micromotion(p, Phi: np.ndarray, eps: np.ndarray, ts):
     for q, t in enumerate(ts):
         UF[q] = np.einsum("s,sib->ib", site_phases(p, t), Phi3)
     return UF, eps[sel].copy()
+
+
+# ---------------------------------------------------------------------------
+# Evolution in a dressed basis (Sec. 4.1, DRESSEDBASIS_SUBSET + Eq. 4)
+# ---------------------------------------------------------------------------
+class _Restricted:
+    pass
+
+
+def restrict_modes(p, axes):
+    """The problem with only the fundamentals in `axes` kept (in that order):
+    the static Hamiltonian plus the couplings oscillating on those axes (the
+    paper's subset of dressing modes, which always includes the static mode)."""
+    q = _Restricted()
+    q.E = np.asarray(p.E, dtype=np.complex128)
+    q.D = q.E.shape[0]
+    new_index = {int(a): i for i, a in enumerate(axes)}
+    q.omega = [float(p.omega[int(a)]) for a in axes]
+    q.N = [int(p.N[int(a)]) for a in axes]
+    q.axis, q.harm, q.V = [], [], []
+    for k in range(len(p.axis)):
+        a = int(p.axis[k])
+        if a in new_index:
+            q.axis.append(new_index[a])
+            q.harm.append(int(p.harm[k]))
+            q.V.append(np.asarray(p.V[k], dtype=np.complex128))
+    q.F = len(q.omega)
+    q.K = len(q.axis)
+    return q
+
+
+def dressed_evolution(p, axes, ts, t0: float):
+    """U_dressed(t, t0) = U_F^sub(t)^H U(t, t0) U_F^sub(t0): the bare evolution
+    of the full problem (Shirley form over all its eigenpairs) seen in the
+    dressed basis of the subset `axes` (micromotion operator of the subset's
+    Floquet problem, one representative per orbit).  Returns
+    (Ud[tau, i, j], U[tau, i, j], eps_dressed)."""
+    sub = restrict_modes(p, axes)
+    Hs = build_floquet(sub)
+    ws, Phis = eigh(Hs)
+    ts = np.atleast_1d(np.asarray(ts, dtype=np.float64))
+    UF, eps_d = micromotion(sub, Phis, ws, np.concatenate([ts, [t0]]))
+    H = build_floquet(p)
+    w, Phi = eigh(H)
+    U = evolve(p, Phi, w, t0, ts)
+    Ud = np.zeros_like(U)
+    for q in range(len(ts)):
+        Ud[q] = UF[q].conj().T @ U[q] @ UF[-1]
+    return Ud, U, eps_d
 
 
 # ---------------------------------------------------------------------------

@@ -289,6 +289,58 @@ def micromotion(dp: DeviceProblem, Pt, w, t, work=None, stream=None):
     return UF.transpose(1, 2), eps, sel, info
 
 
+class _ModeSubset:
+    """The problem restricted to the fundamentals `axes` (static part plus
+    the couplings on those axes), axes renumbered in the given order."""
+
+    def __init__(self, problem, axes):
+        axes = [int(a) for a in axes]
+        pos = {a: i for i, a in enumerate(axes)}
+        keep = [k for k in range(len(problem.axis)) if int(problem.axis[k]) in pos]
+        self.E = problem.E
+        self.omega = [problem.omega[a] for a in axes]
+        self.N = [problem.N[a] for a in axes]
+        self.axis = [pos[int(problem.axis[k])] for k in keep]
+        self.harm = [problem.harm[k] for k in keep]
+        V = np.asarray(problem.V)
+        self.V = V[keep] if len(keep) else np.zeros((0,) + np.asarray(problem.E).shape, np.complex128)
+
+
+def dressed_evolution(problem, dressing_axes, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda",
+                      stream=None):
+    """Evolution of the full problem in the dressed basis of a subset of its
+    modes (the static Hamiltonian plus the drives on `dressing_axes`):
+    U_dressed(t, t0) = U_F^sub(t)^H U(t, t0) U_F^sub(t0).  Returns a dict with
+    'U_dressed' and 'U_bare' [T, D, D] (final, initial), the subset's
+    micromotion operators 'UF' [T, D, D] and dressed energies 'eps_dressed'."""
+    torch = _torch()
+    import contextlib
+    ctx = torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+    with ctx:
+        full = DeviceProblem(problem, device)          # problem: a host problem statement
+        sub = DeviceProblem(_ModeSubset(problem, dressing_axes), device)
+        dev = full.device
+        tt = t if torch.is_tensor(t) else torch.as_tensor(np.asarray(t, dtype=np.float64), device=dev)
+        T = int(tt.shape[0])
+        # subset: eigenpairs, then U_F at the times t and at t0 (one call, t0 last)
+        Hs = build_floquet(sub, stream=stream)
+        ws, Ps, _ = eigh(Hs, prec, stream=stream)
+        tt1 = torch.cat([tt, torch.full((1,), float(t0), dtype=torch.float64, device=dev)])
+        UF, eps, sel, minfo = micromotion(sub, Ps, ws, tt1, stream=stream)
+        # full problem: U(t, t0)
+        Hf = build_floquet(full, stream=stream)
+        wf, Pf, info = eigh(Hf, prec, stream=stream)
+        U = evolve(full, Pf, wf, t0, tt, stream=stream)
+        D = full.D
+        UFs = UF.transpose(1, 2)                 # storage [T+1][b][i] = column-major per time
+        Us = U.transpose(1, 2)
+        Ud = torch.empty((T, D, D), dtype=torch.complex128, device=dev)
+        call("mmf_dressed_evolution", C.c_int32(D), C.c_int32(T), _ptr(UFs), _ptr(Us), _ptr(UFs[T]),
+             _ptr(Ud), _stream(stream))
+    return {"U_dressed": Ud.transpose(1, 2), "U_bare": U, "UF": UF[:T], "eps_dressed": eps,
+            "info": info, "selection_info": minfo}
+
+
 def avg_prob(dp: DeviceProblem, Pt, work=None, stream=None):
     """Averaged transition probabilities P[i, j] (i final, j initial)."""
     torch = _torch()

@@ -59,6 +59,8 @@ _SIGS = {
     "mmf_micromotion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_size_t, C.c_void_p, C.c_void_p]),
+    "mmf_dressed_evolution": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]),
     "mmf_avg_prob_workspace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mmf_avg_prob": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p]),

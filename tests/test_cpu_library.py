@@ -141,3 +141,17 @@ def test_large_bare_dimension_limits_host_only():
     huge = MMFProblem(5000, 1, 1, omega.ctypes.data, N.ctypes.data, axis.ctypes.data, harm.ctypes.data,
                       dummy, dummy)
     assert L.mmf_floquet_dim(C.byref(huge), C.byref(M)) == -1
+
+
+def test_dressed_evolution_argument_checks_host_only():
+    import paper_2005_03426_amd as mmf
+    L = mmf.lib()
+    d = C.c_void_p(16)
+    assert L.mmf_dressed_evolution(0, 4, d, d, d, d, None) == -1
+    assert L.mmf_dressed_evolution(65, 4, d, d, d, d, None) == -1
+    assert L.mmf_dressed_evolution(2, -1, d, d, d, d, None) == -2
+    assert L.mmf_dressed_evolution(2, 0, None, None, None, None, None) == 0     # nothing to do
+    assert L.mmf_dressed_evolution(2, 4, None, d, d, d, None) == -3
+    assert L.mmf_dressed_evolution(2, 4, d, None, d, d, None) == -4
+    assert L.mmf_dressed_evolution(2, 4, d, d, None, d, None) == -5
+    assert L.mmf_dressed_evolution(2, 4, d, d, d, None, None) == -6

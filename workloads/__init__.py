@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Problem", "gue", "tls_problem", "cfg1_tls", "cfg2_large", "cfg3_batch",
     "cfg3_uniform_sweep", "cfg4_precision", "cfg5_serving", "random_problem",
-    "time_grid", "floquet_dim_of", "lattice_problem", "lattice_sweep",
+    "time_grid", "floquet_dim_of", "lattice_problem", "lattice_sweep", "dressed_qubit",
 ]
 
 
@@ -98,6 +98,21 @@ def tls_problem(w0: float, Omega: float, w: float, N: int) -> Problem:
     E = np.diag([w0 / 2.0, -w0 / 2.0]).astype(np.complex128)
     return Problem(E=E, omega=[w], N=[N], axis=[0], harm=[1],
                    V=[(Omega / 4.0) * sx], name=f"tls_w{w}_N{N}")
+
+
+def dressed_qubit(omega_P: float, Omega_X: float = 0.025, omega_D: float = 1.0, Omega_Px: float = 0.005,
+                  Omega_Pz: float = 0.025, omega0: float = 1.0, N=(4, 12)) -> Problem:
+    """Bichromatically driven qubit of Sec. 4.1 (Eq. 8, S = sigma / 2, all
+    phases zero): H = omega0 S_z + Omega_X cos(omega_D t) S_x
+    + cos(omega_P t) (Omega_Px S_x + Omega_Pz S_z).  Fundamental 0 is the
+    dressing drive (omega_D), fundamental 1 the probe (omega_P); truncations
+    N = (N_D, N_P).  Defaults: the figure's parameters (Omega_X = 0.025,
+    resonant dressing omega_D = omega0 = 1, Omega_Px = 0.005, Omega_Pz = 0.025)."""
+    Sx = 0.5 * np.array([[0, 1], [1, 0]], np.complex128)
+    Sz = 0.5 * np.array([[1, 0], [0, -1]], np.complex128)
+    return Problem(E=omega0 * Sz, omega=[omega_D, omega_P], N=list(N), axis=[0, 1], harm=[1, 1],
+                   V=[(Omega_X / 2.0) * Sx, (Omega_Px / 2.0) * Sx + (Omega_Pz / 2.0) * Sz],
+                   name=f"dressed_qubit_wP{omega_P:.5f}")
 
 
 def lattice_problem(omega: float, D: int = 256, V0: float = 0.25, t: float = 0.125, V: float = 0.0625,
