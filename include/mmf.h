@@ -139,6 +139,26 @@ int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int
                      double *const *w, int prec, void *work, size_t work_bytes,
                      int32_t *dev_info, void *stream);
 
+/* Workspace bytes of mmf_eigh_window for order M and at most kmax vectors. */
+int mmf_eigh_window_workspace(int64_t M, int64_t kmax, size_t *bytes);
+
+/* Partial spectrum (Sec. 3.2 restricted to a quasienergy window, the role of
+ * the paper's sparse partial-spectrum path): the eigenvalues of the Hermitian
+ * A in [vl, vu) and their eigenvectors.  Reduction and divide and conquer run
+ * as in mmf_eigh; only the window's k columns are back-transformed (8 M^2 k
+ * instead of 8 M^3 real flops).  For a single-drive Floquet matrix the window
+ * [-w/2, w/2) holds one state per Fourier orbit (the Floquet states).
+ * A: dev M x M (lda), lower triangle read, destroyed (reflectors).
+ * w: dev [kmax] ascending eigenvalues of the window; Z: dev M x kmax (ldz),
+ * column t the eigenvector of w[t]; count: dev int32, the number k of
+ * eigenvalues in the window (only min(k, kmax) are returned; columns beyond
+ * that are zero).  dev_info as for mmf_eigh.
+ * Errors: -1 M < 0, -2 A NULL, -3 lda, -4 not vl < vu, -6 kmax < 0, -7 w NULL,
+ *   -8 Z NULL, -9 ldz < M, -10 count NULL, -11/-12 workspace, -13 dev_info NULL. */
+int mmf_eigh_window(int64_t M, mmf_z *A, int64_t lda, double vl, double vu, int64_t kmax,
+                    double *w, mmf_z *Z, int64_t ldz, int32_t *count, void *work,
+                    size_t work_bytes, int32_t *dev_info, void *stream);
+
 /* Workspace bytes that mmf_eigvalsh_batched needs (count, n as for
  * mmf_eigh_batched_workspace; prec MMF_C128 or MMF_C64_RAW).
  * Errors: -1 count < 0, -2 n NULL or an n[c] < 0, -3 prec unsupported, -4 bytes NULL. */

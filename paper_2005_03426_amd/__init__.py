@@ -161,6 +161,29 @@ def eigh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stre
     return ws, mats, info
 
 
+def eigh_window(At, vl: float, vu: float, kmax: int, work=None, stream=None):
+    """Eigenpairs of the Hermitian matrix in At (column-major, destroyed)
+    with eigenvalue in [vl, vu).  Returns (w, Zt, count, info): w[:k] and the
+    rows Zt[:k] (row t = eigenvector of w[t]) are valid for
+    k = min(count, kmax)."""
+    torch = _torch()
+    M = At.shape[0]
+    dev = At.device
+    kmax = int(min(kmax, M))
+    w = torch.zeros(max(kmax, 1), dtype=torch.float64, device=dev)
+    Zt = torch.zeros((max(kmax, 1), M), dtype=torch.complex128, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if work is None:
+        b = C.c_size_t(0)
+        call("mmf_eigh_window_workspace", C.c_int64(M), C.c_int64(kmax), C.byref(b))
+        work = _workspace(b.value, dev)
+    call("mmf_eigh_window", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), C.c_double(vl),
+         C.c_double(vu), C.c_int64(kmax), _ptr(w), _ptr(Zt), C.c_int64(max(M, 1)), _ptr(count), _ptr(work),
+         C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return w[:kmax], Zt[:kmax], count, info
+
+
 def eigvalsh_batched_workspace_bytes(sizes, prec: int = MMF_C128) -> int:
     n = (C.c_int64 * max(len(sizes), 1))(*[int(m) for m in sizes])
     b = C.c_size_t(0)

@@ -48,6 +48,46 @@ __global__ void eigh_zero_info(int32_t *info, int64_t count) {
   if (i < count) info[i] = 0;
 }
 
+// Window of the ascending spectrum: eigenvalues in [vl, vu) are the index
+// range [kl, ku); column t < min(ku - kl, kmax) of Zk is eigenvector kl + t of
+// the tridiagonal matrix, later columns are zero.  count = ku - kl.
+__device__ inline int64_t count_below(const double *w, int64_t n, double x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t md = (lo + hi) >> 1;
+    if (w[md] < x) lo = md + 1; else hi = md;
+  }
+  return lo;
+}
+
+__global__ void eigh_window_gather(int64_t n, const double *wall, const double *Zall, double vl, double vu,
+                                   int64_t kmax, double *w, double *Zk, int32_t *count) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = blockIdx.y;
+  const int64_t kl = count_below(wall, n, vl), ku = count_below(wall, n, vu);
+  const int64_t k = ku > kl ? ku - kl : 0;
+  if (r == 0 && t == 0) *count = (int32_t)k;
+  if (r == 0 && t < k && t < kmax) w[t] = wall[kl + t];
+  if (r < n) Zk[r + t * n] = (t < k) ? Zall[r + (kl + t) * n] : 0.0;
+}
+
+struct WinWs {
+  EighWs e;
+  double *wall, *Zk;
+  size_t bytes;
+};
+
+inline WinWs win_ws(int64_t M, int64_t kmax, void *base) {
+  WinWs w;
+  w.e = eigh_ws(M, base, 0);
+  Carver cv((char *)base + w.e.bytes);
+  const size_t n = (size_t)(M > 0 ? M : 1);
+  w.wall = cv.take<double>(n);
+  w.Zk = cv.take<double>(n * (size_t)(kmax > 0 ? kmax : 1));
+  w.bytes = w.e.bytes + cv.used();
+  return w;
+}
+
 }  // namespace mmf
 
 using namespace mmf;
@@ -181,4 +221,47 @@ extern "C" int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A
     if (rc) return rc;
   }
   return MMF_OK;
+}
+
+extern "C" int mmf_eigh_window_workspace(int64_t M, int64_t kmax, size_t *bytes) {
+  if (M < 0) return -1;
+  if (kmax < 0) return -2;
+  if (!bytes) return -3;
+  *bytes = win_ws(M, kmax < M ? kmax : M, nullptr).bytes;
+  return MMF_OK;
+}
+
+extern "C" int mmf_eigh_window(int64_t M, mmf_z *A, int64_t lda, double vl, double vu, int64_t kmax, double *w,
+                               mmf_z *Z, int64_t ldz, int32_t *count, void *work, size_t work_bytes,
+                               int32_t *dev_info, void *stream) {
+  if (M < 0) return -1;
+  if (!A && M > 0) return -2;
+  if (lda < M || lda < 1) return -3;
+  if (!(vl < vu)) return -4;
+  if (kmax < 0) return -6;
+  if (!w && kmax > 0) return -7;
+  if (!Z && kmax > 0) return -8;
+  if (ldz < M || ldz < 1) return -9;
+  if (!count) return -10;
+  if (!work) return -11;
+  const int64_t kk = kmax < M ? kmax : M;
+  WinWs ws = win_ws(M, kk, work);
+  if (work_bytes < ws.bytes) return -12;
+  if (!dev_info) return -13;
+  hipStream_t st = (hipStream_t)stream;
+  if (M == 0) return MMF_OK;
+  int rc = hetrd_run(M, A, lda, ws.wall, ws.e.e, ws.e.tau, ws.e.rest, ws.e.rest_bytes, st);
+  if (rc) return rc;
+  rc = stedc_run(M, ws.wall, ws.e.e, ws.e.Z, M, ws.e.rest, ws.e.rest_bytes, dev_info, st);
+  if (rc) return rc;
+  if (kk == 0) {
+    hipLaunchKernelGGL(eigh_window_gather, dim3(1, 1), dim3(1), 0, st, M, ws.wall, ws.e.Z, vl, vu, (int64_t)0, w,
+                       ws.Zk, count);
+    MMF_LAUNCH_CHECK();
+    return MMF_OK;
+  }
+  hipLaunchKernelGGL(eigh_window_gather, dim3(cdiv(M, 256), (unsigned)kk), dim3(256), 0, st, M, ws.wall, ws.e.Z,
+                     vl, vu, kk, w, ws.Zk, count);
+  MMF_LAUNCH_CHECK();
+  return unmtr_cols_run(M, kk, A, lda, ws.e.tau, ws.Zk, M, Z, ldz, ws.e.rest, ws.e.rest_bytes, st);
 }

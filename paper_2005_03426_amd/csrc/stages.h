@@ -22,6 +22,10 @@ size_t unmtr_ws_bytes(int64_t n);
 int unmtr_run(int64_t n, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z,
               int64_t ldz, mmf_z *Phi, int64_t ldphi, void *work, size_t bytes, hipStream_t st);
 
+// back-transformation of nc <= n columns (Phi, Z: n x nc); Phi must not alias V
+int unmtr_cols_run(int64_t n, int64_t nc, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z,
+                   int64_t ldz, mmf_z *Phi, int64_t ldphi, void *work, size_t bytes, hipStream_t st);
+
 // complex64 stages of the precision layer (A, tau, V, Phi are complex64;
 // d, e, Z stay FP64 / are converted on the fly)
 size_t hetrd_ws_bytes_c64(int64_t n);

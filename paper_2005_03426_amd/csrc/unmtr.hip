@@ -67,7 +67,7 @@ size_t unmtr_ws_bytes_c64(int64_t n) { return unmtr_ws<float>(n, nullptr).bytes 
 // One problem of a grouped back-transformation.
 template <typename R>
 struct BtProb {
-  int64_t n, ldv, ldz, ldphi, nblk, nsplit;
+  int64_t n, nc, ldv, ldz, ldphi, nblk, nsplit;     // nc: columns of Z / Phi (n for a full back-transform)
   const cx<R> *V, *tau;
   const double *Z;
   cx<R> *Phi;
@@ -112,11 +112,12 @@ __global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, i
   const int64_t m0 = (blockIdx.x % (BT_NB / GT_M)) * GT_M;     // row tile of W1
   const int64_t k0 = z * BT_KCHUNK;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
-  if (k0 >= mb || n0 >= n) return;
+  const int64_t nc = P.nc;
+  if (k0 >= mb || n0 >= nc) return;
   const cx<R> *Vb = P.Vp + bt_off(n, b);
   // A_C: op(A)[m,k] = conj(A[k + m lda]);  B_N: op(B)[k,n] = B[k + n ldb]
-  GemmArgs s = gemm_args(BT_NB, n, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb,
-                         P.Phi + (p + 1) + k0, P.ldphi, P.Wpart + z * BT_NB * n, BT_NB, 1.0, 0.0, 0.0, 0.0);
+  GemmArgs s = gemm_args(BT_NB, nc, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb,
+                         P.Phi + (p + 1) + k0, P.ldphi, P.Wpart + z * BT_NB * nc, BT_NB, 1.0, 0.0, 0.0, 0.0);
   gemm_tile_t<R, true, A_C, B_N>(s, m0, n0, lds);
 }
 
@@ -221,13 +222,13 @@ __global__ void __launch_bounds__(BT_NB) bt_reduce_t(const BtProb<R> *pr, int64_
   __shared__ cx<R> w1[BT_NB];
   const BtProb<R> &P = pr[blockIdx.z];
   const int64_t c = blockIdx.x;
-  if (b >= P.nblk || c >= P.n) return;
-  const int64_t n = P.n, mb = n - b * BT_NB - 1;
+  if (b >= P.nblk || c >= P.nc) return;
+  const int64_t n = P.n, nc = P.nc, mb = n - b * BT_NB - 1;
   const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
   const cx<R> *Tb = P.Tm + b * BT_NB * BT_NB;
   const int r = threadIdx.x;
   cx<R> s = cmk<R>(0, 0);
-  for (int64_t z = 0; z < nsl; ++z) s = cadd(s, P.Wpart[z * BT_NB * n + r + c * BT_NB]);
+  for (int64_t z = 0; z < nsl; ++z) s = cadd(s, P.Wpart[z * BT_NB * nc + r + c * BT_NB]);
   w1[r] = s;
   __syncthreads();
   cx<R> o = cmk<R>(0, 0);
@@ -243,8 +244,8 @@ __global__ void __launch_bounds__(GEMM_THREADS) bt_update(const BtProb<R> *pr, i
   if (b >= P.nblk) return;
   const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
-  if (m0 >= mb || n0 >= n) return;
-  GemmArgs u = gemm_args(mb, n, BT_NB, P.Vp + bt_off(n, b), mb, P.W2, BT_NB, P.Phi + (p + 1), P.ldphi, -1.0,
+  if (m0 >= mb || n0 >= P.nc) return;
+  GemmArgs u = gemm_args(mb, P.nc, BT_NB, P.Vp + bt_off(n, b), mb, P.W2, BT_NB, P.Phi + (p + 1), P.ldphi, -1.0,
                          0.0, 1.0, 0.0);
   gemm_tile_t<R, true, A_N, B_N>(u, m0, n0, lds);
 }
@@ -257,17 +258,18 @@ __global__ void bt_init_phi(const BtProb<R> *pr) {
   const int64_t n = P.n;
   if (r >= n) return;
   const int64_t c0 = (int64_t)blockIdx.y * 64;
-  const int64_t c1 = c0 + 64 < n ? c0 + 64 : n;
+  const int64_t c1 = c0 + 64 < P.nc ? c0 + 64 : P.nc;
   for (int64_t c = c0; c < c1; ++c) P.Phi[r + c * P.ldphi] = cmk<R>((R)P.Z[r + c * P.ldz], R(0));
 }
 
-// Grouped back-transformation of `count` problems (orders nh[], host copy).
+// Grouped back-transformation of `count` problems (orders nh[], host copy;
+// ncmax >= every problem's column count, default the largest order).
 template <typename R>
-int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStream_t st) {
+int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStream_t st, int64_t ncmax = -1) {
   if (count <= 0) return MMF_OK;
   if (count > 65535) {
     for (int64_t b = 0; b < count; b += 65535) {
-      const int rc = unmtr_grouped<R>(pr + b, nh + b, count - b < 65535 ? count - b : 65535, st);
+      const int rc = unmtr_grouped<R>(pr + b, nh + b, count - b < 65535 ? count - b : 65535, st, ncmax);
       if (rc) return rc;
     }
     return MMF_OK;
@@ -275,6 +277,8 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
   int64_t nmax = 0;
   for (int64_t c = 0; c < count; ++c) nmax = nh[c] > nmax ? nh[c] : nmax;
   if (nmax <= 0) return MMF_OK;
+  const int64_t ncols = ncmax >= 0 ? ncmax : nmax;
+  if (ncols <= 0) return MMF_OK;
   const unsigned Z = (unsigned)count;
   const int64_t nblk = nmax > 1 ? (nmax - 1 + BT_NB - 1) / BT_NB : 0;
   const int64_t nsplit = (nmax + BT_KCHUNK - 1) / BT_KCHUNK;
@@ -292,18 +296,18 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
     MMF_LAUNCH_CHECK();
   }
   // 3. Phi = Z (complex)
-  hipLaunchKernelGGL(bt_init_phi<R>, dim3(cdiv(nmax, 256), cdiv(nmax, 64), Z), dim3(256), 0, st, pr);
+  hipLaunchKernelGGL(bt_init_phi<R>, dim3(cdiv(nmax, 256), cdiv(ncols, 64), Z), dim3(256), 0, st, pr);
   MMF_LAUNCH_CHECK();
   // 4. apply blocks last to first (a problem with fewer blocks idles until its last one)
   for (int64_t b = nblk - 1; b >= 0; --b) {
     const int64_t mb = nmax - b * BT_NB - 1;
     const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
-    hipLaunchKernelGGL(bt_splitk<R>, dim3((unsigned)(nsl * (BT_NB / GT_M)), cdiv(nmax, GT_N), Z),
+    hipLaunchKernelGGL(bt_splitk<R>, dim3((unsigned)(nsl * (BT_NB / GT_M)), cdiv(ncols, GT_N), Z),
                        dim3(GEMM_THREADS), 0, st, pr, b);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)nmax, 1, Z), dim3(BT_NB), 0, st, pr, b);
+    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)ncols, 1, Z), dim3(BT_NB), 0, st, pr, b);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_update<R>, dim3(cdiv(mb, GT_M), cdiv(nmax, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr,
+    hipLaunchKernelGGL(bt_update<R>, dim3(cdiv(mb, GT_M), cdiv(ncols, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr,
                        b);
     MMF_LAUNCH_CHECK();
   }
@@ -312,10 +316,10 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
 
 template <typename R>
 inline BtProb<R> bt_prob(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *tau, const double *Z,
-                         int64_t ldz, cx<R> *Phi, int64_t ldphi, void *ws) {
+                         int64_t ldz, cx<R> *Phi, int64_t ldphi, void *ws, int64_t nc = -1) {
   const BtWs<R> w = unmtr_ws<R>(n, ws);
   BtProb<R> q;
-  q.n = n; q.ldv = ldv; q.ldz = ldz; q.ldphi = ldphi; q.nblk = w.nblk; q.nsplit = w.nsplit;
+  q.n = n; q.nc = nc >= 0 ? nc : n; q.ldv = ldv; q.ldz = ldz; q.ldphi = ldphi; q.nblk = w.nblk; q.nsplit = w.nsplit;
   q.V = V; q.tau = tau; q.Z = Z; q.Phi = Phi;
   q.Vp = w.Vp; q.Tm = w.Tm; q.Wpart = w.Wpart; q.W2 = w.W2; q.Gpart = w.Gpart;
   return q;
@@ -363,6 +367,20 @@ int unmtr_batched_c64(int64_t count, const int64_t *n, const void *const *V, con
   return unmtr_batched_t<float>(count, n, reinterpret_cast<const cf *const *>(V), ldv,
                                 reinterpret_cast<const cf *const *>(tau), Z, ldz,
                                 reinterpret_cast<cf *const *>(Phi), ldphi, stage, table, st);
+}
+
+// Back-transformation of the first nc columns only: Phi (n x nc) = Q Z (n x nc).
+int unmtr_cols_run(int64_t n, int64_t nc, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z,
+                   int64_t ldz, mmf_z *Phi, int64_t ldphi, void *work, size_t bytes, hipStream_t st) {
+  if (n <= 0 || nc <= 0) return MMF_OK;
+  if (bytes < unmtr_ws<double>(n, nullptr).bytes + BT_TABLE_BYTES) return MMF_ERR_WORKSPACE;
+  BtProb<double> *pr = reinterpret_cast<BtProb<double> *>(work);
+  const BtProb<double> q = bt_prob<double>(n, reinterpret_cast<const cd *>(V), ldv, reinterpret_cast<const cd *>(tau),
+                                           Z, ldz, reinterpret_cast<cd *>(Phi), ldphi,
+                                           (char *)work + BT_TABLE_BYTES, nc);
+  const int rc = table_write(pr, &q, 1, st);
+  if (rc) return rc;
+  return unmtr_grouped<double>(pr, &n, 1, st, nc);
 }
 
 int unmtr_run(int64_t n, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z, int64_t ldz,

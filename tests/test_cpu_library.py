@@ -155,3 +155,29 @@ def test_dressed_evolution_argument_checks_host_only():
     assert L.mmf_dressed_evolution(2, 4, d, None, d, d, None) == -4
     assert L.mmf_dressed_evolution(2, 4, d, d, None, d, None) == -5
     assert L.mmf_dressed_evolution(2, 4, d, d, d, None, None) == -6
+
+
+def test_eigh_window_argument_checks_host_only():
+    import paper_2005_03426_amd as mmf
+    L = mmf.lib()
+    d = C.c_void_p(16)
+    b = C.c_size_t(0)
+    assert L.mmf_eigh_window_workspace(C.c_int64(100), C.c_int64(10), C.byref(b)) == 0 and b.value > 0
+    assert L.mmf_eigh_window_workspace(C.c_int64(-1), C.c_int64(10), C.byref(b)) == -1
+
+    def call(M=100, A=d, lda=100, vl=0.0, vu=1.0, kmax=10, w=d, Z=d, ldz=100, cnt=d, work=d, nb=None, info=d):
+        return L.mmf_eigh_window(C.c_int64(M), A, C.c_int64(lda), C.c_double(vl), C.c_double(vu),
+                                 C.c_int64(kmax), w, Z, C.c_int64(ldz), cnt, work,
+                                 C.c_size_t(b.value if nb is None else nb), info, None)
+    assert call(M=-1) == -1
+    assert call(A=None) == -2
+    assert call(lda=99) == -3
+    assert call(vl=1.0, vu=1.0) == -4
+    assert call(kmax=-1) == -6
+    assert call(w=None) == -7
+    assert call(Z=None) == -8
+    assert call(ldz=50) == -9
+    assert call(cnt=None) == -10
+    assert call(work=None) == -11
+    assert call(nb=16) == -12
+    assert call(info=None) == -13

@@ -51,3 +51,13 @@ def test_driven_lattice_spectrum_invariants():
     shift_f2 = D * sum((n * w) ** 2 for n in range(-N, N + 1))
     drive_f2 = 2 * (S - 1) * 2 * (D - 1) * (V / 2) ** 2
     assert abs(np.sum(q ** 2) - (S * static_f2 + shift_f2 + drive_f2)) < 1e-11
+
+
+@pytest.mark.parametrize("w,shift", [(0.4, 0.0), (0.6, 0.0), (0.6, 0.11), (0.9, -0.2)])
+def test_window_of_one_drive_period_holds_one_state_per_orbit(w, shift):
+    """omega-translation symmetry: a converged single-drive truncation has one
+    quasienergy per orbit in any central window of width omega."""
+    D = 32
+    q = oracle.quasienergies(lattice_problem(w, D=D, N=4))
+    lo = -w / 2 + shift
+    assert int(((q >= lo) & (q < lo + w)).sum()) == D
