@@ -285,6 +285,52 @@ def run_lattice_sweep(args, torch, mmf):
     print(json.dumps(out), flush=True)
 
 
+def run_window(args, torch, mmf):
+    """Partial spectrum vs full eigensolve on one lattice Floquet matrix
+    (D = 256, +-10, M = 5376, omega = 0.6): the Brillouin-zone window
+    [-omega/2, omega/2) holds the 256 Floquet states."""
+    from workloads import lattice_problem
+    dev = "cuda"
+    p = lattice_problem(0.6, D=256, N=10)
+    dp = mmf.DeviceProblem(p, dev)
+    M = dp.M
+    HF = torch.empty((M, M), dtype=torch.complex128, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def one(window):
+        mmf.build_floquet(dp, out=HF)
+        ev[0].record()
+        if window:
+            out = mmf.eigh_window(HF, -0.3, 0.3, 256)
+        else:
+            out = mmf.eigh(HF)
+        ev[1].record()
+        return out
+
+    res = {}
+    for name, window in (("window", True), ("full", False)):
+        for _ in range(args.warmup):
+            one(window)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.steps):
+            out = one(window)
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        res[name] = float(np.median(ms))
+        if window:
+            res["count"] = int(out[2].item())
+    out = {
+        "metric": "Floquet eigensolves/s", "value": 1e3 / res["window"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["window"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "window_lattice", "D": 256, "M": M, "omega": 0.6, "window": [-0.3, 0.3],
+                   "states": res["count"]},
+        "full_eigh_ms": res["full"], "window_eigh_ms": res["window"], "speedup": res["full"] / res["window"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +357,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.workload == "window_lattice":
+        run_window(args, torch, mmf)
+        return
     if args.workload == "lattice_sweep":
         run_lattice_sweep(args, torch, mmf)
         return
