@@ -200,6 +200,32 @@ template <typename R> struct NtVec;
 template <> struct NtVec<double> { typedef double v __attribute__((ext_vector_type(2))); };
 template <> struct NtVec<float> { typedef float v __attribute__((ext_vector_type(2))); };
 
+// Panel corrections of the column's HEMV: for row chunk g,
+// dots[g*2NB + q] = sum_rows conj(W[:,q]) v (q < k) and
+// dots[g*2NB + NB + q] = sum_rows conj(V[:,q]) v over rows [i+1, n) of the
+// chunk (DOT_ROWS rows).  Run by extra workgroups of the HEMV launch: one
+// wavefront per product qq (lane l sums rows l, l + 64, ...; shuffle fold).
+template <typename R>
+__device__ void ht_dots_wave(const HtProb<R> &pq, int64_t i, int k, int g, int qq) {
+  const int64_t n = pq.n;
+  const cx<R> *P3 = pq.P3;
+  const int q = qq % k, which = qq / k;
+  const cx<R> *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
+  const cx<R> *v = P3 + (int64_t)k * n;
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = i + 1 + (int64_t)g * DOT_ROWS;
+  cx<R> s = cmk<R>(0, 0);
+#pragma unroll 4
+  for (int j = lane; j < DOT_ROWS; j += 64) {
+    const int64_t r = r0 + j;
+    if (r < n) s = cadd(s, cmulc(X[r], v[r]));
+  }
+  R re = s.re, im = s.im;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
+  if (lane == 0) pq.dots[(int64_t)g * 2 * HT_NB + which * HT_NB + q] = cmk<R>(re, im);
+}
+
 // u = A_trail v over the lower triangle of the trailing matrix
 // A_trail = A[i+1:, i+1:].  Tiles lie on the absolute 64 x 64 grid of A
 // (block b covers rows 64b .. 64b+63), so on a leading dimension divisible by
@@ -219,7 +245,7 @@ template <> struct NtVec<float> { typedef float v __attribute__((ext_vector_type
 //     every element masked (rows/columns in [i+1, n), lower triangle, real
 //     diagonal); lane = row, wave w = columns 16w .. 16w+15.
 template <typename R>
-__global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i, int k) {
+__global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i, int k, int64_t dot_slot) {
   typedef cx<R> C;
   typedef typename NtVec<R>::v nv;
   __shared__ C vcol[HV_T];
@@ -234,6 +260,12 @@ __global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i
   const int64_t bj = b0 + lb;
   if (bj >= nb) return;
   const int64_t slot = blockIdx.y;
+  if (dot_slot >= 0 && slot >= dot_slot) {             // panel dot products of this column
+    const int qq = (int)(slot - dot_slot) * 4 + (threadIdx.x >> 6);
+    if ((int64_t)blockIdx.x < (n - i - 1 + DOT_ROWS - 1) / DOT_ROWS && qq < 2 * k)
+      ht_dots_wave(q, i, k, (int)blockIdx.x, qq);
+    return;
+  }
   const int64_t first = bj + 1 + (slot - 1) * HV_CH;   // interior chunk's first block row
   if (slot > 0 && first >= nfull) return;
   const C *A = q.A;
@@ -351,33 +383,6 @@ __global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i
     for (int o = 1; o < 16; o <<= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
     if (rg == 0) ptrn[(lb * nchmax + slot) * HV_T + cb + j] = cmk<R>(re, im);
   }
-}
-
-// Panel corrections: dots[g*2NB + q] = sum_rows conj(W[:,q]) v (q < k) and
-// dots[g*2NB + NB + q] = sum_rows conj(V[:,q]) v over rows [i+1, n).
-template <typename R>
-__global__ void __launch_bounds__(256) ht_dots(const HtProb<R> *pr, int64_t i, int k) {
-  __shared__ R sh[4];
-  const HtProb<R> &pq = pr[blockIdx.z];
-  const int64_t n = pq.n;
-  if (i >= n - 1) return;
-  if ((int64_t)blockIdx.x >= (n - i - 1 + DOT_ROWS - 1) / DOT_ROWS) return;   // this matrix's partials only
-  const cx<R> *P3 = pq.P3;
-  cx<R> *dots = pq.dots;
-  const int g = blockIdx.x;
-  const int qq = blockIdx.y;                 // 0..2k-1
-  const int q = qq % k, which = qq / k;
-  const cx<R> *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
-  const cx<R> *v = P3 + (int64_t)k * n;
-  cx<R> s = cmk<R>(0, 0);
-  const int64_t r0 = i + 1 + (int64_t)g * DOT_ROWS;
-  for (int j = threadIdx.x; j < DOT_ROWS; j += 256) {
-    const int64_t r = r0 + j;
-    if (r < n) s = cadd(s, cmulc(X[r], v[r]));
-  }
-  const R sr = block_sum256(s.re, sh);
-  const R si = block_sum256(s.im, sh);
-  if (threadIdx.x == 0) dots[(int64_t)g * 2 * HT_NB + which * HT_NB + q] = cmk<R>(sr, si);
 }
 
 // w0 = tau (u - V x1 - W x2), with u assembled from the HEMV partials.
@@ -563,21 +568,22 @@ int hetrd_grouped(const HtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
       const int64_t nbl = (nmax + HV_T - 1) / HV_T - b0;
       const int64_t inner = nmax / HV_T - b0 - 1;
       const int64_t nslot = 1 + (inner > 0 ? (inner + HV_CH - 1) / HV_CH : 0);
+      // extra rows of workgroups for the panel dots: four products per workgroup
+      const int64_t dot_slot = k > 0 ? nslot : -1;
+      const int64_t dot_rows = k > 0 ? (2 * k + 3) / 4 : 0;
       const int ks = ktimer_begin(sizeof(R) == 8 ? "hemv" : "hemv_c64", st);
-      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbl, (unsigned)nslot, Z), dim3(256), 0, st, pr, i, k);
+      hipLaunchKernelGGL(ht_hemv<R>, dim3((unsigned)nbl, (unsigned)(nslot + dot_rows), Z), dim3(256), 0, st, pr,
+                         i, k, dot_slot);
       MMF_LAUNCH_CHECK();
       if (ks >= 0) {
-        // algorithmic bytes: the lower triangle of every trailing matrix, read once
+        // algorithmic bytes: the lower triangle of every trailing matrix, read
+        // once, plus the 2k panel columns and v read by the fused dot products
         double bytes = 0.0;
         for (int64_t c = 0; c < count; ++c) {
           const double mc = (double)(nh[c] - i - 1);
-          if (mc > 0) bytes += 2.0 * sizeof(R) * mc * (mc + 1.0) / 2.0;
+          if (mc > 0) bytes += 2.0 * sizeof(R) * (mc * (mc + 1.0) / 2.0 + (k > 0 ? (2.0 * k + 1.0) * mc : 0.0));
         }
         ktimer_end(ks, st, bytes);
-      }
-      if (k > 0) {
-        hipLaunchKernelGGL(ht_dots<R>, dim3(cdiv(m, DOT_ROWS), 2 * k, Z), dim3(256), 0, st, pr, i, k);
-        MMF_LAUNCH_CHECK();
       }
       hipLaunchKernelGGL(ht_finish_u<R>, dim3((unsigned)nbl, 1, Z), dim3(256), 0, st, pr, i, k);
       MMF_LAUNCH_CHECK();

@@ -110,20 +110,24 @@ __device__ inline MergeGeom dc_geom(int64_t n, int64_t L, int lev, int64_t g) {
 }
 
 // ------------------------------------------------------------------ tearing
+// True when x is one of the leaf boundaries b(j) = floor(j n / L), 0 < j < L.
+__device__ inline bool dc_is_boundary(int64_t x, int64_t n, int64_t L) {
+  if (x <= 0 || x >= n) return false;
+  const int64_t j = (x * L + n - 1) / n;          // smallest j with j n / L >= x
+  return j >= 1 && j < L && dc_b(j, n, L) == x;
+}
+
+// dw = d with |e_{k-1}| taken from d_{k-1} and d_k at every boundary k
+// (one thread per row; boundaries are at least one leaf apart).
 __global__ void dc_tear(const DcProb *pr) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const DcProb &q = pr[blockIdx.z];
   const int64_t n = q.n, L = q.L;
-  const double *d = q.d, *e = q.e;
-  double *dw = q.w.dw;
-  if (n <= 0) return;
-  for (int64_t i = 0; i < n; ++i) dw[i] = d[i];
-  for (int64_t i = 1; i < L; ++i) {
-    const int64_t k = dc_b(i, n, L);
-    const double r = fabs(e[k - 1]);
-    dw[k - 1] -= r;
-    dw[k] -= r;
-  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = q.d[i];
+  if (dc_is_boundary(i + 1, n, L)) v -= fabs(q.e[i]);       // i = k - 1
+  if (dc_is_boundary(i, n, L)) v -= fabs(q.e[i - 1]);       // i = k
+  q.w.dw[i] = v;
 }
 
 // ------------------------------------------------------------------ leaves
@@ -640,7 +644,7 @@ int stedc_grouped(const DcProb *pr, const int64_t *nh, int64_t count, hipStream_
   const unsigned Z = (unsigned)count;
   hipLaunchKernelGGL(dc_info_init, dim3(1, 1, Z), dim3(64), 0, st, pr);
   MMF_LAUNCH_CHECK();
-  hipLaunchKernelGGL(dc_tear, dim3(1, 1, Z), dim3(64), 0, st, pr);
+  hipLaunchKernelGGL(dc_tear, dim3(cdiv(nmax, 256), 1, Z), dim3(256), 0, st, pr);
   MMF_LAUNCH_CHECK();
   int64_t Lall = 0;
   for (int64_t c = 0; c < count; ++c) {
