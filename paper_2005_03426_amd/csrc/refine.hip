@@ -42,6 +42,7 @@ constexpr int CL_MAX = 32;          // clusters are split into chunks of at most
 // convergence bound the next iteration (whose only effect would be to
 // confirm convergence) is skipped.
 constexpr double REF_QUAD = 1e-3;
+constexpr double CONV_TOL_R = 1e-12;  // and orthogonality: max |g_ij - delta_ij| <= CONV_TOL_R
 constexpr double REF_SAFETY = 100.0;
 
 // ---------------------------------------------------------------- conversions
@@ -112,36 +113,47 @@ __global__ void rf_mirror(int64_t n, cd *S, cd *G, const int32_t *skip) {
 
 __global__ void rf_zero_u64(unsigned long long *p) { if (threadIdx.x == 0) *p = 0ull; }
 
-// stop_next <- 1 when the predicted next residual is converged (msml: this
-// iteration's max |s_ij - lam_j g_ij| and max(1, max |lam|)).
+// stop_next <- 1 when the next iteration is predicted converged (msml: this
+// iteration's max |s_ij - lam_j g_ij|, max(1, max |lam|), max |g_ij - delta_ij|).
 __global__ void rf_predict(const unsigned long long *emax_bits, const double *msml, int32_t *stop_next,
                            const int32_t *skip) {
   if (threadIdx.x != 0 || *skip) return;
   const double e = __longlong_as_double((long long)*emax_bits);
-  if (e <= REF_QUAD && REF_SAFETY * msml[0] * e <= CONV_TOL * msml[1]) *stop_next = 1;
+  // after X <- X (I + E): residual ~ ms * max|e|, loss of orthogonality ~ r^2 + max|e|^2
+  if (e <= REF_QUAD && REF_SAFETY * msml[0] * e <= CONV_TOL * msml[1] &&
+      REF_SAFETY * (msml[2] * msml[2] + e * e) <= CONV_TOL_R)
+    *stop_next = 1;
 }
 
 // ---------------------------------------------------------------- per-iteration scalars
 // lam_j = Re s_jj / Re g_jj and, per column, max_{i != j} |s_ij - lam_j g_ij|
-// (the numerator of the first-order correction).
+// (the numerator of the first-order correction) in colmax[j] and
+// max_i |g_ij - delta_ij| (loss of orthogonality) in colmax[n + j].
 __global__ void __launch_bounds__(256) rf_lambda(int64_t n, const cd *S, const cd *G, double *lam,
                                                  double *colmax, const int32_t *skip) {
-  __shared__ double sh[4];
+  __shared__ double sh[2][4];
   if (*skip) return;
   const int64_t j = blockIdx.x;
   const double lj = S[j + j * n].re / G[j + j * n].re;
-  double ms = 0.0;
+  double ms = 0.0, mr = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    if (i == j) continue;
-    const cd v = csub(S[i + j * n], cscale(G[i + j * n], lj));
+    const cd gij = G[i + j * n];
+    if (i == j) {
+      mr = fmax(mr, sqrt((gij.re - 1.0) * (gij.re - 1.0) + gij.im * gij.im));
+      continue;
+    }
+    mr = fmax(mr, sqrt(cabs2(gij)));
+    const cd v = csub(S[i + j * n], cscale(gij, lj));
     ms = fmax(ms, sqrt(cabs2(v)));
   }
   ms = wave_max(ms);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ms;
+  mr = wave_max(mr);
+  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ms; sh[1][threadIdx.x >> 6] = mr; }
   __syncthreads();
   if (threadIdx.x == 0) {
     lam[j] = lj;
-    colmax[j] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    colmax[j] = fmax(fmax(sh[0][0], sh[0][1]), fmax(sh[0][2], sh[0][3]));
+    colmax[n + j] = fmax(fmax(sh[1][0], sh[1][1]), fmax(sh[1][2], sh[1][3]));
   }
 }
 
@@ -151,14 +163,16 @@ __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, 
                             int32_t *clist, int32_t *ncl, double *delta_out, double *msml,
                             const int32_t *skip, int32_t *stop_next) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || *skip) return;
-  double ms = 0.0, ml = 1.0;
+  double ms = 0.0, ml = 1.0, mr = 0.0;
   for (int64_t j = 0; j < n; ++j) {
     ms = fmax(ms, colmax[j]);
+    mr = fmax(mr, colmax[n + j]);
     ml = fmax(ml, fabs(lam[j]));
   }
-  if (ms <= CONV_TOL * ml) *stop_next = 1;     // this iteration's update is the last one
+  if (ms <= CONV_TOL * ml && mr <= CONV_TOL_R) *stop_next = 1;     // this iteration's update is the last one
   msml[0] = ms;
   msml[1] = ml;
+  msml[2] = mr;
   const double delta = CL_FACTOR * ms;
   *delta_out = delta;
   int32_t nc = 0;
@@ -342,6 +356,27 @@ __global__ void rf_carry(int64_t n, const cd *X, cd *Xo, const int32_t *skip) {
   Xo[r + c * n] = X[r + c * n];
 }
 
+// Final eigenvalues: Rayleigh quotients of the refined vectors,
+// lam_j = Re(x_j^H (A x_j)) / Re(x_j^H x_j) (one workgroup per column).  The
+// quotients of the last iteration belong to the vectors before its
+// correction; these are second order in the final (FP64-level) residual.
+__global__ void __launch_bounds__(256) rf_rayleigh(int64_t n, const cd *X, const cd *Y, double *lam) {
+  __shared__ double sh[2][4];
+  const int64_t j = blockIdx.x;
+  double num = 0.0, den = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const cd x = X[i + j * n], y = Y[i + j * n];
+    num += x.re * y.re + x.im * y.im;
+    den += x.re * x.re + x.im * x.im;
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = num; sh[1][threadIdx.x >> 6] = den; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    lam[j] = ((sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3])) / ((sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]));
+}
+
 // Ascending order of the refined eigenvalues (rank by counting, ties by index).
 __global__ void rf_rank(int64_t n, const double *lam, int32_t *dest) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,6 +413,7 @@ struct RefWs {
   int32_t *cid, *clist, *ncl, *band, *dest, *skip, *stop;
   unsigned long long *emax;
   double *msml;
+  int32_t *noskip;        // a flag that stays zero (final products run unconditionally)
   cd *Qbuf;
   size_t bytes;
 };
@@ -414,7 +450,8 @@ inline RefWs ref_ws(int64_t M, bool refine, void *base) {
   w.skip = cv.take<int32_t>(1);
   w.stop = cv.take<int32_t>(1);
   w.emax = cv.take<unsigned long long>(1);
-  w.msml = cv.take<double>(2);
+  w.msml = cv.take<double>(3);
+  w.noskip = cv.take<int32_t>(1);
   w.Qbuf = cv.take<cd>((n / 2 + 1) * CL_MAX * CL_MAX);
   w.bytes = cv.used();
   return w;
@@ -513,7 +550,20 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     hipLaunchKernelGGL(rf_carry, g2, dim3(256), 0, st, n, X, Xo, ws.skip);
     MMF_LAUNCH_CHECK();
   }
-  cd *X = bufs[REF_ITERS % 2];
+  cd *X = bufs[REF_ITERS % 2], *Y = bufs[(REF_ITERS + 1) % 2];
+  // eigenvalues as Rayleigh quotients of the final vectors: Y = A X (banded), then per column
+  hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.noskip);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(rf_hermitize, g2, dim3(256), 0, st, n, A, lda, B2, ws.noskip);
+  MMF_LAUNCH_CHECK();
+  {
+    GemmArgs gy = gemm_args(n, n, n, B2, n, X, n, Y, n, 1.0, 0.0, 0.0, 0.0);
+    gy.band_ptr = ws.band;
+    rc = gemm_launch<true, A_N, B_N>(gy, st);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(rf_rayleigh, dim3((unsigned)n), dim3(256), 0, st, n, X, Y, ws.lam);
+  MMF_LAUNCH_CHECK();
   hipLaunchKernelGGL(rf_rank, dim3(cdiv(n, 256)), dim3(256), 0, st, n, ws.lam, ws.dest);
   MMF_LAUNCH_CHECK();
   hipLaunchKernelGGL(rf_scatter, g2, dim3(256), 0, st, n, X, ws.lam, ws.dest, A, lda, w);

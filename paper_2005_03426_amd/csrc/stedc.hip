@@ -431,7 +431,9 @@ __global__ void __launch_bounds__(256) dc_secular(const DcProb *pr, int lev) {
     dph = rh * wave_sum(dph);
     const double f = 1.0 + ps + ph;
     if (f < 0.0) lo = tau; else hi = tau;
-    const double errb = 8.0 * DC_EPS * (double)K * (1.0 + fabs(ps) + fabs(ph));
+    // rounding bound of f at tau: eps times the absolute sum of its terms
+    // (each of the two partial sums has terms of one sign)
+    const double errb = 8.0 * DC_EPS * (1.0 + fabs(ps) + fabs(ph));
     if (fabs(f) <= errb || (hi - lo) <= 4.0 * DC_EPS * fmax(fabs(lo), fabs(hi))) { conv = true; break; }
     const double b1 = dps * (pk - tau) * (pk - tau);
     const double a1 = ps - b1 / (pk - tau);
