@@ -67,6 +67,10 @@ enum {
   MMF_C64_REFINED = 1,   /* complex64 reduction/back-transform + FP64 refinement          */
   MMF_C64_RAW = 2        /* complex64 reduction/back-transform, no refinement             */
 };
+/* MMF_C64_REFINED iterates (at most six times) until max |s_ij - lam_j g_ij|
+ * <= 1e-13 max(1, max |lam|) and max |g_ij - delta_ij| <= 1e-12 for
+ * S = X^H A X, G = X^H X; otherwise dev_info is set to MMF_ERR_NO_CONVERGENCE
+ * and the last iterate is returned. */
 
 /* positive error codes */
 enum {

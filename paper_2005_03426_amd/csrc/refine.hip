@@ -356,6 +356,10 @@ __global__ void rf_carry(int64_t n, const cd *X, cd *Xo, const int32_t *skip) {
   Xo[r + c * n] = X[r + c * n];
 }
 
+__global__ void rf_flag_unconverged(const int32_t *stop, int32_t *info) {
+  if (threadIdx.x == 0 && *stop == 0 && *info == 0) *info = MMF_ERR_NO_CONVERGENCE;
+}
+
 // Final eigenvalues: Rayleigh quotients of the refined vectors,
 // lam_j = Re(x_j^H (A x_j)) / Re(x_j^H x_j) (one workgroup per column).  The
 // quotients of the last iteration belong to the vectors before its
@@ -461,7 +465,8 @@ size_t eigh_c64_ws_bytes(int64_t M, bool refine) { return ref_ws(M, refine, null
 
 // After the complex64 eigensolve (eigenvectors in ws.Ac): widen them into A
 // (raw), or refine them in FP64 against A and write the refined pairs.
-static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, const RefWs &ws, hipStream_t st) {
+static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, const RefWs &ws, int32_t *info,
+                      hipStream_t st) {
   const dim3 g2(cdiv(n, 256), (unsigned)n);
   int rc = MMF_OK;
   if (!refine) {
@@ -550,6 +555,9 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     hipLaunchKernelGGL(rf_carry, g2, dim3(256), 0, st, n, X, Xo, ws.skip);
     MMF_LAUNCH_CHECK();
   }
+  // the iteration cap was reached without the convergence test passing
+  hipLaunchKernelGGL(rf_flag_unconverged, dim3(1), dim3(64), 0, st, ws.stop, info);
+  MMF_LAUNCH_CHECK();
   cd *X = bufs[REF_ITERS % 2], *Y = bufs[(REF_ITERS + 1) % 2];
   // eigenvalues as Rayleigh quotients of the final vectors: Y = A X (banded), then per column
   hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.noskip);
@@ -587,7 +595,7 @@ int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void
   if (rc) return rc;
   rc = unmtr_run_c64(n, ws.Ac, n, ws.tauc, ws.Z, n, ws.Ac, n, ws.stage, ws.stage_bytes, st);
   if (rc) return rc;
-  return c64_finish(n, A, lda, w, refine, ws, st);
+  return c64_finish(n, A, lda, w, refine, ws, info, st);
 }
 
 int eigh_c64_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda, double *const *w,
@@ -612,7 +620,7 @@ int eigh_c64_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int
                          st);
   if (rc) return rc;
   for (int64_t c = 0; c < count; ++c) {
-    rc = c64_finish(n[c], reinterpret_cast<cd *>(A[c]), lda[c], w[c], refine, ws[c], st);
+    rc = c64_finish(n[c], reinterpret_cast<cd *>(A[c]), lda[c], w[c], refine, ws[c], info[c], st);
     if (rc) return rc;
   }
   return MMF_OK;
