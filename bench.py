@@ -331,6 +331,75 @@ def run_window(args, torch, mmf):
     print(json.dumps(out), flush=True)
 
 
+def run_precision(args, torch, mmf):
+    """16-level spectrum under two drives, M = 41616: the complex64 paths
+    (raw, and refined in FP64) against the plain complex128 solve on the same
+    GPU.  The oracle does not reach this size, so the complex128 GPU result
+    (matched to the oracle at smaller sizes) is the reference; errors are
+    reported for quasienergies, U(t) at 256 times and the averaged P."""
+    from workloads import cfg4_precision
+    dev = "cuda"
+    p, ts, t0 = cfg4_precision()
+    dp = mmf.DeviceProblem(p, dev)
+    M, D = dp.M, dp.D
+    tt = torch.as_tensor(np.asarray(ts), dtype=torch.float64, device=dev)
+    print(f"[bench] precision workload: M={M} D={D}", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    ref = None
+    for name, prec in (("c128", mmf.MMF_C128), ("c64_refined", mmf.MMF_C64_REFINED), ("c64_raw", mmf.MMF_C64_RAW)):
+        if args.prec_only and name not in ("c128", args.prec_only):
+            continue
+        HF = mmf.build_floquet(dp)
+        work = torch.empty(mmf.eigh_workspace_bytes(M, prec), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        ev0.record()
+        w, Pt, info = mmf.eigh(HF, prec, work=work)
+        ev1.record()
+        t_wait = time.perf_counter()
+        while not ev1.query():                       # a progress line while the long solve runs
+            time.sleep(1.0)
+            if time.perf_counter() - t_wait > 30.0:
+                print(f"[bench] precision {name}: solving ...", file=sys.stderr, flush=True)
+                t_wait = time.perf_counter()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        del work
+        U = mmf.evolve(dp, Pt, w, t0, tt)
+        P = mmf.avg_prob(dp, Pt)
+        g = torch.Generator(device="cpu").manual_seed(0)
+        idx = torch.randperm(M, generator=g)[:32].to(dev)
+        H = mmf.build_floquet(dp).T
+        Phi = Pt[idx].T.contiguous()
+        resid = float((H @ Phi - Phi * w[idx][None, :]).abs().max()) / torch.linalg.matrix_norm(H, ord=1).item()
+        del H, Phi
+        r = {"eigh_s": ms / 1e3, "eigh_tflops_nominal": (40.0 / 3.0) * M ** 3 / (ms / 1e3) / 1e12,
+             "info": int(info.item()), "sampled_residual": resid}
+        if ref is None:
+            ref = (w.clone(), U.clone(), P.clone())
+        else:
+            scale = max(1.0, float(ref[0].abs().max()))
+            r["eps_err_vs_c128"] = float((w - ref[0]).abs().max()) / scale
+            r["U_err_vs_c128"] = float((U - ref[1]).abs().max())
+            r["P_err_vs_c128"] = float((P - ref[2]).abs().max())
+        print(f"[bench] precision {name}: {r}", file=sys.stderr, flush=True)
+        res[name] = r
+        del HF, Pt, w, U, P
+        torch.cuda.empty_cache()
+    main_name = "c64_refined" if "c64_refined" in res else "c128"
+    out = {
+        "metric": "Floquet eigensolves/s", "value": 1.0 / res[main_name]["eigh_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": res[main_name]["eigh_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64+f64" if main_name == "c64_refined" else "c128", "data": "synthetic",
+        "config": {"workload": "precision41616", "D": D, "M": M, "times": len(ts),
+                   "drives": [float(x) for x in p.omega], "truncation": [int(x) for x in p.N],
+                   "reference": "complex128 solve on the same GPU"},
+        "runs": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +426,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.workload == "precision41616":
+        run_precision(args, torch, mmf)
+        return
     if args.workload == "window_lattice":
         run_window(args, torch, mmf)
         return
