@@ -42,6 +42,7 @@ __all__ = [
     "evolve", "evolve_expm", "micromotion_select", "micromotion", "avg_prob",
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
     "zero_site", "tridiag_eigh", "quasienergies", "restrict_modes", "dressed_evolution",
+    "spin_ops", "spin_drive",
 ]
 
 
@@ -398,6 +399,39 @@ def dressed_evolution(p, axes, ts, t0: float):
     for q in range(len(ts)):
         Ud[q] = UF[q].conj().T @ U[q] @ UF[-1]
     return Ud, U, eps_d
+
+
+# ---------------------------------------------------------------------------
+# Spin couplings (Sec. 3.3, Eq. 7)
+# ---------------------------------------------------------------------------
+def spin_ops(s: float):
+    """(S_x, S_y, S_z) of spin s from the matrix elements of the standard
+    angular-momentum algebra, basis ordered m = s, s-1, ..., -s:
+        <m +- 1| S_x |m> = sqrt((s -+ m)(s +- m + 1)) / 2,
+        <m +- 1| S_y |m> = -+ i sqrt((s -+ m)(s +- m + 1)) / 2,   <m|S_z|m> = m."""
+    D = int(round(2 * s)) + 1
+    ms = [s - k for k in range(D)]
+    Sx = np.zeros((D, D), complex)
+    Sy = np.zeros((D, D), complex)
+    Sz = np.zeros((D, D), complex)
+    for c, m in enumerate(ms):
+        Sz[c, c] = m
+        for r, mp in enumerate(ms):
+            if abs(mp - (m + 1)) < 1e-9:
+                a = math.sqrt((s - m) * (s + m + 1)) / 2.0
+                Sx[r, c] += a
+                Sy[r, c] += -1j * a
+            elif abs(mp - (m - 1)) < 1e-9:
+                a = math.sqrt((s + m) * (s - m + 1)) / 2.0
+                Sx[r, c] += a
+                Sy[r, c] += 1j * a
+    return Sx, Sy, Sz
+
+
+def spin_drive(S, amplitudes, phases):
+    """Fourier coefficient of sum_i A_i cos(w t + phi_i) S_i (Eq. 7 read with
+    an imaginary exponent and axes x, y, z; cos amplitude -> half, as R8)."""
+    return sum(0.5 * a * np.exp(1j * ph) * Si for a, ph, Si in zip(amplitudes, phases, S))
 
 
 # ---------------------------------------------------------------------------
