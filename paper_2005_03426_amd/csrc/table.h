@@ -21,10 +21,11 @@ __global__ void table_set(T *dst, TableChunk<T, K> c) {
   if ((int)threadIdx.x < c.count) dst[threadIdx.x] = c.v[threadIdx.x];
 }
 
-// Writes host entries [0, count) into the device table, K entries per launch.
+// Writes host entries [0, count) into the device table, K entries per launch
+// (kernel arguments kept under 1 KiB).
 template <class T>
 inline int table_write(T *dev, const T *host, int64_t count, hipStream_t st) {
-  constexpr int K = (3072 / (int)sizeof(T)) > 0 ? (3072 / (int)sizeof(T)) : 1;
+  constexpr int K = (960 / (int)sizeof(T)) > 0 ? (960 / (int)sizeof(T)) : 1;
   for (int64_t base = 0; base < count; base += K) {
     TableChunk<T, K> c;
     c.count = (int32_t)((count - base < K) ? count - base : K);
