@@ -1,9 +1,11 @@
 // Dense Hermitian eigendecomposition H_F = Phi diag(w) Phi^H (the
 // diagonalisation step of Sec. 3.2): reduction to a real tridiagonal matrix,
 // divide and conquer on it, back-transformation, all on the caller's stream.
+#include <stdlib.h>
 #include <vector>
 #include "common.h"
 #include "stages.h"
+#include "twostage.h"
 
 namespace mmf {
 
@@ -88,6 +90,81 @@ inline WinWs win_ws(int64_t M, int64_t kmax, void *base) {
   return w;
 }
 
+// Two-stage path (dense -> band -> tridiagonal, two back-transformations),
+// taken from order two_stage_min() up: the one-stage reduction streams the
+// whole trailing matrix from HBM once per column, the two-stage one runs
+// almost all of its reduction flops on the matrix cores.
+constexpr int64_t TWO_STAGE_MIN_DEFAULT = 4096;
+
+inline int64_t two_stage_min() {
+  const char *s = getenv("MMF_EIGH_TWO_STAGE_MIN");
+  if (s && *s) {
+    const long long v = atoll(s);
+    return v < 0 ? 0 : (int64_t)v;
+  }
+  return TWO_STAGE_MIN_DEFAULT;
+}
+
+struct Eigh2Ws {
+  double *e;
+  mmf_z *tau1;
+  double *Z;
+  mmf_z *AB, *V2, *tau2;
+  double *wall, *Zk;          // window path only
+  void *rest;
+  size_t rest_bytes, bt1_bytes;
+  size_t bytes;
+};
+
+// nc: eigenvector columns back-transformed (M for the full solve); window: also
+// the gathered eigenvalues / tridiagonal eigenvectors of a window of nc columns.
+inline Eigh2Ws eigh2_ws(int64_t M, int64_t nc, bool window, void *base) {
+  Carver cv(base);
+  Eigh2Ws w;
+  const size_t n = (size_t)(M > 0 ? M : 1);
+  w.e = cv.take<double>(n);
+  w.tau1 = cv.take<mmf_z>(n);
+  w.Z = cv.take<double>(n * n);
+  w.AB = cv.take<mmf_z>(n * LDAB);
+  w.V2 = cv.take<mmf_z>(hb_v2_elems(M));
+  w.tau2 = cv.take<mmf_z>(hb_v2_elems(M) / BW + 1);
+  w.wall = window ? cv.take<double>(n) : nullptr;
+  w.Zk = window ? cv.take<double>(n * (size_t)(nc > 0 ? nc : 1)) : nullptr;
+  w.bt1_bytes = (unmtr_band_ws_bytes(M, nc) + 255) & ~(size_t)255;
+  size_t stage = he2hb_ws_bytes(M);
+  const size_t s2 = stedc_ws_bytes(M), s3 = w.bt1_bytes + bt2_ws_bytes(M, nc);
+  if (s2 > stage) stage = s2;
+  if (s3 > stage) stage = s3;
+  w.rest = cv.take<char>(stage);
+  w.rest_bytes = stage;
+  w.bytes = cv.used();
+  return w;
+}
+
+// Band reduction, bulge chase and divide and conquer: eigenvalues in w,
+// tridiagonal eigenvectors in ws.Z, stage-1 reflectors in A.
+inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh2Ws &ws, int32_t *dev_info,
+                         hipStream_t st) {
+  int rc = he2hb_run(M, A, lda, ws.tau1, ws.AB, ws.rest, ws.rest_bytes, st);
+  if (rc) return rc;
+  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, st);
+  if (rc) return rc;
+  return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st);
+}
+
+inline int eigh2_run(int64_t M, mmf_z *A, int64_t lda, double *w, void *work, int32_t *dev_info, hipStream_t st) {
+  const Eigh2Ws ws = eigh2_ws(M, M, false, work);
+  int rc = eigh2_tridiag(M, A, lda, w, ws, dev_info, st);
+  if (rc) return rc;
+  char *bt1 = (char *)ws.rest;
+  // copy the stage-1 reflectors out of A, then Phi = Q2 Z over A, then Phi <- Q1 Phi
+  rc = unmtr_band_run(M, M, A, lda, ws.tau1, A, lda, bt1, ws.bt1_bytes, st, 1);
+  if (rc) return rc;
+  rc = bt2_run(M, M, ws.V2, ws.tau2, ws.Z, M, A, lda, bt1 + ws.bt1_bytes, ws.rest_bytes - ws.bt1_bytes, st);
+  if (rc) return rc;
+  return unmtr_band_run(M, M, A, lda, ws.tau1, A, lda, bt1, ws.bt1_bytes, st, 2);
+}
+
 }  // namespace mmf
 
 using namespace mmf;
@@ -96,7 +173,8 @@ extern "C" int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes) {
   if (M < 0) return -1;
   if (prec != MMF_C128 && prec != MMF_C64_REFINED && prec != MMF_C64_RAW) return -2;
   if (!bytes) return -3;
-  size_t b = (prec == MMF_C128) ? eigh_ws(M, nullptr, 0).bytes
+  size_t b = (prec == MMF_C128) ? (M >= two_stage_min() ? eigh2_ws(M, M, false, nullptr).bytes
+                                                        : eigh_ws(M, nullptr, 0).bytes)
                                  : eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED);
   // every stage entry point accepts a workspace of this size
   const size_t s1 = hetrd_ws_bytes(M), s2 = stedc_ws_bytes(M), s3 = unmtr_ws_bytes(M);
@@ -120,6 +198,10 @@ extern "C" int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, v
   if (prec != MMF_C128) {
     if (work_bytes < eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED)) return -7;
     return eigh_c64_run(M, A, lda, w, prec == MMF_C64_REFINED, work, work_bytes, dev_info, st);
+  }
+  if (M > 0 && M >= two_stage_min()) {
+    if (work_bytes < eigh2_ws(M, M, false, nullptr).bytes) return -7;
+    return eigh2_run(M, A, lda, w, work, dev_info, st);
   }
   EighWs ws = eigh_ws(M, work, work_bytes);
   if (work_bytes < ws.bytes) return -7;
@@ -227,7 +309,8 @@ extern "C" int mmf_eigh_window_workspace(int64_t M, int64_t kmax, size_t *bytes)
   if (M < 0) return -1;
   if (kmax < 0) return -2;
   if (!bytes) return -3;
-  *bytes = win_ws(M, kmax < M ? kmax : M, nullptr).bytes;
+  const int64_t kk = kmax < M ? kmax : M;
+  *bytes = (M > 0 && M >= two_stage_min()) ? eigh2_ws(M, kk, true, nullptr).bytes : win_ws(M, kk, nullptr).bytes;
   return MMF_OK;
 }
 
@@ -245,11 +328,26 @@ extern "C" int mmf_eigh_window(int64_t M, mmf_z *A, int64_t lda, double vl, doub
   if (!count) return -10;
   if (!work) return -11;
   const int64_t kk = kmax < M ? kmax : M;
-  WinWs ws = win_ws(M, kk, work);
-  if (work_bytes < ws.bytes) return -12;
+  const bool two = M > 0 && M >= two_stage_min();
+  if (work_bytes < (two ? eigh2_ws(M, kk, true, nullptr).bytes : win_ws(M, kk, nullptr).bytes)) return -12;
   if (!dev_info) return -13;
   hipStream_t st = (hipStream_t)stream;
   if (M == 0) return MMF_OK;
+  if (two) {
+    const Eigh2Ws ws = eigh2_ws(M, kk, true, work);
+    int rc = eigh2_tridiag(M, A, lda, ws.wall, ws, dev_info, st);
+    if (rc) return rc;
+    const int64_t g = kk > 0 ? kk : 0;
+    hipLaunchKernelGGL(eigh_window_gather, dim3(g > 0 ? cdiv(M, 256) : 1, g > 0 ? (unsigned)g : 1),
+                       dim3(g > 0 ? 256 : 1), 0, st, M, ws.wall, ws.Z, vl, vu, g, w, ws.Zk, count);
+    MMF_LAUNCH_CHECK();
+    if (kk == 0) return MMF_OK;
+    char *bt1 = (char *)ws.rest;
+    rc = bt2_run(M, kk, ws.V2, ws.tau2, ws.Zk, M, Z, ldz, bt1 + ws.bt1_bytes, ws.rest_bytes - ws.bt1_bytes, st);
+    if (rc) return rc;
+    return unmtr_band_run(M, kk, A, lda, ws.tau1, Z, ldz, bt1, ws.bt1_bytes, st, 3);
+  }
+  WinWs ws = win_ws(M, kk, work);
   int rc = hetrd_run(M, A, lda, ws.wall, ws.e.e, ws.e.tau, ws.e.rest, ws.e.rest_bytes, st);
   if (rc) return rc;
   rc = stedc_run(M, ws.wall, ws.e.e, ws.e.Z, M, ws.e.rest, ws.e.rest_bytes, dev_info, st);

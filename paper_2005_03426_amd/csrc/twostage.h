@@ -1,0 +1,45 @@
+// Internal interface of the two-stage Hermitian eigensolver (dense -> band ->
+// real tridiagonal) and its two back-transformations.
+#pragma once
+#include "common.h"
+
+namespace mmf {
+
+constexpr int BW = 64;            // half-bandwidth of the intermediate band matrix
+constexpr int LDAB = 2 * BW;      // rows of the band array (band + room for the bulges)
+constexpr int BT2_G = 64;         // sweeps per block of the second back-transformation
+
+// Stage 1: A (n x n, lower triangle read) -> band; reflectors stay below the
+// band of A (column c: rows c + BW + 1 .., unit at row c + BW), tau[0 .. n-2];
+// the band goes to AB (n x LDAB).
+size_t he2hb_ws_bytes(int64_t n);
+int he2hb_run(int64_t n, mmf_z *A, int64_t lda, mmf_z *tau, mmf_z *AB, void *work, size_t bytes,
+              hipStream_t st);
+
+// Stage 2: band AB -> real tridiagonal (d, e) by bulge chasing; reflector
+// (sweep s, position k) is stored at V2[hb_voff(n, k) + s BW + 0 .. BW-1]
+// (zero padded), its tau at tau2[hb_voff(n, k) / BW + s].
+__host__ __device__ inline int64_t hb_voff(int64_t n, int64_t k) {
+  // sum over positions k' < k of (n - 1 - k' BW) sweeps, BW entries each
+  return (int64_t)BW * (k * (n - 1) - (int64_t)BW * (k * (k - 1) / 2));
+}
+inline int64_t hb_npos(int64_t n) { return n > 1 ? (n - 2) / BW + 1 : 0; }
+inline size_t hb_v2_elems(int64_t n) { return n > 1 ? (size_t)hb_voff(n, hb_npos(n)) : 1; }
+size_t hb2st_ws_bytes(int64_t n);
+int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, hipStream_t st);
+
+// Second back-transformation Phi = Q2 Z: Phi (n x nc, ld ldphi, complex) is
+// set from the real Z (n x nc, ld ldz) and the stage-2 reflectors are applied
+// in blocks of BT2_G sweeps.
+size_t bt2_ws_bytes(int64_t n, int64_t nc);
+int bt2_run(int64_t n, int64_t nc, const mmf_z *V2, const mmf_z *tau2, const double *Z, int64_t ldz,
+            mmf_z *Phi, int64_t ldphi, void *work, size_t bytes, hipStream_t st);
+
+// First back-transformation (stage-1 reflectors of A) applied in place to
+// Phi (n x nc); phases: bit 0 copies the reflectors out of A (so Phi may
+// overwrite A afterwards), bit 1 applies them.
+size_t unmtr_band_ws_bytes(int64_t n, int64_t nc);
+int unmtr_band_run(int64_t n, int64_t nc, const mmf_z *A, int64_t lda, const mmf_z *tau, mmf_z *Phi,
+                   int64_t ldphi, void *work, size_t bytes, hipStream_t st, int phases);
+
+}  // namespace mmf

@@ -21,6 +21,7 @@
 #include <vector>
 #include "common.h"
 #include "stages.h"
+#include "twostage.h"
 #include "gemm_core.h"
 #include "table.h"
 
@@ -44,17 +45,19 @@ __host__ __device__ inline int64_t bt_off(int64_t n, int64_t b) {
   return BT_NB * (b * (n - 1) - (int64_t)BT_NB * (b * (b - 1) / 2));
 }
 
+// nc: columns of Phi (n when negative); the split-K buffers hold nc columns.
 template <typename R>
-inline BtWs<R> unmtr_ws(int64_t n, void *base) {
+inline BtWs<R> unmtr_ws(int64_t n, void *base, int64_t nc = -1) {
   Carver cv(base);
   BtWs<R> w;
+  const int64_t ncol = nc >= 0 ? nc : n;
   w.nblk = n > 1 ? (n - 1 + BT_NB - 1) / BT_NB : 0;
   w.nsplit = (n + BT_KCHUNK - 1) / BT_KCHUNK;
   if (w.nsplit < 1) w.nsplit = 1;
   w.Vp = cv.take<cx<R>>((size_t)(w.nblk ? bt_off(n, w.nblk) : 1));
   w.Tm = cv.take<cx<R>>((size_t)(w.nblk ? w.nblk : 1) * BT_NB * BT_NB);
-  w.Wpart = cv.take<cx<R>>((size_t)w.nsplit * BT_NB * (n > 0 ? n : 1));
-  w.W2 = cv.take<cx<R>>((size_t)BT_NB * (n > 0 ? n : 1));
+  w.Wpart = cv.take<cx<R>>((size_t)w.nsplit * BT_NB * (ncol > 0 ? ncol : 1));
+  w.W2 = cv.take<cx<R>>((size_t)BT_NB * (ncol > 0 ? ncol : 1));
   w.Gpart = cv.take<cx<R>>((size_t)(w.nblk ? w.nblk : 1) * w.nsplit * BT_NB * BT_NB);
   w.bytes = cv.used();
   return w;
@@ -250,10 +253,12 @@ __global__ void __launch_bounds__(GEMM_THREADS) bt_update(const BtProb<R> *pr, i
   gemm_tile_t<R, true, A_N, B_N>(u, m0, n0, lds);
 }
 
-// Phi = Z (complex); grid y walks 64-column chunks.
+// Phi = Z (complex); grid y walks 64-column chunks.  Without Z, Phi already
+// holds the matrix to transform.
 template <typename R>
 __global__ void bt_init_phi(const BtProb<R> *pr) {
   const BtProb<R> &P = pr[blockIdx.z];
+  if (!P.Z) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = P.n;
   if (r >= n) return;
@@ -264,12 +269,15 @@ __global__ void bt_init_phi(const BtProb<R> *pr) {
 
 // Grouped back-transformation of `count` problems (orders nh[], host copy;
 // ncmax >= every problem's column count, default the largest order).
+// phases: bit 0 copies the reflectors and forms the T factors, bit 1 sets
+// Phi and applies the blocks (the copy lets Phi overwrite V in between).
 template <typename R>
-int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStream_t st, int64_t ncmax = -1) {
+int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStream_t st, int64_t ncmax = -1,
+                  int phases = 3) {
   if (count <= 0) return MMF_OK;
   if (count > 65535) {
     for (int64_t b = 0; b < count; b += 65535) {
-      const int rc = unmtr_grouped<R>(pr + b, nh + b, count - b < 65535 ? count - b : 65535, st, ncmax);
+      const int rc = unmtr_grouped<R>(pr + b, nh + b, count - b < 65535 ? count - b : 65535, st, ncmax, phases);
       if (rc) return rc;
     }
     return MMF_OK;
@@ -283,7 +291,7 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
   const int64_t nblk = nmax > 1 ? (nmax - 1 + BT_NB - 1) / BT_NB : 0;
   const int64_t nsplit = (nmax + BT_KCHUNK - 1) / BT_KCHUNK;
   // 1. clean copies of every reflector block (Phi may alias V)
-  if (nblk > 0) {
+  if (nblk > 0 && (phases & 1)) {
     hipLaunchKernelGGL(bt_pack<R>, dim3(cdiv(nmax - 1, 256), (unsigned)nblk, Z), dim3(256), 0, st, pr);
     MMF_LAUNCH_CHECK();
     // 2. T factors
@@ -295,6 +303,7 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
     hipLaunchKernelGGL(bt_tcross<R>, dim3((unsigned)nblk, 1, Z), dim3(256), 0, st, pr);
     MMF_LAUNCH_CHECK();
   }
+  if (!(phases & 2)) return MMF_OK;
   // 3. Phi = Z (complex)
   hipLaunchKernelGGL(bt_init_phi<R>, dim3(cdiv(nmax, 256), cdiv(ncols, 64), Z), dim3(256), 0, st, pr);
   MMF_LAUNCH_CHECK();
@@ -317,7 +326,7 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
 template <typename R>
 inline BtProb<R> bt_prob(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *tau, const double *Z,
                          int64_t ldz, cx<R> *Phi, int64_t ldphi, void *ws, int64_t nc = -1) {
-  const BtWs<R> w = unmtr_ws<R>(n, ws);
+  const BtWs<R> w = unmtr_ws<R>(n, ws, nc);
   BtProb<R> q;
   q.n = n; q.nc = nc >= 0 ? nc : n; q.ldv = ldv; q.ldz = ldz; q.ldphi = ldphi; q.nblk = w.nblk; q.nsplit = w.nsplit;
   q.V = V; q.tau = tau; q.Z = Z; q.Phi = Phi;
@@ -381,6 +390,31 @@ int unmtr_cols_run(int64_t n, int64_t nc, const mmf_z *V, int64_t ldv, const mmf
   const int rc = table_write(pr, &q, 1, st);
   if (rc) return rc;
   return unmtr_grouped<double>(pr, &n, 1, st, nc);
+}
+
+// Back-transformation by the stage-1 reflectors of the two-stage reduction
+// (reflector c below the band of A: unit at row c + BW).  This is the
+// tridiagonal form's back-transformation on the matrix shifted by BW - 1 rows:
+// order n - BW + 1, V = A + BW - 1, Phi rows BW - 1 .. (all nc columns); Phi
+// already holds the input.  phases as for unmtr_grouped.
+size_t unmtr_band_ws_bytes(int64_t n, int64_t nc) {
+  const int64_t ns = n - BW + 1;
+  return unmtr_ws<double>(ns > 1 ? ns : 1, nullptr, nc).bytes + BT_TABLE_BYTES;
+}
+
+int unmtr_band_run(int64_t n, int64_t nc, const mmf_z *A, int64_t lda, const mmf_z *tau, mmf_z *Phi,
+                   int64_t ldphi, void *work, size_t bytes, hipStream_t st, int phases) {
+  const int64_t ns = n - BW + 1;
+  if (ns <= 1 || nc <= 0) return MMF_OK;
+  if (bytes < unmtr_band_ws_bytes(n, nc)) return MMF_ERR_WORKSPACE;
+  BtProb<double> *pr = reinterpret_cast<BtProb<double> *>(work);
+  const BtProb<double> q = bt_prob<double>(ns, reinterpret_cast<const cd *>(A) + (BW - 1), lda,
+                                           reinterpret_cast<const cd *>(tau), nullptr, 0,
+                                           reinterpret_cast<cd *>(Phi) + (BW - 1), ldphi,
+                                           (char *)work + BT_TABLE_BYTES, nc);
+  const int rc = table_write(pr, &q, 1, st);
+  if (rc) return rc;
+  return unmtr_grouped<double>(pr, &ns, 1, st, nc, phases);
 }
 
 int unmtr_run(int64_t n, const mmf_z *V, int64_t ldv, const mmf_z *tau, const double *Z, int64_t ldz,
