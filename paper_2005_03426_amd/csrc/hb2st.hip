@@ -24,38 +24,28 @@
 // H_{s',k} and H_{s',k-1} for s' > s.  Blocks B_{G,k} of the BT2_G sweeps
 // s0 = G BT2_G .. at position k (rows [s0 + 1 + k BW, s0 + k BW + BW + BT2_G - 1),
 // reflector j shifted down by j rows) are therefore applied in the order
-// G descending, k ascending, each as I - V T V^H (compact WY), and blocks with
-// equal k + (Gmax - G) are row-disjoint: they form one launch step.
+// G descending, k ascending (inside a block: sweep descending), and blocks
+// with equal k + (Gmax - G) are row-disjoint: they form one launch step.
 #include <vector>
 #include "common.h"
 #include "twostage.h"
-#include "gemm_core.h"
 
 namespace mmf {
 
 // ---------------------------------------------------------------- chase
-__device__ inline cd chase_csum(cd v, double *sh) {
-  double re = wave_sum(v.re), im = wave_sum(v.im);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) { sh[2 * wv] = re; sh[2 * wv + 1] = im; }
-  __syncthreads();
-  return cmake((sh[0] + sh[2]) + (sh[4] + sh[6]), (sh[1] + sh[3]) + (sh[5] + sh[7]));
-}
-
-// Householder vector of x (length len <= BW, x[0] = alpha): H^H x = beta e0,
-// beta real.  Every thread calls it (thread i < BW holds x_i, the others a
-// copy); lane i < len gets v_i; tau and beta are returned to all.  The identity (tau = 0) when x is already real e0.
-__device__ inline cd chase_larfg(cd xi, int i, int len, double *sh, cd *bc, cd &tau, double &beta) {
-  const cd alpha = bc[0];
-  const double xn2 = chase_csum(cmake((threadIdx.x < BW && i >= 1 && i < len) ? cabs2(xi) : 0.0, 0.0), sh).re;
+// Householder vector of x held by the 64 lanes of one wavefront (lane i: x_i,
+// len <= BW entries): H^H x = beta e0, beta real, v_0 = 1.  The identity
+// (tau = 0) when x is already real e0.
+__device__ inline cd wave_larfg(cd xi, int i, int len, cd &tau, double &beta) {
+  const double are = __shfl(xi.re, 0, 64), aim = __shfl(xi.im, 0, 64);
+  const double xn2 = wave_sum((i >= 1 && i < len) ? cabs2(xi) : 0.0);
   tau = cmake(0.0, 0.0);
-  beta = alpha.re;
-  if (xn2 == 0.0 && alpha.im == 0.0) return (i == 0) ? cmake(1.0, 0.0) : cmake(0.0, 0.0);
-  const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
-  beta = alpha.re >= 0.0 ? -nrm : nrm;
-  tau = cmake((beta - alpha.re) / beta, -alpha.im / beta);
-  const cd am = cmake(alpha.re - beta, alpha.im);
+  beta = are;
+  if (xn2 == 0.0 && aim == 0.0) return (i == 0) ? cmake(1.0, 0.0) : cmake(0.0, 0.0);
+  const double nrm = sqrt(are * are + aim * aim + xn2);
+  beta = are >= 0.0 ? -nrm : nrm;
+  tau = cmake((beta - are) / beta, -aim / beta);
+  const cd am = cmake(are - beta, aim);
   const double den = am.re * am.re + am.im * am.im;
   const cd scale = cmake(am.re / den, -am.im / den);
   if (i == 0) return cmake(1.0, 0.0);
@@ -63,12 +53,14 @@ __device__ inline cd chase_larfg(cd xi, int i, int len, double *sh, cd *bc, cd &
 }
 
 // One step of the pipelined chase: task (s, k = t - 2 s) for s = smin + blockIdx.x.
+// Thread (i, q) = (tid % 64, tid / 64); the scalar work (reflectors, sums over
+// 64 entries) stays in wavefront 0.
 __global__ void __launch_bounds__(256) hb_chase(int64_t n, cd *AB, cd *V2, cd *tau2, int64_t t, int64_t smin) {
   __shared__ cd D[BW][BW + 1];
   __shared__ cd E[BW][BW + 1];
-  __shared__ cd vs[BW], v2[BW], wv[BW], red[4][BW];
-  __shared__ cd bc[2];
-  __shared__ double sh[8];
+  __shared__ cd vs[BW], v2[BW], wv[BW], zz[BW], red[4][BW], red2[4][BW];
+  __shared__ cd tsh[2];
+  __shared__ double bsh[2];
   const int64_t s = smin + blockIdx.x;
   const int64_t k = t - 2 * s;
   const int64_t r0 = s + 1 + k * BW;
@@ -77,59 +69,77 @@ __global__ void __launch_bounds__(256) hb_chase(int64_t n, cd *AB, cd *V2, cd *t
   const int tid = threadIdx.x, i = tid & 63, q = tid >> 6;
   const int64_t voff = hb_voff(n, k) + s * BW;
   const int64_t toff = hb_voff(n, k) / BW + s;
+  const int64_t e0 = r0 + L;
+  const bool hasE = e0 <= n - 1;          // uniform (then L = BW)
+  const int Le = hasE ? (int)((n - e0 < BW) ? n - e0 : BW) : 0;
 
-  // ---- current reflector H_{s,k}
-  cd tau;
-  if (k == 0) {
-    cd *col = AB + s * (int64_t)LDAB;
-    const cd xi = (i < L) ? col[1 + i] : cmake(0.0, 0.0);
-    if (tid == 0) bc[0] = xi;
-    __syncthreads();
-    double beta;
-    const cd v = chase_larfg(xi, i, L, sh, bc, tau, beta);
-    if (tid < BW) {
+  // ---- all global loads first: column s or the current reflector, the lower
+  // band of D_k, the block E_k
+  cd *col = AB + s * (int64_t)LDAB;
+  cd xi = cmake(0.0, 0.0);
+  if (q == 0) xi = (k == 0) ? ((i < L) ? col[1 + i] : cmake(0.0, 0.0)) : V2[voff + i];
+  cd dreg[16], ereg[16];
+#pragma unroll
+  for (int q2 = 0; q2 < 16; ++q2) {
+    const int e = tid + 256 * q2, ii = e & 63, jj = e >> 6;
+    dreg[q2] = (ii >= jj && ii < L) ? AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
+  }
+#pragma unroll
+  for (int q2 = 0; q2 < 16; ++q2) {
+    const int e = tid + 256 * q2, ii = e & 63, jj = e >> 6;
+    ereg[q2] = (hasE && ii < Le) ? AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
+  }
+  // ---- current reflector H = H_{s,k} (wavefront 0)
+  if (q == 0) {
+    if (k == 0) {
+      cd tau;
+      double beta;
+      const cd v = wave_larfg(xi, i, L, tau, beta);
       vs[i] = v;
       V2[voff + i] = v;
       if (i < L) col[1 + i] = (i == 0) ? cmake(beta, 0.0) : cmake(0.0, 0.0);
-    }
-    if (tid == 0) tau2[toff] = tau;
-  } else {
-    if (tid < BW) vs[i] = V2[voff + i];
-    tau = tau2[toff];
-  }
-  // ---- D_k (Hermitian, from its lower band)
-  for (int e = tid; e < BW * BW; e += 256) {
-    const int ii = e & 63, jj = e >> 6;
-    if (ii >= jj && ii < L) D[ii][jj] = AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB];
-  }
-  __syncthreads();
-  for (int e = tid; e < BW * BW; e += 256) {
-    const int ii = e & 63, jj = e >> 6;
-    if (ii < L && jj < L) {
-      if (ii < jj) D[ii][jj] = cconj(D[jj][ii]);
-      else if (ii == jj) D[ii][ii].im = 0.0;
+      if (i == 0) { tau2[toff] = tau; tsh[0] = tau; }
+    } else {
+      vs[i] = xi;
+      if (i == 0) tsh[0] = tau2[toff];
     }
   }
+#pragma unroll
+  for (int q2 = 0; q2 < 16; ++q2) {
+    const int e = tid + 256 * q2, ii = e & 63, jj = e >> 6;
+    if (ii >= jj) D[ii][jj] = dreg[q2];
+    E[ii][jj] = ereg[q2];
+  }
   __syncthreads();
-  // y = D v (row i, quarter q of the columns)
+  const cd tau = tsh[0];
+  // ---- y = D v from the lower triangle, z = E v (row i, quarter q of the columns)
   {
-    cd p = cmake(0.0, 0.0);
-    if (i < L)
-      for (int jj = 16 * q; jj < 16 * q + 16 && jj < L; ++jj) p = cadd(p, cmul(D[i][jj], vs[jj]));
-    red[q][i] = p;
+    cd py = cmake(0.0, 0.0), pz = cmake(0.0, 0.0);
+    for (int jj = 16 * q; jj < 16 * q + 16; ++jj) {
+      const cd vj = vs[jj];
+      if (i < L && jj < L) {
+        cd h = (jj <= i) ? D[i][jj] : cconj(D[jj][i]);
+        if (jj == i) h.im = 0.0;
+        py = cadd(py, cmul(h, vj));
+      }
+      pz = cadd(pz, cmul(E[i][jj], vj));
+    }
+    red[q][i] = py;
+    red2[q][i] = pz;
   }
   __syncthreads();
-  cd y = cmake(0.0, 0.0);
-  if (tid < BW) y = cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i]));
-  // gamma = v^H y (real); w = tau y - (|tau|^2 gamma / 2) v
-  const double gamma = chase_csum((tid < BW && i < L) ? cmulc(vs[i], y) : cmake(0.0, 0.0), sh).re;
-  if (tid < BW) {
+  // ---- w = tau y - (|tau|^2 gamma / 2) v, gamma = v^H y;  zz = tau z (wavefront 0)
+  if (q == 0) {
+    const cd y = cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i]));
+    const cd v = vs[i];
+    const double gamma = wave_sum(i < L ? cmulc(v, y).re : 0.0);
     const double h = 0.5 * cabs2(tau) * gamma;
     const cd ty = cmul(tau, y);
-    wv[i] = cmake(ty.re - h * vs[i].re, ty.im - h * vs[i].im);
+    wv[i] = cmake(ty.re - h * v.re, ty.im - h * v.im);
+    zz[i] = cmul(tau, cadd(cadd(red2[0][i], red2[1][i]), cadd(red2[2][i], red2[3][i])));
   }
   __syncthreads();
-  // D <- D - w v^H - v w^H (lower band written back)
+  // ---- D <- D - w v^H - v w^H (lower band to AB); E <- E - (tau z) v^H
   for (int e = tid; e < BW * BW; e += 256) {
     const int ii = e & 63, jj = e >> 6;
     if (ii >= jj && ii < L) {
@@ -137,69 +147,45 @@ __global__ void __launch_bounds__(256) hb_chase(int64_t n, cd *AB, cd *V2, cd *t
       if (ii == jj) d.im = 0.0;
       AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB] = d;
     }
+    if (hasE) E[ii][jj] = csub(E[ii][jj], cmul(zz[ii], cconj(vs[jj])));
   }
-  // ---- E_k
-  const int64_t e0 = r0 + L;
-  if (e0 > n - 1) return;                 // uniform: no block below
-  const int Le = (int)((n - e0 < BW) ? n - e0 : BW);
-  for (int e = tid; e < BW * BW; e += 256) {
-    const int ii = e & 63, jj = e >> 6;
-    E[ii][jj] = (ii < Le) ? AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
-  }
+  if (!hasE) return;                      // uniform: no block below
   __syncthreads();
-  // z = E v ; E <- E - tau z v^H
-  {
-    cd p = cmake(0.0, 0.0);
-    for (int jj = 16 * q; jj < 16 * q + 16; ++jj) p = cadd(p, cmul(E[i][jj], vs[jj]));
-    red[q][i] = p;
+  // ---- H_{s,k+1} from the first column of E (wavefront 0)
+  if (q == 0) {
+    const cd x = (i < Le) ? E[i][0] : cmake(0.0, 0.0);
+    cd t1 = cmake(0.0, 0.0);
+    double b1 = x.re;
+    cd v = (i == 0) ? cmake(1.0, 0.0) : cmake(0.0, 0.0);
+    if (Le >= 2) v = wave_larfg(x, i, Le, t1, b1);
+    v2[i] = v;
+    if (i == 0) { tsh[1] = t1; bsh[0] = b1; }
   }
   __syncthreads();
-  if (tid < BW) wv[i] = cmul(tau, cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i])));
-  __syncthreads();
-  for (int e = tid; e < BW * BW; e += 256) {
-    const int ii = e & 63, jj = e >> 6;
-    E[ii][jj] = csub(E[ii][jj], cmul(wv[ii], cconj(vs[jj])));
-  }
-  __syncthreads();
-  // H_{s,k+1} from the first column of E
-  cd tau1 = cmake(0.0, 0.0);
-  double beta1 = 0.0;
-  {
-    const cd xi = (i < Le) ? E[i][0] : cmake(0.0, 0.0);
-    if (tid == 0) bc[0] = xi;
-    __syncthreads();
-    cd v = cmake(0.0, 0.0);
-    if (Le >= 2) {
-      v = chase_larfg(xi, i, Le, sh, bc, tau1, beta1);
-    } else {
-      v = (i == 0) ? cmake(1.0, 0.0) : cmake(0.0, 0.0);
-      beta1 = bc[0].re;
-    }
-    if (tid < BW) v2[i] = v;
-  }
-  __syncthreads();
-  const bool active = (Le >= 2) && (tau1.re != 0.0 || tau1.im != 0.0);
+  const cd tau1 = tsh[1];
+  const double beta1 = bsh[0];
+  const bool active = (Le >= 2) && (tau1.re != 0.0 || tau1.im != 0.0);     // uniform
   if (active) {
     // u_j = v2^H E[:, j] (column j = i, quarter q of the rows)
     cd p = cmake(0.0, 0.0);
     for (int ii = 16 * q; ii < 16 * q + 16; ++ii) p = cadd(p, cmulc(v2[ii], E[ii][i]));
     red[q][i] = p;
     __syncthreads();
-    if (tid < BW) wv[i] = cmulc(tau1, cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i])));
-    __syncthreads();
-    for (int e = tid; e < BW * BW; e += 256) {
-      const int ii = e & 63, jj = e >> 6;
-      if (jj == 0) E[ii][0] = (ii == 0) ? cmake(beta1, 0.0) : cmake(0.0, 0.0);
-      else E[ii][jj] = csub(E[ii][jj], cmul(v2[ii], wv[jj]));
-    }
+    if (q == 0) wv[i] = cmulc(tau1, cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i])));
     __syncthreads();
   }
   for (int e = tid; e < BW * BW; e += 256) {
     const int ii = e & 63, jj = e >> 6;
-    if (ii < Le) AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] = E[ii][jj];
+    if (ii >= Le) continue;
+    cd x = E[ii][jj];
+    if (active) {
+      if (jj == 0) x = (ii == 0) ? cmake(beta1, 0.0) : cmake(0.0, 0.0);
+      else x = csub(x, cmul(v2[ii], wv[jj]));
+    }
+    AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] = x;
   }
   const int64_t voff1 = hb_voff(n, k + 1) + s * BW;
-  if (tid < BW) V2[voff1 + i] = v2[i];
+  if (q == 0) V2[voff1 + i] = v2[i];
   if (tid == 0) tau2[hb_voff(n, k + 1) / BW + s] = tau1;
 }
 
@@ -234,110 +220,98 @@ int hb2st_run(int64_t n, mmf_z *ABz, mmf_z *V2z, mmf_z *tau2z, double *d, double
 }
 
 // ---------------------------------------------------------------- back-transformation
-constexpr int BT2_LV = 128;        // rows of a block's dense V (BW + BT2_G - 1, padded)
-constexpr int BT2_CHUNK = 32;      // blocks per launch
+constexpr int BT2_CHUNK = 64;      // blocks per launch
 
-struct Bt2Ws {
-  cd *Vd;    // BT2_CHUNK x BT2_LV x BT2_G: dense V of the launch's blocks
-  cd *VT;    // BT2_CHUNK x BT2_LV x BT2_G: V T
-  cd *W;     // BT2_CHUNK x ntile x BT2_G x 64: V^H Phi per column tile
-  int64_t ntile;
-  size_t bytes;
-};
+size_t bt2_ws_bytes(int64_t n, int64_t nc) { (void)n; (void)nc; return 256; }
 
-inline Bt2Ws bt2_ws(int64_t n, int64_t nc, void *base) {
-  (void)n;
-  Carver cv(base);
-  Bt2Ws w;
-  w.ntile = nc > 0 ? (nc + 63) / 64 : 1;
-  w.Vd = cv.take<cd>((size_t)BT2_CHUNK * BT2_LV * BT2_G);
-  w.VT = cv.take<cd>((size_t)BT2_CHUNK * BT2_LV * BT2_G);
-  w.W = cv.take<cd>((size_t)BT2_CHUNK * w.ntile * BT2_G * 64);
-  w.bytes = cv.used();
-  return w;
-}
+// Apply the launch's blocks to Phi with vector FMAs, one reflector at a time
+// (exactly 8 n^3 real flops over the whole back-transformation; on this GPU
+// the FP64 vector rate equals the FP64 matrix-core rate, and the compact-WY
+// form of these parallelogram blocks would execute twice the flops).
+// Workgroup (column tile x, block y); wavefront w owns 16 columns, lane l
+// column 16 w + l / 4 and the rows rho + 4 u (rho = l % 4) of a sliding
+// window of 17 slots.  The block's reflectors j = 63 .. 0 (sweep s0 + j, rows
+// j .. j + 63 of the block) are applied in groups of four; after a group the
+// window moves up four rows: its last slot is final and goes to HBM, a new
+// first slot is read.  v^H x is summed over the four lanes of a column.
+constexpr int BT2_VPAD = BW + 8;          // LDS row of a reflector: 4 zeros, v, 4 zeros
 
-size_t bt2_ws_bytes(int64_t n, int64_t nc) { return bt2_ws(n, nc, nullptr).bytes; }
-
-// Dense V, T and V T of block (G = g0 - blockIdx.x * ... ) : the launch covers
-// blocks G = Gb - blockIdx.x at position k = tau - (Gmax - G).
-__global__ void __launch_bounds__(256) bt2_prep(int64_t n, const cd *V2, const cd *tau2, int64_t Gmax, int64_t step,
-                                                int64_t Gb, Bt2Ws ws) {
-  __shared__ cd G[BT2_G][BT2_G + 1];
-  __shared__ cd T[BT2_G][BT2_G + 1];
-  const int64_t Gi = Gb - blockIdx.x;
-  const int64_t k = step - (Gmax - Gi);
-  const int64_t s0 = Gi * BT2_G;
-  const int64_t base = hb_voff(n, k);
-  const int64_t smax = n - 2 - k * BW;            // last sweep with position k
-  cd *Vd = ws.Vd + (int64_t)blockIdx.x * BT2_LV * BT2_G;
-  cd *VT = ws.VT + (int64_t)blockIdx.x * BT2_LV * BT2_G;
-  const int tid = threadIdx.x;
-  // dense V (column j: sweep s0 + j, rows j .. j + BW - 1)
-  for (int e = tid; e < BT2_LV * BT2_G; e += 256) {
-    const int r = e % BT2_LV, j = e / BT2_LV;
-    cd v = cmake(0.0, 0.0);
-    if (s0 + j <= smax && r >= j && r - j < BW) v = V2[base + (s0 + j) * BW + (r - j)];
-    Vd[e] = v;
-  }
-  // Gram G[a][b] = v_a^H v_b for a < b (overlap rows b .. a + BW - 1)
-  for (int e = tid; e < BT2_G * BT2_G; e += 256) {
-    const int a = e % BT2_G, b = e / BT2_G;
-    cd s = cmake(0.0, 0.0);
-    if (a < b && b - a < BW && s0 + b <= smax) {
-      const cd *va = V2 + base + (s0 + a) * BW, *vb = V2 + base + (s0 + b) * BW;
-      for (int l = 0; l < BW - (b - a); ++l) s = cadd(s, cmulc(va[l + (b - a)], vb[l]));
-    }
-    G[a][b] = s;
-    T[a][b] = cmake(0.0, 0.0);
-  }
-  __syncthreads();
-  const int r = tid;
-  for (int kk = 0; kk < BT2_G; ++kk) {
-    const cd tk = (s0 + kk <= smax) ? tau2[base / BW + s0 + kk] : cmake(0.0, 0.0);
-    cd s = cmake(0.0, 0.0);
-    if (r < kk)
-      for (int j = r; j < kk; ++j) s = cadd(s, cmul(T[r][j], G[j][kk]));
-    __syncthreads();
-    if (r < kk) T[r][kk] = cscale(cmul(tk, s), -1.0);
-    if (r == kk) T[r][kk] = tk;
-    __syncthreads();
-  }
-  // V T (V read back from the dense copy written above by this workgroup)
-  __syncthreads();
-  for (int e = tid; e < BT2_LV * BT2_G; e += 256) {
-    const int rr = e % BT2_LV, c = e / BT2_LV;
-    cd s = cmake(0.0, 0.0);
-    const int jlo = rr - BW + 1 > 0 ? rr - BW + 1 : 0;
-    for (int j = jlo; j <= c && j <= rr; ++j) s = cadd(s, cmul(Vd[rr + j * BT2_LV], T[j][c]));
-    VT[e] = s;
-  }
-}
-
-// Apply the launch's blocks to Phi: workgroup (column tile x, block y):
-// W = V^H Phi[rows, tile], then Phi[rows, tile] -= (V T) W.
-__global__ void __launch_bounds__(GEMM_THREADS) bt2_apply(int64_t n, int64_t nc, cd *Phi, int64_t ldphi,
-                                                          int64_t Gmax, int64_t step, int64_t Gb, Bt2Ws ws) {
-  __shared__ double lds[GEMM_LDS_ELEMS];
+__global__ void __launch_bounds__(256) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *tau2, cd *Phi,
+                                                 int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb) {
+  __shared__ cd vsh[BT2_G][BT2_VPAD];
+  __shared__ cd tsh[BT2_G];
   const int64_t Gi = Gb - blockIdx.y;
   const int64_t k = step - (Gmax - Gi);
-  const int64_t R0 = Gi * BT2_G + 1 + k * BW;
+  const int64_t s0 = Gi * BT2_G;
+  const int64_t R0 = s0 + 1 + k * BW;
   const int64_t Lr = (n - R0 < BW + BT2_G - 1) ? n - R0 : BW + BT2_G - 1;
-  const int64_t n0 = (int64_t)blockIdx.x * 64;
-  if (Lr <= 0 || n0 >= nc) return;
-  const int64_t ncol = (nc - n0 < 64) ? nc - n0 : 64;
-  const cd *Vd = ws.Vd + (int64_t)blockIdx.y * BT2_LV * BT2_G;
-  const cd *VT = ws.VT + (int64_t)blockIdx.y * BT2_LV * BT2_G;
-  cd *W = ws.W + ((int64_t)blockIdx.y * ws.ntile + blockIdx.x) * BT2_G * 64;
-  cd *P = Phi + R0 + n0 * ldphi;
-  GemmArgs g1 = gemm_args(BT2_G, ncol, Lr, Vd, BT2_LV, P, ldphi, W, BT2_G, 1.0, 0.0, 0.0, 0.0);
-  gemm_tile<true, A_C, B_N>(g1, 0, 0, lds);
+  const int64_t base = hb_voff(n, k);
+  const int64_t smax = n - 2 - k * BW;            // last sweep with position k
+  const int tid = threadIdx.x;
+  for (int e = tid; e < BT2_G * BT2_VPAD; e += 256) {
+    const int j = e / BT2_VPAD, idx = e % BT2_VPAD - 4;
+    cd v = cmake(0.0, 0.0);
+    if (idx >= 0 && idx < BW && s0 + j <= smax) v = V2[base + (s0 + j) * BW + idx];
+    vsh[j][e % BT2_VPAD] = v;
+  }
+  if (tid < BT2_G) tsh[tid] = (s0 + tid <= smax) ? tau2[base / BW + s0 + tid] : cmake(0.0, 0.0);
   __syncthreads();
-  GemmArgs g2 = gemm_args(Lr, ncol, BT2_G, VT, BT2_LV, W, BT2_G, P, ldphi, -1.0, 0.0, 1.0, 0.0);
-  gemm_tile<true, A_N, B_N>(g2, 0, 0, lds);
-  if (Lr > 64) {
-    __syncthreads();
-    gemm_tile<true, A_N, B_N>(g2, 64, 0, lds);
+  const int lane = tid & 63, wave = tid >> 6, rho = lane & 3;
+  const int64_t col = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 2);
+  const bool cok = col < nc;
+  cd *P = Phi + R0 + (cok ? col : 0) * ldphi;
+  cd x[17];
+  // window of the first group (j = 63 .. 60): rows 60 + rho + 4 u
+#pragma unroll
+  for (int u = 0; u < 17; ++u) {
+    const int row = 60 + rho + 4 * u;
+    x[u] = (cok && row < Lr) ? P[row] : cmake(0.0, 0.0);
+  }
+  for (int a = BT2_G / 4 - 1; a >= 0; --a) {
+#pragma unroll
+    for (int b = 3; b >= 0; --b) {
+      const int j = 4 * a + b;
+      const cd tj = tsh[j];
+      if (tj.re == 0.0 && tj.im == 0.0) continue;        // uniform
+      // slot u holds row 4 a + rho + 4 u, i.e. entry rho + 4 u - b of v_j
+      const cd *vj = &vsh[j][rho - b + 4];
+      cd vv[17];
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int u = 0; u < 17; ++u) {
+        vv[u] = vj[4 * u];
+        dr = fma(vv[u].re, x[u].re, dr);
+        dr = fma(vv[u].im, x[u].im, dr);
+        di = fma(vv[u].re, x[u].im, di);
+        di = fma(-vv[u].im, x[u].re, di);
+      }
+      dr += __shfl_xor(dr, 1, 64);
+      di += __shfl_xor(di, 1, 64);
+      dr += __shfl_xor(dr, 2, 64);
+      di += __shfl_xor(di, 2, 64);
+      // x <- x - v (tau v^H x)
+      const double fr = tj.re * dr - tj.im * di, fi = tj.re * di + tj.im * dr;
+#pragma unroll
+      for (int u = 0; u < 17; ++u) {
+        x[u].re = fma(-vv[u].re, fr, x[u].re);
+        x[u].re = fma(vv[u].im, fi, x[u].re);
+        x[u].im = fma(-vv[u].re, fi, x[u].im);
+        x[u].im = fma(-vv[u].im, fr, x[u].im);
+      }
+    }
+    if (a > 0) {
+      const int last = 4 * a + rho + 64;
+      if (cok && last < Lr) P[last] = x[16];
+#pragma unroll
+      for (int u = 16; u > 0; --u) x[u] = x[u - 1];
+      const int first = 4 * (a - 1) + rho;
+      x[0] = (cok && first < Lr) ? P[first] : cmake(0.0, 0.0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 17; ++u) {
+    const int row = rho + 4 * u;
+    if (cok && row < Lr) P[row] = x[u];
   }
 }
 
@@ -351,9 +325,8 @@ __global__ void bt2_init(int64_t n, int64_t nc, const double *Z, int64_t ldz, cd
 
 int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const double *Z, int64_t ldz,
             mmf_z *Phiz, int64_t ldphi, void *work, size_t bytes, hipStream_t st) {
+  (void)work; (void)bytes;
   if (n <= 0 || nc <= 0) return MMF_OK;
-  Bt2Ws ws = bt2_ws(n, nc, work);
-  if (bytes < ws.bytes) return MMF_ERR_WORKSPACE;
   const cd *V2 = reinterpret_cast<const cd *>(V2z);
   const cd *tau2 = reinterpret_cast<const cd *>(tau2z);
   cd *Phi = reinterpret_cast<cd *>(Phiz);
@@ -364,6 +337,7 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
   if (n < 2) return MMF_OK;
   const int64_t Gmax = (n - 2) / BT2_G;
   const int64_t Kmax = (n - 2) / BW;
+  const unsigned ntile = cdiv(nc, 64);
   for (int64_t step = 0; step <= Gmax + Kmax; ++step) {
     // blocks G with k = step - (Gmax - G) in [0, Kmax] and BT2_G G + BW k <= n - 2
     int64_t Glo = Gmax - step > 0 ? Gmax - step : 0;
@@ -372,10 +346,8 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
     if (Ghi < Glo) continue;
     for (int64_t Gb = Ghi; Gb >= Glo; Gb -= BT2_CHUNK) {
       const int64_t cnt = (Gb - Glo + 1 < BT2_CHUNK) ? Gb - Glo + 1 : BT2_CHUNK;
-      hipLaunchKernelGGL(bt2_prep, dim3((unsigned)cnt), dim3(256), 0, st, n, V2, tau2, Gmax, step, Gb, ws);
-      MMF_LAUNCH_CHECK();
-      hipLaunchKernelGGL(bt2_apply, dim3((unsigned)ws.ntile, (unsigned)cnt), dim3(GEMM_THREADS), 0, st, n, nc, Phi,
-                         ldphi, Gmax, step, Gb, ws);
+      hipLaunchKernelGGL(bt2_apply, dim3(ntile, (unsigned)cnt), dim3(256), 0, st, n, nc, V2, tau2, Phi, ldphi, Gmax,
+                         step, Gb);
       MMF_LAUNCH_CHECK();
     }
   }

@@ -40,7 +40,6 @@ struct HbWs {
   cd *T, *U;   // BW x BW each
   cd *qpart;   // nwg x BW: column dot partials of the panel factorization
   double *npart;  // nwg: norm partials
-  cd *Gp;      // nwg x BW x BW: Gram partials (column j, entries i < j)
   double *beta;   // BW: beta of the panel's reflectors
   int64_t nks, nwg;
   size_t bytes;
@@ -60,7 +59,6 @@ inline HbWs hb_ws(int64_t n, void *base) {
   w.U = cv.take<cd>(BW * BW);
   w.qpart = cv.take<cd>((size_t)w.nwg * BW);
   w.npart = cv.take<double>((size_t)w.nwg);
-  w.Gp = cv.take<cd>((size_t)w.nwg * BW * BW);
   w.beta = cv.take<double>(BW);
   w.bytes = cv.used();
   return w;
@@ -124,14 +122,16 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_update(int64_t n, cd *A, int64_
 }
 
 // Reflector j of the panel from column c0 + j (rows q0 + j ..), stored in A
-// and in the V slots of P3; then partial dots v^H P[:, c] (c > j) and Gram
-// entries v_i^H v_j (i < j) over this workgroup's rows.
+// and in the V slots of P3; then this workgroup's partial dots v^H P[:, c]
+// (c > j), summed over its rows through LDS in chunks of 16 columns.
 __global__ void __launch_bounds__(QR_ROWS) hb_qr_refl(int64_t n, cd *A, int64_t lda, int64_t c0, int j, int bw,
                                                       cd *tau, HbWs ws) {
-  __shared__ double sh[8];
+  __shared__ double bre[QR_ROWS][17], bim[QR_ROWS][17];
+  __shared__ cd psum[16][16];
   const int64_t q0 = c0 + BW;
   const int64_t rj = q0 + j;
-  const int64_t r = q0 + (int64_t)blockIdx.x * QR_ROWS + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t r = q0 + (int64_t)blockIdx.x * QR_ROWS + tid;
   double xn2 = 0.0;
   for (int64_t w = 0; w < gridDim.x; ++w) xn2 += ws.npart[w];
   const cd alpha = A[rj + (c0 + j) * lda];
@@ -159,52 +159,78 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_refl(int64_t n, cd *A, int64_t 
   }
   // alpha stays in A until the panel is done (other workgroups read it); beta
   // is written there by hb_tmat
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     tau[c0 + j] = tj;
     ws.beta[j] = beta;
   }
-  for (int c = 0; c < bw; ++c) {
-    if (c == j) continue;
-    cd p = cmake(0.0, 0.0);
-    if (r < n && r >= rj) {
-      if (c > j) p = cmulc(v, A[r + (c0 + c) * lda]);
-      else p = cmulc(ws.P3[r + (int64_t)c * n], v);
+  const bool live = r < n && r >= rj;
+  for (int cb = j + 1; cb < bw; cb += 16) {
+#pragma unroll 4
+    for (int cc = 0; cc < 16; ++cc) {
+      cd p = cmake(0.0, 0.0);
+      if (live && cb + cc < bw) p = cmulc(v, A[r + (c0 + cb + cc) * lda]);
+      bre[tid][cc] = p.re;
+      bim[tid][cc] = p.im;
     }
-    const cd s = hb_block_csum(p, sh);
-    if (threadIdx.x == 0) {
-      if (c > j) ws.qpart[blockIdx.x * BW + c] = s;
-      else ws.Gp[((int64_t)blockIdx.x * BW + j) * BW + c] = s;
+    __syncthreads();
+    {
+      const int cc = tid & 15, g = tid >> 4;
+      double sr = 0.0, si = 0.0;
+      for (int q = 0; q < 16; ++q) { sr += bre[16 * g + q][cc]; si += bim[16 * g + q][cc]; }
+      psum[g][cc] = cmake(sr, si);
     }
+    __syncthreads();
+    if (tid < 16 && cb + tid < bw) {
+      cd s = cmake(0.0, 0.0);
+      for (int g = 0; g < 16; ++g) s = cadd(s, psum[g][tid]);
+      ws.qpart[blockIdx.x * BW + cb + tid] = s;
+    }
+    __syncthreads();
   }
 }
 
-// T of the panel (upper triangular BW x BW) from the Gram partials (one
-// wavefront); the betas go to the band block R.
-__global__ void __launch_bounds__(BW) hb_tmat(cd *A, int64_t lda, int64_t c0, int nr, int64_t nwg, const cd *tau,
-                                              HbWs ws) {
-  __shared__ cd G[BW][BW + 1];
+// Gram partials Sp[z] = V^H V over row slice z (for T).
+__global__ void __launch_bounds__(GEMM_THREADS) hb_gram(int64_t q0, int64_t m, int64_t n, HbWs ws) {
+  __shared__ double lds[GEMM_LDS_ELEMS];
+  const int64_t z = blockIdx.x;
+  const int64_t k0 = z * HEMM_KC, k1 = (k0 + HEMM_KC < m) ? k0 + HEMM_KC : m;
+  if (k0 >= m) return;
+  const cd *V = ws.P3 + q0 + k0;
+  GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, V, n, ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
+  gemm_tile<true, A_C, B_N>(g, 0, 0, lds);
+}
+
+// T of the panel (upper triangular BW x BW) from the summed Gram partials
+// (four partial sums per element of the recurrence); the betas go to the
+// band block R.
+__global__ void __launch_bounds__(256) hb_tmat(cd *A, int64_t lda, int64_t c0, int nr, int64_t nks, const cd *tau,
+                                               HbWs ws) {
   __shared__ cd T[BW][BW + 1];
-  const int r = threadIdx.x;
-  for (int c = 0; c < BW; ++c) {
+  __shared__ cd part[4][BW];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < BW * BW; e += 256) {
     cd s = cmake(0.0, 0.0);
-    if (r < c && c < nr)
-      for (int64_t w = 0; w < nwg; ++w) s = cadd(s, ws.Gp[(w * BW + c) * BW + r]);
-    G[r][c] = s;
-    T[r][c] = cmake(0.0, 0.0);
+    for (int64_t z = 0; z < nks; ++z) s = cadd(s, ws.Sp[z * BW * BW + e]);
+    T[e % BW][e / BW] = s;
   }
   __syncthreads();
-  for (int k = 0; k < nr; ++k) {
-    const cd tk = tau[c0 + k];
+  const int r = tid & 63, qp = tid >> 6;
+  for (int kk = 0; kk < BW; ++kk) {
     cd s = cmake(0.0, 0.0);
-    if (r < k)
-      for (int j = r; j < k; ++j) s = cadd(s, cmul(T[r][j], G[j][k]));
+    if (r < kk && kk < nr)
+      for (int j = r + qp; j < kk; j += 4) s = cadd(s, cmul(T[r][j], T[j][kk]));
+    part[qp][r] = s;
     __syncthreads();
-    if (r < k) T[r][k] = cscale(cmul(tk, s), -1.0);
-    if (r == k) T[r][k] = tk;
+    if (qp == 0) {
+      const cd tk = kk < nr ? tau[c0 + kk] : cmake(0.0, 0.0);
+      if (r < kk) T[r][kk] = cscale(cmul(tk, cadd(cadd(part[0][r], part[1][r]), cadd(part[2][r], part[3][r]))), -1.0);
+      else if (r == kk) T[r][kk] = tk;
+      else T[r][kk] = cmake(0.0, 0.0);
+    }
     __syncthreads();
   }
-  for (int c = 0; c < BW; ++c) ws.T[r + c * BW] = T[r][c];
-  if (r < nr) A[(c0 + BW + r) + (c0 + r) * lda] = cmake(ws.beta[r], 0.0);
+  for (int e = tid; e < BW * BW; e += 256) ws.T[e] = T[e % BW][e / BW];
+  if (tid < nr) A[(c0 + BW + tid) + (c0 + tid) * lda] = cmake(ws.beta[tid], 0.0);
 }
 
 // Make the 64 x 64 diagonal tiles of A22 (grid anchored at q0) Hermitian:
@@ -323,11 +349,13 @@ int he2hb_run(int64_t n, mmf_z *Az, int64_t lda, mmf_z *tauz, mmf_z *ABz, void *
     }
     // reflectors of length one: identity
     for (int j = nr; j < bw; ++j) MMF_HIP_TRY(hipMemsetAsync(tau + c0 + j, 0, sizeof(cd), st));
-    hipLaunchKernelGGL(hb_tmat, dim3(1), dim3(BW), 0, st, A, lda, c0, nr, (int64_t)nwg, tau, ws);
-    MMF_LAUNCH_CHECK();
-    // Y = A22 V
     const unsigned ntile = cdiv(m, GT_M);
     const int64_t nks = (m + HEMM_KC - 1) / HEMM_KC;
+    hipLaunchKernelGGL(hb_gram, dim3((unsigned)nks), dim3(GEMM_THREADS), 0, st, q0, m, n, ws);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_tmat, dim3(1), dim3(256), 0, st, A, lda, c0, nr, nks, tau, ws);
+    MMF_LAUNCH_CHECK();
+    // Y = A22 V
     hipLaunchKernelGGL(hb_mirror_diag, dim3(ntile), dim3(256), 0, st, A, lda, q0, m);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(hb_hemm, dim3(ntile, (unsigned)nks), dim3(GEMM_THREADS), 0, st, A, lda, q0, m, n, ws);
