@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+# FP64 vector FMA rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+FP64_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
@@ -488,8 +490,11 @@ def main():
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     L = mmf.lib()
     torch.cuda.synchronize()
+    # dominant kernel: the HEMV of the one-stage reduction, or the
+    # back-transformation by the bulge-chasing reflectors of the two-stage one
+    two_stage = prec == mmf.MMF_C128 and M >= mmf.eigh_two_stage_min()
     if not args.no_ktimer:
-        mmf.call("mmf_ktimer_arm", b"hemv")
+        mmf.call("mmf_ktimer_arm", b"bt2" if two_stage else b"hemv")
     t_start = time.perf_counter()
     for k in range(args.steps):
         U, P = step(evs[k])
@@ -548,7 +553,8 @@ def main():
         "dtype": "c128" if prec == mmf.MMF_C128 else ("c64+f64" if prec == mmf.MMF_C64_REFINED else "c64"),
         "data": "synthetic",
         "config": {"workload": args.workload, "precision": args.prec, "D": D, "M": M, "times": T,
-                   "drives": [float(x) for x in p.omega], "truncation": [int(x) for x in p.N]},
+                   "drives": [float(x) for x in p.omega], "truncation": [int(x) for x in p.N],
+                   "reduction": "two-stage" if two_stage else "one-stage"},
         "eigh_tflops": eigh_tflops,
         "eigh_frac_fp64_peak": eigh_tflops / FP64_MFMA_PEAK_TFLOPS,
         "stage_ms": med,
@@ -556,7 +562,19 @@ def main():
         "step_ms_p99": float(np.percentile(step_ms, 99)),
         "check": check,
     }
-    if kt and kt["launches"]:
+    if kt and kt["launches"] and two_stage:
+        per_launch_flops = kt["bytes"] / kt["launches"]
+        avg_ms = kt["total_ms"] / kt["launches"]
+        tfs = per_launch_flops / (avg_ms / 1e3) / 1e12
+        out["roofline"] = {
+            "bound": "alu", "achieved": tfs, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tfs / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+            "kernel": "bt2_apply (back-transformation by the bulge-chasing reflectors, FP64 vector FMAs)",
+            "launches": kt["launches"], "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_flops_per_launch": per_launch_flops,
+            "share_of_step": kt["total_ms"] / (elapsed * 1e3),
+        }
+    elif kt and kt["launches"]:
         per_launch_bytes = kt["bytes"] / kt["launches"]
         avg_ms = kt["total_ms"] / kt["launches"]
         gbs = per_launch_bytes / (avg_ms / 1e3) / 1e9

@@ -111,14 +111,25 @@ int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
  * w:   dev [M], eigenvalues in ascending order.
  * work/work_bytes: dev scratch of at least mmf_eigh_workspace() bytes.
  * dev_info: dev int32, set to 0 or to MMF_ERR_NO_CONVERGENCE by the kernels.
- * Method: blocked Householder reduction to a real symmetric tridiagonal
- * matrix (trailing updates and back-transformation on FP64 matrix cores),
- * Cuppen divide and conquer with Gu-Eisenstat eigenvector recomputation.
+ * Method: Householder reduction to a real symmetric tridiagonal matrix,
+ * Cuppen divide and conquer with Gu-Eisenstat eigenvector recomputation,
+ * back-transformation.  Below order mmf_eigh_two_stage_min() the reduction is
+ * one-stage (blocked, trailing updates and back-transformation on the FP64
+ * matrix cores); from that order up it is two-stage: dense -> band of
+ * half-width 64 (matrix-core GEMMs), band -> tridiagonal by bulge chasing,
+ * then the two back-transformations.  Both give the same results to rounding.
  * Errors: -1 M < 0, -2 A NULL, -3 lda < M, -4 w NULL, -5 prec unknown,
  *         -6/-7 workspace NULL or too small, -8 dev_info NULL, MMF_ERR_HIP,
  *         MMF_ERR_NOT_IMPLEMENTED for a precision not built. */
 int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec,
              void *work, size_t work_bytes, int32_t *dev_info, void *stream);
+
+/* Order from which mmf_eigh and mmf_eigh_window take the two-stage reduction
+ * (default 12288, the measured crossover; the environment variable
+ * MMF_EIGH_TWO_STAGE_MIN, read at every call, overrides it and also the
+ * eigenvalue-only thresholds of mmf_eigvalsh_batched).  Query the workspace
+ * size and call the solver under the same setting.  Host-only, never fails. */
+int64_t mmf_eigh_two_stage_min(void);
 
 /* Workspace bytes that mmf_eigh_batched needs for `count` problems of orders
  * n[0..count) (host array) at precision prec.
@@ -172,7 +183,10 @@ int mmf_eigvalsh_batched_workspace(int64_t count, const int64_t *n, int prec, si
  * eigenvectors; the quasienergy scans of Sec. 4.2): each A[c] (n[c] x n[c],
  * lower triangle read, destroyed) is reduced to a real tridiagonal matrix by
  * the grouped Householder reduction (complex128, or complex64 for
- * MMF_C64_RAW, from a complex64 copy; A[c] then stays intact), and all
+ * MMF_C64_RAW, from a complex64 copy; A[c] then stays intact; complex128
+ * problems take the grouped two-stage reduction, dense -> band ->
+ * tridiagonal, from order 8192 up, or from 2048 up when the call holds at
+ * least 8 problems of order >= 2048), and all
  * eigenvalues are found by bisection on Sturm counts in FP64; w[c] receives
  * them in ascending order.  Arguments, ownership and errors as for
  * mmf_eigh_batched (-6: prec not MMF_C128 / MMF_C64_RAW); dev_info[c] is set
@@ -251,12 +265,14 @@ int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, double *P,
                  void *work, size_t work_bytes, void *stream);
 
 /* Benchmark instrumentation (not needed for computation).  mmf_ktimer_arm
- * starts recording HIP events around every launch of one kernel class
- * ("hemv": the Hermitian matrix-vector product of the tridiagonal
- * reduction) on the stream it is launched on, together with the algorithmic
- * bytes of each launch; mmf_ktimer_read disarms, waits for the events and
- * returns the launch count, the summed kernel time in ms and the summed
- * bytes.  Process-wide state: use from one host thread, never concurrently
+ * starts recording HIP events around every launch of one kernel class on
+ * the stream it is launched on, together with the algorithmic work of each
+ * launch: "hemv" (the Hermitian matrix-vector product of the one-stage
+ * reduction; work = bytes read) or "bt2" (the back-transformation by the
+ * bulge-chasing reflectors of the two-stage reduction; work = real flops,
+ * 16 per reflector entry and eigenvector column).  mmf_ktimer_read disarms,
+ * waits for the events and returns the launch count, the summed kernel time
+ * in ms and the summed work.  Process-wide state: use from one host thread, never concurrently
  * with other library calls on other threads.
  * Errors: arm: -1 name NULL or longer than 63 chars; read: -k pointer k NULL,
  * MMF_ERR_HIP. */

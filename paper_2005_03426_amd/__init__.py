@@ -105,6 +105,11 @@ def eigh_workspace_bytes(M: int, prec: int = MMF_C128) -> int:
     return int(b.value)
 
 
+def eigh_two_stage_min() -> int:
+    """Order from which eigh / eigh_window use the two-stage reduction."""
+    return int(lib().mmf_eigh_two_stage_min())
+
+
 def _workspace(nbytes, device):
     torch = _torch()
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)

@@ -91,26 +91,14 @@ inline WinWs win_ws(int64_t M, int64_t kmax, void *base) {
 }
 
 // Two-stage path (dense -> band -> tridiagonal, two back-transformations),
-// taken from order two_stage_min() up: the one-stage reduction streams the
-// whole trailing matrix from HBM once per column, the two-stage one runs
-// almost all of its reduction flops on the matrix cores.
-constexpr int64_t TWO_STAGE_MIN_DEFAULT = 4096;
-
-inline int64_t two_stage_min() {
-  const char *s = getenv("MMF_EIGH_TWO_STAGE_MIN");
-  if (s && *s) {
-    const long long v = atoll(s);
-    return v < 0 ? 0 : (int64_t)v;
-  }
-  return TWO_STAGE_MIN_DEFAULT;
-}
-
+// taken from order two_stage_min() up.
 struct Eigh2Ws {
   double *e;
   mmf_z *tau1;
   double *Z;
   mmf_z *AB, *V2, *tau2;
   double *wall, *Zk;          // window path only
+  void *table;                // one-entry table of the chase
   void *rest;
   size_t rest_bytes, bt1_bytes;
   size_t bytes;
@@ -130,6 +118,7 @@ inline Eigh2Ws eigh2_ws(int64_t M, int64_t nc, bool window, void *base) {
   w.tau2 = cv.take<mmf_z>(hb_v2_elems(M) / BW + 1);
   w.wall = window ? cv.take<double>(n) : nullptr;
   w.Zk = window ? cv.take<double>(n * (size_t)(nc > 0 ? nc : 1)) : nullptr;
+  w.table = cv.take<char>(STAGE_TABLE_BYTES);
   w.bt1_bytes = (unmtr_band_ws_bytes(M, nc) + 255) & ~(size_t)255;
   size_t stage = he2hb_ws_bytes(M);
   const size_t s2 = stedc_ws_bytes(M), s3 = w.bt1_bytes + bt2_ws_bytes(M, nc);
@@ -147,7 +136,7 @@ inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh
                          hipStream_t st) {
   int rc = he2hb_run(M, A, lda, ws.tau1, ws.AB, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;
-  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, st);
+  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, st);
   if (rc) return rc;
   return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st);
 }
@@ -168,6 +157,8 @@ inline int eigh2_run(int64_t M, mmf_z *A, int64_t lda, double *w, void *work, in
 }  // namespace mmf
 
 using namespace mmf;
+
+extern "C" int64_t mmf_eigh_two_stage_min(void) { return two_stage_min(); }
 
 extern "C" int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes) {
   if (M < 0) return -1;

@@ -19,6 +19,7 @@
 #include "common.h"
 #include "stages.h"
 #include "table.h"
+#include "twostage.h"
 
 namespace mmf {
 
@@ -26,21 +27,31 @@ struct EvWs {
   double *d, *e, *bounds;   // bounds: gl, gu, pivmin, tnorm
   void *tau;
   void *Ac;                 // complex64 copy of A (complex64 path)
+  mmf_z *AB, *V2, *tau2;    // two-stage path: band array, current chase reflectors
   void *stage;
   size_t stage_bytes, bytes;
 };
 
-inline EvWs ev_ws(int64_t n, bool c64, void *base) {
+// two: the complex128 two-stage reduction (dense -> band -> tridiagonal)
+inline EvWs ev_ws(int64_t n, bool c64, bool two, void *base) {
   Carver cv(base);
   EvWs w;
   const size_t N = (size_t)(n > 0 ? n : 1);
   w.d = cv.take<double>(N);
   w.e = cv.take<double>(N);
   w.bounds = cv.take<double>(4);
+  w.AB = w.V2 = w.tau2 = nullptr;
   if (c64) {
     w.Ac = cv.take<cf>(N * N);
     w.tau = cv.take<cf>(N);
     w.stage_bytes = hetrd_ws_bytes_c64(n);
+  } else if (two) {
+    w.Ac = nullptr;
+    w.tau = cv.take<mmf_z>(N);
+    w.AB = cv.take<mmf_z>(N * LDAB);
+    w.V2 = cv.take<mmf_z>(N * BW);
+    w.tau2 = cv.take<mmf_z>(N);
+    w.stage_bytes = he2hb_ws_bytes(n);
   } else {
     w.Ac = nullptr;
     w.tau = cv.take<mmf_z>(N);
@@ -50,6 +61,13 @@ inline EvWs ev_ws(int64_t n, bool c64, void *base) {
   w.bytes = cv.used();
   return w;
 }
+
+inline int64_t ev_threshold(int64_t count, const int64_t *n) {
+  int64_t nbig = 0;
+  for (int64_t c = 0; c < count; ++c) nbig += n[c] >= EV_TWO_STAGE_MIN_BATCH;
+  return ev_two_stage_min(nbig);
+}
+inline bool ev_two(int64_t n, int prec, int64_t thr) { return prec == MMF_C128 && n > 0 && n >= thr; }
 
 struct EvProb {
   int64_t n;
@@ -156,10 +174,11 @@ extern "C" int mmf_eigvalsh_batched_workspace(int64_t count, const int64_t *n, i
   if (!bytes) return -4;
   const int64_t group = count < EV_GROUP_MAX ? count : EV_GROUP_MAX;
   size_t b = align256((size_t)(group > 0 ? group : 1) * STAGE_TABLE_BYTES);
-  for (int64_t c = 0; c < count; ++c) {
+  for (int64_t c = 0; c < count; ++c)
     if (n[c] < 0) return -2;
-    if (n[c] > 0) b += align256(ev_ws(n[c], prec == MMF_C64_RAW, nullptr).bytes);
-  }
+  const int64_t thr = ev_threshold(count, n);
+  for (int64_t c = 0; c < count; ++c)
+    if (n[c] > 0) b += align256(ev_ws(n[c], prec == MMF_C64_RAW, ev_two(n[c], prec, thr), nullptr).bytes);
   *bytes = b;
   return MMF_OK;
 }
@@ -192,58 +211,77 @@ extern "C" int mmf_eigvalsh_batched(int64_t count, const int64_t *n, mmf_z *cons
   const int64_t group = count < EV_GROUP_MAX ? count : EV_GROUP_MAX;
   char *table = (char *)work;
   char *cur = table + align256((size_t)group * STAGE_TABLE_BYTES);
+  // problems in call order; the one-stage and two-stage ones are reduced in
+  // separate grouped passes
   std::vector<int64_t> nn, ld;
   std::vector<mmf_z *> Av;
   std::vector<double *> wv;
   std::vector<EvWs> ws;
+  std::vector<char> two;
+  const int64_t thr = ev_threshold(count, n);
   for (int64_t c = 0; c < count; ++c) {
     if (n[c] == 0) continue;
+    const bool t = ev_two(n[c], prec, thr);
     nn.push_back(n[c]);
     ld.push_back(lda[c]);
     Av.push_back(A[c]);
     wv.push_back(w[c]);
-    ws.push_back(ev_ws(n[c], c64, cur));
+    two.push_back(t ? 1 : 0);
+    ws.push_back(ev_ws(n[c], c64, t, cur));
     cur += align256(ws.back().bytes);
   }
-  const int64_t live = (int64_t)nn.size();
-  for (int64_t g0 = 0; g0 < live; g0 += EV_GROUP_MAX) {
-    const int64_t gc = (live - g0 < EV_GROUP_MAX) ? live - g0 : EV_GROUP_MAX;
-    const int64_t *gn = nn.data() + g0;
-    std::vector<double *> d((size_t)gc), e((size_t)gc);
-    std::vector<void *> tau((size_t)gc), stage((size_t)gc), Ac((size_t)gc);
-    int64_t nmax = 0;
-    for (int64_t c = 0; c < gc; ++c) {
-      const EvWs &q = ws[g0 + c];
-      d[c] = q.d; e[c] = q.e; tau[c] = q.tau; stage[c] = q.stage; Ac[c] = q.Ac;
-      nmax = gn[c] > nmax ? gn[c] : nmax;
-      if (c64) {
-        hipLaunchKernelGGL(ev_to_c64, dim3(cdiv(gn[c], 256), cdiv(gn[c], 64)), dim3(256), 0, st, gn[c],
-                           reinterpret_cast<const cd *>(Av[g0 + c]), ld[g0 + c], reinterpret_cast<cf *>(q.Ac));
-        MMF_LAUNCH_CHECK();
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int64_t> idx;
+    for (size_t c = 0; c < nn.size(); ++c)
+      if (two[c] == pass) idx.push_back((int64_t)c);
+    const int64_t live = (int64_t)idx.size();
+    for (int64_t g0 = 0; g0 < live; g0 += EV_GROUP_MAX) {
+      const int64_t gc = (live - g0 < EV_GROUP_MAX) ? live - g0 : EV_GROUP_MAX;
+      std::vector<int64_t> gn((size_t)gc), gld((size_t)gc);
+      std::vector<double *> d((size_t)gc), e((size_t)gc);
+      std::vector<void *> tau((size_t)gc), stage((size_t)gc), Ac((size_t)gc);
+      std::vector<mmf_z *> Ag((size_t)gc), tz((size_t)gc), AB((size_t)gc), V2((size_t)gc), t2((size_t)gc);
+      int64_t nmax = 0;
+      for (int64_t c = 0; c < gc; ++c) {
+        const int64_t p = idx[g0 + c];
+        const EvWs &q = ws[p];
+        gn[c] = nn[p]; gld[c] = ld[p]; Ag[c] = Av[p];
+        d[c] = q.d; e[c] = q.e; tau[c] = q.tau; stage[c] = q.stage; Ac[c] = q.Ac;
+        tz[c] = reinterpret_cast<mmf_z *>(q.tau); AB[c] = q.AB; V2[c] = q.V2; t2[c] = q.tau2;
+        nmax = gn[c] > nmax ? gn[c] : nmax;
+        if (c64) {
+          hipLaunchKernelGGL(ev_to_c64, dim3(cdiv(gn[c], 256), cdiv(gn[c], 64)), dim3(256), 0, st, gn[c],
+                             reinterpret_cast<const cd *>(Ag[c]), gld[c], reinterpret_cast<cf *>(q.Ac));
+          MMF_LAUNCH_CHECK();
+        }
       }
+      int rc;
+      if (pass == 1) {
+        rc = he2hb_batched(gc, gn.data(), Ag.data(), gld.data(), tz.data(), AB.data(), stage.data(), table, st);
+        if (rc) return rc;
+        rc = hb2st_batched(gc, gn.data(), AB.data(), V2.data(), t2.data(), d.data(), e.data(), table, st);
+      } else if (c64) {
+        rc = hetrd_batched_c64(gc, gn.data(), Ac.data(), gn.data(), d.data(), e.data(), tau.data(), stage.data(),
+                               table, st);
+      } else {
+        rc = hetrd_batched(gc, gn.data(), Ag.data(), gld.data(), d.data(), e.data(), tz.data(), stage.data(), table,
+                           st);
+      }
+      if (rc) return rc;
+      std::vector<EvProb> h((size_t)gc);
+      for (int64_t c = 0; c < gc; ++c) {
+        const int64_t p = idx[g0 + c];
+        h[c].n = gn[c]; h[c].d = d[c]; h[c].e = e[c]; h[c].bounds = ws[p].bounds; h[c].w = wv[p];
+      }
+      static_assert(sizeof(EvProb) <= STAGE_TABLE_BYTES, "table entry");
+      EvProb *pr = reinterpret_cast<EvProb *>(table);
+      rc = table_write(pr, h.data(), gc, st);
+      if (rc) return rc;
+      hipLaunchKernelGGL(ev_bounds, dim3(1, 1, (unsigned)gc), dim3(256), 0, st, pr);
+      MMF_LAUNCH_CHECK();
+      hipLaunchKernelGGL(ev_bisect, dim3(cdiv(nmax, 256), 1, (unsigned)gc), dim3(256), 0, st, pr);
+      MMF_LAUNCH_CHECK();
     }
-    int rc;
-    if (c64) {
-      rc = hetrd_batched_c64(gc, gn, Ac.data(), gn, d.data(), e.data(), tau.data(), stage.data(), table, st);
-    } else {
-      std::vector<mmf_z *> tz((size_t)gc);
-      for (int64_t c = 0; c < gc; ++c) tz[c] = reinterpret_cast<mmf_z *>(tau[c]);
-      rc = hetrd_batched(gc, gn, Av.data() + g0, ld.data() + g0, d.data(), e.data(), tz.data(), stage.data(),
-                         table, st);
-    }
-    if (rc) return rc;
-    std::vector<EvProb> h((size_t)gc);
-    for (int64_t c = 0; c < gc; ++c) {
-      h[c].n = gn[c]; h[c].d = d[c]; h[c].e = e[c]; h[c].bounds = ws[g0 + c].bounds; h[c].w = wv[g0 + c];
-    }
-    static_assert(sizeof(EvProb) <= STAGE_TABLE_BYTES, "table entry");
-    EvProb *pr = reinterpret_cast<EvProb *>(table);
-    rc = table_write(pr, h.data(), gc, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(ev_bounds, dim3(1, 1, (unsigned)gc), dim3(256), 0, st, pr);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(ev_bisect, dim3(cdiv(nmax, 256), 1, (unsigned)gc), dim3(256), 0, st, pr);
-    MMF_LAUNCH_CHECK();
   }
   return MMF_OK;
 }

@@ -22,26 +22,34 @@
 // c .. c + BW of column c, diagonal real) is also copied to the band array AB
 // (lower band storage, ldab = 2 BW rows: element (r, c) at AB[(r - c) + c ldab],
 // rows BW+1 .. 2 BW - 1 zero) for the second stage.
+//
+// Grouped execution: every kernel reads its problem from a device table
+// (HbProb) at grid index z and works on panel c0 of it; a problem without
+// that panel (or step) exits, so one launch advances every matrix of a batch.
+// A single reduction is the one-entry case.
 #include <vector>
 #include "common.h"
 #include "twostage.h"
 #include "gemm_core.h"
+#include "stages.h"
+#include "table.h"
 
 namespace mmf {
 
 constexpr int QR_ROWS = 256;      // rows per workgroup of the panel factorization
 constexpr int64_t HEMM_KC = 1024; // K slice of the A22 V product
+constexpr int64_t PAN_KC = 256;   // row slice of the panel products V^H V, V^H X
 
 struct HbWs {
   cd *P3;      // n x 3 BW (ld n): [V | W | V] of the current panel
   cd *Yp;      // nks x n x BW: K-slice partials of A22 V
   cd *Yb;      // n x BW: A22 V
-  cd *Sp;      // nks x BW x BW: partials of V^H X
+  cd *Sp;      // npk x BW x BW: row-slice partials of V^H V, then of V^H X
   cd *T, *U;   // BW x BW each
-  cd *qpart;   // nwg x BW: column dot partials of the panel factorization
-  double *npart;  // nwg: norm partials
+  cd *gpart;   // 2 x nwg x BW: column dot partials of the panel factorization
+  cd *prow;    // 2 x BW: published panel row
   double *beta;   // BW: beta of the panel's reflectors
-  int64_t nks, nwg;
+  int64_t nks, npk, nwg;
   size_t bytes;
 };
 
@@ -50,125 +58,147 @@ inline HbWs hb_ws(int64_t n, void *base) {
   HbWs w;
   const size_t N = (size_t)(n > 0 ? n : 1);
   w.nks = (int64_t)((N + HEMM_KC - 1) / HEMM_KC);
+  w.npk = (int64_t)((N + PAN_KC - 1) / PAN_KC);
   w.nwg = (int64_t)((N + QR_ROWS - 1) / QR_ROWS) + 1;
   w.P3 = cv.take<cd>(N * 3 * BW);
   w.Yp = cv.take<cd>((size_t)w.nks * N * BW);
   w.Yb = cv.take<cd>(N * BW);
-  w.Sp = cv.take<cd>((size_t)w.nks * BW * BW);
+  w.Sp = cv.take<cd>((size_t)w.npk * BW * BW);
   w.T = cv.take<cd>(BW * BW);
   w.U = cv.take<cd>(BW * BW);
-  w.qpart = cv.take<cd>((size_t)w.nwg * BW);
-  w.npart = cv.take<double>((size_t)w.nwg);
+  w.gpart = cv.take<cd>((size_t)2 * w.nwg * BW);
+  w.prow = cv.take<cd>((size_t)2 * BW);
   w.beta = cv.take<double>(BW);
   w.bytes = cv.used();
   return w;
 }
 
-size_t he2hb_ws_bytes(int64_t n) { return hb_ws(n, nullptr).bytes; }
+size_t he2hb_ws_bytes(int64_t n) { return hb_ws(n, nullptr).bytes + STAGE_TABLE_BYTES; }
 
-// Sum of a complex value over the 256 threads of a workgroup (fixed order).
-__device__ inline cd hb_block_csum(cd v, double *sh) {
-  double re = wave_sum(v.re), im = wave_sum(v.im);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) { sh[2 * wv] = re; sh[2 * wv + 1] = im; }
-  __syncthreads();
-  return cmake((sh[0] + sh[2]) + (sh[4] + sh[6]), (sh[1] + sh[3]) + (sh[5] + sh[7]));
+// one row of the problem table
+struct HbProb {
+  int64_t n, lda;
+  cd *A, *tau, *AB;
+  HbWs ws;
+};
+
+// Panel c0 of problem P: trailing start q0, trailing order m, panel width bw,
+// reflector count nr; false when the panel does not exist.
+struct HbPanel {
+  int64_t q0, m;
+  int bw, nr;
+};
+__device__ inline bool hb_panel(const HbProb &P, int64_t c0, HbPanel &pp) {
+  if (c0 + BW >= P.n - 1) return false;
+  pp.q0 = c0 + BW;
+  pp.m = P.n - pp.q0;
+  pp.bw = (int)((P.n - c0 < BW) ? P.n - c0 : BW);
+  pp.nr = (int)((pp.m - 1 < pp.bw) ? pp.m - 1 : pp.bw);
+  return true;
 }
 
 // Zero the three panel slots of P3 (rows q0 .. n-1).
-__global__ void hb_zero_p3(int64_t n, int64_t q0, cd *P3) {
-  const int64_t r = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  for (int c = 0; c < 3 * BW; ++c) P3[r + (int64_t)c * n] = cmake(0.0, 0.0);
+__global__ void hb_zero_p3(const HbProb *pr, int64_t c0) {
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t r = pp.q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.n) return;
+  for (int c = 0; c < 3 * BW; ++c) P.ws.P3[r + (int64_t)c * P.n] = cmake(0.0, 0.0);
 }
 
-// Column update by reflector j-1 (j >= 1) and norm partial of column j (j < nr).
-// Workgroup w owns rows q0 + 256 w .. of the panel.
-__global__ void __launch_bounds__(QR_ROWS) hb_qr_update(int64_t n, cd *A, int64_t lda, int64_t c0, int j,
-                                                        int bw, int nr, const cd *tau, HbWs ws) {
-  __shared__ cd d[BW];
-  __shared__ double sh[8];
-  const int64_t q0 = c0 + BW;
-  const int64_t r = q0 + (int64_t)blockIdx.x * QR_ROWS + threadIdx.x;
+// One launch per panel column j = 0 .. nr (workgroup w owns rows q0 + 256 w ..).
+// With x~ the part of column j below row rj = q0 + j and
+// v_j = (1, s x~), s = 1 / (alpha - beta), the product v_j^H P[:, c] equals
+// P[rj, c] + conj(s) (x~^H P[:, c]); so the launch for column j forms the
+// partial sums g[c] = x~^H P[:, c] (c >= j; g[j] = |x~|^2) while beta and s
+// are still unknown, and publishes row rj of the panel.  The next launch
+// derives beta, tau, s from the summed partials in every workgroup, scales its
+// rows of column j into v_j (stored below the band and in the V slots of P3),
+// applies H_j^H to the panel columns right of j, and forms the partials of
+// column j + 1.  Partials and the published row alternate between two buffers.
+__global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t c0, int j) {
+  __shared__ double bre[QR_ROWS][17], bim[QR_ROWS][17];
+  __shared__ cd psum[16][16];
+  __shared__ cd gs[BW], d[BW], gq[4][BW];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp) || j > pp.nr) return;
+  const int64_t nwg = (pp.m + QR_ROWS - 1) / QR_ROWS;
+  if ((int64_t)blockIdx.x >= nwg) return;
+  const int64_t n = P.n, lda = P.lda, q0 = pp.q0;
+  const int bw = pp.bw, nr = pp.nr;
+  cd *A = P.A;
+  const HbWs &ws = P.ws;
+  const int tid = threadIdx.x;
+  const int64_t r = q0 + (int64_t)blockIdx.x * QR_ROWS + tid;
+  const int wr = j & 1, rd = wr ^ 1;
+  cd *gw = ws.gpart + (int64_t)wr * ws.nwg * BW, *gr = ws.gpart + (int64_t)rd * ws.nwg * BW;
+  cd *pw = ws.prow + wr * BW, *prd = ws.prow + rd * BW;
   if (j >= 1) {
-    if (threadIdx.x < BW) {
-      const int c = threadIdx.x;
-      cd s = cmake(0.0, 0.0);
-      if (c >= j && c < bw)
-        for (int64_t w = 0; w < gridDim.x; ++w) s = cadd(s, ws.qpart[w * BW + c]);
-      // d[c] = conj(tau_{j-1}) (v^H P[:, c])
-      d[c] = cmulc(tau[c0 + j - 1], s);
+    // ---- reflector jp = j - 1 from the previous launch's sums
+    const int jp = j - 1;
+    const int64_t rjp = q0 + jp;
+    {
+      // four threads per column sum interleaved partials, then fixed-order combine
+      const int c = tid & 63, qp = tid >> 6;
+      cd sum = cmake(0.0, 0.0);
+      if (c >= jp && c < bw) {
+#pragma unroll 4
+        for (int64_t w = qp; w < nwg; w += 4) sum = cadd(sum, gr[w * BW + c]);
+      }
+      gq[qp][c] = sum;
     }
     __syncthreads();
-    if (r < n && r >= q0 + j - 1) {
-      const cd v = ws.P3[r + (int64_t)(j - 1) * n];
+    if (tid < BW) gs[tid] = cadd(cadd(gq[0][tid], gq[1][tid]), cadd(gq[2][tid], gq[3][tid]));
+    __syncthreads();
+    const double xn2 = gs[jp].re;
+    const cd alpha = prd[jp];
+    cd tj = cmake(0.0, 0.0), sc = cmake(0.0, 0.0);
+    double beta = alpha.re;
+    if (xn2 > 0.0 || alpha.im != 0.0) {
+      const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
+      beta = alpha.re >= 0.0 ? -nrm : nrm;
+      tj = cmake((beta - alpha.re) / beta, -alpha.im / beta);
+      const cd am = cmake(alpha.re - beta, alpha.im);
+      const double den = am.re * am.re + am.im * am.im;
+      sc = cmake(am.re / den, -am.im / den);
+    }
+    if (tid < BW) {
+      // d[c] = conj(tau) (P[rjp, c] + conj(s) g[c])
+      d[tid] = (tid >= j && tid < bw) ? cmulc(tj, cadd(prd[tid], cmulc(sc, gs[tid]))) : cmake(0.0, 0.0);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      P.tau[c0 + jp] = tj;
+      ws.beta[jp] = beta;
+    }
+    __syncthreads();
+    if (r < n && r >= rjp) {
+      cd v = cmake(1.0, 0.0);
+      if (r > rjp) {
+        v = cmul(A[r + (c0 + jp) * lda], sc);
+        A[r + (c0 + jp) * lda] = v;
+      }
+      ws.P3[r + (int64_t)jp * n] = v;
+      ws.P3[r + (int64_t)(2 * BW + jp) * n] = v;
       for (int c = j; c < bw; ++c) {
         cd *p = A + r + (c0 + c) * lda;
         *p = csub(*p, cmul(v, d[c]));
       }
     }
   }
-  if (j < nr) {
-    double s = 0.0;
-    if (r < n && r > q0 + j) s = cabs2(A[r + (c0 + j) * lda]);
-    s = wave_sum(s);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wv] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) ws.npart[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-  }
-}
-
-// Reflector j of the panel from column c0 + j (rows q0 + j ..), stored in A
-// and in the V slots of P3; then this workgroup's partial dots v^H P[:, c]
-// (c > j), summed over its rows through LDS in chunks of 16 columns.
-__global__ void __launch_bounds__(QR_ROWS) hb_qr_refl(int64_t n, cd *A, int64_t lda, int64_t c0, int j, int bw,
-                                                      cd *tau, HbWs ws) {
-  __shared__ double bre[QR_ROWS][17], bim[QR_ROWS][17];
-  __shared__ cd psum[16][16];
-  const int64_t q0 = c0 + BW;
+  if (j >= nr) return;                       // uniform
+  // ---- partials of column j (after the update above)
   const int64_t rj = q0 + j;
-  const int tid = threadIdx.x;
-  const int64_t r = q0 + (int64_t)blockIdx.x * QR_ROWS + tid;
-  double xn2 = 0.0;
-  for (int64_t w = 0; w < gridDim.x; ++w) xn2 += ws.npart[w];
-  const cd alpha = A[rj + (c0 + j) * lda];
-  cd tj = cmake(0.0, 0.0), scale = cmake(0.0, 0.0);
-  double beta = alpha.re;
-  if (xn2 > 0.0 || alpha.im != 0.0) {
-    const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2);
-    beta = alpha.re >= 0.0 ? -nrm : nrm;
-    tj = cmake((beta - alpha.re) / beta, -alpha.im / beta);
-    // 1 / (alpha - beta)
-    const cd am = cmake(alpha.re - beta, alpha.im);
-    const double den = am.re * am.re + am.im * am.im;
-    scale = cmake(am.re / den, -am.im / den);
-  }
-  cd v = cmake(0.0, 0.0);
-  if (r < n && r >= rj) {
-    if (r == rj) {
-      v = cmake(1.0, 0.0);
-    } else {
-      v = cmul(A[r + (c0 + j) * lda], scale);
-      A[r + (c0 + j) * lda] = v;
-    }
-    ws.P3[r + (int64_t)j * n] = v;
-    ws.P3[r + (int64_t)(2 * BW + j) * n] = v;
-  }
-  // alpha stays in A until the panel is done (other workgroups read it); beta
-  // is written there by hb_tmat
-  if (blockIdx.x == 0 && tid == 0) {
-    tau[c0 + j] = tj;
-    ws.beta[j] = beta;
-  }
-  const bool live = r < n && r >= rj;
-  for (int cb = j + 1; cb < bw; cb += 16) {
+  if (r == rj)
+    for (int c = j; c < bw; ++c) pw[c] = A[rj + (c0 + c) * lda];
+  const bool live = r < n && r > rj;
+  const cd xr = live ? A[r + (c0 + j) * lda] : cmake(0.0, 0.0);
+  for (int cb = j; cb < bw; cb += 16) {
 #pragma unroll 4
     for (int cc = 0; cc < 16; ++cc) {
       cd p = cmake(0.0, 0.0);
-      if (live && cb + cc < bw) p = cmulc(v, A[r + (c0 + cb + cc) * lda]);
+      if (live && cb + cc < bw) p = cmulc(xr, A[r + (c0 + cb + cc) * lda]);
       bre[tid][cc] = p.re;
       bim[tid][cc] = p.im;
     }
@@ -181,38 +211,59 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_refl(int64_t n, cd *A, int64_t 
     }
     __syncthreads();
     if (tid < 16 && cb + tid < bw) {
-      cd s = cmake(0.0, 0.0);
-      for (int g = 0; g < 16; ++g) s = cadd(s, psum[g][tid]);
-      ws.qpart[blockIdx.x * BW + cb + tid] = s;
+      cd sum = cmake(0.0, 0.0);
+      for (int g = 0; g < 16; ++g) sum = cadd(sum, psum[g][tid]);
+      gw[blockIdx.x * BW + cb + tid] = sum;
     }
     __syncthreads();
   }
 }
 
-// Gram partials Sp[z] = V^H V over row slice z (for T).
-__global__ void __launch_bounds__(GEMM_THREADS) hb_gram(int64_t q0, int64_t m, int64_t n, HbWs ws) {
+// Gram partials Sp[z] = V^H V over row slice z = blockIdx.x (for T).
+__global__ void __launch_bounds__(GEMM_THREADS) hb_gram(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
-  const int64_t z = blockIdx.x;
-  const int64_t k0 = z * HEMM_KC, k1 = (k0 + HEMM_KC < m) ? k0 + HEMM_KC : m;
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t z = blockIdx.x, m = pp.m, n = P.n;
+  const int64_t k0 = z * PAN_KC, k1 = (k0 + PAN_KC < m) ? k0 + PAN_KC : m;
   if (k0 >= m) return;
-  const cd *V = ws.P3 + q0 + k0;
-  GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, V, n, ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
+  const cd *V = P.ws.P3 + pp.q0 + k0;
+  GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, V, n, P.ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
   gemm_tile<true, A_C, B_N>(g, 0, 0, lds);
+}
+
+// Sum of the row-slice partials Sp[z] into Sp[0] (element per thread).
+__global__ void __launch_bounds__(256) hb_sum_sp(const HbProb *pr, int64_t c0) {
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= BW * BW) return;
+  const int64_t npk = (pp.m + PAN_KC - 1) / PAN_KC;
+  cd s0 = cmake(0.0, 0.0), s1 = cmake(0.0, 0.0);
+  int64_t z = 0;
+  for (; z + 1 < npk; z += 2) {
+    s0 = cadd(s0, P.ws.Sp[z * BW * BW + e]);
+    s1 = cadd(s1, P.ws.Sp[(z + 1) * BW * BW + e]);
+  }
+  if (z < npk) s0 = cadd(s0, P.ws.Sp[z * BW * BW + e]);
+  P.ws.Sp[e] = cadd(s0, s1);
 }
 
 // T of the panel (upper triangular BW x BW) from the summed Gram partials
 // (four partial sums per element of the recurrence); the betas go to the
-// band block R.
-__global__ void __launch_bounds__(256) hb_tmat(cd *A, int64_t lda, int64_t c0, int nr, int64_t nks, const cd *tau,
-                                               HbWs ws) {
+// band block R, reflectors of length one get tau = 0.
+__global__ void __launch_bounds__(256) hb_tmat(const HbProb *pr, int64_t c0) {
   __shared__ cd T[BW][BW + 1];
   __shared__ cd part[4][BW];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int nr = pp.nr;
+  const HbWs &ws = P.ws;
   const int tid = threadIdx.x;
-  for (int e = tid; e < BW * BW; e += 256) {
-    cd s = cmake(0.0, 0.0);
-    for (int64_t z = 0; z < nks; ++z) s = cadd(s, ws.Sp[z * BW * BW + e]);
-    T[e % BW][e / BW] = s;
-  }
+  for (int e = tid; e < BW * BW; e += 256) T[e % BW][e / BW] = ws.Sp[e];
   __syncthreads();
   const int r = tid & 63, qp = tid >> 6;
   for (int kk = 0; kk < BW; ++kk) {
@@ -222,7 +273,7 @@ __global__ void __launch_bounds__(256) hb_tmat(cd *A, int64_t lda, int64_t c0, i
     part[qp][r] = s;
     __syncthreads();
     if (qp == 0) {
-      const cd tk = kk < nr ? tau[c0 + kk] : cmake(0.0, 0.0);
+      const cd tk = kk < nr ? P.tau[c0 + kk] : cmake(0.0, 0.0);
       if (r < kk) T[r][kk] = cscale(cmul(tk, cadd(cadd(part[0][r], part[1][r]), cadd(part[2][r], part[3][r]))), -1.0);
       else if (r == kk) T[r][kk] = tk;
       else T[r][kk] = cmake(0.0, 0.0);
@@ -230,34 +281,42 @@ __global__ void __launch_bounds__(256) hb_tmat(cd *A, int64_t lda, int64_t c0, i
     __syncthreads();
   }
   for (int e = tid; e < BW * BW; e += 256) ws.T[e] = T[e % BW][e / BW];
-  if (tid < nr) A[(c0 + BW + tid) + (c0 + tid) * lda] = cmake(ws.beta[tid], 0.0);
+  if (tid < nr) P.A[(c0 + BW + tid) + (c0 + tid) * P.lda] = cmake(ws.beta[tid], 0.0);
+  if (tid >= nr && tid < pp.bw) P.tau[c0 + tid] = cmake(0.0, 0.0);
 }
 
 // Make the 64 x 64 diagonal tiles of A22 (grid anchored at q0) Hermitian:
 // upper part from the lower one, real diagonal.
-__global__ void __launch_bounds__(256) hb_mirror_diag(cd *A, int64_t lda, int64_t q0, int64_t m) {
-  const int64_t t0 = (int64_t)blockIdx.x * 64;
+__global__ void __launch_bounds__(256) hb_mirror_diag(const HbProb *pr, int64_t c0) {
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t t0 = (int64_t)blockIdx.x * 64, m = pp.m, lda = P.lda;
+  if (t0 >= m) return;
+  cd *base = P.A + (pp.q0 + t0) + (pp.q0 + t0) * lda;
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int i = e & 63, j = e >> 6;
     if (t0 + i >= m || t0 + j >= m) continue;
-    cd *base = A + (q0 + t0) + (q0 + t0) * lda;
     if (i < j) base[i + j * lda] = cconj(base[j + i * lda]);
     else if (i == j) base[i + i * lda].im = 0.0;
   }
 }
 
-// Yp[z] = (A22 V) restricted to K slice z: row tile I = blockIdx.x.
-__global__ void __launch_bounds__(GEMM_THREADS) hb_hemm(const cd *A, int64_t lda, int64_t q0, int64_t m, int64_t n,
-                                                        HbWs ws) {
+// Yp[z] = (A22 V) restricted to K slice z = blockIdx.y: row tile blockIdx.x.
+__global__ void __launch_bounds__(GEMM_THREADS) hb_hemm(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t m = pp.m, n = P.n, lda = P.lda, q0 = pp.q0;
   const int64_t I = blockIdx.x, z = blockIdx.y;
   const int64_t m0 = I * GT_M;
   const int64_t k0 = z * HEMM_KC, k1 = (k0 + HEMM_KC < m) ? k0 + HEMM_KC : m;
   if (m0 >= m || k0 >= m) return;
   const int64_t kb = (m0 + GT_M < m) ? m0 + GT_M : m;   // columns < kb: lower part of row tile I
-  const cd *A22 = A + q0 + q0 * lda;
-  const cd *V = ws.P3 + q0;
-  cd *Y = ws.Yp + z * n * BW;
+  const cd *A22 = P.A + q0 + q0 * lda;
+  const cd *V = P.ws.P3 + q0;
+  cd *Y = P.ws.Yp + z * n * BW;
   bool first = true;
   if (k0 < kb) {
     const int64_t ke = k1 < kb ? k1 : kb;
@@ -273,36 +332,56 @@ __global__ void __launch_bounds__(GEMM_THREADS) hb_hemm(const cd *A, int64_t lda
   }
 }
 
-__global__ void hb_reduce_y(int64_t m, int64_t n, int64_t nks, HbWs ws) {
+__global__ void hb_reduce_y(const HbProb *pr, int64_t c0) {
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t m = pp.m, n = P.n;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * BW) return;
+  const int64_t nks = (m + HEMM_KC - 1) / HEMM_KC;
   const int64_t r = e % m, c = e / m;
   cd s = cmake(0.0, 0.0);
-  for (int64_t z = 0; z < nks; ++z) s = cadd(s, ws.Yp[z * n * BW + r + c * n]);
-  ws.Yb[r + c * n] = s;
+  for (int64_t z = 0; z < nks; ++z) s = cadd(s, P.ws.Yp[z * n * BW + r + c * n]);
+  P.ws.Yb[r + c * n] = s;
 }
 
-// Sp[z] = V^H X over row slice z.
-__global__ void __launch_bounds__(GEMM_THREADS) hb_vhx(int64_t q0, int64_t m, int64_t n, HbWs ws) {
+// X = Y T into the W slot (row tile blockIdx.x).
+__global__ void __launch_bounds__(GEMM_THREADS) hb_xyt(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
-  const int64_t z = blockIdx.x;
-  const int64_t k0 = z * HEMM_KC, k1 = (k0 + HEMM_KC < m) ? k0 + HEMM_KC : m;
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n = P.n;
+  if (m0 >= pp.m) return;
+  GemmArgs g = gemm_args(pp.m, BW, BW, P.ws.Yb, n, P.ws.T, BW, P.ws.P3 + pp.q0 + (int64_t)BW * n, n, 1.0, 0.0, 0.0,
+                         0.0);
+  gemm_tile<true, A_N, B_N>(g, m0, 0, lds);
+}
+
+// Sp[z] = V^H X over row slice z = blockIdx.x.
+__global__ void __launch_bounds__(GEMM_THREADS) hb_vhx(const HbProb *pr, int64_t c0) {
+  __shared__ double lds[GEMM_LDS_ELEMS];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t z = blockIdx.x, m = pp.m, n = P.n;
+  const int64_t k0 = z * PAN_KC, k1 = (k0 + PAN_KC < m) ? k0 + PAN_KC : m;
   if (k0 >= m) return;
-  const cd *V = ws.P3 + q0 + k0;
-  const cd *X = ws.P3 + q0 + k0 + (int64_t)BW * n;
-  GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, X, n, ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
+  const cd *V = P.ws.P3 + pp.q0 + k0;
+  const cd *X = P.ws.P3 + pp.q0 + k0 + (int64_t)BW * n;
+  GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, X, n, P.ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
   gemm_tile<true, A_C, B_N>(g, 0, 0, lds);
 }
 
 // U = T^H (sum_z Sp[z])   (element per thread)
-__global__ void __launch_bounds__(256) hb_tu(int64_t nks, HbWs ws) {
+__global__ void __launch_bounds__(256) hb_tu(const HbProb *pr, int64_t c0) {
   __shared__ cd S[BW][BW + 1];
-  for (int e = threadIdx.x; e < BW * BW; e += 256) {
-    const int i = e % BW, j = e / BW;
-    cd s = cmake(0.0, 0.0);
-    for (int64_t z = 0; z < nks; ++z) s = cadd(s, ws.Sp[z * BW * BW + e]);
-    S[i][j] = s;
-  }
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const HbWs &ws = P.ws;
+  for (int e = threadIdx.x; e < BW * BW; e += 256) S[e % BW][e / BW] = ws.Sp[e];
   __syncthreads();
   for (int e = threadIdx.x; e < BW * BW; e += 256) {
     const int i = e % BW, j = e / BW;
@@ -312,81 +391,153 @@ __global__ void __launch_bounds__(256) hb_tu(int64_t nks, HbWs ws) {
   }
 }
 
-// Lower band of A (offsets 0 .. BW, real diagonal) into AB (ldab = 2 BW), zero below.
-__global__ void hb_band_copy(int64_t n, const cd *A, int64_t lda, cd *AB) {
-  const int64_t c = blockIdx.x;
+// W = X - V U / 2 in place of X (row tile blockIdx.x).
+__global__ void __launch_bounds__(GEMM_THREADS) hb_wupd(const HbProb *pr, int64_t c0) {
+  __shared__ double lds[GEMM_LDS_ELEMS];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n = P.n;
+  if (m0 >= pp.m) return;
+  GemmArgs g = gemm_args(pp.m, BW, BW, P.ws.P3 + pp.q0, n, P.ws.U, BW, P.ws.P3 + pp.q0 + (int64_t)BW * n, n, -0.5,
+                         0.0, 1.0, 0.0);
+  gemm_tile<true, A_N, B_N>(g, m0, 0, lds);
+}
+
+// A22 -= [V W] [W V]^H, lower tiles (tile (blockIdx.x, blockIdx.y)).
+__global__ void __launch_bounds__(GEMM_THREADS) hb_her2k(const HbProb *pr, int64_t c0) {
+  __shared__ double lds[GEMM_LDS_ELEMS];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t m = pp.m, n = P.n, q0 = pp.q0;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  if (m0 >= m || n0 >= m || m0 + GT_M <= n0) return;
+  GemmArgs g = gemm_args(m, m, 2 * BW, P.ws.P3 + q0, n, P.ws.P3 + q0 + (int64_t)BW * n, n, P.A + q0 + q0 * P.lda,
+                         P.lda, -1.0, 0.0, 1.0, 0.0);
+  g.lower = 1;
+  gemm_tile<true, A_N, B_C>(g, m0, n0, lds);
+}
+
+// Lower band of A (offsets 0 .. BW, real diagonal) into AB (ldab = 2 BW), zero
+// below; tau = 0 for the columns past the last panel (no reflector).
+__global__ void hb_band_copy(const HbProb *pr) {
+  const HbProb &P = pr[blockIdx.z];
+  const int64_t c = blockIdx.x, n = P.n;
+  if (c >= n) return;
   const int o = threadIdx.x;        // 0 .. 2 BW - 1
   const int64_t r = c + o;
   cd v = cmake(0.0, 0.0);
-  if (o <= BW && r < n) v = A[r + c * lda];
+  if (o <= BW && r < n) v = P.A[r + c * P.lda];
   if (o == 0) v.im = 0.0;
-  AB[o + c * (int64_t)LDAB] = v;
+  P.AB[o + c * (int64_t)LDAB] = v;
+  const int64_t first_none = n > BW + 1 ? ((n - BW - 2) / BW + 1) * BW : 0;
+  if (o == 0 && c >= first_none && c < n - 1) P.tau[c] = cmake(0.0, 0.0);
 }
 
+// Grouped band reduction of `count` problems in the device table pr (orders
+// nh[] on the host).
+int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_t st) {
+  if (count <= 0) return MMF_OK;
+  if (count > 65535) {
+    for (int64_t b = 0; b < count; b += 65535) {
+      const int rc = he2hb_grouped(pr + b, nh + b, count - b < 65535 ? count - b : 65535, st);
+      if (rc) return rc;
+    }
+    return MMF_OK;
+  }
+  int64_t nmax = 0;
+  for (int64_t c = 0; c < count; ++c) nmax = nh[c] > nmax ? nh[c] : nmax;
+  if (nmax <= 0) return MMF_OK;
+  const unsigned Z = (unsigned)count;
+  for (int64_t c0 = 0; c0 + BW < nmax - 1; c0 += BW) {
+    // sized for the largest problem that has this panel
+    const int64_t m = nmax - c0 - BW;
+    const int bw = (int)((nmax - c0 < BW) ? nmax - c0 : BW);
+    int nrmax = 0;
+    for (int64_t c = 0; c < count; ++c) {
+      if (c0 + BW >= nh[c] - 1) continue;
+      const int64_t mc = nh[c] - c0 - BW;
+      const int bwc = (int)((nh[c] - c0 < BW) ? nh[c] - c0 : BW);
+      const int nrc = (int)((mc - 1 < bwc) ? mc - 1 : bwc);
+      nrmax = nrc > nrmax ? nrc : nrmax;
+    }
+    (void)bw;
+    const unsigned nwg = cdiv(m, QR_ROWS), ntile = cdiv(m, GT_M);
+    const unsigned nks = cdiv(m, HEMM_KC), npk = cdiv(m, PAN_KC);
+    hipLaunchKernelGGL(hb_zero_p3, dim3(cdiv(m, 256), 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    // panel factorization: one launch per column
+    for (int j = 0; j <= nrmax; ++j) {
+      hipLaunchKernelGGL(hb_qr_step, dim3(nwg, 1, Z), dim3(QR_ROWS), 0, st, pr, c0, j);
+      MMF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(hb_gram, dim3(npk, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_sum_sp, dim3(BW * BW / 256, 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_tmat, dim3(1, 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    // Y = A22 V
+    hipLaunchKernelGGL(hb_mirror_diag, dim3(ntile, 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_hemm, dim3(ntile, nks, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_reduce_y, dim3(cdiv(m * BW, 256), 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    // X = Y T ; U = T^H V^H X ; W = X - V U / 2
+    hipLaunchKernelGGL(hb_xyt, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_vhx, dim3(npk, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_sum_sp, dim3(BW * BW / 256, 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_tu, dim3(1, 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hb_wupd, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+    // A22 -= [V W] [W V]^H  (lower tiles)
+    hipLaunchKernelGGL(hb_her2k, dim3(ntile, ntile, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(hb_band_copy, dim3((unsigned)nmax, 1, Z), dim3(LDAB), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+inline HbProb hb_prob(int64_t n, cd *A, int64_t lda, cd *tau, cd *AB, void *ws) {
+  HbProb q;
+  q.n = n; q.lda = lda; q.A = A; q.tau = tau; q.AB = AB;
+  q.ws = hb_ws(n, ws);
+  return q;
+}
+
+// Single reduction: the one-entry table sits at the start of the workspace.
 int he2hb_run(int64_t n, mmf_z *Az, int64_t lda, mmf_z *tauz, mmf_z *ABz, void *work, size_t bytes,
               hipStream_t st) {
   if (n <= 0) return MMF_OK;
-  HbWs ws = hb_ws(n, work);
-  if (bytes < ws.bytes) return MMF_ERR_WORKSPACE;
-  cd *A = reinterpret_cast<cd *>(Az);
-  cd *tau = reinterpret_cast<cd *>(tauz);
-  for (int64_t c0 = 0; c0 + BW < n - 1; c0 += BW) {
-    const int64_t q0 = c0 + BW, m = n - q0;
-    const int bw = (int)((n - c0 < BW) ? n - c0 : BW);
-    const int nr = (int)((m - 1 < bw) ? m - 1 : bw);
-    const unsigned nwg = cdiv(m, QR_ROWS);
-    hipLaunchKernelGGL(hb_zero_p3, dim3(cdiv(m, 256)), dim3(256), 0, st, n, q0, ws.P3);
-    MMF_LAUNCH_CHECK();
-    // panel factorization
-    for (int j = 0; j <= nr; ++j) {
-      if (j == nr && nr == bw) break;
-      hipLaunchKernelGGL(hb_qr_update, dim3(nwg), dim3(QR_ROWS), 0, st, n, A, lda, c0, j, bw, nr, tau, ws);
-      MMF_LAUNCH_CHECK();
-      if (j < nr) {
-        hipLaunchKernelGGL(hb_qr_refl, dim3(nwg), dim3(QR_ROWS), 0, st, n, A, lda, c0, j, bw, tau, ws);
-        MMF_LAUNCH_CHECK();
-      }
-    }
-    // reflectors of length one: identity
-    for (int j = nr; j < bw; ++j) MMF_HIP_TRY(hipMemsetAsync(tau + c0 + j, 0, sizeof(cd), st));
-    const unsigned ntile = cdiv(m, GT_M);
-    const int64_t nks = (m + HEMM_KC - 1) / HEMM_KC;
-    hipLaunchKernelGGL(hb_gram, dim3((unsigned)nks), dim3(GEMM_THREADS), 0, st, q0, m, n, ws);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(hb_tmat, dim3(1), dim3(256), 0, st, A, lda, c0, nr, nks, tau, ws);
-    MMF_LAUNCH_CHECK();
-    // Y = A22 V
-    hipLaunchKernelGGL(hb_mirror_diag, dim3(ntile), dim3(256), 0, st, A, lda, q0, m);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(hb_hemm, dim3(ntile, (unsigned)nks), dim3(GEMM_THREADS), 0, st, A, lda, q0, m, n, ws);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(hb_reduce_y, dim3(cdiv(m * BW, 256)), dim3(256), 0, st, m, n, nks, ws);
-    MMF_LAUNCH_CHECK();
-    // X = Y T  (into the W slot)
-    cd *Vs = ws.P3 + q0, *Ws = ws.P3 + q0 + (int64_t)BW * n;
-    int rc = gemm_launch<true, A_N, B_N>(gemm_args(m, BW, BW, ws.Yb, n, ws.T, BW, Ws, n, 1.0, 0.0, 0.0, 0.0), st);
-    if (rc) return rc;
-    // U = T^H V^H X ; W = X - V U / 2
-    hipLaunchKernelGGL(hb_vhx, dim3((unsigned)nks), dim3(GEMM_THREADS), 0, st, q0, m, n, ws);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(hb_tu, dim3(1), dim3(256), 0, st, nks, ws);
-    MMF_LAUNCH_CHECK();
-    rc = gemm_launch<true, A_N, B_N>(gemm_args(m, BW, BW, Vs, n, ws.U, BW, Ws, n, -0.5, 0.0, 1.0, 0.0), st);
-    if (rc) return rc;
-    // A22 -= [V W] [W V]^H  (lower tiles)
-    GemmArgs g = gemm_args(m, m, 2 * BW, Vs, n, Ws, n, A + q0 + q0 * lda, lda, -1.0, 0.0, 1.0, 0.0);
-    g.lower = 1;
-    rc = gemm_launch<true, A_N, B_C>(g, st);
-    if (rc) return rc;
-  }
-  // columns past the last panel carry no reflector
-  const int64_t first_none = n > BW + 1 ? ((n - BW - 2) / BW + 1) * BW : 0;
-  if (n - 1 > first_none)
-    MMF_HIP_TRY(hipMemsetAsync(tau + first_none, 0, sizeof(cd) * (size_t)(n - 1 - first_none), st));
-  hipLaunchKernelGGL(hb_band_copy, dim3((unsigned)n), dim3(LDAB), 0, st, n, A, lda,
-                     reinterpret_cast<cd *>(ABz));
-  MMF_LAUNCH_CHECK();
-  return MMF_OK;
+  static_assert(sizeof(HbProb) <= STAGE_TABLE_BYTES, "table entry");
+  if (bytes < he2hb_ws_bytes(n)) return MMF_ERR_WORKSPACE;
+  HbProb *pr = reinterpret_cast<HbProb *>(work);
+  const HbProb q = hb_prob(n, reinterpret_cast<cd *>(Az), lda, reinterpret_cast<cd *>(tauz),
+                           reinterpret_cast<cd *>(ABz), (char *)work + STAGE_TABLE_BYTES);
+  const int rc = table_write(pr, &q, 1, st);
+  if (rc) return rc;
+  return he2hb_grouped(pr, &n, 1, st);
+}
+
+// Batch: problem c reduces A[c] with the stage workspace stage[c] (laid out as
+// for a single reduction); the table goes to `table` (count * STAGE_TABLE_BYTES).
+int he2hb_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda, mmf_z *const *tau,
+                  mmf_z *const *AB, void *const *stage, void *table, hipStream_t st) {
+  std::vector<HbProb> h((size_t)count);
+  for (int64_t c = 0; c < count; ++c)
+    h[c] = hb_prob(n[c], reinterpret_cast<cd *>(A[c]), lda[c], reinterpret_cast<cd *>(tau[c]),
+                   reinterpret_cast<cd *>(AB[c]), (char *)stage[c] + STAGE_TABLE_BYTES);
+  HbProb *pr = reinterpret_cast<HbProb *>(table);
+  const int rc = table_write(pr, h.data(), count, st);
+  if (rc) return rc;
+  return he2hb_grouped(pr, n, count, st);
 }
 
 }  // namespace mmf

@@ -1,7 +1,7 @@
 """GPU parity of the two-stage eigensolver (dense -> band -> real tridiagonal
 by bulge chasing, then the two back-transformations) against the oracle.
 
-mmf_eigh takes this path from order MMF_EIGH_TWO_STAGE_MIN up (default 4096);
+mmf_eigh takes this path from order MMF_EIGH_TWO_STAGE_MIN up (default 12288);
 the tests lower the threshold to 0 so that small orders, which the oracle
 solves in milliseconds, exercise every edge of the band reduction: partial
 last panels, sweeps shorter than the bandwidth, single-element reflectors,
@@ -113,3 +113,26 @@ def test_two_stage_window(two_stage, n, kmax):
     Z = Zt.cpu().numpy()[:kk].T
     assert np.linalg.norm(H @ Z - Z * w.cpu().numpy()[:kk]) / np.linalg.norm(H) < 1e-12
     assert np.abs(Z.conj().T @ Z - np.eye(kk)).max() < 1e-12
+
+
+@pytest.mark.parametrize("thr", ["0", "200"], ids=["all_two_stage", "mixed"])
+def test_two_stage_eigvalsh_batched(monkeypatch, thr):
+    """Grouped two-stage reduction + Sturm bisection over mixed orders (with
+    threshold 200 one call holds one-stage and two-stage problems)."""
+    torch, mmf = require_gpu()
+    monkeypatch.setenv("MMF_EIGH_TWO_STAGE_MIN", thr)
+    sizes = [65, 1, 0, 130, 2, 300, 64, 513, 3, 257]
+    Hs = [_herm(n, 4000 + n) if n else np.zeros((0, 0), complex) for n in sizes]
+    mats = [to_dev_cm(torch, H) if n else torch.empty((0, 0), dtype=torch.complex128, device="cuda")
+            for H, n in zip(Hs, sizes)]
+    log(f"two-stage eigvalsh batched threshold {thr}")
+    ws, info = mmf.eigvalsh_batched(mats, 0)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0] * len(sizes)
+    for H, w in zip(Hs, ws):
+        if H.shape[0] == 0:
+            continue
+        wo, _ = oracle.eigh(H)
+        wg = w.cpu().numpy()
+        assert np.all(np.diff(wg) >= 0)
+        assert np.abs(wg - wo).max() <= 1e-10 * max(1.0, np.abs(wo).max()), H.shape[0]
