@@ -49,6 +49,7 @@ struct HbWs {
   cd *gpart;   // 2 x nwg x BW: column dot partials of the panel factorization
   cd *prow;    // 2 x BW: published panel row
   double *beta;   // BW: beta of the panel's reflectors
+  cd *WVh;     // 2 BW x n (ld 2 BW): [W V]^H of the current panel (operand of the update)
   int64_t nks, npk, nwg;
   size_t bytes;
 };
@@ -69,6 +70,7 @@ inline HbWs hb_ws(int64_t n, void *base) {
   w.gpart = cv.take<cd>((size_t)2 * w.nwg * BW);
   w.prow = cv.take<cd>((size_t)2 * BW);
   w.beta = cv.take<double>(BW);
+  w.WVh = cv.take<cd>((size_t)2 * BW * N);
   w.bytes = cv.used();
   return w;
 }
@@ -404,7 +406,30 @@ __global__ void __launch_bounds__(GEMM_THREADS) hb_wupd(const HbProb *pr, int64_
   gemm_tile<true, A_N, B_N>(g, m0, 0, lds);
 }
 
-// A22 -= [V W] [W V]^H, lower tiles (tile (blockIdx.x, blockIdx.y)).
+// WVh = [W V]^H (2 BW x m, ld 2 BW), through LDS so that both the reads (rows
+// of P3) and the writes (columns of WVh) are contiguous: workgroup x takes 32
+// rows of the panel.
+__global__ void __launch_bounds__(256) hb_wv_transpose(const HbProb *pr, int64_t c0) {
+  __shared__ cd t[32][2 * BW + 1];
+  const HbProb &P = pr[blockIdx.z];
+  HbPanel pp;
+  if (!hb_panel(P, c0, pp)) return;
+  const int64_t r0 = (int64_t)blockIdx.x * 32, m = pp.m, n = P.n;
+  if (r0 >= m) return;
+  const cd *WV = P.ws.P3 + pp.q0 + (int64_t)BW * n;     // columns BW .. 3 BW - 1 of P3: [W V]
+  for (int e = threadIdx.x; e < 32 * 2 * BW; e += 256) {
+    const int rr = e & 31, k = e >> 5;
+    t[rr][k] = (r0 + rr < m) ? WV[(r0 + rr) + (int64_t)k * n] : cmake(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 2 * BW; e += 256) {
+    const int k = e & (2 * BW - 1), rr = e >> 7;
+    if (r0 + rr < m) P.ws.WVh[k + (r0 + rr) * (int64_t)(2 * BW)] = cconj(t[rr][k]);
+  }
+}
+
+// A22 -= [V W] [W V]^H, lower tiles (tile (blockIdx.x, blockIdx.y)); the right
+// operand is the explicit [W V]^H, so both operands are read column-contiguous.
 __global__ void __launch_bounds__(GEMM_THREADS) hb_her2k(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
@@ -413,10 +438,10 @@ __global__ void __launch_bounds__(GEMM_THREADS) hb_her2k(const HbProb *pr, int64
   const int64_t m = pp.m, n = P.n, q0 = pp.q0;
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
   if (m0 >= m || n0 >= m || m0 + GT_M <= n0) return;
-  GemmArgs g = gemm_args(m, m, 2 * BW, P.ws.P3 + q0, n, P.ws.P3 + q0 + (int64_t)BW * n, n, P.A + q0 + q0 * P.lda,
-                         P.lda, -1.0, 0.0, 1.0, 0.0);
+  GemmArgs g = gemm_args(m, m, 2 * BW, P.ws.P3 + q0, n, P.ws.WVh, 2 * BW, P.A + q0 + q0 * P.lda, P.lda, -1.0, 0.0,
+                         1.0, 0.0);
   g.lower = 1;
-  gemm_tile<true, A_N, B_C>(g, m0, n0, lds);
+  gemm_tile<true, A_N, B_N>(g, m0, n0, lds);
 }
 
 // Lower band of A (offsets 0 .. BW, real diagonal) into AB (ldab = 2 BW), zero
@@ -497,6 +522,8 @@ int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_
     hipLaunchKernelGGL(hb_wupd, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
     MMF_LAUNCH_CHECK();
     // A22 -= [V W] [W V]^H  (lower tiles)
+    hipLaunchKernelGGL(hb_wv_transpose, dim3(cdiv(m, 32), 1, Z), dim3(256), 0, st, pr, c0);
+    MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(hb_her2k, dim3(ntile, ntile, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
     MMF_LAUNCH_CHECK();
   }

@@ -31,7 +31,8 @@ constexpr int BT_KCHUNK = 2048;   // rows per split-K slice
 
 template <typename R>
 struct BtWs {
-  cx<R> *Vp;      // packed clean reflector blocks
+  cx<R> *Vp;      // packed clean reflector blocks (mb x BT_NB each)
+  cx<R> *VpT;     // the same blocks conjugate-transposed (BT_NB x mb each)
   cx<R> *Tm;      // nblk x NB x NB
   cx<R> *Wpart;   // nsplit x NB x n
   cx<R> *W2;      // NB x n
@@ -55,6 +56,7 @@ inline BtWs<R> unmtr_ws(int64_t n, void *base, int64_t nc = -1) {
   w.nsplit = (n + BT_KCHUNK - 1) / BT_KCHUNK;
   if (w.nsplit < 1) w.nsplit = 1;
   w.Vp = cv.take<cx<R>>((size_t)(w.nblk ? bt_off(n, w.nblk) : 1));
+  w.VpT = cv.take<cx<R>>((size_t)(w.nblk ? bt_off(n, w.nblk) : 1));
   w.Tm = cv.take<cx<R>>((size_t)(w.nblk ? w.nblk : 1) * BT_NB * BT_NB);
   w.Wpart = cv.take<cx<R>>((size_t)w.nsplit * BT_NB * (ncol > 0 ? ncol : 1));
   w.W2 = cv.take<cx<R>>((size_t)BT_NB * (ncol > 0 ? ncol : 1));
@@ -74,7 +76,7 @@ struct BtProb {
   const cx<R> *V, *tau;
   const double *Z;
   cx<R> *Phi;
-  cx<R> *Vp, *Tm, *Wpart, *W2, *Gpart;
+  cx<R> *Vp, *VpT, *Tm, *Wpart, *W2, *Gpart;
 };
 
 // Clean copy of block b = blockIdx.y: Vb[r', q] (r' = 0..mb-1 is row p+1+r'),
@@ -91,6 +93,7 @@ __global__ void bt_pack(const BtProb<R> *pr) {
   if (rr >= mb) return;
   const int64_t row = p + 1 + rr;
   cx<R> *Vb = P.Vp + bt_off(n, b);
+  cx<R> *Vt = P.VpT + bt_off(n, b);
   for (int q = 0; q < BT_NB; ++q) {
     const int64_t i = p + q;
     cx<R> v = cmk<R>(0, 0);
@@ -99,6 +102,7 @@ __global__ void bt_pack(const BtProb<R> *pr) {
       else if (row > i + 1) v = P.V[row + i * P.ldv];
     }
     Vb[rr + (int64_t)q * mb] = v;
+    Vt[q + rr * (int64_t)BT_NB] = cconj(v);
   }
 }
 
@@ -117,11 +121,11 @@ __global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, i
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   const int64_t nc = P.nc;
   if (k0 >= mb || n0 >= nc) return;
-  const cx<R> *Vb = P.Vp + bt_off(n, b);
-  // A_C: op(A)[m,k] = conj(A[k + m lda]);  B_N: op(B)[k,n] = B[k + n ldb]
-  GemmArgs s = gemm_args(BT_NB, nc, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vb + k0, mb,
+  // V^H from its explicit copy (A_N reads whole columns)
+  const cx<R> *Vt = P.VpT + bt_off(n, b);
+  GemmArgs s = gemm_args(BT_NB, nc, (mb - k0 < BT_KCHUNK) ? mb - k0 : BT_KCHUNK, Vt + k0 * (int64_t)BT_NB, BT_NB,
                          P.Phi + (p + 1) + k0, P.ldphi, P.Wpart + z * BT_NB * nc, BT_NB, 1.0, 0.0, 0.0, 0.0);
-  gemm_tile_t<R, true, A_C, B_N>(s, m0, n0, lds);
+  gemm_tile_t<R, true, A_N, B_N>(s, m0, n0, lds);
 }
 
 // Gram partials of every block at once: Gpart[b][z] = Vb^H Vb over slice z
@@ -330,7 +334,7 @@ inline BtProb<R> bt_prob(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *ta
   BtProb<R> q;
   q.n = n; q.nc = nc >= 0 ? nc : n; q.ldv = ldv; q.ldz = ldz; q.ldphi = ldphi; q.nblk = w.nblk; q.nsplit = w.nsplit;
   q.V = V; q.tau = tau; q.Z = Z; q.Phi = Phi;
-  q.Vp = w.Vp; q.Tm = w.Tm; q.Wpart = w.Wpart; q.W2 = w.W2; q.Gpart = w.Gpart;
+  q.Vp = w.Vp; q.VpT = w.VpT; q.Tm = w.Tm; q.Wpart = w.Wpart; q.W2 = w.W2; q.Gpart = w.Gpart;
   return q;
 }
 
