@@ -44,6 +44,9 @@ struct HsProb {
 };
 
 // ---------------------------------------------------------------- chase
+constexpr int CH_THREADS = 512;           // threads per chase task (8 wavefronts)
+constexpr int CH_Q = CH_THREADS / 64;     // row / column groups of the block products
+constexpr int CH_W = BW / CH_Q;           // entries per group
 // Householder vector of x held by the 64 lanes of one wavefront (lane i: x_i,
 // len <= BW entries): H^H x = beta e0, beta real, v_0 = 1.  The identity
 // (tau = 0) when x is already real e0.
@@ -78,10 +81,10 @@ __host__ __device__ inline void hb_step_range(int64_t n, int64_t t, int64_t &smi
 // of problem blockIdx.z.  Thread (i, q) = (tid % 64, tid / 64); the scalar work
 // (reflectors, sums over 64 entries) stays in wavefront 0.  With compact
 // storage only the current reflector of each sweep is kept (slot s).
-__global__ void __launch_bounds__(256) hb_chase(const HsProb *pr, int64_t t) {
+__global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t t) {
   __shared__ cd D[BW][BW + 1];
   __shared__ cd E[BW][BW + 1];
-  __shared__ cd vs[BW], v2[BW], wv[BW], zz[BW], red[4][BW], red2[4][BW];
+  __shared__ cd vs[BW], v2[BW], wv[BW], zz[BW], red[CH_Q][BW], red2[CH_Q][BW];
   __shared__ cd tsh[2];
   __shared__ double bsh[2];
   const HsProb &P = pr[blockIdx.z];
@@ -107,15 +110,16 @@ __global__ void __launch_bounds__(256) hb_chase(const HsProb *pr, int64_t t) {
   cd *col = AB + s * (int64_t)LDAB;
   cd xi = cmake(0.0, 0.0);
   if (q == 0) xi = (k == 0) ? ((i < L) ? col[1 + i] : cmake(0.0, 0.0)) : V2[voff + i];
-  cd dreg[16], ereg[16];
+  constexpr int NE = BW * BW / CH_THREADS;
+  cd dreg[NE], ereg[NE];
 #pragma unroll
-  for (int q2 = 0; q2 < 16; ++q2) {
-    const int e = tid + 256 * q2, ii = e & 63, jj = e >> 6;
+  for (int q2 = 0; q2 < NE; ++q2) {
+    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
     dreg[q2] = (ii >= jj && ii < L) ? AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
   }
 #pragma unroll
-  for (int q2 = 0; q2 < 16; ++q2) {
-    const int e = tid + 256 * q2, ii = e & 63, jj = e >> 6;
+  for (int q2 = 0; q2 < NE; ++q2) {
+    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
     ereg[q2] = (hasE && ii < Le) ? AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
   }
   // ---- current reflector H = H_{s,k} (wavefront 0)
@@ -134,17 +138,17 @@ __global__ void __launch_bounds__(256) hb_chase(const HsProb *pr, int64_t t) {
     }
   }
 #pragma unroll
-  for (int q2 = 0; q2 < 16; ++q2) {
-    const int e = tid + 256 * q2, ii = e & 63, jj = e >> 6;
+  for (int q2 = 0; q2 < NE; ++q2) {
+    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
     if (ii >= jj) D[ii][jj] = dreg[q2];
     E[ii][jj] = ereg[q2];
   }
   __syncthreads();
   const cd tau = tsh[0];
-  // ---- y = D v from the lower triangle, z = E v (row i, quarter q of the columns)
+  // ---- y = D v from the lower triangle, z = E v (row i, column group q)
   {
     cd py = cmake(0.0, 0.0), pz = cmake(0.0, 0.0);
-    for (int jj = 16 * q; jj < 16 * q + 16; ++jj) {
+    for (int jj = CH_W * q; jj < CH_W * q + CH_W; ++jj) {
       const cd vj = vs[jj];
       if (i < L && jj < L) {
         cd h = (jj <= i) ? D[i][jj] : cconj(D[jj][i]);
@@ -159,17 +163,19 @@ __global__ void __launch_bounds__(256) hb_chase(const HsProb *pr, int64_t t) {
   __syncthreads();
   // ---- w = tau y - (|tau|^2 gamma / 2) v, gamma = v^H y;  zz = tau z (wavefront 0)
   if (q == 0) {
-    const cd y = cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i]));
+    cd y = red[0][i], z = red2[0][i];
+#pragma unroll
+    for (int g = 1; g < CH_Q; ++g) { y = cadd(y, red[g][i]); z = cadd(z, red2[g][i]); }
     const cd v = vs[i];
     const double gamma = wave_sum(i < L ? cmulc(v, y).re : 0.0);
     const double h = 0.5 * cabs2(tau) * gamma;
     const cd ty = cmul(tau, y);
     wv[i] = cmake(ty.re - h * v.re, ty.im - h * v.im);
-    zz[i] = cmul(tau, cadd(cadd(red2[0][i], red2[1][i]), cadd(red2[2][i], red2[3][i])));
+    zz[i] = cmul(tau, z);
   }
   __syncthreads();
   // ---- D <- D - w v^H - v w^H (lower band to AB); E <- E - (tau z) v^H
-  for (int e = tid; e < BW * BW; e += 256) {
+  for (int e = tid; e < BW * BW; e += CH_THREADS) {
     const int ii = e & 63, jj = e >> 6;
     if (ii >= jj && ii < L) {
       cd d = csub(D[ii][jj], cadd(cmul(wv[ii], cconj(vs[jj])), cmul(vs[ii], cconj(wv[jj]))));
@@ -195,15 +201,20 @@ __global__ void __launch_bounds__(256) hb_chase(const HsProb *pr, int64_t t) {
   const double beta1 = bsh[0];
   const bool active = (Le >= 2) && (tau1.re != 0.0 || tau1.im != 0.0);     // uniform
   if (active) {
-    // u_j = v2^H E[:, j] (column j = i, quarter q of the rows)
+    // u_j = v2^H E[:, j] (column j = i, row group q)
     cd p = cmake(0.0, 0.0);
-    for (int ii = 16 * q; ii < 16 * q + 16; ++ii) p = cadd(p, cmulc(v2[ii], E[ii][i]));
+    for (int ii = CH_W * q; ii < CH_W * q + CH_W; ++ii) p = cadd(p, cmulc(v2[ii], E[ii][i]));
     red[q][i] = p;
     __syncthreads();
-    if (q == 0) wv[i] = cmulc(tau1, cadd(cadd(red[0][i], red[1][i]), cadd(red[2][i], red[3][i])));
+    if (q == 0) {
+      cd u = red[0][i];
+#pragma unroll
+      for (int g = 1; g < CH_Q; ++g) u = cadd(u, red[g][i]);
+      wv[i] = cmulc(tau1, u);
+    }
     __syncthreads();
   }
-  for (int e = tid; e < BW * BW; e += 256) {
+  for (int e = tid; e < BW * BW; e += CH_THREADS) {
     const int ii = e & 63, jj = e >> 6;
     if (ii >= Le) continue;
     cd x = E[ii][jj];
@@ -251,7 +262,7 @@ int hb2st_grouped(const HsProb *pr, const int64_t *nh, int64_t count, hipStream_
         if (hi - lo + 1 > width) width = hi - lo + 1;
       }
       if (width <= 0) continue;
-      hipLaunchKernelGGL(hb_chase, dim3((unsigned)width, 1, Z), dim3(256), 0, st, pr, t);
+      hipLaunchKernelGGL(hb_chase, dim3((unsigned)width, 1, Z), dim3(CH_THREADS), 0, st, pr, t);
       MMF_LAUNCH_CHECK();
     }
   }

@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
   const int wr = j & 1, rd = wr ^ 1;
   cd *gw = ws.gpart + (int64_t)wr * ws.nwg * BW, *gr = ws.gpart + (int64_t)rd * ws.nwg * BW;
   cd *pw = ws.prow + wr * BW, *prd = ws.prow + rd * BW;
+  cd vown = cmake(0.0, 0.0);                // this row's entry of v_{j-1}
   if (j >= 1) {
     // ---- reflector jp = j - 1 from the previous launch's sums
     const int jp = j - 1;
@@ -183,26 +184,43 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
       }
       ws.P3[r + (int64_t)jp * n] = v;
       ws.P3[r + (int64_t)(2 * BW + jp) * n] = v;
-      for (int c = j; c < bw; ++c) {
-        cd *p = A + r + (c0 + c) * lda;
-        *p = csub(*p, cmul(v, d[c]));
-      }
+      vown = v;
     }
   }
-  if (j >= nr) return;                       // uniform
-  // ---- partials of column j (after the update above)
+  // ---- update of columns j .. bw-1 by reflector j - 1 (j >= 1), fused with
+  // the partials of column j (g[c] = x~^H P[:, c], c >= j, x~ = column j below
+  // row rj), 16 columns per chunk held in registers
+  const bool upd = j >= 1 && r < n && r >= q0 + j - 1;
+  const bool last = j >= nr;                 // uniform: no partials after the last reflector
   const int64_t rj = q0 + j;
-  if (r == rj)
-    for (int c = j; c < bw; ++c) pw[c] = A[rj + (c0 + c) * lda];
-  const bool live = r < n && r > rj;
-  const cd xr = live ? A[r + (c0 + j) * lda] : cmake(0.0, 0.0);
+  const bool live = !last && r < n && r > rj;
+  cd xr = cmake(0.0, 0.0);
   for (int cb = j; cb < bw; cb += 16) {
-#pragma unroll 4
+    cd xv[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+      xv[cc] = (cb + cc < bw && r < n && (upd || live || r == rj)) ? A[r + (c0 + cb + cc) * lda] : cmake(0.0, 0.0);
+    if (upd) {
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) {
+        if (cb + cc < bw) {
+          xv[cc] = csub(xv[cc], cmul(vown, d[cb + cc]));
+          A[r + (c0 + cb + cc) * lda] = xv[cc];
+        }
+      }
+    }
+    if (last) continue;                      // uniform
+    if (cb == j) xr = xv[0];
+    if (r == rj) {
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc)
+        if (cb + cc < bw) pw[cb + cc] = xv[cc];
+    }
+#pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
-      cd p = cmake(0.0, 0.0);
-      if (live && cb + cc < bw) p = cmulc(xr, A[r + (c0 + cb + cc) * lda]);
-      bre[tid][cc] = p.re;
-      bim[tid][cc] = p.im;
+      const cd pp2 = (live && cb + cc < bw) ? cmulc(xr, xv[cc]) : cmake(0.0, 0.0);
+      bre[tid][cc] = pp2.re;
+      bim[tid][cc] = pp2.im;
     }
     __syncthreads();
     {
