@@ -36,12 +36,14 @@
 namespace mmf {
 
 constexpr int DC_LEAF = 64;
+constexpr int DC_CNT = 5;     // per merge: K, rotations, deflated, top-only, top-only + mixed columns
 constexpr double DC_EPS = DBL_EPSILON;
 
 struct DcWs {
   double *dw, *lam, *T1, *T2;
   double *ds, *zs, *dn, *zn, *ddef, *rc, *rs, *lamt, *zhat, *rho;
-  int32_t *src, *ndidx, *dfidx, *rp, *rj, *lamo, *colmap, *cnt;   // cnt: [3*n] K, R, ndef per merge
+  int32_t *src, *ndidx, *dfidx, *rp, *rj, *lamo, *colmap, *cnt;   // cnt: [DC_CNT * n] per merge
+  int32_t *ctype, *perm;      // child type of each column (1 top, 2 bottom, 3 both); T1/T2 slot of each kept column
   size_t bytes;
 };
 
@@ -70,7 +72,9 @@ inline DcWs stedc_ws(int64_t n, void *base) {
   w.rj = cv.take<int32_t>(N);
   w.lamo = cv.take<int32_t>(N);
   w.colmap = cv.take<int32_t>(N);
-  w.cnt = cv.take<int32_t>(3 * N);
+  w.cnt = cv.take<int32_t>(DC_CNT * N);
+  w.ctype = cv.take<int32_t>(N);
+  w.perm = cv.take<int32_t>(N);
   w.bytes = cv.used();
   return w;
 }
@@ -296,8 +300,11 @@ __global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
   double *ds = P.w.ds, *zs = P.w.zs, *rc = P.w.rc, *rs = P.w.rs;
   const double *rho = P.w.rho;
   int32_t *ndidx = P.w.ndidx, *dfidx = P.w.dfidx, *rp = P.w.rp, *rj = P.w.rj, *cnt = P.w.cnt;
+  int32_t *ctype = P.w.ctype, *perm = P.w.perm;
+  const int32_t *src = P.w.src;
   const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t s = q.s, m = q.m;
+  for (int64_t j = 0; j < m; ++j) ctype[s + j] = src[s + j] < q.n1 ? 1 : 2;
   const double rh = rho[s];
   double dmax = fmax(fabs(ds[s]), fabs(ds[s + m - 1]));
   const double tol = 8.0 * DC_EPS * fmax(dmax, rh);
@@ -322,6 +329,7 @@ __global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
       rc[s + R] = cv;
       rs[s + R] = sv;
       ++R;
+      ctype[s + j] |= ctype[s + prev];        // the kept column now spans both children's rows
       dfidx[s + ND++] = (int32_t)prev;
       prev = j;
     } else {
@@ -330,9 +338,25 @@ __global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
     }
   }
   if (prev >= 0) ndidx[s + K++] = (int32_t)prev;
-  cnt[3 * g + 0] = K;
-  cnt[3 * g + 1] = R;
-  cnt[3 * g + 2] = ND;
+  // kept columns grouped [top only | both | bottom only] (d order inside each
+  // group): the merge GEMM then multiplies the top rows by the first two
+  // groups and the bottom rows by the last two only
+  int32_t c1 = 0, c3 = 0;
+  for (int32_t k = 0; k < K; ++k) {
+    const int32_t t = ctype[s + ndidx[s + k]];
+    c1 += t == 1;
+    c3 += t == 3;
+  }
+  int32_t p1 = 0, p3 = c1, p2 = c1 + c3;
+  for (int32_t k = 0; k < K; ++k) {
+    const int32_t t = ctype[s + ndidx[s + k]];
+    perm[s + k] = t == 1 ? p1++ : (t == 3 ? p3++ : p2++);
+  }
+  cnt[DC_CNT * g + 0] = K;
+  cnt[DC_CNT * g + 1] = R;
+  cnt[DC_CNT * g + 2] = ND;
+  cnt[DC_CNT * g + 3] = c1;
+  cnt[DC_CNT * g + 4] = c1 + c3;
 }
 
 // ------------------------------------------------------------------ merge: rotate + gather
@@ -353,7 +377,7 @@ __global__ void dc_gather(const DcProb *pr, int lev) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= q.m) return;
   const int64_t s = q.s;
-  const int32_t K = cnt[3 * g], R = cnt[3 * g + 1], ND = cnt[3 * g + 2];
+  const int32_t K = cnt[DC_CNT * g], R = cnt[DC_CNT * g + 1], ND = cnt[DC_CNT * g + 2];
   double *zrow = Z + (s + r);
   for (int32_t k = 0; k < R; ++k) {
     const int64_t cp = s + src[s + rp[s + k]], cj = s + src[s + rj[s + k]];
@@ -363,7 +387,8 @@ __global__ void dc_gather(const DcProb *pr, int lev) {
     zrow[cj * ldz] = sn * zp + c * zj;
   }
   double *trow = T1 + (s + r);
-  for (int32_t k = 0; k < K; ++k) trow[(s + k) * n] = zrow[(s + src[s + ndidx[s + k]]) * ldz];
+  const int32_t *perm = P.w.perm;
+  for (int32_t k = 0; k < K; ++k) trow[(s + perm[s + k]) * n] = zrow[(s + src[s + ndidx[s + k]]) * ldz];
   for (int32_t k = 0; k < ND; ++k) trow[(s + K + k) * n] = zrow[(s + src[s + dfidx[s + k]]) * ldz];
   if (r < K) {
     dn[s + r] = ds[s + ndidx[s + r]];
@@ -383,7 +408,7 @@ __global__ void __launch_bounds__(256) dc_secular(const DcProb *pr, int lev) {
   int32_t *lamo = P.w.lamo, *info = P.info;
   double *lamt = P.w.lamt;
   const MergeGeom q = dc_geom(P.n, P.L, lev, g);
-  const int K = cnt[3 * g];
+  const int K = cnt[DC_CNT * g];
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= K) return;
@@ -486,7 +511,7 @@ __global__ void __launch_bounds__(256) dc_lowner(const DcProb *pr, int lev) {
   const int32_t *cnt = P.w.cnt, *lamo = P.w.lamo;
   double *zhat = P.w.zhat;
   const MergeGeom q = dc_geom(P.n, P.L, lev, g);
-  const int K = cnt[3 * g];
+  const int K = cnt[DC_CNT * g];
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= K) return;
@@ -519,24 +544,25 @@ __global__ void __launch_bounds__(256) dc_vectors(const DcProb *pr, int lev) {
   const int32_t *cnt = P.w.cnt, *lamo = P.w.lamo;
   double *T2 = P.w.T2;
   const MergeGeom q = dc_geom(n, P.L, lev, g);
-  const int K = cnt[3 * g];
+  const int K = cnt[DC_CNT * g];
   const int j = blockIdx.x;
   if (j >= K) return;
   const int64_t s = q.s;
   const double *d = dn + s;
   const double dorg = d[lamo[s + j]], tj = lamt[s + j];
   double *col = T2 + s + (s + j) * n;
+  const int32_t *perm = P.w.perm + s;
   double ss = 0.0;
   for (int i = threadIdx.x; i < K; i += 256) {
     const double u = zhat[s + i] / ((d[i] - dorg) - tj);
-    col[i] = u;
+    col[perm[i]] = u;
     ss += u * u;
   }
   ss = wave_sum(ss);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ss;
   __syncthreads();
   const double inv = 1.0 / sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
-  for (int i = threadIdx.x; i < K; i += 256) col[i] *= inv;
+  for (int i = threadIdx.x; i < K; i += 256) col[perm[i]] *= inv;
 }
 
 // Final ascending position of every eigenvalue of the merge (roots first in
@@ -554,7 +580,7 @@ __global__ void dc_final_pos(const DcProb *pr, int lev) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= q.m) return;
   const int64_t s = q.s;
-  const int K = cnt[3 * g];
+  const int K = cnt[DC_CNT * g];
   auto val = [&](int64_t x) -> double {
     return x < K ? dn[s + lamo[s + x]] + lamt[s + x] : ddef[s + (x - K)];
   };
@@ -578,10 +604,15 @@ __global__ void __launch_bounds__(GEMM_THREADS) dc_gemm(const DcProb *pr, int le
   const double *T1 = P.w.T1, *T2 = P.w.T2;
   double *Z = P.Z;
   const MergeGeom q = dc_geom(n, P.L, lev, g);
-  const int K = cnt[3 * g];
+  const int K = cnt[DC_CNT * g], c1 = cnt[DC_CNT * g + 3], c12 = cnt[DC_CNT * g + 4];
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
   if (m0 >= q.m || n0 >= K) return;
-  GemmArgs a = gemm_args(q.m, K, K, T1 + q.s + q.s * n, n, T2 + q.s + q.s * n, n, Z + q.s, ldz,
+  // rows of the first child meet only kept columns [0, c12), rows of the
+  // second only [c1, K); a row tile across the boundary takes all K
+  int64_t k0 = 0, k1 = K;
+  if (m0 + GT_M <= q.n1) k1 = c12;
+  else if (m0 >= q.n1) k0 = c1;
+  GemmArgs a = gemm_args(q.m, K, k1 - k0, T1 + q.s + (q.s + k0) * n, n, T2 + (q.s + k0) + q.s * n, n, Z + q.s, ldz,
                          1.0, 0.0, 0.0, 0.0);
   a.colmap = colmap + q.s;
   gemm_tile<false, A_N, B_N>(a, m0, n0, lds);
@@ -598,7 +629,7 @@ __global__ void dc_copy_def(const DcProb *pr, int lev) {
   const MergeGeom q = dc_geom(n, P.L, lev, g);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= q.m) return;
-  const int K = cnt[3 * g];
+  const int K = cnt[DC_CNT * g];
   for (int64_t k = K; k < q.m; ++k)
     Z[(q.s + r) + (int64_t)colmap[q.s + k] * ldz] = T1[(q.s + r) + (q.s + k) * n];
 }
