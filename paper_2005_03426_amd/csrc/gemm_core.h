@@ -5,9 +5,17 @@
 // A 256-thread workgroup computes a 64x64 tile of C; each of its four
 // wavefronts owns a 32x32 quadrant made of 2x2 blocks of the 16x16x4 MFMA
 // (v_mfma_f64_16x16x4f64 for R = double, v_mfma_f32_16x16x4f32 for
-// R = float, FP32 accumulation).  Complex products use four real MFMAs per
-// k-step (re += ar*br - ai*bi, im += ar*bi + ai*br) on operands split into
-// real and imaginary planes in LDS.  K advances in slices of 16 with a
+// R = float, FP32 accumulation).  Complex FP64 products use three real MFMAs
+// per k-step (the 3M form: P1 = ar*br, P2 = ai*bi, P3 = (ar+ai)*(br+bi),
+// re = P1 - P2, im = P3 - P1 - P2), on operands split into real and
+// imaginary planes in LDS; the sums ar+ai, br+bi are formed from the register
+// fragments.  The 3M product is normwise stable (its error is bounded by a
+// small multiple of eps |A| |B| in norm, like the 4M one, though not
+// componentwise for the imaginary part), which is what the eigenvector
+// transformations need.  Complex FP32 products (the complex64 stages of the
+// precision layer) keep four MFMAs (re += ar*br - ai*bi, im += ar*bi +
+// ai*br): there the larger 3M constant leaves starting vectors that the FP64
+// refinement needs more iterations to fix.  K advances in slices of 16 with a
 // register prefetch of the next slice while the current one is multiplied.
 // The epilogue stages the tile through LDS so that every wavefront writes 64
 // consecutive rows of one column (coalesced).
@@ -163,13 +171,17 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
 
   auto plane = [&](int s, int p) { return lds + (s * 4 + p) * (GT_K * GT_LD); };
 
-  v4 acc_re[2][2], acc_im[2][2];
+  // real: acc1 only; complex 3M: acc1 = sum ar*br, acc2 = sum ai*bi,
+  // acc3 = sum (ar+ai)(br+bi); complex 4M: acc1 = re, acc2 = im
+  constexpr bool M3 = CPLX && sizeof(R) == 8;
+  v4 acc1[2][2], acc2[2][2], acc3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      acc_re[a][b] = (v4){R(0), R(0), R(0), R(0)};
-      acc_im[a][b] = (v4){R(0), R(0), R(0), R(0)};
+      acc1[a][b] = (v4){R(0), R(0), R(0), R(0)};
+      acc2[a][b] = (v4){R(0), R(0), R(0), R(0)};
+      acc3[a][b] = (v4){R(0), R(0), R(0), R(0)};
     }
 
   // K range of this tile (band clipping keeps slices aligned to GT_K from kbeg)
@@ -211,15 +223,26 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
           fb_i[t] = Bi[(kk + lk) * GT_LD + wc + t * 16 + lrow];
         }
       }
+      R fa_s[2], fb_s[2];
+      if (M3) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          fa_s[t] = fa_r[t] + fa_i[t];
+          fb_s[t] = fb_r[t] + fb_i[t];
+        }
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          acc_re[a][b] = MF::run(fa_r[a], fb_r[b], acc_re[a][b]);
-          if (CPLX) {
-            acc_re[a][b] = MF::run(-fa_i[a], fb_i[b], acc_re[a][b]);
-            acc_im[a][b] = MF::run(fa_r[a], fb_i[b], acc_im[a][b]);
-            acc_im[a][b] = MF::run(fa_i[a], fb_r[b], acc_im[a][b]);
+          acc1[a][b] = MF::run(fa_r[a], fb_r[b], acc1[a][b]);
+          if (M3) {
+            acc2[a][b] = MF::run(fa_i[a], fb_i[b], acc2[a][b]);
+            acc3[a][b] = MF::run(fa_s[a], fb_s[b], acc3[a][b]);
+          } else if (CPLX) {
+            acc1[a][b] = MF::run(-fa_i[a], fb_i[b], acc1[a][b]);
+            acc2[a][b] = MF::run(fa_r[a], fb_i[b], acc2[a][b]);
+            acc2[a][b] = MF::run(fa_i[a], fb_r[b], acc2[a][b]);
           }
         }
     }
@@ -240,8 +263,14 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
       for (int r = 0; r < 4; ++r) {
         const int row = wr + a * 16 + MF::row(r, lk);
         const int col = wc + b * 16 + lrow;
-        Cr[col * GT_LD + row] = acc_re[a][b][r];
-        if (CPLX) Ci[col * GT_LD + row] = acc_im[a][b][r];
+        if (M3) {
+          const R p1 = acc1[a][b][r], p2 = acc2[a][b][r];
+          Cr[col * GT_LD + row] = p1 - p2;
+          Ci[col * GT_LD + row] = (acc3[a][b][r] - p1) - p2;
+        } else {
+          Cr[col * GT_LD + row] = acc1[a][b][r];
+          if (CPLX) Ci[col * GT_LD + row] = acc2[a][b][r];
+        }
       }
   __syncthreads();
   const int row = tid & 63;
@@ -284,7 +313,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t m0, int64_t n0, doub
 }
 
 template <typename R, bool CPLX, int OA, int OB>
-__global__ void __launch_bounds__(GEMM_THREADS) gemm_kernel_t(GemmArgs g) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) gemm_kernel_t(GemmArgs g) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const int64_t m0 = (int64_t)blockIdx.x * GT_M;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;

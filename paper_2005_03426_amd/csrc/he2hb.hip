@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
 }
 
 // Gram partials Sp[z] = V^H V over row slice z = blockIdx.x (for T).
-__global__ void __launch_bounds__(GEMM_THREADS) hb_gram(const HbProb *pr, int64_t c0) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_gram(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(256) hb_mirror_diag(const HbProb *pr, int64_t 
 }
 
 // Yp[z] = (A22 V) restricted to K slice z = blockIdx.y: row tile blockIdx.x.
-__global__ void __launch_bounds__(GEMM_THREADS) hb_hemm(const HbProb *pr, int64_t c0) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_hemm(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
@@ -367,7 +367,7 @@ __global__ void hb_reduce_y(const HbProb *pr, int64_t c0) {
 }
 
 // X = Y T into the W slot (row tile blockIdx.x).
-__global__ void __launch_bounds__(GEMM_THREADS) hb_xyt(const HbProb *pr, int64_t c0) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_xyt(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) hb_xyt(const HbProb *pr, int64_t
 }
 
 // Sp[z] = V^H X over row slice z = blockIdx.x.
-__global__ void __launch_bounds__(GEMM_THREADS) hb_vhx(const HbProb *pr, int64_t c0) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_vhx(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(256) hb_tu(const HbProb *pr, int64_t c0) {
 }
 
 // W = X - V U / 2 in place of X (row tile blockIdx.x).
-__global__ void __launch_bounds__(GEMM_THREADS) hb_wupd(const HbProb *pr, int64_t c0) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_wupd(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(256) hb_wv_transpose(const HbProb *pr, int64_t
 
 // A22 -= [V W] [W V]^H, lower tiles (tile (blockIdx.x, blockIdx.y)); the right
 // operand is the explicit [W V]^H, so both operands are read column-contiguous.
-__global__ void __launch_bounds__(GEMM_THREADS) hb_her2k(const HbProb *pr, int64_t c0) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_her2k(const HbProb *pr, int64_t c0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;

@@ -524,7 +524,7 @@ __global__ void ht_last_diag(const HtProb<R> *pr) {
 // Trailing update A[q0:, q0:] -= [V W] [W V]^H (lower tiles) after the panel
 // starting at column p, for every matrix of the table.
 template <typename R>
-__global__ void __launch_bounds__(GEMM_THREADS) ht_her2k(const HtProb<R> *pr, int64_t p) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) ht_her2k(const HtProb<R> *pr, int64_t p) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const HtProb<R> &q = pr[blockIdx.z];
   const int64_t n = q.n;

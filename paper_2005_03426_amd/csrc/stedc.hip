@@ -270,6 +270,7 @@ __global__ void dc_prep(const DcProb *pr, int lev) {
   ds[q.s + pos] = dv;
   zs[q.s + pos] = zv * inv_sqrt2;
   src[q.s + pos] = (int32_t)j;
+  P.w.ctype[q.s + pos] = j < q.n1 ? 1 : 2;    // child whose rows the column spans
   if (j == 0) rho[q.s] = 2.0 * fabs(ek);
 }
 
@@ -301,10 +302,8 @@ __global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
   const double *rho = P.w.rho;
   int32_t *ndidx = P.w.ndidx, *dfidx = P.w.dfidx, *rp = P.w.rp, *rj = P.w.rj, *cnt = P.w.cnt;
   int32_t *ctype = P.w.ctype, *perm = P.w.perm;
-  const int32_t *src = P.w.src;
   const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t s = q.s, m = q.m;
-  for (int64_t j = 0; j < m; ++j) ctype[s + j] = src[s + j] < q.n1 ? 1 : 2;
   const double rh = rho[s];
   double dmax = fmax(fabs(ds[s]), fabs(ds[s + m - 1]));
   const double tol = 8.0 * DC_EPS * fmax(dmax, rh);
@@ -594,7 +593,7 @@ __global__ void dc_final_pos(const DcProb *pr, int lev) {
   colmap[s + e] = (int32_t)(s + pos);
 }
 
-__global__ void __launch_bounds__(GEMM_THREADS) dc_gemm(const DcProb *pr, int lev, int64_t Gmax) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) dc_gemm(const DcProb *pr, int lev, int64_t Gmax) {
   __shared__ double lds[GEMM_LDS_DOUBLES];
   const DcProb &P = pr[blockIdx.z / Gmax];
   const int64_t g = blockIdx.z % Gmax;

@@ -110,7 +110,7 @@ __global__ void bt_pack(const BtProb<R> *pr) {
 // times the two 64-row tiles of W1; slice z covers rows [z*BT_KCHUNK, ...) of
 // the block; result to Wpart + z*NB*n.
 template <typename R>
-__global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, int64_t b) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) bt_splitk(const BtProb<R> *pr, int64_t b) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const BtProb<R> &P = pr[blockIdx.z];
   if (b >= P.nblk) return;
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(GEMM_THREADS) bt_splitk(const BtProb<R> *pr, i
 // Gram partials of every block at once: Gpart[b][z] = Vb^H Vb over slice z
 // (BT_NB x BT_NB, four 64 x 64 tiles: blockIdx.x = 4 b + tile).
 template <typename R>
-__global__ void __launch_bounds__(GEMM_THREADS) bt_gram(const BtProb<R> *pr) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) bt_gram(const BtProb<R> *pr) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const BtProb<R> &P = pr[blockIdx.z];
   const int64_t b = blockIdx.x >> 2;
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(BT_NB) bt_reduce_t(const BtProb<R> *pr, int64_
 
 // Rank-BT_NB update Phi[p+1:, :] -= Vb W2 of block b.
 template <typename R>
-__global__ void __launch_bounds__(GEMM_THREADS) bt_update(const BtProb<R> *pr, int64_t b) {
+__global__ void __launch_bounds__(GEMM_THREADS, 2) bt_update(const BtProb<R> *pr, int64_t b) {
   __shared__ R lds[GEMM_LDS_ELEMS];
   const BtProb<R> &P = pr[blockIdx.z];
   if (b >= P.nblk) return;
