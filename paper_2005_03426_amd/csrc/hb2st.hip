@@ -299,160 +299,310 @@ int hb2st_batched(int64_t count, const int64_t *n, mmf_z *const *AB, mmf_z *cons
 }
 
 // ---------------------------------------------------------------- back-transformation
-constexpr int BT2_CHUNK = 64;      // blocks per launch
+constexpr int BT2_CHUNK = 64;             // blocks per launch
+constexpr int BT2_NB = 16;                // reflectors per compact-WY group
+constexpr int BT2_NG = BT2_G / BT2_NB;    // groups per block
+constexpr int BT2_VR = BW + BT2_NB;       // rows of a group's V (80; the last is zero)
+constexpr int MFMA_NEG_A = 1;             // FP64 MFMA modifier bits (last operand): negate A
+constexpr int BT2_TILE = 64;              // columns per tile (16 per wavefront)
+constexpr int BT2_SLOTS = 512;            // workgroups resident at once (two per CU)
 
-size_t bt2_ws_bytes(int64_t n, int64_t nc) { (void)n; (void)nc; return 256; }
+size_t bt2_ws_bytes(int64_t n, int64_t nc) {
+  (void)n; (void)nc;
+  return 256 + sizeof(cd) * (size_t)BT2_CHUNK * BT2_NG * BT2_NB * BT2_NB;
+}
 
-// Apply the launch's blocks to Phi with vector FMAs, one reflector at a time
-// (exactly 8 n^3 real flops over the whole back-transformation; on this GPU
-// the FP64 vector rate equals the FP64 matrix-core rate, and the compact-WY
-// form of these parallelogram blocks would execute twice the flops).
-// Workgroup (column tile x of 128 columns, block y); wavefront w owns 32
-// columns, lane l the columns 32 w + l / 4 and 32 w + 16 + l / 4 (every
-// reflector entry read from LDS serves both) and the rows rho + 4 u
-// (rho = l % 4) of a sliding window of 17 slots.  The block's reflectors
-// j = 63 .. 0 (sweep s0 + j, rows j .. j + 63 of the block) are applied in
-// groups of four; after a group the window moves up four rows: its last slot
-// is final and goes to HBM, a new first slot enters (read two groups ahead:
-// rows above the window are not touched by the reflectors still to come).
-// v^H x is summed over the four lanes of a column with DPP quad permutations.
-constexpr int BT2_VPAD = BW + 8;          // LDS row of a reflector: 4 zeros, v, 4 zeros
-constexpr int BT2_TILE = 128;             // columns per workgroup
+// Block B_{G,k} holds the reflectors j = 0 .. 63 of sweeps s0 + j at position
+// k; reflector j covers rows j .. j + 63 of the block (block row 0 = global row
+// s0 + 1 + k BW).  Inside the block they are applied as four groups of 16,
+// group g = 3, 2, 1, 0 holding j = 16 g .. 16 g + 15, each in the compact WY
+// form H_{16g} H_{16g+1} ... H_{16g+15} = I - V T V^H: V is the 80 x 16 matrix
+// of the group (column i = reflector 16 g + i shifted down by i rows, rows
+// 16 g .. 16 g + 79 of the block) and T the upper triangular factor of the
+// forward recurrence T_ii = tau_i, T_{0:i,i} = -tau_i T_{0:i,0:i} V_{:,0:i}^H v_i.
 
-// Value of lane l ^ 1 / l ^ 2 within each group of four lanes (DPP quad
-// permutations, on the two 32-bit halves of the double).
-__device__ inline double quad_perm_f64(double v, int ctrl_sel) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  int plo, phi;
-  if (ctrl_sel == 1) {
-    plo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    phi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
-  } else {
-    plo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    phi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+// T of group g of the launch's block b (one workgroup each), row-major 16 x 16
+// at Tws + (b BT2_NG + g) 256.
+__global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const cd *tau2, cd *Tws, int64_t Gmax,
+                                              int64_t step, int64_t Gb) {
+  __shared__ cd v[BT2_NB][BW];
+  __shared__ cd tau[BT2_NB];
+  __shared__ cd G[BT2_NB][BT2_NB + 1];
+  __shared__ cd T[BT2_NB][BT2_NB + 1];
+  const int g = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  const int64_t Gi = Gb - b;
+  const int64_t k = step - (Gmax - Gi);
+  const int64_t s0 = Gi * BT2_G + g * BT2_NB;      // sweep of the group's column 0
+  const int64_t base = hb_voff(n, k);
+  const int64_t smax = n - 2 - k * BW;
+  const int tid = threadIdx.x;
+  {
+    constexpr int NV = BT2_NB * BW / 256;
+    cd vbuf[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int e = tid + 256 * m, jj = e / BW, idx = e % BW;
+      vbuf[m] = V2[base + (s0 + jj <= smax ? s0 + jj : smax) * BW + idx];
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int e = tid + 256 * m, jj = e / BW, idx = e % BW;
+      v[jj][idx] = (s0 + jj <= smax) ? vbuf[m] : cmake(0.0, 0.0);
+    }
   }
-  return __hiloint2double(phi, plo);
-}
-__device__ inline double quad_sum(double v) {
-  v += quad_perm_f64(v, 1);
-  return v + quad_perm_f64(v, 2);
+  if (tid < BT2_NB) tau[tid] = (s0 + tid <= smax) ? tau2[base / BW + s0 + tid] : cmake(0.0, 0.0);
+  __syncthreads();
+  // Gram entries G[a][c] = v_a^H v_c (a < c): column c starts c - a rows lower
+  {
+    const int a = tid >> 4, c = tid & 15;
+    cd acc = cmake(0.0, 0.0);
+    if (a < c)
+      for (int r = c - a; r < BW; ++r) acc = cadd(acc, cmulc(v[a][r], v[c][r - (c - a)]));
+    G[a][c] = acc;
+  }
+  __syncthreads();
+  // T column by column; thread a owns row a and reads only its own row
+  if (tid < BT2_NB) {
+    const int a = tid;
+    for (int i = 0; i < BT2_NB; ++i) {
+      cd t = cmake(0.0, 0.0);
+      if (a < i) {
+        const cd mt = cmake(-tau[i].re, -tau[i].im);
+        for (int c = a; c < i; ++c) t = cadd(t, cmul(T[a][c], cmul(mt, G[c][i])));
+      } else if (a == i) {
+        t = tau[i];
+      }
+      T[a][i] = t;
+    }
+  }
+  __syncthreads();
+  cd *out = Tws + (b * BT2_NG + g) * (BT2_NB * BT2_NB);
+  out[tid] = T[tid >> 4][tid & 15];
 }
 
-__global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *tau2, cd *Phi,
-                                                 int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb) {
-  __shared__ cd vsh[BT2_G][BT2_VPAD];
-  __shared__ cd tsh[BT2_G];
-  const int64_t Gi = Gb - blockIdx.y;
+// Apply the launch's blocks to Phi on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64; element r of lane l of a 16 x 16 result holds row
+// 4 r + l / 16, column l % 16; operands A[i][k] in lane i + 16 k, B[k][j] in
+// lane j + 16 k).  Workgroup (x, block y) stages the block's reflectors in
+// LDS once and then works through the column tiles x, x + gridDim.x, ... of
+// 64 columns; wavefront w owns the 16 columns 16 w .. 16 w + 15 of a tile, and
+// the block's rows are held as 16-row tiles in result layout (tile u: rows
+// 16 u .. 16 u + 15, element r of lane l = row 16 u + 4 r + l / 16 of column
+// l % 16).  Group g works on the window of tiles g .. g + 4:
+//   W  = V^H X   (16 x 16, k-step r of tile t contracts the rows 4 r .. 4 r + 3,
+//                 i.e. element r of the window's registers is the B operand),
+//   W' = T W,    X <- X - V W'  (element r of W, W' is again the B operand),
+// complex products as four real MFMAs.  Tile g + 4 is then final (no later
+// group reaches it) and goes to HBM at the start of group g - 1, when tile
+// g - 2 is read for the group after.  The last group also reads tiles 6 and 7
+// of the next column tile; the tiles 0 .. 4 left at the end go to HBM at the
+// start of the next column tile, whose tiles 3 .. 5 are read then (its first
+// group contracts tiles 6 and 7 first).
+__global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *Tws, cd *Phi,
+                                                 int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb, int64_t ntile,
+                                                 cd *sink) {
+  // V of the four groups, zeros included, row rho / column i at
+  // vg[g][rho][i ^ (rho % 16)]: both operand reads (16 consecutive columns of
+  // one row, 16 consecutive rows of one column) then touch 16 distinct banks
+  __shared__ cd vg[BT2_NG][BT2_VR][BT2_NB];
+  const int64_t b = blockIdx.y;
+  const int64_t Gi = Gb - b;
   const int64_t k = step - (Gmax - Gi);
   const int64_t s0 = Gi * BT2_G;
   const int64_t R0 = s0 + 1 + k * BW;
-  const int64_t Lr = (n - R0 < BW + BT2_G - 1) ? n - R0 : BW + BT2_G - 1;
+  const int Lr = (int)((n - R0 < BW + BT2_G - 1) ? n - R0 : BW + BT2_G - 1);
   const int64_t base = hb_voff(n, k);
-  const int64_t smax = n - 2 - k * BW;            // last sweep with position k
+  const int64_t smax = n - 2 - k * BW;
   const int tid = threadIdx.x;
-  for (int e = tid; e < BT2_G * BT2_VPAD; e += 256) {
-    const int j = e / BT2_VPAD, idx = e % BT2_VPAD - 4;
-    cd v = cmake(0.0, 0.0);
-    if (idx >= 0 && idx < BW && s0 + j <= smax) v = V2[base + (s0 + j) * BW + idx];
-    vsh[j][e % BT2_VPAD] = v;
+  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, li = lane & 15;
+  const cd *Tb = Tws + b * (BT2_NG * BT2_NB * BT2_NB);
+  // column of this lane in tile ct (idle lanes past nc read column 0)
+  auto colp = [&](int64_t ct, bool &ok) {
+    const int64_t col = ct * BT2_TILE + wave * 16 + li;
+    ok = col < nc;
+    return Phi + R0 + (ok ? col : 0) * ldphi;
+  };
+
+  // Rows past the block's end (row >= Lr) and the columns of idle lanes are
+  // loaded from clamped addresses and never stored: the reflector entries of
+  // rows past the matrix end are zero, so these values neither change nor
+  // reach the others.  Real and imaginary parts are read separately, straight
+  // into the accumulator registers, so that nothing waits for a tile before
+  // its first use.
+  // (Lv is Lr behind an empty asm statement in every column tile: row offsets
+  // are then formed where they are used instead of being kept in registers
+  // across the loop)
+  int Lv = Lr;
+  v4d xr[8], xi[8];
+  auto load_tile = [&](const cd *P, int u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * u + 4 * r + q;
+      const int ir = 2 * (row < Lv ? row : Lv - 1);
+      int ii = ir + 1;
+      asm volatile("" : "+v"(ii));                 // keep the two loads apart
+      xr[u][r] = reinterpret_cast<const double *>(P)[ir];
+      xi[u][r] = reinterpret_cast<const double *>(P)[ii];
+    }
+  };
+  auto store_tile = [&](cd *P, bool ok, int u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * u + 4 * r + q;
+      *((ok && row < Lv) ? P + row : sink) = cmake(xr[u][r], xi[u][r]);
+    }
+  };
+  cd tv[4];
+  auto load_t = [&](int g) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tv[r] = Tb[g * (BT2_NB * BT2_NB) + li * BT2_NB + 4 * r + q];
+  };
+
+  // reflector j = 16 g + i, entry e goes to row rho = e + i of group g: read
+  // the block's reflectors in storage order, then clear the 2 x 16 x 15 / 2
+  // + 16 slots of each group that no reflector reaches (rho < i, rho >= i + 64)
+  // (all loads first, from clamped sweeps, so that they are in flight together)
+  {
+    constexpr int NV = BT2_G * BW / 256;
+    cd vbuf[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int f = tid + 256 * m, j = f / BW, e = f % BW;
+      vbuf[m] = V2[base + (s0 + j <= smax ? s0 + j : smax) * BW + e];
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int f = tid + 256 * m, j = f / BW, e = f % BW, g = j / BT2_NB, i = j % BT2_NB, rho = e + i;
+      vg[g][rho][i ^ (rho & 15)] = (s0 + j <= smax) ? vbuf[m] : cmake(0.0, 0.0);
+    }
   }
-  if (tid < BT2_G) tsh[tid] = (s0 + tid <= smax) ? tau2[base / BW + s0 + tid] : cmake(0.0, 0.0);
+  for (int f = tid; f < BT2_NG * BT2_NB * BT2_NB; f += 256) {
+    const int g = f / (BT2_NB * BT2_NB), i = (f / BT2_NB) % BT2_NB, m = f % BT2_NB;
+    const int rho = m < i ? m : BW + m;         // the i slots above, 16 - i below
+    vg[g][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
+  }
+  // the first window and T: the first group waits for them tile by tile
+  int64_t ct = blockIdx.x;
+  bool ok;
+  cd *P = colp(ct, ok);
+#pragma unroll
+  for (int u = BT2_NG - 1; u < 8; ++u) load_tile(P, u);
+  load_t(BT2_NG - 1);
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6, rho = lane & 3;
-  const int64_t c0 = (int64_t)blockIdx.x * BT2_TILE + wave * 32 + (lane >> 2);
-  const bool ok0 = c0 < nc, ok1 = c0 + 16 < nc;
-  cd *P0 = Phi + R0 + (ok0 ? c0 : 0) * ldphi;
-  cd *P1 = Phi + R0 + (ok1 ? c0 + 16 : 0) * ldphi;
-  cd x0[17], x1[17];
-  // window of the first group (j = 63 .. 60): rows 60 + rho + 4 u
+
+  cd *Pprev = P;
+  bool okprev = ok;
+  for (bool first = true;; first = false) {
+    asm volatile("" : "+s"(Lv));
+    const int64_t ctn = ct + gridDim.x;
+    const bool more = ctn < ntile;                 // uniform
+    bool okn;
+    cd *Pn = colp(more ? ctn : ct, okn);
 #pragma unroll
-  for (int u = 0; u < 17; ++u) {
-    const int row = 60 + rho + 4 * u;
-    x0[u] = (ok0 && row < Lr) ? P0[row] : cmake(0.0, 0.0);
-    x1[u] = (ok1 && row < Lr) ? P1[row] : cmake(0.0, 0.0);
-  }
-  cd xn00 = (ok0 && 56 + rho < Lr) ? P0[56 + rho] : cmake(0.0, 0.0);     // enter after group 15
-  cd xn10 = (ok1 && 56 + rho < Lr) ? P1[56 + rho] : cmake(0.0, 0.0);
-  cd xn01 = (ok0 && 52 + rho < Lr) ? P0[52 + rho] : cmake(0.0, 0.0);     // enter after group 14
-  cd xn11 = (ok1 && 52 + rho < Lr) ? P1[52 + rho] : cmake(0.0, 0.0);
-  for (int a = BT2_G / 4 - 1; a >= 0; --a) {
-#pragma unroll 1
-    for (int b = 3; b >= 0; --b) {
-      const int j = 4 * a + b;
-      const cd tj = tsh[j];
-      if (tj.re == 0.0 && tj.im == 0.0) continue;        // uniform
-      // slot u holds row 4 a + rho + 4 u, i.e. entry rho + 4 u - b of v_j
-      const cd *vj = &vsh[j][rho - b + 4];
-      cd vv[17];
+    for (int g = BT2_NG - 1; g >= 0; --g) {
+      // Memory operations of a group: wait for everything issued during the
+      // previous group (its tiles and T were read a group ahead), then store
+      // the tiles that became final there and read the tiles that take their
+      // registers.  Stores and loads share one counter that does not keep
+      // their order, so a wait for a load is a wait for every store before
+      // it: with this order no wait meets a store younger than a group.  (The
+      // very first group has no store before it: its waits are per tile.)
+      if (g < BT2_NG - 1 || !first) __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (g < BT2_NG - 1) store_tile(P, ok, g + 5);
+      if (g == 0 && more) {
+        load_tile(Pn, 6);
+        load_tile(Pn, 7);
+      }
+      if (g == BT2_NG - 1 && !first) {
 #pragma unroll
-      for (int u = 0; u < 17; ++u) vv[u] = vj[4 * u];
-      double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0, br0 = 0.0, bi0 = 0.0, br1 = 0.0, bi1 = 0.0;
+        for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
+        __builtin_amdgcn_sched_barrier(0);         // registers of 3, 4 are reused
+        load_tile(P, 5);
+        load_tile(P, 3);
+        load_tile(P, 4);
+      }
+      if (g > 0) load_tile(P, g - 1);
+      __builtin_amdgcn_sched_barrier(0);
+      // Products are issued as chains of MFMAs into one accumulator: a chain
+      // runs back to back on the matrix core, while alternating accumulators
+      // costs a register-file round trip of the 16 x 16 result each time.
+      // The compiler would interleave independent chains; an empty asm
+      // statement between two chains (the end of one, the start of the next)
+      // fixes them.
+      // W = V^H X: A operand of lane (q, li) = conj V[16 t + 4 r + q][li]
+      // (tiles t = 3, 4 first: in the first group the others arrive last)
+      v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr, pr = wr, pi = wr;
 #pragma unroll
-      for (int u = 0; u < 17; u += 2) {
-        ar0 = fma(vv[u].re, x0[u].re, ar0);
-        ar0 = fma(vv[u].im, x0[u].im, ar0);
-        ai0 = fma(vv[u].re, x0[u].im, ai0);
-        ai0 = fma(-vv[u].im, x0[u].re, ai0);
-        br0 = fma(vv[u].re, x1[u].re, br0);
-        br0 = fma(vv[u].im, x1[u].im, br0);
-        bi0 = fma(vv[u].re, x1[u].im, bi0);
-        bi0 = fma(-vv[u].im, x1[u].re, bi0);
-        if (u + 1 < 17) {
-          ar1 = fma(vv[u + 1].re, x0[u + 1].re, ar1);
-          ar1 = fma(vv[u + 1].im, x0[u + 1].im, ar1);
-          ai1 = fma(vv[u + 1].re, x0[u + 1].im, ai1);
-          ai1 = fma(-vv[u + 1].im, x0[u + 1].re, ai1);
-          br1 = fma(vv[u + 1].re, x1[u + 1].re, br1);
-          br1 = fma(vv[u + 1].im, x1[u + 1].im, br1);
-          bi1 = fma(vv[u + 1].re, x1[u + 1].im, bi1);
-          bi1 = fma(-vv[u + 1].im, x1[u + 1].re, bi1);
+      for (int tt = 0; tt < 5; ++tt) {
+        const int t = (tt + 3) % 5;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rho = 16 * t + 4 * r + q;
+          const cd v = vg[g][rho][li ^ (rho & 15)];
+          wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xr[g + t][r], wr, 0, 0, 0);
+          wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xi[g + t][r], wr, 0, 0, 0);
         }
       }
-      const double dr0 = quad_sum(ar0 + ar1), di0 = quad_sum(ai0 + ai1);
-      const double dr1 = quad_sum(br0 + br1), di1 = quad_sum(bi0 + bi1);
-      // x <- x - v (tau v^H x)
-      const double fr0 = tj.re * dr0 - tj.im * di0, fi0 = tj.re * di0 + tj.im * dr0;
-      const double fr1 = tj.re * dr1 - tj.im * di1, fi1 = tj.re * di1 + tj.im * dr1;
+      asm volatile("" : "+v"(wr), "+v"(wi));
 #pragma unroll
-      for (int u = 0; u < 17; ++u) {
-        x0[u].re = fma(-vv[u].re, fr0, x0[u].re);
-        x0[u].re = fma(vv[u].im, fi0, x0[u].re);
-        x0[u].im = fma(-vv[u].re, fi0, x0[u].im);
-        x0[u].im = fma(-vv[u].im, fr0, x0[u].im);
-        x1[u].re = fma(-vv[u].re, fr1, x1[u].re);
-        x1[u].re = fma(vv[u].im, fi1, x1[u].re);
-        x1[u].im = fma(-vv[u].re, fi1, x1[u].im);
-        x1[u].im = fma(-vv[u].im, fr1, x1[u].im);
+      for (int t = 0; t < 5; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rho = 16 * t + 4 * r + q;
+          const cd v = vg[g][rho][li ^ (rho & 15)];
+          wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xi[g + t][r], wi, 0, 0, 0);
+          wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xr[g + t][r], wi, 0, 0, MFMA_NEG_A);
+        }
+      }
+      asm volatile("" : "+v"(wi), "+v"(pr));
+      // W' = T W: A operand of lane (q, li) = T[li][4 r + q]
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].re, wr[r], pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].im, wi[r], pr, 0, 0, MFMA_NEG_A);
+      }
+      asm volatile("" : "+v"(pr), "+v"(pi));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].re, wi[r], pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].im, wr[r], pi, 0, 0, 0);
+      }
+      asm volatile("" : "+v"(pi), "+v"(xr[g]));
+      if (g > 0) load_t(g - 1);
+      else if (more) load_t(BT2_NG - 1);
+      // X <- X - V W': A operand of lane (q, li) = V[16 t + li][4 r + q]
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        const int u = g + t, rho = 16 * t + li;
+        cd v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = vg[g][rho][(4 * r + q) ^ li];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, pr[r], xr[u], 0, 0, MFMA_NEG_A);
+          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, pi[r], xr[u], 0, 0, 0);
+        }
+        asm volatile("" : "+v"(xr[u]), "+v"(xi[u]));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, pi[r], xi[u], 0, 0, MFMA_NEG_A);
+          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, pr[r], xi[u], 0, 0, MFMA_NEG_A);
+        }
+        if (t < 4) asm volatile("" : "+v"(xi[u]), "+v"(xr[u + 1]));
       }
     }
-    if (a > 0) {
-      const int last = 4 * a + rho + 64;
-      if (last < Lr) {
-        if (ok0) P0[last] = x0[16];
-        if (ok1) P1[last] = x1[16];
-      }
-#pragma unroll
-      for (int u = 16; u > 0; --u) {
-        x0[u] = x0[u - 1];
-        x1[u] = x1[u - 1];
-      }
-      x0[0] = xn00;                                  // row 4 (a - 1) + rho
-      x1[0] = xn10;
-      xn00 = xn01;
-      xn10 = xn11;
-      const int ahead = 4 * (a - 3) + rho;
-      xn01 = (a >= 3 && ok0 && ahead < Lr) ? P0[ahead] : cmake(0.0, 0.0);
-      xn11 = (a >= 3 && ok1 && ahead < Lr) ? P1[ahead] : cmake(0.0, 0.0);
-    }
+    Pprev = P;
+    okprev = ok;
+    if (!more) break;
+    ct = ctn;
+    P = Pn;
+    ok = okn;
   }
+  // the last column tile's tiles 0 .. 4
 #pragma unroll
-  for (int u = 0; u < 17; ++u) {
-    const int row = rho + 4 * u;
-    if (row < Lr) {
-      if (ok0) P0[row] = x0[u];
-      if (ok1) P1[row] = x1[u];
-    }
-  }
+  for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
 }
 
 __global__ void bt2_init(int64_t n, int64_t nc, const double *Z, int64_t ldz, cd *Phi, int64_t ldphi) {
@@ -465,8 +615,10 @@ __global__ void bt2_init(int64_t n, int64_t nc, const double *Z, int64_t ldz, cd
 
 int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const double *Z, int64_t ldz,
             mmf_z *Phiz, int64_t ldphi, void *work, size_t bytes, hipStream_t st) {
-  (void)work; (void)bytes;
   if (n <= 0 || nc <= 0) return MMF_OK;
+  if (!work || bytes < bt2_ws_bytes(n, nc)) return MMF_ERR_WORKSPACE;
+  cd *sink = reinterpret_cast<cd *>(work);          // target of masked-out stores, never read
+  cd *Tws = reinterpret_cast<cd *>(static_cast<char *>(work) + 256);
   const cd *V2 = reinterpret_cast<const cd *>(V2z);
   const cd *tau2 = reinterpret_cast<const cd *>(tau2z);
   cd *Phi = reinterpret_cast<cd *>(Phiz);
@@ -486,9 +638,14 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
     if (Ghi < Glo) continue;
     for (int64_t Gb = Ghi; Gb >= Glo; Gb -= BT2_CHUNK) {
       const int64_t cnt = (Gb - Glo + 1 < BT2_CHUNK) ? Gb - Glo + 1 : BT2_CHUNK;
+      hipLaunchKernelGGL(bt2_tgen, dim3(BT2_NG, (unsigned)cnt), dim3(256), 0, st, n, V2, tau2, Tws, Gmax, step, Gb);
+      MMF_LAUNCH_CHECK();
       const int ks = ktimer_begin("bt2", st);
-      hipLaunchKernelGGL(bt2_apply, dim3(ntile, (unsigned)cnt), dim3(256), 0, st, n, nc, V2, tau2, Phi, ldphi, Gmax,
-                         step, Gb);
+      // column tiles per workgroup: enough workgroups for two per CU
+      const int64_t per = ((int64_t)ntile * cnt + BT2_SLOTS - 1) / BT2_SLOTS;
+      const unsigned gx = cdiv(ntile, per);
+      hipLaunchKernelGGL(bt2_apply, dim3(gx, (unsigned)cnt), dim3(256), 0, st, n, nc, V2, Tws, Phi, ldphi, Gmax,
+                         step, Gb, (int64_t)ntile, sink);
       MMF_LAUNCH_CHECK();
       if (ks >= 0) {
         // algorithmic flops: v^H x and x -= v f, 8 real flops per complex
