@@ -12,6 +12,14 @@
   } while (0)
 
 #define MMF_LAUNCH_CHECK() MMF_HIP_TRY(hipGetLastError())
+// the same with a clean-up statement before the error return
+#define MMF_LAUNCH_CHECK_OR(cleanup)                        \
+  do {                                                      \
+    if (hipGetLastError() != hipSuccess) {                  \
+      cleanup;                                              \
+      return MMF_ERR_HIP;                                   \
+    }                                                       \
+  } while (0)
 
 namespace mmf {
 

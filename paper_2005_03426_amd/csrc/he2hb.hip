@@ -41,7 +41,9 @@ constexpr int64_t HEMM_KC = 1024; // K slice of the A22 V product
 constexpr int64_t PAN_KC = 256;   // row slice of the panel products V^H V, V^H X
 
 struct HbWs {
-  cd *P3;      // n x 3 BW (ld n): [V | W | V] of the current panel
+  cd *P3;      // 2 x n x 3 BW (ld n): [V | W | V] of a panel; even and odd
+               // panels alternate between the two buffers
+  int64_t p3stride;
   cd *Yp;      // nks x n x BW: K-slice partials of A22 V
   cd *Yb;      // n x BW: A22 V
   cd *Sp;      // npk x BW x BW: row-slice partials of V^H V, then of V^H X
@@ -61,7 +63,8 @@ inline HbWs hb_ws(int64_t n, void *base) {
   w.nks = (int64_t)((N + HEMM_KC - 1) / HEMM_KC);
   w.npk = (int64_t)((N + PAN_KC - 1) / PAN_KC);
   w.nwg = (int64_t)((N + QR_ROWS - 1) / QR_ROWS) + 1;
-  w.P3 = cv.take<cd>(N * 3 * BW);
+  w.p3stride = (int64_t)(N * 3 * BW);
+  w.P3 = cv.take<cd>(2 * N * 3 * BW);
   w.Yp = cv.take<cd>((size_t)w.nks * N * BW);
   w.Yb = cv.take<cd>(N * BW);
   w.Sp = cv.take<cd>((size_t)w.npk * BW * BW);
@@ -99,6 +102,12 @@ __device__ inline bool hb_panel(const HbProb &P, int64_t c0, HbPanel &pp) {
   return true;
 }
 
+// P3 buffer of panel c0: the update of one panel still reads its [V W] on the
+// side stream while the next panel is factored.
+__device__ inline cd *hb_p3(const HbProb &P, int64_t c0) {
+  return P.ws.P3 + ((c0 / BW) & 1) * P.ws.p3stride;
+}
+
 // Zero the three panel slots of P3 (rows q0 .. n-1).
 __global__ void hb_zero_p3(const HbProb *pr, int64_t c0) {
   const HbProb &P = pr[blockIdx.z];
@@ -106,7 +115,8 @@ __global__ void hb_zero_p3(const HbProb *pr, int64_t c0) {
   if (!hb_panel(P, c0, pp)) return;
   const int64_t r = pp.q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= P.n) return;
-  for (int c = 0; c < 3 * BW; ++c) P.ws.P3[r + (int64_t)c * P.n] = cmake(0.0, 0.0);
+  cd *P3 = hb_p3(P, c0);
+  for (int c = 0; c < 3 * BW; ++c) P3[r + (int64_t)c * P.n] = cmake(0.0, 0.0);
 }
 
 // One launch per panel column j = 0 .. nr (workgroup w owns rows q0 + 256 w ..).
@@ -182,8 +192,8 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
         v = cmul(A[r + (c0 + jp) * lda], sc);
         A[r + (c0 + jp) * lda] = v;
       }
-      ws.P3[r + (int64_t)jp * n] = v;
-      ws.P3[r + (int64_t)(2 * BW + jp) * n] = v;
+      hb_p3(P, c0)[r + (int64_t)jp * n] = v;
+      hb_p3(P, c0)[r + (int64_t)(2 * BW + jp) * n] = v;
       vown = v;
     }
   }
@@ -248,7 +258,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) hb_gram(const HbProb *pr, int
   const int64_t z = blockIdx.x, m = pp.m, n = P.n;
   const int64_t k0 = z * PAN_KC, k1 = (k0 + PAN_KC < m) ? k0 + PAN_KC : m;
   if (k0 >= m) return;
-  const cd *V = P.ws.P3 + pp.q0 + k0;
+  const cd *V = hb_p3(P, c0) + pp.q0 + k0;
   GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, V, n, P.ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
   gemm_tile<true, A_C, B_N>(g, 0, 0, lds);
 }
@@ -335,7 +345,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) hb_hemm(const HbProb *pr, int
   if (m0 >= m || k0 >= m) return;
   const int64_t kb = (m0 + GT_M < m) ? m0 + GT_M : m;   // columns < kb: lower part of row tile I
   const cd *A22 = P.A + q0 + q0 * lda;
-  const cd *V = P.ws.P3 + q0;
+  const cd *V = hb_p3(P, c0) + q0;
   cd *Y = P.ws.Yp + z * n * BW;
   bool first = true;
   if (k0 < kb) {
@@ -374,7 +384,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) hb_xyt(const HbProb *pr, int6
   if (!hb_panel(P, c0, pp)) return;
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n = P.n;
   if (m0 >= pp.m) return;
-  GemmArgs g = gemm_args(pp.m, BW, BW, P.ws.Yb, n, P.ws.T, BW, P.ws.P3 + pp.q0 + (int64_t)BW * n, n, 1.0, 0.0, 0.0,
+  GemmArgs g = gemm_args(pp.m, BW, BW, P.ws.Yb, n, P.ws.T, BW, hb_p3(P, c0) + pp.q0 + (int64_t)BW * n, n, 1.0, 0.0, 0.0,
                          0.0);
   gemm_tile<true, A_N, B_N>(g, m0, 0, lds);
 }
@@ -388,8 +398,8 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) hb_vhx(const HbProb *pr, int6
   const int64_t z = blockIdx.x, m = pp.m, n = P.n;
   const int64_t k0 = z * PAN_KC, k1 = (k0 + PAN_KC < m) ? k0 + PAN_KC : m;
   if (k0 >= m) return;
-  const cd *V = P.ws.P3 + pp.q0 + k0;
-  const cd *X = P.ws.P3 + pp.q0 + k0 + (int64_t)BW * n;
+  const cd *V = hb_p3(P, c0) + pp.q0 + k0;
+  const cd *X = hb_p3(P, c0) + pp.q0 + k0 + (int64_t)BW * n;
   GemmArgs g = gemm_args(BW, BW, k1 - k0, V, n, X, n, P.ws.Sp + z * BW * BW, BW, 1.0, 0.0, 0.0, 0.0);
   gemm_tile<true, A_C, B_N>(g, 0, 0, lds);
 }
@@ -419,7 +429,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) hb_wupd(const HbProb *pr, int
   if (!hb_panel(P, c0, pp)) return;
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n = P.n;
   if (m0 >= pp.m) return;
-  GemmArgs g = gemm_args(pp.m, BW, BW, P.ws.P3 + pp.q0, n, P.ws.U, BW, P.ws.P3 + pp.q0 + (int64_t)BW * n, n, -0.5,
+  GemmArgs g = gemm_args(pp.m, BW, BW, hb_p3(P, c0) + pp.q0, n, P.ws.U, BW, hb_p3(P, c0) + pp.q0 + (int64_t)BW * n, n, -0.5,
                          0.0, 1.0, 0.0);
   gemm_tile<true, A_N, B_N>(g, m0, 0, lds);
 }
@@ -434,7 +444,7 @@ __global__ void __launch_bounds__(256) hb_wv_transpose(const HbProb *pr, int64_t
   if (!hb_panel(P, c0, pp)) return;
   const int64_t r0 = (int64_t)blockIdx.x * 32, m = pp.m, n = P.n;
   if (r0 >= m) return;
-  const cd *WV = P.ws.P3 + pp.q0 + (int64_t)BW * n;     // columns BW .. 3 BW - 1 of P3: [W V]
+  const cd *WV = hb_p3(P, c0) + pp.q0 + (int64_t)BW * n;     // columns BW .. 3 BW - 1 of P3: [W V]
   for (int e = threadIdx.x; e < 32 * 2 * BW; e += 256) {
     const int rr = e & 31, k = e >> 5;
     t[rr][k] = (r0 + rr < m) ? WV[(r0 + rr) + (int64_t)k * n] : cmake(0.0, 0.0);
@@ -446,17 +456,18 @@ __global__ void __launch_bounds__(256) hb_wv_transpose(const HbProb *pr, int64_t
   }
 }
 
-// A22 -= [V W] [W V]^H, lower tiles (tile (blockIdx.x, blockIdx.y)); the right
-// operand is the explicit [W V]^H, so both operands are read column-contiguous.
-__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_her2k(const HbProb *pr, int64_t c0) {
+// A22 -= [V W] [W V]^H, lower tiles (tile (blockIdx.x, jt0 + blockIdx.y)); the
+// right operand is the explicit [W V]^H, so both operands are read
+// column-contiguous.
+__global__ void __launch_bounds__(GEMM_THREADS, 2) hb_her2k(const HbProb *pr, int64_t c0, int jt0) {
   __shared__ double lds[GEMM_LDS_ELEMS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
   if (!hb_panel(P, c0, pp)) return;
   const int64_t m = pp.m, n = P.n, q0 = pp.q0;
-  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)(blockIdx.y + jt0) * GT_N;
   if (m0 >= m || n0 >= m || m0 + GT_M <= n0) return;
-  GemmArgs g = gemm_args(m, m, 2 * BW, P.ws.P3 + q0, n, P.ws.WVh, 2 * BW, P.A + q0 + q0 * P.lda, P.lda, -1.0, 0.0,
+  GemmArgs g = gemm_args(m, m, 2 * BW, hb_p3(P, c0) + q0, n, P.ws.WVh, 2 * BW, P.A + q0 + q0 * P.lda, P.lda, -1.0, 0.0,
                          1.0, 0.0);
   g.lower = 1;
   gemm_tile<true, A_N, B_N>(g, m0, n0, lds);
@@ -493,10 +504,34 @@ int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_
   for (int64_t c = 0; c < count; ++c) nmax = nh[c] > nmax ? nh[c] : nmax;
   if (nmax <= 0) return MMF_OK;
   const unsigned Z = (unsigned)count;
+  // Look-ahead: the rank-2 BW update of panel c0 is split into its first
+  // column tile (the columns of panel c0 + BW), done on the caller's stream,
+  // and the rest, done on a side stream while the caller's stream factors the
+  // next panel; the next panel's A22 V product waits for the side stream.
+  // The two panels use different P3 buffers; the factorization only touches
+  // the next panel's columns, which the rest of the update does not.  (If the
+  // side stream cannot be created, everything runs on the caller's stream.)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (side) (void)hipStreamDestroy(side);
+    if (fork) (void)hipEventDestroy(fork);
+    side = nullptr;
+  }
+  auto release = [&]() {
+    if (side) {
+      (void)hipEventDestroy(fork);
+      (void)hipEventDestroy(join);
+      (void)hipStreamDestroy(side);
+    }
+  };
+  bool pending = false;                            // side stream holds an update
   for (int64_t c0 = 0; c0 + BW < nmax - 1; c0 += BW) {
     // sized for the largest problem that has this panel
     const int64_t m = nmax - c0 - BW;
-    const int bw = (int)((nmax - c0 < BW) ? nmax - c0 : BW);
     int nrmax = 0;
     for (int64_t c = 0; c < count; ++c) {
       if (c0 + BW >= nh[c] - 1) continue;
@@ -505,46 +540,68 @@ int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_
       const int nrc = (int)((mc - 1 < bwc) ? mc - 1 : bwc);
       nrmax = nrc > nrmax ? nrc : nrmax;
     }
-    (void)bw;
     const unsigned nwg = cdiv(m, QR_ROWS), ntile = cdiv(m, GT_M);
     const unsigned nks = cdiv(m, HEMM_KC), npk = cdiv(m, PAN_KC);
     hipLaunchKernelGGL(hb_zero_p3, dim3(cdiv(m, 256), 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     // panel factorization: one launch per column
     for (int j = 0; j <= nrmax; ++j) {
       hipLaunchKernelGGL(hb_qr_step, dim3(nwg, 1, Z), dim3(QR_ROWS), 0, st, pr, c0, j);
-      MMF_LAUNCH_CHECK();
+      MMF_LAUNCH_CHECK_OR(release());
     }
     hipLaunchKernelGGL(hb_gram, dim3(npk, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_sum_sp, dim3(BW * BW / 256, 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_tmat, dim3(1, 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
+    if (pending) {
+      if (hipStreamWaitEvent(st, join, 0) != hipSuccess) { release(); return MMF_ERR_HIP; }
+      pending = false;
+    }
     // Y = A22 V
     hipLaunchKernelGGL(hb_mirror_diag, dim3(ntile, 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_hemm, dim3(ntile, nks, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_reduce_y, dim3(cdiv(m * BW, 256), 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     // X = Y T ; U = T^H V^H X ; W = X - V U / 2
     hipLaunchKernelGGL(hb_xyt, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_vhx, dim3(npk, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_sum_sp, dim3(BW * BW / 256, 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_tu, dim3(1, 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_wupd, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
-    // A22 -= [V W] [W V]^H  (lower tiles)
+    MMF_LAUNCH_CHECK_OR(release());
+    // A22 -= [V W] [W V]^H  (lower tiles): first column tile here, the rest
+    // on the side stream
     hipLaunchKernelGGL(hb_wv_transpose, dim3(cdiv(m, 32), 1, Z), dim3(256), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(hb_her2k, dim3(ntile, ntile, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
-    MMF_LAUNCH_CHECK();
+    MMF_LAUNCH_CHECK_OR(release());
+    if (side && ntile > 1) {
+      if (hipEventRecord(fork, st) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess) {
+        release();
+        return MMF_ERR_HIP;
+      }
+      hipLaunchKernelGGL(hb_her2k, dim3(ntile, ntile - 1, Z), dim3(GEMM_THREADS), 0, side, pr, c0, 1);
+      MMF_LAUNCH_CHECK_OR(release());
+      if (hipEventRecord(join, side) != hipSuccess) { release(); return MMF_ERR_HIP; }
+      pending = true;
+      hipLaunchKernelGGL(hb_her2k, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0, 0);
+      MMF_LAUNCH_CHECK_OR(release());
+    } else {
+      hipLaunchKernelGGL(hb_her2k, dim3(ntile, ntile, Z), dim3(GEMM_THREADS), 0, st, pr, c0, 0);
+      MMF_LAUNCH_CHECK_OR(release());
+    }
   }
+  if (pending && hipStreamWaitEvent(st, join, 0) != hipSuccess) {
+    release();
+    return MMF_ERR_HIP;
+  }
+  release();
   hipLaunchKernelGGL(hb_band_copy, dim3((unsigned)nmax, 1, Z), dim3(LDAB), 0, st, pr);
   MMF_LAUNCH_CHECK();
   return MMF_OK;
