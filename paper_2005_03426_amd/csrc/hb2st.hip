@@ -137,24 +137,30 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
       if (i == 0) tsh[0] = tau2[toff];
     }
   }
+  // D is kept as the full Hermitian block (the upper triangle mirrored, the
+  // diagonal real, zero past L) so that y = D v needs no branch
 #pragma unroll
   for (int q2 = 0; q2 < NE; ++q2) {
     const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
-    if (ii >= jj) D[ii][jj] = dreg[q2];
+    if (ii > jj) {
+      D[ii][jj] = dreg[q2];
+      D[jj][ii] = cconj(dreg[q2]);
+    } else if (ii == jj) {
+      D[ii][ii] = cmake(dreg[q2].re, 0.0);
+    }
     E[ii][jj] = ereg[q2];
   }
   __syncthreads();
   const cd tau = tsh[0];
-  // ---- y = D v from the lower triangle, z = E v (row i, column group q)
+  // ---- y = D v, z = E v (row i, column group q); y_i = sum_j conj(D[j][i]) v_j
+  // reads consecutive entries across the wavefront
   {
     cd py = cmake(0.0, 0.0), pz = cmake(0.0, 0.0);
-    for (int jj = CH_W * q; jj < CH_W * q + CH_W; ++jj) {
+#pragma unroll
+    for (int c = 0; c < CH_W; ++c) {
+      const int jj = CH_W * q + c;
       const cd vj = vs[jj];
-      if (i < L && jj < L) {
-        cd h = (jj <= i) ? D[i][jj] : cconj(D[jj][i]);
-        if (jj == i) h.im = 0.0;
-        py = cadd(py, cmul(h, vj));
-      }
+      py = cadd(py, cmulc(D[jj][i], vj));
       pz = cadd(pz, cmul(E[i][jj], vj));
     }
     red[q][i] = py;
@@ -175,8 +181,9 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
   }
   __syncthreads();
   // ---- D <- D - w v^H - v w^H (lower band to AB); E <- E - (tau z) v^H
-  for (int e = tid; e < BW * BW; e += CH_THREADS) {
-    const int ii = e & 63, jj = e >> 6;
+#pragma unroll
+  for (int q2 = 0; q2 < NE; ++q2) {
+    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
     if (ii >= jj && ii < L) {
       cd d = csub(D[ii][jj], cadd(cmul(wv[ii], cconj(vs[jj])), cmul(vs[ii], cconj(wv[jj]))));
       if (ii == jj) d.im = 0.0;
@@ -203,7 +210,8 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
   if (active) {
     // u_j = v2^H E[:, j] (column j = i, row group q)
     cd p = cmake(0.0, 0.0);
-    for (int ii = CH_W * q; ii < CH_W * q + CH_W; ++ii) p = cadd(p, cmulc(v2[ii], E[ii][i]));
+#pragma unroll
+    for (int c = 0; c < CH_W; ++c) p = cadd(p, cmulc(v2[CH_W * q + c], E[CH_W * q + c][i]));
     red[q][i] = p;
     __syncthreads();
     if (q == 0) {
@@ -214,15 +222,17 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
     }
     __syncthreads();
   }
-  for (int e = tid; e < BW * BW; e += CH_THREADS) {
-    const int ii = e & 63, jj = e >> 6;
-    if (ii >= Le) continue;
-    cd x = E[ii][jj];
-    if (active) {
-      if (jj == 0) x = (ii == 0) ? cmake(beta1, 0.0) : cmake(0.0, 0.0);
-      else x = csub(x, cmul(v2[ii], wv[jj]));
+#pragma unroll
+  for (int q2 = 0; q2 < NE; ++q2) {
+    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
+    if (ii < Le) {
+      cd x = E[ii][jj];
+      if (active) {
+        if (jj == 0) x = (ii == 0) ? cmake(beta1, 0.0) : cmake(0.0, 0.0);
+        else x = csub(x, cmul(v2[ii], wv[jj]));
+      }
+      AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] = x;
     }
-    AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] = x;
   }
   const int64_t voff1 = P.compact ? s * BW : hb_voff(n, k + 1) + s * BW;
   const int64_t toff1 = P.compact ? s : hb_voff(n, k + 1) / BW + s;
