@@ -19,8 +19,8 @@ constexpr int BT2_G = 64;         // sweeps per block of the second back-transfo
 // (the chase steps of all problems share each launch).  The environment
 // variable MMF_EIGH_TWO_STAGE_MIN overrides every default.
 constexpr int64_t TWO_STAGE_MIN_DEFAULT = 8192;
-constexpr int64_t EV_TWO_STAGE_MIN_ONE = 8192;     // eigenvalues only, few problems
-constexpr int64_t EV_TWO_STAGE_MIN_BATCH = 2048;   // eigenvalues only, >= EV_TWO_STAGE_BATCH such problems
+constexpr int64_t EV_TWO_STAGE_MIN_ONE = 6144;     // eigenvalues only, few problems
+constexpr int64_t EV_TWO_STAGE_MIN_BATCH = 1536;   // eigenvalues only, >= EV_TWO_STAGE_BATCH such problems
 constexpr int64_t EV_TWO_STAGE_BATCH = 8;
 inline int64_t two_stage_env() {
   const char *s = getenv("MMF_EIGH_TWO_STAGE_MIN");
