@@ -29,11 +29,14 @@
  *     (apart from the opt-in benchmark timer at the end of this header):
  *     every call is reentrant.  Kernels are enqueued on `stream` (a
  *     hipStream_t, NULL = default stream) and the call returns without
- *     synchronising.  The two-stage band reduction (mmf_eigh,
- *     mmf_eigh_window, mmf_eigvalsh_batched at large orders) also creates a
- *     stream of its own for the duration of the call (default priority),
- *     forked from and joined back into `stream` with events: all its work is
- *     ordered after the earlier work of `stream` and before the later.
+ *     synchronising (a call that enqueues tens of thousands of launches,
+ *     like the two-stage eigensolve, can wait for room in the launch queue:
+ *     at M = 20808 it returns after about 1.6 s of a 5 s solve).  The two-stage band reduction (mmf_eigh,
+ *     mmf_eigh_window, mmf_eigvalsh_batched at large orders) also uses a
+ *     stream of its own (one per host thread and device, default priority,
+ *     created on first use and kept), forked from and joined back into
+ *     `stream` with per-call events: all its work is ordered after the
+ *     earlier work of `stream` and before the later.
  *   - Return value: 0 on success; -k when argument k (1-based) is invalid
  *     (checked on the host before anything is enqueued); a positive MMF_ERR_*
  *     code on a runtime failure.  Numerical failures found on the device are

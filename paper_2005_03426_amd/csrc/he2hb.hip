@@ -491,6 +491,25 @@ __global__ void hb_band_copy(const HbProb *pr) {
 
 // Grouped band reduction of `count` problems in the device table pr (orders
 // nh[] on the host).
+// Side stream of the look-ahead: one per host thread and device, created on
+// first use with default priority and kept until the process ends (destroying
+// a stream can wait for its work, which would make the call synchronous).
+// Null when it cannot be created.
+static hipStream_t lookahead_stream() {
+  constexpr int MAXDEV = 64;
+  thread_local hipStream_t streams[MAXDEV] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    streams[dev] = nullptr;
+  }
+  return streams[dev];
+}
+
 int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_t st) {
   if (count <= 0) return MMF_OK;
   if (count > 65535) {
@@ -509,15 +528,15 @@ int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_
   // and the rest, done on a side stream while the caller's stream factors the
   // next panel; the next panel's A22 V product waits for the side stream.
   // The two panels use different P3 buffers; the factorization only touches
-  // the next panel's columns, which the rest of the update does not.  (If the
-  // side stream cannot be created, everything runs on the caller's stream.)
-  hipStream_t side = nullptr;
+  // the next panel's columns, which the rest of the update does not.  The
+  // events are per call, so calls from several host threads or on several
+  // streams stay ordered.  (If the side stream or its events cannot be
+  // created, everything runs on the caller's stream.)
+  hipStream_t side = lookahead_stream();
   hipEvent_t fork = nullptr, join = nullptr;
-  if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+  if (side && (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+               hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)) {
     (void)hipGetLastError();
-    if (side) (void)hipStreamDestroy(side);
     if (fork) (void)hipEventDestroy(fork);
     side = nullptr;
   }
@@ -525,7 +544,6 @@ int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_
     if (side) {
       (void)hipEventDestroy(fork);
       (void)hipEventDestroy(join);
-      (void)hipStreamDestroy(side);
     }
   };
   bool pending = false;                            // side stream holds an update
