@@ -38,7 +38,7 @@ namespace mmf {
 
 constexpr int QR_ROWS = 256;      // rows per workgroup of the panel factorization
 constexpr int64_t HEMM_KC = 1024; // K slice of the A22 V product
-constexpr int64_t PAN_KC = 256;   // row slice of the panel products V^H V, V^H X
+constexpr int64_t PAN_KC = 128;   // row slice of the panel products V^H V, V^H X
 
 struct HbWs {
   cd *P3;      // 2 x n x 3 BW (ld n): [V | W | V] of a panel; even and odd
@@ -404,21 +404,24 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) hb_vhx(const HbProb *pr, int6
   gemm_tile<true, A_C, B_N>(g, 0, 0, lds);
 }
 
-// U = T^H (sum_z Sp[z])   (element per thread)
+// U = T^H (sum_z Sp[z]): workgroup x computes the columns 4 x .. 4 x + 3 (one
+// element per thread) from T and those columns staged in LDS.
+constexpr int TU_COLS = 4;
 __global__ void __launch_bounds__(256) hb_tu(const HbProb *pr, int64_t c0) {
-  __shared__ cd S[BW][BW + 1];
+  __shared__ cd Tl[BW][BW + 1];
+  __shared__ cd S[BW][TU_COLS];
   const HbProb &P = pr[blockIdx.z];
   HbPanel pp;
   if (!hb_panel(P, c0, pp)) return;
   const HbWs &ws = P.ws;
-  for (int e = threadIdx.x; e < BW * BW; e += 256) S[e % BW][e / BW] = ws.Sp[e];
+  const int j0 = blockIdx.x * TU_COLS;
+  for (int e = threadIdx.x; e < BW * BW; e += 256) Tl[e / BW][e % BW] = ws.T[e];   // Tl[i][l] = T[l, i]
+  for (int e = threadIdx.x; e < BW * TU_COLS; e += 256) S[e % BW][e / BW] = ws.Sp[e % BW + (j0 + e / BW) * BW];
   __syncthreads();
-  for (int e = threadIdx.x; e < BW * BW; e += 256) {
-    const int i = e % BW, j = e / BW;
-    cd s = cmake(0.0, 0.0);
-    for (int l = 0; l <= i; ++l) s = cadd(s, cmulc(ws.T[l + i * BW], S[l][j]));
-    ws.U[e] = s;
-  }
+  const int i = threadIdx.x & 63, jj = threadIdx.x >> 6;
+  cd s = cmake(0.0, 0.0);
+  for (int l = 0; l <= i; ++l) s = cadd(s, cmulc(Tl[i][l], S[l][jj]));
+  ws.U[i + (j0 + jj) * BW] = s;
 }
 
 // W = X - V U / 2 in place of X (row tile blockIdx.x).
@@ -591,7 +594,7 @@ int he2hb_grouped(const HbProb *pr, const int64_t *nh, int64_t count, hipStream_
     MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_sum_sp, dim3(BW * BW / 256, 1, Z), dim3(256), 0, st, pr, c0);
     MMF_LAUNCH_CHECK_OR(release());
-    hipLaunchKernelGGL(hb_tu, dim3(1, 1, Z), dim3(256), 0, st, pr, c0);
+    hipLaunchKernelGGL(hb_tu, dim3(BW / TU_COLS, 1, Z), dim3(256), 0, st, pr, c0);
     MMF_LAUNCH_CHECK_OR(release());
     hipLaunchKernelGGL(hb_wupd, dim3(ntile, 1, Z), dim3(GEMM_THREADS), 0, st, pr, c0);
     MMF_LAUNCH_CHECK_OR(release());
