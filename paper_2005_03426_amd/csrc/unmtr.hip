@@ -12,8 +12,9 @@
 // The reflectors are first copied into clean dense blocks (explicit unit and
 // zeros), which also lets Phi overwrite the matrix that held them.  V^H Phi
 // and V^H V are long-K contractions, computed split-K on the matrix cores
-// and reduced in fixed order (the T product is fused into that reduction);
-// the rank-BT_NB update is a plain MFMA GEMM.  8 n^3 real flops in total.
+// and reduced in fixed order; the rank-BT_NB update is a plain MFMA GEMM
+// with the left factor V T formed per block (a 128-wide GEMM).  8 n^3 real
+// flops in total, plus 8 n^2 128 for the V T products.
 // Templated over the scalar type (complex128, or complex64 with FP32
 // accumulation for the precision layer; Z is read in FP64 and rounded).
 // Grouped: every kernel reads its problem from a device table (BtProb) at
@@ -36,6 +37,7 @@ struct BtWs {
   cx<R> *Tm;      // nblk x NB x NB
   cx<R> *Wpart;   // nsplit x NB x n
   cx<R> *W2;      // NB x n
+  cx<R> *VT;      // mb x NB: V T of the block being applied
   cx<R> *Gpart;   // nblk x nsplit x NB x NB (Gram partials)
   int64_t nblk, nsplit;
   size_t bytes;
@@ -60,6 +62,7 @@ inline BtWs<R> unmtr_ws(int64_t n, void *base, int64_t nc = -1) {
   w.Tm = cv.take<cx<R>>((size_t)(w.nblk ? w.nblk : 1) * BT_NB * BT_NB);
   w.Wpart = cv.take<cx<R>>((size_t)w.nsplit * BT_NB * (ncol > 0 ? ncol : 1));
   w.W2 = cv.take<cx<R>>((size_t)BT_NB * (ncol > 0 ? ncol : 1));
+  w.VT = cv.take<cx<R>>((size_t)BT_NB * (n > 0 ? n : 1));
   w.Gpart = cv.take<cx<R>>((size_t)(w.nblk ? w.nblk : 1) * w.nsplit * BT_NB * BT_NB);
   w.bytes = cv.used();
   return w;
@@ -76,7 +79,7 @@ struct BtProb {
   const cx<R> *V, *tau;
   const double *Z;
   cx<R> *Phi;
-  cx<R> *Vp, *VpT, *Tm, *Wpart, *W2, *Gpart;
+  cx<R> *Vp, *VpT, *Tm, *Wpart, *W2, *VT, *Gpart;
 };
 
 // Clean copy of block b = blockIdx.y: Vb[r', q] (r' = 0..mb-1 is row p+1+r'),
@@ -223,27 +226,37 @@ __global__ void __launch_bounds__(256) bt_tcross(const BtProb<R> *pr) {
   }
 }
 
-// W2[:, c] = T_b (sum_z Wpart[z][:, c]) for every column c (BT_NB threads per column).
+// VT = Vb T_b (mb x BT_NB; row tile blockIdx.x, column tile blockIdx.y): the
+// update then needs only the plain sum of the split-K partials.
 template <typename R>
-__global__ void __launch_bounds__(BT_NB) bt_reduce_t(const BtProb<R> *pr, int64_t b) {
-  __shared__ cx<R> w1[BT_NB];
+__global__ void __launch_bounds__(GEMM_THREADS, 2) bt_vt(const BtProb<R> *pr, int64_t b) {
+  __shared__ R lds[GEMM_LDS_ELEMS];
   const BtProb<R> &P = pr[blockIdx.z];
-  const int64_t c = blockIdx.x;
-  if (b >= P.nblk || c >= P.nc) return;
-  const int64_t n = P.n, nc = P.nc, mb = n - b * BT_NB - 1;
-  const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
-  const cx<R> *Tb = P.Tm + b * BT_NB * BT_NB;
-  const int r = threadIdx.x;
-  cx<R> s = cmk<R>(0, 0);
-  for (int64_t z = 0; z < nsl; ++z) s = cadd(s, P.Wpart[z * BT_NB * nc + r + c * BT_NB]);
-  w1[r] = s;
-  __syncthreads();
-  cx<R> o = cmk<R>(0, 0);
-  for (int j = r; j < BT_NB; ++j) o = cadd(o, cmul(Tb[r + j * BT_NB], w1[j]));
-  P.W2[r + c * BT_NB] = o;
+  if (b >= P.nblk) return;
+  const int64_t n = P.n, mb = n - b * BT_NB - 1;
+  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  if (m0 >= mb) return;
+  GemmArgs g = gemm_args(mb, BT_NB, BT_NB, P.Vp + bt_off(n, b), mb, P.Tm + b * BT_NB * BT_NB, BT_NB, P.VT, mb, 1.0,
+                         0.0, 0.0, 0.0);
+  gemm_tile_t<R, true, A_N, B_N>(g, m0, n0, lds);
 }
 
-// Rank-BT_NB update Phi[p+1:, :] -= Vb W2 of block b.
+// W2 = sum_z Wpart[z] (BT_NB x nc, fixed summation order).
+template <typename R>
+__global__ void bt_reduce(const BtProb<R> *pr, int64_t b) {
+  const BtProb<R> &P = pr[blockIdx.z];
+  if (b >= P.nblk) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nc = P.nc;
+  if (e >= BT_NB * nc) return;
+  const int64_t mb = P.n - b * BT_NB - 1;
+  const int64_t nsl = (mb + BT_KCHUNK - 1) / BT_KCHUNK;
+  cx<R> s = cmk<R>(0, 0);
+  for (int64_t z = 0; z < nsl; ++z) s = cadd(s, P.Wpart[z * BT_NB * nc + e]);
+  P.W2[e] = s;
+}
+
+// Rank-BT_NB update Phi[p+1:, :] -= (Vb T_b) W2 of block b.
 template <typename R>
 __global__ void __launch_bounds__(GEMM_THREADS, 2) bt_update(const BtProb<R> *pr, int64_t b) {
   __shared__ R lds[GEMM_LDS_ELEMS];
@@ -252,8 +265,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) bt_update(const BtProb<R> *pr
   const int64_t n = P.n, p = b * BT_NB, mb = n - p - 1;
   const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
   if (m0 >= mb || n0 >= P.nc) return;
-  GemmArgs u = gemm_args(mb, P.nc, BT_NB, P.Vp + bt_off(n, b), mb, P.W2, BT_NB, P.Phi + (p + 1), P.ldphi, -1.0,
-                         0.0, 1.0, 0.0);
+  GemmArgs u = gemm_args(mb, P.nc, BT_NB, P.VT, mb, P.W2, BT_NB, P.Phi + (p + 1), P.ldphi, -1.0, 0.0, 1.0, 0.0);
   gemm_tile_t<R, true, A_N, B_N>(u, m0, n0, lds);
 }
 
@@ -318,7 +330,9 @@ int unmtr_grouped(const BtProb<R> *pr, const int64_t *nh, int64_t count, hipStre
     hipLaunchKernelGGL(bt_splitk<R>, dim3((unsigned)(nsl * (BT_NB / GT_M)), cdiv(ncols, GT_N), Z),
                        dim3(GEMM_THREADS), 0, st, pr, b);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(bt_reduce_t<R>, dim3((unsigned)ncols, 1, Z), dim3(BT_NB), 0, st, pr, b);
+    hipLaunchKernelGGL(bt_vt<R>, dim3(cdiv(mb, GT_M), BT_NB / GT_N, Z), dim3(GEMM_THREADS), 0, st, pr, b);
+    MMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bt_reduce<R>, dim3(cdiv(BT_NB * ncols, 256), 1, Z), dim3(256), 0, st, pr, b);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(bt_update<R>, dim3(cdiv(mb, GT_M), cdiv(ncols, GT_N), Z), dim3(GEMM_THREADS), 0, st, pr,
                        b);
@@ -334,7 +348,7 @@ inline BtProb<R> bt_prob(int64_t n, const cx<R> *V, int64_t ldv, const cx<R> *ta
   BtProb<R> q;
   q.n = n; q.nc = nc >= 0 ? nc : n; q.ldv = ldv; q.ldz = ldz; q.ldphi = ldphi; q.nblk = w.nblk; q.nsplit = w.nsplit;
   q.V = V; q.tau = tau; q.Z = Z; q.Phi = Phi;
-  q.Vp = w.Vp; q.VpT = w.VpT; q.Tm = w.Tm; q.Wpart = w.Wpart; q.W2 = w.W2; q.Gpart = w.Gpart;
+  q.Vp = w.Vp; q.VpT = w.VpT; q.Tm = w.Tm; q.Wpart = w.Wpart; q.W2 = w.W2; q.VT = w.VT; q.Gpart = w.Gpart;
   return q;
 }
 
