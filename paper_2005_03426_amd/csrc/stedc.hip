@@ -293,8 +293,21 @@ __global__ void dc_zero_off(const DcProb *pr, int lev, int64_t Gmax) {
 }
 
 // ------------------------------------------------------------------ merge: deflation scan
-__global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
-  if (threadIdx.x != 0) return;
+// One wavefront per merge.  The scan over the m entries is sequential (each
+// test involves the last kept entry), so the whole wavefront walks it in
+// lockstep: chunks of 64 entries are read at once (one per lane) and taken
+// entry by entry with lane broadcasts; the current last kept entry (its z, d
+// and child type) stays in registers; lane 0 writes the results.  Each kept
+// column's child type is final when it is kept (only the later entry of a
+// rotated pair changes type), so the slots of the kept columns grouped
+// [top only | both | bottom only] are then formed in parallel, 64 at a time.
+__device__ inline double lane_bcast(double v, int u) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), u);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), u);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ void __launch_bounds__(64) dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
   const DcProb &P = pr[blockIdx.x / Gmax];
   const int64_t g = blockIdx.x % Gmax;
   if (lev > P.h || g >= (P.L >> lev)) return;
@@ -304,80 +317,123 @@ __global__ void dc_deflate(const DcProb *pr, int lev, int64_t Gmax) {
   int32_t *ctype = P.w.ctype, *perm = P.w.perm;
   const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t s = q.s, m = q.m;
+  const int lane = threadIdx.x;
+  const bool w0 = lane == 0;
   const double rh = rho[s];
   double dmax = fmax(fabs(ds[s]), fabs(ds[s + m - 1]));
   const double tol = 8.0 * DC_EPS * fmax(dmax, rh);
-  int32_t K = 0, ND = 0, R = 0;
+  int32_t K = 0, ND = 0, R = 0, c1 = 0, c3 = 0;
   int64_t prev = -1;
-  for (int64_t j = 0; j < m; ++j) {
-    const double zj = zs[s + j];
-    if (rh * fabs(zj) <= tol) { dfidx[s + ND++] = (int32_t)j; continue; }
-    if (prev < 0) { prev = j; continue; }
-    double sv = zs[s + prev], cv = zj;
-    const double tt = hypot(cv, sv);
-    cv /= tt;
-    sv /= tt;
-    const double dp = ds[s + prev], dj = ds[s + j];
-    if (fabs((dj - dp) * cv * sv) <= tol) {
-      zs[s + j] = tt;
-      zs[s + prev] = 0.0;
-      ds[s + prev] = cv * cv * dp + sv * sv * dj;
-      ds[s + j] = sv * sv * dp + cv * cv * dj;
-      rp[s + R] = (int32_t)prev;
-      rj[s + R] = (int32_t)j;
-      rc[s + R] = cv;
-      rs[s + R] = sv;
-      ++R;
-      ctype[s + j] |= ctype[s + prev];        // the kept column now spans both children's rows
-      dfidx[s + ND++] = (int32_t)prev;
-      prev = j;
-    } else {
-      ndidx[s + K++] = (int32_t)prev;
-      prev = j;
+  double zp = 0.0, dp = 0.0;                       // z, d of the last kept entry
+  int32_t tp = 0;                                  // its child type
+  for (int64_t j0 = 0; j0 < m; j0 += 64) {
+    const int64_t jl = j0 + lane;
+    const double zl = jl < m ? zs[s + jl] : 0.0;
+    const double dl = jl < m ? ds[s + jl] : 0.0;
+    const int32_t tl = jl < m ? ctype[s + jl] : 0;
+    const int nu = (int)((m - j0 < 64) ? m - j0 : 64);
+    for (int u = 0; u < nu; ++u) {
+      const int64_t j = j0 + u;
+      const double zj = lane_bcast(zl, u);
+      if (rh * fabs(zj) <= tol) {
+        if (w0) dfidx[s + ND] = (int32_t)j;
+        ++ND;
+        continue;
+      }
+      const double dj = lane_bcast(dl, u);
+      const int32_t tj = __builtin_amdgcn_readlane(tl, u);
+      if (prev < 0) {
+        prev = j; zp = zj; dp = dj; tp = tj;
+        continue;
+      }
+      double sv = zp, cv = zj;
+      const double tt = hypot(cv, sv);
+      cv /= tt;
+      sv /= tt;
+      if (fabs((dj - dp) * cv * sv) <= tol) {
+        const double dpn = cv * cv * dp + sv * sv * dj, djn = sv * sv * dp + cv * cv * dj;
+        if (w0) {
+          zs[s + j] = tt;
+          zs[s + prev] = 0.0;
+          ds[s + prev] = dpn;
+          ds[s + j] = djn;
+          rp[s + R] = (int32_t)prev;
+          rj[s + R] = (int32_t)j;
+          rc[s + R] = cv;
+          rs[s + R] = sv;
+          ctype[s + j] = tj | tp;                  // the kept column now spans both children's rows
+          dfidx[s + ND] = (int32_t)prev;
+        }
+        ++R;
+        ++ND;
+        prev = j; zp = tt; dp = djn; tp = tj | tp;
+      } else {
+        if (w0) {
+          ndidx[s + K] = (int32_t)prev;
+          perm[s + K] = tp;                        // child type for now, slot below
+        }
+        ++K;
+        c1 += tp == 1;
+        c3 += tp == 3;
+        prev = j; zp = zj; dp = dj; tp = tj;
+      }
     }
   }
-  if (prev >= 0) ndidx[s + K++] = (int32_t)prev;
+  if (prev >= 0) {
+    if (w0) {
+      ndidx[s + K] = (int32_t)prev;
+      perm[s + K] = tp;
+    }
+    ++K;
+    c1 += tp == 1;
+    c3 += tp == 3;
+  }
   // kept columns grouped [top only | both | bottom only] (d order inside each
   // group): the merge GEMM then multiplies the top rows by the first two
   // groups and the bottom rows by the last two only
-  int32_t c1 = 0, c3 = 0;
-  for (int32_t k = 0; k < K; ++k) {
-    const int32_t t = ctype[s + ndidx[s + k]];
-    c1 += t == 1;
-    c3 += t == 3;
-  }
+  __threadfence();
   int32_t p1 = 0, p3 = c1, p2 = c1 + c3;
-  for (int32_t k = 0; k < K; ++k) {
-    const int32_t t = ctype[s + ndidx[s + k]];
-    perm[s + k] = t == 1 ? p1++ : (t == 3 ? p3++ : p2++);
+  for (int32_t k0 = 0; k0 < K; k0 += 64) {
+    const int32_t k = k0 + lane;
+    const int32_t t = k < K ? perm[s + k] : 0;
+    const uint64_t b1 = __ballot(t == 1), b3 = __ballot(t == 3), b2 = __ballot(k < K && t != 1 && t != 3);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (k < K) {
+      const int32_t pos = t == 1 ? p1 + __popcll(b1 & below)
+                                 : (t == 3 ? p3 + __popcll(b3 & below) : p2 + __popcll(b2 & below));
+      perm[s + k] = pos;
+    }
+    p1 += __popcll(b1);
+    p3 += __popcll(b3);
+    p2 += __popcll(b2);
   }
-  cnt[DC_CNT * g + 0] = K;
-  cnt[DC_CNT * g + 1] = R;
-  cnt[DC_CNT * g + 2] = ND;
-  cnt[DC_CNT * g + 3] = c1;
-  cnt[DC_CNT * g + 4] = c1 + c3;
+  if (w0) {
+    cnt[DC_CNT * g + 0] = K;
+    cnt[DC_CNT * g + 1] = R;
+    cnt[DC_CNT * g + 2] = ND;
+    cnt[DC_CNT * g + 3] = c1;
+    cnt[DC_CNT * g + 4] = c1 + c3;
+  }
 }
 
 // ------------------------------------------------------------------ merge: rotate + gather
 // Thread = row of the merged block: applies the deflation rotations in order
-// to its row of Z, then gathers the non-deflated columns (in d order) into
-// T1[:, 0:K] and the deflated ones into T1[:, K:m].
-__global__ void dc_gather(const DcProb *pr, int lev) {
+// to its row of Z (a row's rotations chain through shared columns).
+__global__ void dc_rotate(const DcProb *pr, int lev) {
   const DcProb &P = pr[blockIdx.z];
   const int64_t g = blockIdx.y;
   if (lev > P.h || g >= (P.L >> lev)) return;
-  const int64_t n = P.n, ldz = P.ldz;
-  double *Z = P.Z;
+  const int64_t ldz = P.ldz;
   const int32_t *src = P.w.src, *ndidx = P.w.ndidx, *dfidx = P.w.dfidx, *rp = P.w.rp, *rj = P.w.rj;
   const int32_t *cnt = P.w.cnt;
   const double *rc = P.w.rc, *rs = P.w.rs, *ds = P.w.ds, *zs = P.w.zs;
-  double *dn = P.w.dn, *zn = P.w.zn, *ddef = P.w.ddef, *T1 = P.w.T1;
-  const MergeGeom q = dc_geom(n, P.L, lev, g);
+  double *dn = P.w.dn, *zn = P.w.zn, *ddef = P.w.ddef;
+  const MergeGeom q = dc_geom(P.n, P.L, lev, g);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= q.m) return;
   const int64_t s = q.s;
   const int32_t K = cnt[DC_CNT * g], R = cnt[DC_CNT * g + 1], ND = cnt[DC_CNT * g + 2];
-  double *zrow = Z + (s + r);
+  double *zrow = P.Z + (s + r);
   for (int32_t k = 0; k < R; ++k) {
     const int64_t cp = s + src[s + rp[s + k]], cj = s + src[s + rj[s + k]];
     const double c = rc[s + k], sn = rs[s + k];
@@ -385,15 +441,45 @@ __global__ void dc_gather(const DcProb *pr, int lev) {
     zrow[cp * ldz] = c * zp - sn * zj;
     zrow[cj * ldz] = sn * zp + c * zj;
   }
-  double *trow = T1 + (s + r);
-  const int32_t *perm = P.w.perm;
-  for (int32_t k = 0; k < K; ++k) trow[(s + perm[s + k]) * n] = zrow[(s + src[s + ndidx[s + k]]) * ldz];
-  for (int32_t k = 0; k < ND; ++k) trow[(s + K + k) * n] = zrow[(s + src[s + dfidx[s + k]]) * ldz];
   if (r < K) {
     dn[s + r] = ds[s + ndidx[s + r]];
     zn[s + r] = zs[s + ndidx[s + r]];
   }
   if (r < ND) ddef[s + r] = ds[s + dfidx[s + r]];
+}
+
+// Gathers the non-deflated columns (in d order, at their kept-column slots)
+// into T1[:, 0:K] and the deflated ones into T1[:, K:m].  Workgroup (row tile
+// x, y = merge g * nch + column chunk): a chunk of 256 output columns, thread
+// = row, the column indices uniform per iteration.
+constexpr int DC_GCOLS = 256;
+__global__ void dc_gather(const DcProb *pr, int lev, int64_t nch) {
+  const DcProb &P = pr[blockIdx.z];
+  const int64_t g = blockIdx.y / nch, ch = blockIdx.y % nch;
+  if (lev > P.h || g >= (P.L >> lev)) return;
+  const int64_t n = P.n, ldz = P.ldz;
+  const int32_t *src = P.w.src, *ndidx = P.w.ndidx, *dfidx = P.w.dfidx, *perm = P.w.perm;
+  const int32_t *cnt = P.w.cnt;
+  const MergeGeom q = dc_geom(n, P.L, lev, g);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o0 = ch * DC_GCOLS;
+  if (r >= q.m || o0 >= q.m) return;
+  const int64_t s = q.s;
+  const int32_t K = cnt[DC_CNT * g];
+  const int64_t o1 = (o0 + DC_GCOLS < q.m) ? o0 + DC_GCOLS : q.m;
+  const double *zrow = P.Z + (s + r);
+  double *trow = P.w.T1 + (s + r);
+  for (int64_t o = o0; o < o1; ++o) {
+    int64_t from, to;
+    if (o < K) {
+      from = s + src[s + ndidx[s + o]];
+      to = s + perm[s + o];
+    } else {
+      from = s + src[s + dfidx[s + (o - K)]];
+      to = s + o;
+    }
+    trow[to * n] = zrow[from * ldz];
+  }
 }
 
 // ------------------------------------------------------------------ merge: secular equation
@@ -708,7 +794,10 @@ int stedc_grouped(const DcProb *pr, const int64_t *nh, int64_t count, hipStream_
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(dc_deflate, dim3((unsigned)(Gmax * count)), dim3(64), 0, st, pr, lev, Gmax);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(dc_gather, rows, dim3(256), 0, st, pr, lev);
+    hipLaunchKernelGGL(dc_rotate, rows, dim3(256), 0, st, pr, lev);
+    MMF_LAUNCH_CHECK();
+    const int64_t nch = cdiv(maxm, DC_GCOLS);
+    hipLaunchKernelGGL(dc_gather, dim3(cdiv(maxm, 256), (unsigned)(Gmax * nch), Z), dim3(256), 0, st, pr, lev, nch);
     MMF_LAUNCH_CHECK();
     const dim3 roots(cdiv(maxm, 4), (unsigned)Gmax, Z);
     hipLaunchKernelGGL(dc_secular, roots, dim3(256), 0, st, pr, lev);
