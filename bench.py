@@ -569,7 +569,7 @@ def main():
             "frac": tfs / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
             "kernel": "bt2_apply (back-transformation by the bulge-chasing reflectors: compact-WY groups "
                       "of 16 on the FP64 matrix cores; achieved counts the algorithmic flops, the kernel "
-                      "executes 1.375 times as many)",
+                      "executes 1.25 times as many)",
             "launches": kt["launches"], "avg_launch_us": avg_ms * 1e3,
             "algorithmic_flops_per_launch": per_launch_flops,
             "share_of_step": kt["total_ms"] / (elapsed * 1e3),

@@ -314,12 +314,13 @@ constexpr int BT2_NB = 16;                // reflectors per compact-WY group
 constexpr int BT2_NG = BT2_G / BT2_NB;    // groups per block
 constexpr int BT2_VR = BW + BT2_NB;       // rows of a group's V (80; the last is zero)
 constexpr int MFMA_NEG_A = 1;             // FP64 MFMA modifier bits (last operand): negate A
-constexpr int BT2_TILE = 64;              // columns per tile (16 per wavefront)
-constexpr int BT2_SLOTS = 512;            // workgroups resident at once (two per CU)
+constexpr int BT2_THREADS = 512;          // eight wavefronts per workgroup, one workgroup per CU
+constexpr int BT2_TILE = 128;             // columns per tile (16 per wavefront)
+constexpr int BT2_SLOTS = 256;            // workgroups resident at once
 
 size_t bt2_ws_bytes(int64_t n, int64_t nc) {
   (void)n; (void)nc;
-  return 256 + sizeof(cd) * (size_t)BT2_CHUNK * BT2_NG * BT2_NB * BT2_NB;
+  return 256 + sizeof(cd) * (size_t)BT2_CHUNK * BT2_NG * BT2_VR * BT2_NB;
 }
 
 // Block B_{G,k} holds the reflectors j = 0 .. 63 of sweeps s0 + j at position
@@ -331,8 +332,8 @@ size_t bt2_ws_bytes(int64_t n, int64_t nc) {
 // 16 g .. 16 g + 79 of the block) and T the upper triangular factor of the
 // forward recurrence T_ii = tau_i, T_{0:i,i} = -tau_i T_{0:i,0:i} V_{:,0:i}^H v_i.
 
-// T of group g of the launch's block b (one workgroup each), row-major 16 x 16
-// at Tws + (b BT2_NG + g) 256.
+// T of group g of the launch's block b (one workgroup each), then V T (80 x 16)
+// at Tws + (b BT2_NG + g) 1280.
 __global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const cd *tau2, cd *Tws, int64_t Gmax,
                                               int64_t step, int64_t Gb) {
   __shared__ cd v[BT2_NB][BW];
@@ -387,35 +388,46 @@ __global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const c
     }
   }
   __syncthreads();
-  cd *out = Tws + (b * BT2_NG + g) * (BT2_NB * BT2_NB);
-  out[tid] = T[tid >> 4][tid & 15];
+  // V T (80 x 16): row rho, column c = sum_{i <= c} v_i[rho - i] T[i][c], stored
+  // row-major with the columns XOR-swizzled by row as the apply kernel keeps it
+  cd *out = Tws + (b * BT2_NG + g) * (BT2_VR * BT2_NB);
+  for (int e = tid; e < BT2_VR * BT2_NB; e += 256) {
+    const int rho = e / BT2_NB, c = e % BT2_NB;
+    cd acc = cmake(0.0, 0.0);
+    for (int i = 0; i <= c; ++i) {
+      const int ee = rho - i;
+      if (ee >= 0 && ee < BW) acc = cadd(acc, cmul(v[i][ee], T[i][c]));
+    }
+    out[rho * BT2_NB + (c ^ (rho & 15))] = acc;
+  }
 }
 
 // Apply the launch's blocks to Phi on the FP64 matrix cores
 // (v_mfma_f64_16x16x4f64; element r of lane l of a 16 x 16 result holds row
 // 4 r + l / 16, column l % 16; operands A[i][k] in lane i + 16 k, B[k][j] in
-// lane j + 16 k).  Workgroup (x, block y) stages the block's reflectors in
-// LDS once and then works through the column tiles x, x + gridDim.x, ... of
-// 64 columns; wavefront w owns the 16 columns 16 w .. 16 w + 15 of a tile, and
-// the block's rows are held as 16-row tiles in result layout (tile u: rows
+// lane j + 16 k).  Workgroup (x, block y) stages the block's V and V T in LDS
+// once and then works through the column tiles x, x + gridDim.x, ... of 128
+// columns; wavefront w owns the 16 columns 16 w .. 16 w + 15 of a tile, and the
+// block's rows are held as 16-row tiles in result layout (tile u: rows
 // 16 u .. 16 u + 15, element r of lane l = row 16 u + 4 r + l / 16 of column
 // l % 16).  Group g works on the window of tiles g .. g + 4:
-//   W  = V^H X   (16 x 16, k-step r of tile t contracts the rows 4 r .. 4 r + 3,
+//   W = V^H X    (16 x 16, k-step r of tile t contracts the rows 4 r .. 4 r + 3,
 //                 i.e. element r of the window's registers is the B operand),
-//   W' = T W,    X <- X - V W'  (element r of W, W' is again the B operand),
+//   X <- X - (V T) W  (element r of W is again the B operand),
 // complex products as four real MFMAs.  Tile g + 4 is then final (no later
 // group reaches it) and goes to HBM at the start of group g - 1, when tile
 // g - 2 is read for the group after.  The last group also reads tiles 6 and 7
 // of the next column tile; the tiles 0 .. 4 left at the end go to HBM at the
 // start of the next column tile, whose tiles 3 .. 5 are read then (its first
 // group contracts tiles 6 and 7 first).
-__global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *Tws, cd *Phi,
-                                                 int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb, int64_t ntile,
-                                                 cd *sink) {
-  // V of the four groups, zeros included, row rho / column i at
-  // vg[g][rho][i ^ (rho % 16)]: both operand reads (16 consecutive columns of
+__global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *Tws, cd *Phi,
+                                                          int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb,
+                                                          int64_t ntile, cd *sink) {
+  // V and V T of the four groups, zeros included, row rho / column i at
+  // [g][rho][i ^ (rho % 16)]: both operand reads (16 consecutive columns of
   // one row, 16 consecutive rows of one column) then touch 16 distinct banks
   __shared__ cd vg[BT2_NG][BT2_VR][BT2_NB];
+  __shared__ cd vt[BT2_NG][BT2_VR][BT2_NB];
   const int64_t b = blockIdx.y;
   const int64_t Gi = Gb - b;
   const int64_t k = step - (Gmax - Gi);
@@ -426,7 +438,6 @@ __global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const
   const int64_t smax = n - 2 - k * BW;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, li = lane & 15;
-  const cd *Tb = Tws + b * (BT2_NG * BT2_NB * BT2_NB);
   // column of this lane in tile ct (idle lanes past nc read column 0)
   auto colp = [&](int64_t ct, bool &ok) {
     const int64_t col = ct * BT2_TILE + wave * 16 + li;
@@ -463,42 +474,43 @@ __global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const
       *((ok && row < Lv) ? P + row : sink) = cmake(xr[u][r], xi[u][r]);
     }
   };
-  cd tv[4];
-  auto load_t = [&](int g) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) tv[r] = Tb[g * (BT2_NB * BT2_NB) + li * BT2_NB + 4 * r + q];
-  };
 
   // reflector j = 16 g + i, entry e goes to row rho = e + i of group g: read
   // the block's reflectors in storage order, then clear the 2 x 16 x 15 / 2
   // + 16 slots of each group that no reflector reaches (rho < i, rho >= i + 64)
-  // (all loads first, from clamped sweeps, so that they are in flight together)
+  // (all loads first, from clamped sweeps, so that they are in flight together);
+  // V T comes swizzled from the T kernel
   {
-    constexpr int NV = BT2_G * BW / 256;
-    cd vbuf[NV];
+    constexpr int NV = BT2_G * BW / BT2_THREADS;
+    constexpr int NT = BT2_NG * BT2_VR * BT2_NB / BT2_THREADS;
+    cd vbuf[NV], tbuf[NT];
+    const cd *Tb = Tws + b * (BT2_NG * BT2_VR * BT2_NB);
 #pragma unroll
     for (int m = 0; m < NV; ++m) {
-      const int f = tid + 256 * m, j = f / BW, e = f % BW;
+      const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW;
       vbuf[m] = V2[base + (s0 + j <= smax ? s0 + j : smax) * BW + e];
     }
 #pragma unroll
+    for (int m = 0; m < NT; ++m) tbuf[m] = Tb[tid + BT2_THREADS * m];
+#pragma unroll
     for (int m = 0; m < NV; ++m) {
-      const int f = tid + 256 * m, j = f / BW, e = f % BW, g = j / BT2_NB, i = j % BT2_NB, rho = e + i;
+      const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW, g = j / BT2_NB, i = j % BT2_NB, rho = e + i;
       vg[g][rho][i ^ (rho & 15)] = (s0 + j <= smax) ? vbuf[m] : cmake(0.0, 0.0);
     }
+#pragma unroll
+    for (int m = 0; m < NT; ++m) (&vt[0][0][0])[tid + BT2_THREADS * m] = tbuf[m];
   }
-  for (int f = tid; f < BT2_NG * BT2_NB * BT2_NB; f += 256) {
+  for (int f = tid; f < BT2_NG * BT2_NB * BT2_NB; f += BT2_THREADS) {
     const int g = f / (BT2_NB * BT2_NB), i = (f / BT2_NB) % BT2_NB, m = f % BT2_NB;
     const int rho = m < i ? m : BW + m;         // the i slots above, 16 - i below
     vg[g][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
   }
-  // the first window and T: the first group waits for them tile by tile
+  // the first window: the first group waits for it tile by tile
   int64_t ct = blockIdx.x;
   bool ok;
   cd *P = colp(ct, ok);
 #pragma unroll
   for (int u = BT2_NG - 1; u < 8; ++u) load_tile(P, u);
-  load_t(BT2_NG - 1);
   __syncthreads();
 
   cd *Pprev = P;
@@ -512,8 +524,8 @@ __global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const
 #pragma unroll
     for (int g = BT2_NG - 1; g >= 0; --g) {
       // Memory operations of a group: wait for everything issued during the
-      // previous group (its tiles and T were read a group ahead), then store
-      // the tiles that became final there and read the tiles that take their
+      // previous group (its tiles were read a group ahead), then store the
+      // tiles that became final there and read the tiles that take their
       // registers.  Stores and loads share one counter that does not keep
       // their order, so a wait for a load is a wait for every store before
       // it: with this order no wait meets a store younger than a group.  (The
@@ -542,8 +554,9 @@ __global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const
       // statement between two chains (the end of one, the start of the next)
       // fixes them.
       // W = V^H X: A operand of lane (q, li) = conj V[16 t + 4 r + q][li]
-      // (tiles t = 3, 4 first: in the first group the others arrive last)
-      v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr, pr = wr, pi = wr;
+      // (tiles t = 3, 4 first: in the first group of a column tile the others
+      // arrive last)
+      v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr;
 #pragma unroll
       for (int tt = 0; tt < 5; ++tt) {
         const int t = (tt + 3) % 5;
@@ -566,39 +579,24 @@ __global__ void __launch_bounds__(256, 2) bt2_apply(int64_t n, int64_t nc, const
           wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xr[g + t][r], wi, 0, 0, MFMA_NEG_A);
         }
       }
-      asm volatile("" : "+v"(wi), "+v"(pr));
-      // W' = T W: A operand of lane (q, li) = T[li][4 r + q]
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].re, wr[r], pr, 0, 0, 0);
-        pr = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].im, wi[r], pr, 0, 0, MFMA_NEG_A);
-      }
-      asm volatile("" : "+v"(pr), "+v"(pi));
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].re, wi[r], pi, 0, 0, 0);
-        pi = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[r].im, wr[r], pi, 0, 0, 0);
-      }
-      asm volatile("" : "+v"(pi), "+v"(xr[g]));
-      if (g > 0) load_t(g - 1);
-      else if (more) load_t(BT2_NG - 1);
-      // X <- X - V W': A operand of lane (q, li) = V[16 t + li][4 r + q]
+      asm volatile("" : "+v"(wi), "+v"(xr[g]));
+      // X <- X - (V T) W: A operand of lane (q, li) = (V T)[16 t + li][4 r + q]
 #pragma unroll
       for (int t = 0; t < 5; ++t) {
         const int u = g + t, rho = 16 * t + li;
         cd v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = vg[g][rho][(4 * r + q) ^ li];
+        for (int r = 0; r < 4; ++r) v[r] = vt[g][rho][(4 * r + q) ^ li];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, pr[r], xr[u], 0, 0, MFMA_NEG_A);
-          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, pi[r], xr[u], 0, 0, 0);
+          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wr[r], xr[u], 0, 0, MFMA_NEG_A);
+          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wi[r], xr[u], 0, 0, 0);
         }
         asm volatile("" : "+v"(xr[u]), "+v"(xi[u]));
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, pi[r], xi[u], 0, 0, MFMA_NEG_A);
-          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, pr[r], xi[u], 0, 0, MFMA_NEG_A);
+          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wi[r], xi[u], 0, 0, MFMA_NEG_A);
+          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wr[r], xi[u], 0, 0, MFMA_NEG_A);
         }
         if (t < 4) asm volatile("" : "+v"(xi[u]), "+v"(xr[u + 1]));
       }
@@ -651,11 +649,11 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
       hipLaunchKernelGGL(bt2_tgen, dim3(BT2_NG, (unsigned)cnt), dim3(256), 0, st, n, V2, tau2, Tws, Gmax, step, Gb);
       MMF_LAUNCH_CHECK();
       const int ks = ktimer_begin("bt2", st);
-      // column tiles per workgroup: enough workgroups for two per CU
+      // column tiles per workgroup: enough workgroups for one per CU
       const int64_t per = ((int64_t)ntile * cnt + BT2_SLOTS - 1) / BT2_SLOTS;
       const unsigned gx = cdiv(ntile, per);
-      hipLaunchKernelGGL(bt2_apply, dim3(gx, (unsigned)cnt), dim3(256), 0, st, n, nc, V2, Tws, Phi, ldphi, Gmax,
-                         step, Gb, (int64_t)ntile, sink);
+      hipLaunchKernelGGL(bt2_apply, dim3(gx, (unsigned)cnt), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi,
+                         Gmax, step, Gb, (int64_t)ntile, sink);
       MMF_LAUNCH_CHECK();
       if (ks >= 0) {
         // algorithmic flops: v^H x and x -= v f, 8 real flops per complex
