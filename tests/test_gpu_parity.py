@@ -130,12 +130,20 @@ def test_stedc_random(n):
     assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-12 * max(1, math.log2(n + 1))
 
 
-@pytest.mark.parametrize("kind", ["glued", "constant", "wilkinson", "zero_offdiag", "floquet"])
+@pytest.mark.parametrize("kind", ["glued", "constant", "wilkinson", "zero_offdiag", "floquet", "glued_2000",
+                                  "mixed_2000"])
 def test_stedc_structured(kind):
-    """Deflation-heavy tridiagonals: clusters, exact degeneracy, split matrix."""
+    """Deflation-heavy tridiagonals: clusters, exact degeneracy, split matrix;
+    at n = 2000 the merges' deflation scans and gathers span many 64-entry and
+    256-column chunks."""
     torch, mmf = require_gpu()
-    n = 300
-    if kind == "glued":
+    n = 2000 if kind.endswith("_2000") else 300
+    if kind == "mixed_2000":
+        # half the spectrum in tight clusters, half spread: both deflation kinds
+        rng = np.random.default_rng(11)
+        d = np.where(np.arange(n) % 2 == 0, np.round(rng.normal(size=n), 1), rng.normal(size=n))
+        e = np.where(np.arange(n - 1) % 3 == 0, 1e-10, rng.normal(size=n - 1))
+    elif kind.startswith("glued"):
         d = np.ones(n); e = np.full(n - 1, 1e-9)
     elif kind == "constant":
         d = np.full(n, 2.0); e = np.full(n - 1, -1.0)
