@@ -416,10 +416,10 @@ __global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const c
 //   X <- X - (V T) W  (element r of W is again the B operand),
 // complex products as four real MFMAs.  Tile g + 4 is then final (no later
 // group reaches it) and goes to HBM at the start of group g - 1, when tile
-// g - 2 is read for the group after.  The last group also reads tiles 6 and 7
+// g - 2 is read for the group after.  The last group also reads tiles 5 .. 7
 // of the next column tile; the tiles 0 .. 4 left at the end go to HBM at the
-// start of the next column tile, whose tiles 3 .. 5 are read then (its first
-// group contracts tiles 6 and 7 first).
+// start of the next column tile, whose tiles 3 and 4 are read then (its first
+// group contracts tiles 5 .. 7 first).
 __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *Tws, cd *Phi,
                                                           int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb,
                                                           int64_t ntile, cd *sink) {
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
     const int rho = m < i ? m : BW + m;         // the i slots above, 16 - i below
     vg[g][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
   }
-  // the first window: the first group waits for it tile by tile
+  // the first window
   int64_t ct = blockIdx.x;
   bool ok;
   cd *P = colp(ct, ok);
@@ -528,12 +528,14 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
       // tiles that became final there and read the tiles that take their
       // registers.  Stores and loads share one counter that does not keep
       // their order, so a wait for a load is a wait for every store before
-      // it: with this order no wait meets a store younger than a group.  (The
-      // very first group has no store before it: its waits are per tile.)
-      if (g < BT2_NG - 1 || !first) __builtin_amdgcn_s_waitcnt(0);
+      // it: with this order no wait meets a store younger than a group.  The
+      // wait is unconditional (also before the very first group), so that the
+      // compiler knows every register loaded earlier to be ready.
+      __builtin_amdgcn_s_waitcnt(0);
       __builtin_amdgcn_sched_barrier(0);
       if (g < BT2_NG - 1) store_tile(P, ok, g + 5);
       if (g == 0 && more) {
+        load_tile(Pn, 5);
         load_tile(Pn, 6);
         load_tile(Pn, 7);
       }
@@ -541,7 +543,6 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
 #pragma unroll
         for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
         __builtin_amdgcn_sched_barrier(0);         // registers of 3, 4 are reused
-        load_tile(P, 5);
         load_tile(P, 3);
         load_tile(P, 4);
       }
@@ -554,12 +555,12 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
       // statement between two chains (the end of one, the start of the next)
       // fixes them.
       // W = V^H X: A operand of lane (q, li) = conj V[16 t + 4 r + q][li]
-      // (tiles t = 3, 4 first: in the first group of a column tile the others
-      // arrive last)
+      // (tiles t = 2, 3, 4 first: in the first group of a column tile the
+      // others arrive last)
       v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr;
 #pragma unroll
       for (int tt = 0; tt < 5; ++tt) {
-        const int t = (tt + 3) % 5;
+        const int t = (tt + 2) % 5;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int rho = 16 * t + 4 * r + q;
@@ -649,8 +650,11 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
       hipLaunchKernelGGL(bt2_tgen, dim3(BT2_NG, (unsigned)cnt), dim3(256), 0, st, n, V2, tau2, Tws, Gmax, step, Gb);
       MMF_LAUNCH_CHECK();
       const int ks = ktimer_begin("bt2", st);
-      // column tiles per workgroup: enough workgroups for one per CU
-      const int64_t per = ((int64_t)ntile * cnt + BT2_SLOTS - 1) / BT2_SLOTS;
+      // column tiles per workgroup: as few as allow all gx * cnt workgroups
+      // to be resident at once (one per CU; a workgroup that had to wait for
+      // a free CU would double the launch)
+      const int64_t wpb = cnt < BT2_SLOTS ? BT2_SLOTS / cnt : 1;
+      const int64_t per = ((int64_t)ntile + wpb - 1) / wpb;
       const unsigned gx = cdiv(ntile, per);
       hipLaunchKernelGGL(bt2_apply, dim3(gx, (unsigned)cnt), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi,
                          Gmax, step, Gb, (int64_t)ntile, sink);
