@@ -278,30 +278,50 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
   if (m >= g.M) return;
   const R alr = (R)g.alpha_re, ali = (R)g.alpha_im, ber = (R)g.beta_re, bei = (R)g.beta_im;
   const bool usebeta = (g.beta_re != 0.0 || g.beta_im != 0.0);
-#pragma unroll 4
+  // the thread's 16 columns (tid >> 6) + 4 q: every read of C is issued before
+  // the first one is used (a skipped column reads column 0 of row m instead),
+  // so that the tile waits for memory once
+  int64_t off[16];
+  bool ok[16];
+#pragma unroll
   for (int q = 0; q < 16; ++q) {
+    const int64_t n = n0 + (tid >> 6) + 4 * q;
+    ok[q] = n < g.N && !(g.lower && m < n);
+    const int64_t cn = ok[q] ? (g.colmap ? (int64_t)g.colmap[n] : n) : 0;
+    off[q] = m + cn * g.ldc;
+  }
+  R cr[16], ci[16];
+  if (usebeta) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (CPLX) {
+        const cx<R> c = reinterpret_cast<const cx<R> *>(g.C)[off[q]];
+        cr[q] = c.re;
+        ci[q] = c.im;
+      } else {
+        cr[q] = reinterpret_cast<const R *>(g.C)[off[q]];
+        ci[q] = R(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (!ok[q]) continue;
     const int col = (tid >> 6) + 4 * q;
-    const int64_t n = n0 + col;
-    if (n >= g.N) break;
-    if (g.lower && m < n) continue;
-    const int64_t cn = g.colmap ? (int64_t)g.colmap[n] : n;
     const R vr = Cr[col * GT_LD + row];
     if (CPLX) {
       const R vi = Ci[col * GT_LD + row];
-      cx<R> *cp = reinterpret_cast<cx<R> *>(g.C) + (m + cn * g.ldc);
       R rr = alr * vr - ali * vi;
       R ri = alr * vi + ali * vr;
       if (usebeta) {
-        const cx<R> c = *cp;
-        rr += ber * c.re - bei * c.im;
-        ri += ber * c.im + bei * c.re;
+        rr += ber * cr[q] - bei * ci[q];
+        ri += ber * ci[q] + bei * cr[q];
       }
-      *cp = cmk<R>(rr, ri);
+      reinterpret_cast<cx<R> *>(g.C)[off[q]] = cmk<R>(rr, ri);
     } else {
-      R *cp = reinterpret_cast<R *>(g.C) + (m + cn * g.ldc);
       R rr = alr * vr;
-      if (usebeta) rr += ber * (*cp);
-      *cp = rr;
+      if (usebeta) rr += ber * cr[q];
+      reinterpret_cast<R *>(g.C)[off[q]] = rr;
     }
   }
 }
