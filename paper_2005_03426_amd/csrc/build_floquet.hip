@@ -9,7 +9,7 @@
 // The kernel is a pure HBM store stream (16 M^2 bytes): each thread owns one
 // row and walks a strip of columns, so a wavefront writes 64 consecutive
 // complex numbers (1 KB) of one column per step.  The column site is uniform
-// across the workgroup, so its mixed-radix decode is scalar work.
+// across the workgroup, so its mixed-radix digits are scalar work.
 #include "common.h"
 #include "problem.h"
 
@@ -28,9 +28,11 @@ __device__ inline void decode_site(const FloqParams &fp, int64_t s, int32_t *n) 
 }
 
 // E_ii + n.w evaluated as ((E_ii + n_0 w_0) + n_1 w_1) + ..., one rounding per
-// product and per sum (no fused multiply-add), in the same order as the
-// CPU definition.
-__device__ __noinline__ double diag_shift(double e, const FloqParams &fp, const int32_t *n) {
+// product and per sum (no fused multiply-add: the pragma keeps the operations
+// unfused also where the function is inlined), in the same order as the CPU
+// definition.  (Inlined: a call would take the address of the by-value
+// parameter block and make every thread copy it to scratch memory.)
+__device__ inline double diag_shift(double e, const FloqParams &fp, const int32_t *n) {
 #pragma clang fp contract(off)
   double x = e;
   for (int l = 0; l < MAX_F; ++l) {
@@ -53,11 +55,13 @@ assemble_kernel(FloqParams fp, const mmf_z *__restrict__ E, const mmf_z *__restr
   int32_t nr[MAX_F];
   decode_site(fp, sr, nr);
   const int64_t cend = (c0 + ASM_COLS < fp.M) ? c0 + ASM_COLS : fp.M;
+  // column c = j + D sc: decoded once, then advanced like an odometer (the
+  // site index s + 1 raises digit q_0 = N_0 - n_0, wrapping 2 N_0 -> 0 with a
+  // carry into the next fundamental), so the loop does no integer division
+  int j = (int)(c0 % D);
+  int32_t nc[MAX_F];
+  decode_site(fp, c0 / D, nc);
   for (int64_t c = c0; c < cend; ++c) {
-    const int j = (int)(c % D);
-    const int64_t sc = c / D;
-    int32_t nc[MAX_F];
-    decode_site(fp, sc, nc);
     int nnz = 0, lax = -1, dval = 0;
     for (int l = 0; l < MAX_F; ++l) {
       if (l >= fp.F) break;
@@ -81,6 +85,17 @@ assemble_kernel(FloqParams fp, const mmf_z *__restrict__ E, const mmf_z *__restr
       }
     }
     stz(HF + r + c * ldh, v);
+    if (++j == D) {
+      j = 0;
+      for (int l = 0; l < MAX_F; ++l) {
+        if (l >= fp.F) break;
+        if (nc[l] > -fp.N[l]) {
+          --nc[l];
+          break;
+        }
+        nc[l] = fp.N[l];
+      }
+    }
   }
 }
 
