@@ -192,8 +192,8 @@ int mmf_eigvalsh_batched_workspace(int64_t count, const int64_t *n, int prec, si
  * the grouped Householder reduction (complex128, or complex64 for
  * MMF_C64_RAW, from a complex64 copy; A[c] then stays intact; complex128
  * problems take the grouped two-stage reduction, dense -> band ->
- * tridiagonal, from order 6144 up, or from 1536 up when the call holds at
- * least 8 problems of order >= 1536), and all
+ * tridiagonal, from order 4608 up, or from 1280 up when the call holds at
+ * least 8 problems of order >= 1280), and all
  * eigenvalues are found by bisection on Sturm counts in FP64; w[c] receives
  * them in ascending order.  Arguments, ownership and errors as for
  * mmf_eigh_batched (-6: prec not MMF_C128 / MMF_C64_RAW); dev_info[c] is set
