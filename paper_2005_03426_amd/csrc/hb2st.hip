@@ -405,9 +405,10 @@ __global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const c
 // Apply the launch's blocks to Phi on the FP64 matrix cores
 // (v_mfma_f64_16x16x4f64; element r of lane l of a 16 x 16 result holds row
 // 4 r + l / 16, column l % 16; operands A[i][k] in lane i + 16 k, B[k][j] in
-// lane j + 16 k).  Workgroup (x, block y) stages the block's V and V T in LDS
-// once and then works through the column tiles x, x + gridDim.x, ... of 128
-// columns; wavefront w owns the 16 columns 16 w .. 16 w + 15 of a tile, and the
+// lane j + 16 k).  A workgroup takes a contiguous share of the launch's
+// (block, column tile) pairs; for each block in it, it stages the block's V
+// and V T in LDS once and then works through its column tiles of 128 columns
+// in order; wavefront w owns the 16 columns 16 w .. 16 w + 15 of a tile, and the
 // block's rows are held as 16-row tiles in result layout (tile u: rows
 // 16 u .. 16 u + 15, element r of lane l = row 16 u + 4 r + l / 16 of column
 // l % 16).  Group g works on the window of tiles g .. g + 4:
@@ -422,196 +423,211 @@ __global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const c
 // group contracts tiles 5 .. 7 first).
 __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *Tws, cd *Phi,
                                                           int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb,
-                                                          int64_t ntile, cd *sink) {
+                                                          int64_t cnt, int64_t ntile, cd *sink) {
   // V and V T of the four groups, zeros included, row rho / column i at
   // [g][rho][i ^ (rho % 16)]: both operand reads (16 consecutive columns of
   // one row, 16 consecutive rows of one column) then touch 16 distinct banks
   __shared__ cd vg[BT2_NG][BT2_VR][BT2_NB];
   __shared__ cd vt[BT2_NG][BT2_VR][BT2_NB];
-  const int64_t b = blockIdx.y;
-  const int64_t Gi = Gb - b;
-  const int64_t k = step - (Gmax - Gi);
-  const int64_t s0 = Gi * BT2_G;
-  const int64_t R0 = s0 + 1 + k * BW;
-  const int Lr = (int)((n - R0 < BW + BT2_G - 1) ? n - R0 : BW + BT2_G - 1);
-  const int64_t base = hb_voff(n, k);
-  const int64_t smax = n - 2 - k * BW;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, li = lane & 15;
-  // column of this lane in tile ct (idle lanes past nc read column 0)
-  auto colp = [&](int64_t ct, bool &ok) {
-    const int64_t col = ct * BT2_TILE + wave * 16 + li;
-    ok = col < nc;
-    return Phi + R0 + (ok ? col : 0) * ldphi;
-  };
+  // this workgroup's share of the launch's (block, column tile) pairs, pair
+  // b ntile + ct, split evenly over the workgroups: one segment per block it
+  // reaches (at most two)
+  const int64_t tot = cnt * ntile;
+  const int64_t pend = (int64_t)(blockIdx.x + 1) * tot / gridDim.x;
+  for (int64_t pr = (int64_t)blockIdx.x * tot / gridDim.x; pr < pend;) {
+    const int64_t b = pr / ntile;
+    const int64_t ctb = pr % ntile;                   // the segment's column tiles ctb .. cte - 1
+    const int64_t cte = (ctb + (pend - pr) < ntile) ? ctb + (pend - pr) : ntile;
+    pr += cte - ctb;
+    __syncthreads();                                  // the previous segment's last reads of vg, vt
+    const int64_t Gi = Gb - b;
+    const int64_t k = step - (Gmax - Gi);
+    const int64_t s0 = Gi * BT2_G;
+    const int64_t R0 = s0 + 1 + k * BW;
+    const int Lr = (int)((n - R0 < BW + BT2_G - 1) ? n - R0 : BW + BT2_G - 1);
+    const int64_t base = hb_voff(n, k);
+    const int64_t smax = n - 2 - k * BW;
+    // (the thread index behind an empty asm statement: the values derived
+    // from it are formed per segment instead of being kept across segments)
+    int tidv = threadIdx.x;
+    asm volatile("" : "+v"(tidv));
+    const int tid = tidv;
+    const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, li = lane & 15;
+    // column of this lane in tile ct (idle lanes past nc read column 0)
+    auto colp = [&](int64_t ct, bool &ok) {
+      const int64_t col = ct * BT2_TILE + wave * 16 + li;
+      ok = col < nc;
+      return Phi + R0 + (ok ? col : 0) * ldphi;
+    };
 
-  // Rows past the block's end (row >= Lr) and the columns of idle lanes are
-  // loaded from clamped addresses and never stored: the reflector entries of
-  // rows past the matrix end are zero, so these values neither change nor
-  // reach the others.  Real and imaginary parts are read separately, straight
-  // into the accumulator registers, so that nothing waits for a tile before
-  // its first use.
-  // (Lv is Lr behind an empty asm statement in every column tile: row offsets
-  // are then formed where they are used instead of being kept in registers
-  // across the loop)
-  int Lv = Lr;
-  v4d xr[8], xi[8];
-  auto load_tile = [&](const cd *P, int u) {
+    // Rows past the block's end (row >= Lr) and the columns of idle lanes are
+    // loaded from clamped addresses and never stored: the reflector entries of
+    // rows past the matrix end are zero, so these values neither change nor
+    // reach the others.  Real and imaginary parts are read separately, straight
+    // into the accumulator registers, so that nothing waits for a tile before
+    // its first use.
+    // (Lv is Lr behind an empty asm statement in every column tile: row offsets
+    // are then formed where they are used instead of being kept in registers
+    // across the loop)
+    int Lv = Lr;
+    v4d xr[8], xi[8];
+    auto load_tile = [&](const cd *P, int u) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * u + 4 * r + q;
-      const int ir = 2 * (row < Lv ? row : Lv - 1);
-      int ii = ir + 1;
-      asm volatile("" : "+v"(ii));                 // keep the two loads apart
-      xr[u][r] = reinterpret_cast<const double *>(P)[ir];
-      xi[u][r] = reinterpret_cast<const double *>(P)[ii];
-    }
-  };
-  auto store_tile = [&](cd *P, bool ok, int u) {
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * u + 4 * r + q;
+        const int ir = 2 * (row < Lv ? row : Lv - 1);
+        int ii = ir + 1;
+        asm volatile("" : "+v"(ii));                 // keep the two loads apart
+        xr[u][r] = reinterpret_cast<const double *>(P)[ir];
+        xi[u][r] = reinterpret_cast<const double *>(P)[ii];
+      }
+    };
+    auto store_tile = [&](cd *P, bool ok, int u) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * u + 4 * r + q;
-      *((ok && row < Lv) ? P + row : sink) = cmake(xr[u][r], xi[u][r]);
-    }
-  };
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * u + 4 * r + q;
+        *((ok && row < Lv) ? P + row : sink) = cmake(xr[u][r], xi[u][r]);
+      }
+    };
 
-  // reflector j = 16 g + i, entry e goes to row rho = e + i of group g: read
-  // the block's reflectors in storage order, then clear the 2 x 16 x 15 / 2
-  // + 16 slots of each group that no reflector reaches (rho < i, rho >= i + 64)
-  // (all loads first, from clamped sweeps, so that they are in flight together);
-  // V T comes swizzled from the T kernel
-  {
-    constexpr int NV = BT2_G * BW / BT2_THREADS;
-    constexpr int NT = BT2_NG * BT2_VR * BT2_NB / BT2_THREADS;
-    cd vbuf[NV], tbuf[NT];
-    const cd *Tb = Tws + b * (BT2_NG * BT2_VR * BT2_NB);
+    // reflector j = 16 g + i, entry e goes to row rho = e + i of group g: read
+    // the block's reflectors in storage order, then clear the 2 x 16 x 15 / 2
+    // + 16 slots of each group that no reflector reaches (rho < i, rho >= i + 64)
+    // (all loads first, from clamped sweeps, so that they are in flight together);
+    // V T comes swizzled from the T kernel
+    {
+      constexpr int NV = BT2_G * BW / BT2_THREADS;
+      constexpr int NT = BT2_NG * BT2_VR * BT2_NB / BT2_THREADS;
+      cd vbuf[NV], tbuf[NT];
+      const cd *Tb = Tws + b * (BT2_NG * BT2_VR * BT2_NB);
 #pragma unroll
-    for (int m = 0; m < NV; ++m) {
-      const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW;
-      vbuf[m] = V2[base + (s0 + j <= smax ? s0 + j : smax) * BW + e];
+      for (int m = 0; m < NV; ++m) {
+        const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW;
+        vbuf[m] = V2[base + (s0 + j <= smax ? s0 + j : smax) * BW + e];
+      }
+#pragma unroll
+      for (int m = 0; m < NT; ++m) tbuf[m] = Tb[tid + BT2_THREADS * m];
+#pragma unroll
+      for (int m = 0; m < NV; ++m) {
+        const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW, g = j / BT2_NB, i = j % BT2_NB, rho = e + i;
+        vg[g][rho][i ^ (rho & 15)] = (s0 + j <= smax) ? vbuf[m] : cmake(0.0, 0.0);
+      }
+#pragma unroll
+      for (int m = 0; m < NT; ++m) (&vt[0][0][0])[tid + BT2_THREADS * m] = tbuf[m];
     }
-#pragma unroll
-    for (int m = 0; m < NT; ++m) tbuf[m] = Tb[tid + BT2_THREADS * m];
-#pragma unroll
-    for (int m = 0; m < NV; ++m) {
-      const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW, g = j / BT2_NB, i = j % BT2_NB, rho = e + i;
-      vg[g][rho][i ^ (rho & 15)] = (s0 + j <= smax) ? vbuf[m] : cmake(0.0, 0.0);
+    for (int f = tid; f < BT2_NG * BT2_NB * BT2_NB; f += BT2_THREADS) {
+      const int g = f / (BT2_NB * BT2_NB), i = (f / BT2_NB) % BT2_NB, m = f % BT2_NB;
+      const int rho = m < i ? m : BW + m;         // the i slots above, 16 - i below
+      vg[g][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
     }
+    // the first window
+    int64_t ct = ctb;
+    bool ok;
+    cd *P = colp(ct, ok);
 #pragma unroll
-    for (int m = 0; m < NT; ++m) (&vt[0][0][0])[tid + BT2_THREADS * m] = tbuf[m];
-  }
-  for (int f = tid; f < BT2_NG * BT2_NB * BT2_NB; f += BT2_THREADS) {
-    const int g = f / (BT2_NB * BT2_NB), i = (f / BT2_NB) % BT2_NB, m = f % BT2_NB;
-    const int rho = m < i ? m : BW + m;         // the i slots above, 16 - i below
-    vg[g][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
-  }
-  // the first window
-  int64_t ct = blockIdx.x;
-  bool ok;
-  cd *P = colp(ct, ok);
-#pragma unroll
-  for (int u = BT2_NG - 1; u < 8; ++u) load_tile(P, u);
-  __syncthreads();
+    for (int u = BT2_NG - 1; u < 8; ++u) load_tile(P, u);
+    __syncthreads();
 
-  cd *Pprev = P;
-  bool okprev = ok;
-  for (bool first = true;; first = false) {
-    asm volatile("" : "+s"(Lv));
-    const int64_t ctn = ct + gridDim.x;
-    const bool more = ctn < ntile;                 // uniform
-    bool okn;
-    cd *Pn = colp(more ? ctn : ct, okn);
+    cd *Pprev = P;
+    bool okprev = ok;
+    for (bool first = true;; first = false) {
+      asm volatile("" : "+s"(Lv));
+      const int64_t ctn = ct + 1;
+      const bool more = ctn < cte;                   // uniform
+      bool okn;
+      cd *Pn = colp(more ? ctn : ct, okn);
 #pragma unroll
-    for (int g = BT2_NG - 1; g >= 0; --g) {
-      // Memory operations of a group: wait for everything issued during the
-      // previous group (its tiles were read a group ahead), then store the
-      // tiles that became final there and read the tiles that take their
-      // registers.  Stores and loads share one counter that does not keep
-      // their order, so a wait for a load is a wait for every store before
-      // it: with this order no wait meets a store younger than a group.  The
-      // wait is unconditional (also before the very first group), so that the
-      // compiler knows every register loaded earlier to be ready.
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_sched_barrier(0);
-      if (g < BT2_NG - 1) store_tile(P, ok, g + 5);
-      if (g == 0 && more) {
-        load_tile(Pn, 5);
-        load_tile(Pn, 6);
-        load_tile(Pn, 7);
-      }
-      if (g == BT2_NG - 1 && !first) {
+      for (int g = BT2_NG - 1; g >= 0; --g) {
+        // Memory operations of a group: wait for everything issued during the
+        // previous group (its tiles were read a group ahead), then store the
+        // tiles that became final there and read the tiles that take their
+        // registers.  Stores and loads share one counter that does not keep
+        // their order, so a wait for a load is a wait for every store before
+        // it: with this order no wait meets a store younger than a group.  The
+        // wait is unconditional (also before the very first group), so that the
+        // compiler knows every register loaded earlier to be ready.
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g < BT2_NG - 1) store_tile(P, ok, g + 5);
+        if (g == 0 && more) {
+          load_tile(Pn, 5);
+          load_tile(Pn, 6);
+          load_tile(Pn, 7);
+        }
+        if (g == BT2_NG - 1 && !first) {
 #pragma unroll
-        for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
-        __builtin_amdgcn_sched_barrier(0);         // registers of 3, 4 are reused
-        load_tile(P, 3);
-        load_tile(P, 4);
-      }
-      if (g > 0) load_tile(P, g - 1);
-      __builtin_amdgcn_sched_barrier(0);
-      // Products are issued as chains of MFMAs into one accumulator: a chain
-      // runs back to back on the matrix core, while alternating accumulators
-      // costs a register-file round trip of the 16 x 16 result each time.
-      // The compiler would interleave independent chains; an empty asm
-      // statement between two chains (the end of one, the start of the next)
-      // fixes them.
-      // W = V^H X: A operand of lane (q, li) = conj V[16 t + 4 r + q][li]
-      // (tiles t = 2, 3, 4 first: in the first group of a column tile the
-      // others arrive last)
-      v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr;
+          for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
+          __builtin_amdgcn_sched_barrier(0);         // registers of 3, 4 are reused
+          load_tile(P, 3);
+          load_tile(P, 4);
+        }
+        if (g > 0) load_tile(P, g - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        // Products are issued as chains of MFMAs into one accumulator: a chain
+        // runs back to back on the matrix core, while alternating accumulators
+        // costs a register-file round trip of the 16 x 16 result each time.
+        // The compiler would interleave independent chains; an empty asm
+        // statement between two chains (the end of one, the start of the next)
+        // fixes them.
+        // W = V^H X: A operand of lane (q, li) = conj V[16 t + 4 r + q][li]
+        // (tiles t = 2, 3, 4 first: in the first group of a column tile the
+        // others arrive last)
+        v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr;
 #pragma unroll
-      for (int tt = 0; tt < 5; ++tt) {
-        const int t = (tt + 2) % 5;
+        for (int tt = 0; tt < 5; ++tt) {
+          const int t = (tt + 2) % 5;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int rho = 16 * t + 4 * r + q;
-          const cd v = vg[g][rho][li ^ (rho & 15)];
-          wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xr[g + t][r], wr, 0, 0, 0);
-          wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xi[g + t][r], wr, 0, 0, 0);
+          for (int r = 0; r < 4; ++r) {
+            const int rho = 16 * t + 4 * r + q;
+            const cd v = vg[g][rho][li ^ (rho & 15)];
+            wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xr[g + t][r], wr, 0, 0, 0);
+            wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xi[g + t][r], wr, 0, 0, 0);
+          }
+        }
+        asm volatile("" : "+v"(wr), "+v"(wi));
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rho = 16 * t + 4 * r + q;
+            const cd v = vg[g][rho][li ^ (rho & 15)];
+            wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xi[g + t][r], wi, 0, 0, 0);
+            wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xr[g + t][r], wi, 0, 0, MFMA_NEG_A);
+          }
+        }
+        asm volatile("" : "+v"(wi), "+v"(xr[g]));
+        // X <- X - (V T) W: A operand of lane (q, li) = (V T)[16 t + li][4 r + q]
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const int u = g + t, rho = 16 * t + li;
+          cd v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = vt[g][rho][(4 * r + q) ^ li];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wr[r], xr[u], 0, 0, MFMA_NEG_A);
+            xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wi[r], xr[u], 0, 0, 0);
+          }
+          asm volatile("" : "+v"(xr[u]), "+v"(xi[u]));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wi[r], xi[u], 0, 0, MFMA_NEG_A);
+            xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wr[r], xi[u], 0, 0, MFMA_NEG_A);
+          }
+          if (t < 4) asm volatile("" : "+v"(xi[u]), "+v"(xr[u + 1]));
         }
       }
-      asm volatile("" : "+v"(wr), "+v"(wi));
-#pragma unroll
-      for (int t = 0; t < 5; ++t) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int rho = 16 * t + 4 * r + q;
-          const cd v = vg[g][rho][li ^ (rho & 15)];
-          wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xi[g + t][r], wi, 0, 0, 0);
-          wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xr[g + t][r], wi, 0, 0, MFMA_NEG_A);
-        }
-      }
-      asm volatile("" : "+v"(wi), "+v"(xr[g]));
-      // X <- X - (V T) W: A operand of lane (q, li) = (V T)[16 t + li][4 r + q]
-#pragma unroll
-      for (int t = 0; t < 5; ++t) {
-        const int u = g + t, rho = 16 * t + li;
-        cd v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = vt[g][rho][(4 * r + q) ^ li];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wr[r], xr[u], 0, 0, MFMA_NEG_A);
-          xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wi[r], xr[u], 0, 0, 0);
-        }
-        asm volatile("" : "+v"(xr[u]), "+v"(xi[u]));
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wi[r], xi[u], 0, 0, MFMA_NEG_A);
-          xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wr[r], xi[u], 0, 0, MFMA_NEG_A);
-        }
-        if (t < 4) asm volatile("" : "+v"(xi[u]), "+v"(xr[u + 1]));
-      }
+      Pprev = P;
+      okprev = ok;
+      if (!more) break;
+      ct = ctn;
+      P = Pn;
+      ok = okn;
     }
-    Pprev = P;
-    okprev = ok;
-    if (!more) break;
-    ct = ctn;
-    P = Pn;
-    ok = okn;
-  }
-  // the last column tile's tiles 0 .. 4
+    // the last column tile's tiles 0 .. 4
 #pragma unroll
-  for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
+    for (int u = 0; u < 5; ++u) store_tile(Pprev, okprev, u);
+  }
 }
 
 __global__ void bt2_init(int64_t n, int64_t nc, const double *Z, int64_t ldz, cd *Phi, int64_t ldphi) {
@@ -650,14 +666,13 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
       hipLaunchKernelGGL(bt2_tgen, dim3(BT2_NG, (unsigned)cnt), dim3(256), 0, st, n, V2, tau2, Tws, Gmax, step, Gb);
       MMF_LAUNCH_CHECK();
       const int ks = ktimer_begin("bt2", st);
-      // column tiles per workgroup: as few as allow all gx * cnt workgroups
-      // to be resident at once (one per CU; a workgroup that had to wait for
-      // a free CU would double the launch)
-      const int64_t wpb = cnt < BT2_SLOTS ? BT2_SLOTS / cnt : 1;
-      const int64_t per = ((int64_t)ntile + wpb - 1) / wpb;
-      const unsigned gx = cdiv(ntile, per);
-      hipLaunchKernelGGL(bt2_apply, dim3(gx, (unsigned)cnt), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi,
-                         Gmax, step, Gb, (int64_t)ntile, sink);
+      // one workgroup per CU at most (all resident at once: a workgroup that
+      // had to wait for a free CU would double the launch), the launch's
+      // cnt * ntile (block, column tile) pairs spread evenly over them
+      const int64_t pairs = cnt * (int64_t)ntile;
+      const unsigned nwg = (unsigned)(pairs < BT2_SLOTS ? pairs : BT2_SLOTS);
+      hipLaunchKernelGGL(bt2_apply, dim3(nwg), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi, Gmax, step,
+                         Gb, cnt, (int64_t)ntile, sink);
       MMF_LAUNCH_CHECK();
       if (ks >= 0) {
         // algorithmic flops: v^H x and x -= v f, 8 real flops per complex
