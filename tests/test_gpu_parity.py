@@ -23,6 +23,9 @@ ASSEMBLY_CASES = [
     ("dup_axis_h", lambda: random_problem(2, (3,), seed=6, harmonics=[(0, 1), (0, 1), (0, 2)])),
     ("beyond_box", lambda: random_problem(2, (1,), seed=3, harmonics=[(0, 1), (0, 3)])),
     ("f3", lambda: random_problem(2, (2, 1, 2), seed=8)),
+    # four fundamentals, one truncated at N = 0 (a one-site axis the column
+    # walk always carries through), D = 3 so column blocks start mid-site
+    ("f4_zero_axis", lambda: random_problem(3, (1, 0, 2, 1), seed=10)),
     ("static_f0", lambda: Problem(E=gue(np.random.default_rng(1), 4, 1.0), omega=[], N=[], axis=[],
                                   harm=[], V=np.zeros((0, 4, 4)))),
     ("d16", lambda: random_problem(16, (2, 2), seed=9)),
