@@ -155,7 +155,7 @@ def run_grouped_batch(args, torch, mmf):
             ev1.record()
             res = []
             for (p, ts, t0), dp, tt, HF, w in zip(items, dps, tts, HFs, ws):
-                res.append((mmf.evolve(dp, HF, w, t0, tt), mmf.avg_prob(dp, HF)))
+                res.append((mmf.evolve(dp, HF, w, t0, tt), mmf.avg_prob(dp, HF, w)[0]))
             ev2.record()
             return res
 
@@ -366,7 +366,7 @@ def run_precision(args, torch, mmf):
         ms = ev0.elapsed_time(ev1)
         del work
         U = mmf.evolve(dp, Pt, w, t0, tt)
-        P = mmf.avg_prob(dp, Pt)
+        P, _ = mmf.avg_prob(dp, Pt, w)
         g = torch.Generator(device="cpu").manual_seed(0)
         idx = torch.randperm(M, generator=g)[:32].to(dev)
         H = mmf.build_floquet(dp).T
@@ -457,6 +457,7 @@ def main():
     uwork = torch.empty(b.value, dtype=torch.uint8, device=dev)
     mmf.call("mmf_avg_prob_workspace", dp.ref, C.byref(b))
     pwork = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
+    pstat = torch.zeros(1, dtype=torch.int32, device=dev)
 
     stages = ("assemble", "eigh", "evolve", "avg_prob")
 
@@ -468,7 +469,7 @@ def main():
         if ev: ev[2].record()
         U = mmf.evolve(dp, HF, w, t0, tt, work=uwork)
         if ev: ev[3].record()
-        P = mmf.avg_prob(dp, HF, work=pwork)
+        P, _ = mmf.avg_prob(dp, HF, w, work=pwork, status=pstat)
         if ev: ev[4].record()
         return U, P
 

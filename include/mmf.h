@@ -11,7 +11,7 @@
  *                         (Eqs. 3-5) from the eigenpairs
  *   mmf_micromotion    -- the micromotion operator U_F(t) (Eq. 5)
  *   mmf_avg_prob       -- time/phase-averaged transition probabilities
- *                         (the MULTIMODETRANSITIONAVG task of Sec. 5)
+ *                         (multimodetransitionavg of the Python-wrapper example)
  * plus the stages of mmf_eigh (tridiagonal reduction, tridiagonal
  * divide-and-conquer, back-transformation) as separate calls.
  *
@@ -64,9 +64,14 @@ typedef struct {
   const int32_t *N;     /* host [F]: truncation, n_l in [-N_l, N_l], N_l >= 0              */
   const int32_t *axis;  /* host [K]: fundamental index l_k in [0, F)                      */
   const int32_t *harm;  /* host [K]: harmonic order h_k >= 1                              */
-  const mmf_z   *E;     /* dev [D*D]: static Hamiltonian, column-major, Hermitian         */
-  const mmf_z   *V;     /* dev [K*D*D]: V_k column-major at offset k*D*D (any complex)    */
+  const mmf_z   *E;     /* host [D*D]: static Hamiltonian, column-major, Hermitian: an
+                           imaginary part on the diagonal or |E_ij - conj(E_ji)| above
+                           1e-14 max(1, max|E|) makes the problem invalid (-k)            */
+  const mmf_z   *V;     /* host [K*D*D]: V_k column-major at offset k*D*D (any complex)   */
 } mmf_problem;
+/* The whole problem statement is host memory, read during a call only.  Only
+ * mmf_build_floquet reads E and V (it stages them on the device); the other
+ * calls use the sizes, frequencies and truncations. */
 
 /* eigensolver precision */
 enum {
@@ -87,7 +92,10 @@ enum {
   MMF_ERR_NOT_IMPLEMENTED = 3, /* option not available in this build                     */
   MMF_ERR_NO_CONVERGENCE = 4,  /* device status: an iteration did not converge           */
   MMF_ERR_SELECTION = 5,       /* micromotion: not exactly D orbit representatives found */
-  MMF_ERR_TOO_LARGE = 6        /* size beyond what the library supports                   */
+  MMF_ERR_TOO_LARGE = 6,       /* size beyond what the library supports                   */
+  MMF_ERR_DEGENERATE = 7       /* device status of mmf_avg_prob: quasienergies closer than
+                                  1e-8 max(1, max|w|) share weight on the zero Fourier site,
+                                  so P depends on the eigenvector basis (no unique value)    */
 };
 
 /* Human-readable text for a return code (static storage). */
@@ -97,6 +105,10 @@ const char *mmf_strerror(int code);
  * Errors: -1 p NULL or malformed, -2 M NULL, MMF_ERR_TOO_LARGE if M > 2^31-1. */
 int mmf_floquet_dim(const mmf_problem *p, int64_t *M);
 
+/* Workspace bytes of mmf_build_floquet: the device copy of E and the V_k,
+ * (1 + K) D^2 complex numbers.  Errors: -1 bad problem, -2 bytes NULL. */
+int mmf_build_floquet_workspace(const mmf_problem *p, size_t *bytes);
+
 /* Assemble H_F (Sec. 2, Eq. 6 with the conjugate term indexed U^{n-m};
  * Appendix A layout):
  *   HF[(i,n),(j,m)] = H^{[n-m]}_{ij} + delta_{nm} delta_{ij} (n . w),
@@ -105,8 +117,13 @@ int mmf_floquet_dim(const mmf_problem *p, int64_t *M);
  * The diagonal is evaluated as ((E_ii + n_0 w_0) + n_1 w_1) + ... in FP64.
  * All M x M entries are written (both triangles).
  * HF: dev, M x M, column-major, ldh >= M.
- * Errors: -1 bad problem, -2 HF NULL, -3 ldh < M, MMF_ERR_HIP. */
-int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *stream);
+ * work: dev, at least mmf_build_floquet_workspace() bytes; E and V are copied
+ * into it on `stream` (from pageable host memory: the host arrays may be
+ * released when the call returns) and the assembly kernel reads them there.
+ * Errors: -1 bad problem (including a non-Hermitian E, checked on the host),
+ * -2 HF NULL, -3 ldh < M, -4/-5 workspace NULL or too small, MMF_ERR_HIP. */
+int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *work, size_t work_bytes,
+                      void *stream);
 
 /* Workspace bytes that mmf_eigh needs for an M x M problem at precision prec. */
 int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
@@ -130,6 +147,24 @@ int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
  *         MMF_ERR_NOT_IMPLEMENTED for a precision not built. */
 int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec,
              void *work, size_t work_bytes, int32_t *dev_info, void *stream);
+
+/* Iteration limits of the eigensolver (a zero field keeps its default).  For
+ * callers that need a different budget, and for testing the failure report:
+ * a limit that is reached sets dev_info to MMF_ERR_NO_CONVERGENCE. */
+typedef struct {
+  int32_t refine_max_iters;   /* MMF_C64_REFINED refinement iterations, default 6, at most 64  */
+  int32_t secular_max_iters;  /* divide and conquer: steps per secular-equation root, default
+                                 200, at most 100000                                            */
+  int32_t leaf_max_iters;     /* divide and conquer: implicit-QL steps per eigenvalue of a leaf,
+                                 default 60, at most 100000                                     */
+} mmf_eigh_opts;
+
+/* mmf_eigh with iteration limits (opts may be NULL: the defaults, identical
+ * to mmf_eigh).  Arguments as for mmf_eigh with opts inserted after prec.
+ * Errors: as mmf_eigh with the workspace, size and dev_info positions moved
+ * to -7, -8 and -9; -6 a limit out of range. */
+int mmf_eigh_ex(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, const mmf_eigh_opts *opts,
+                void *work, size_t work_bytes, int32_t *dev_info, void *stream);
 
 /* Order from which mmf_eigh and mmf_eigh_window take the two-stage reduction
  * (default 6400, the measured crossover; the environment variable
@@ -267,9 +302,17 @@ int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes);
  *   P[i + D*j] = sum_a ( sum_n |Phi[(i,n),a]|^2 ) |Phi[(j,0),a]|^2
  * (long-time average of |U_ij|^2 for a nondegenerate quasienergy spectrum;
  * columns sum to one for any orthonormal Phi).  Deterministic (fixed
- * reduction order).  P: dev [D*D] doubles, i final, j initial. */
-int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, double *P,
-                 void *work, size_t work_bytes, void *stream);
+ * reduction order).  P: dev [D*D] doubles, i final, j initial.
+ * w: dev [M] ascending eigenvalues of Phi's columns, used for the cluster
+ * check: with z_a = sum_j |Phi[(j,0),a]|^2, a pair a < b with
+ * w[b] - w[a] <= 1e-8 max(1, |w[0]|, |w[M-1]|) and z_a z_b > 1e-20 makes the
+ * exact average depend on the basis chosen inside the degenerate subspace
+ * (cross terms of size up to sqrt(z_a z_b) survive the time average); then
+ * dev_status is set to MMF_ERR_DEGENERATE, else to 0.  P is written either way.
+ * Errors: -1 problem, -2 Phi, -3 ld, -4 w, -5 P, -6 dev_status NULL,
+ * -7/-8 workspace NULL or too small, MMF_ERR_HIP. */
+int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w, double *P,
+                 int32_t *dev_status, void *work, size_t work_bytes, void *stream);
 
 /* Benchmark instrumentation (not needed for computation).  mmf_ktimer_arm
  * starts recording HIP events around every launch of one kernel class on

@@ -42,7 +42,7 @@ __all__ = [
     "evolve", "evolve_expm", "micromotion_select", "micromotion", "avg_prob",
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
     "zero_site", "tridiag_eigh", "quasienergies", "restrict_modes", "dressed_evolution",
-    "spin_ops", "spin_drive",
+    "spin_ops", "spin_drive", "avg_prob_degenerate", "evolve_expm_sparse",
 ]
 
 
@@ -309,6 +309,30 @@ def evolve_expm(p, H: np.ndarray, t0: float, ts) -> np.ndarray:
     return U
 
 
+def evolve_expm_sparse(p, H: np.ndarray, t0: float, ts) -> np.ndarray:
+    """`evolve_expm` for large truncations: H_F is sparse (at most D (1 + 2K)
+    nonzeros per row), so exp(-i H_F (t - t0)) is applied to the D columns
+    of the n = 0 block by SciPy's action-of-the-exponential routine (the
+    truncated Taylor method of Al-Mohy and Higham, 2011) on a sparse copy of
+    H_F, then the same Fourier sum over sites."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.linalg import expm_multiply
+    D = p.D
+    M = H.shape[0]
+    S = M // D
+    s0 = zero_site(p.N)
+    Hs = csr_matrix(H)
+    B0 = np.zeros((M, D), dtype=np.complex128)
+    B0[D * s0:D * s0 + D, :] = np.eye(D)
+    ts = np.atleast_1d(np.asarray(ts, dtype=np.float64))
+    U = np.zeros((len(ts), D, D), dtype=np.complex128)
+    for q, t in enumerate(ts):
+        G = expm_multiply(-1j * (t - t0) * Hs, B0)                # (M, D)
+        B = site_phases(p, t)
+        U[q] = np.einsum("s,sij->ij", B, G.reshape(S, D, D))
+    return U
+
+
 def _round_half_away(x: np.ndarray) -> np.ndarray:
     return np.sign(x) * np.floor(np.abs(x) + 0.5)
 
@@ -402,7 +426,7 @@ def dressed_evolution(p, axes, ts, t0: float):
 
 
 # ---------------------------------------------------------------------------
-# Spin couplings (Sec. 3.3, Eq. 7)
+# Spin couplings (Sec. 3.4, Eq. 7)
 # ---------------------------------------------------------------------------
 def spin_ops(s: float):
     """(S_x, S_y, S_z) of spin s from the matrix elements of the standard
@@ -450,6 +474,31 @@ def avg_prob(p, Phi: np.ndarray) -> np.ndarray:
     W = A2.sum(axis=0)                          # (D, M)
     Z = A2[zero_site(p.N)]                      # (D, M)
     return W @ Z.T
+
+
+def avg_prob_degenerate(p, Phi: np.ndarray, eps, rel: float = 1e-8, shared: float = 1e-20) -> bool:
+    """True when `avg_prob` has no unique value for these eigenpairs.
+
+    The time average of |U_ij|^2 drops the cross terms of a pair of
+    eigenvectors a != b only if eps_a != eps_b; for a degenerate pair the
+    surviving cross terms (size up to sqrt(z_a z_b), z_a the weight of
+    column a on the zero Fourier site, the only site U's initial index sees)
+    depend on the basis chosen inside the degenerate subspace.  Reading of
+    the paper's averaged-probability routine, which also receives the
+    quasienergies: a pair counts as degenerate when
+    |eps_b - eps_a| <= rel * max(1, max|eps|), and it matters when
+    z_a z_b > shared.  Written as a plain loop over all pairs."""
+    eps = np.asarray(eps, dtype=np.float64)
+    D = p.D
+    s0 = zero_site(p.N)
+    z = (np.abs(Phi[D * s0:D * s0 + D, :]) ** 2).sum(axis=0)
+    tol = rel * max(1.0, float(np.abs(eps).max()))
+    M = len(eps)
+    for a in range(M):
+        for b in range(a + 1, M):
+            if abs(eps[b] - eps[a]) <= tol and z[a] * z[b] > shared:
+                return True
+    return False
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,7 @@ from __future__ import annotations
 import ctypes as C
 import numpy as np
 
-from ._lib import (lib, call, check, MMFProblem, MMFError, EXPORTED, LIB_PATH,
+from ._lib import (lib, call, check, MMFProblem, MMFEighOpts, MMFError, EXPORTED, LIB_PATH, MMF_ERR_DEGENERATE,
                    MMF_C128, MMF_C64_REFINED, MMF_C64_RAW)
 
 __all__ = [
@@ -42,35 +42,38 @@ def _ptr(t):
 
 
 class DeviceProblem:
-    """A problem statement (see workloads.Problem) staged for the library:
-    E and V in device memory (column-major), frequencies, truncations and the
-    coupling table as host arrays kept alive for the ctypes structure."""
+    """A problem statement (see workloads.Problem) prepared for the library:
+    E and V as column-major host arrays (the library validates E and stages
+    both on the device when it assembles H_F, into `ev_work`), frequencies,
+    truncations and the coupling table as host arrays kept alive for the
+    ctypes structure."""
 
     def __init__(self, problem, device="cuda"):
         torch = _torch()
         self.D = int(problem.E.shape[0])
         self.F = int(len(problem.omega))
         self.K = int(len(problem.axis))
-        E = np.asarray(problem.E, dtype=np.complex128)
-        if not np.allclose(E, E.conj().T, rtol=0, atol=1e-14 * max(1.0, np.abs(E).max())):
-            raise ValueError("E must be Hermitian")
         self.omega = np.ascontiguousarray(problem.omega, dtype=np.float64)
         self.N = np.ascontiguousarray(problem.N, dtype=np.int32)
         self.axis = np.ascontiguousarray(problem.axis, dtype=np.int32)
         self.harm = np.ascontiguousarray(problem.harm, dtype=np.int32)
-        self.E = torch.from_numpy(np.ascontiguousarray(E.T)).to(device)
+        # column-major storage: the transposed array in C order
+        self.E = np.ascontiguousarray(np.asarray(problem.E, dtype=np.complex128).T)
         if self.K:
             V = np.asarray(problem.V, dtype=np.complex128)
-            self.V = torch.from_numpy(np.ascontiguousarray(V.transpose(0, 2, 1))).to(device)
+            self.V = np.ascontiguousarray(V.transpose(0, 2, 1))
         else:
-            self.V = torch.zeros(1, dtype=torch.complex128, device=device)
+            self.V = None
         self.struct = MMFProblem(
             self.D, self.F, self.K,
             self.omega.ctypes.data if self.F else None, self.N.ctypes.data if self.F else None,
             self.axis.ctypes.data if self.K else None, self.harm.ctypes.data if self.K else None,
-            self.E.data_ptr(), self.V.data_ptr() if self.K else None)
+            self.E.ctypes.data, self.V.ctypes.data if self.K else None)
         self.M = floquet_dim(self)
         self.device = device
+        b = C.c_size_t(0)
+        call("mmf_build_floquet_workspace", self.ref, C.byref(b))
+        self.ev_work = _workspace(b.value, device)
         S = self.M // self.D
         s0, stride = 0, 1
         for n in self.N:
@@ -95,7 +98,8 @@ def build_floquet(dp: DeviceProblem, out=None, stream=None):
     M = dp.M
     if out is None:
         out = torch.empty((M, M), dtype=torch.complex128, device=dp.device)
-    call("mmf_build_floquet", dp.ref, _ptr(out), C.c_int64(out.stride(0)), _stream(stream))
+    call("mmf_build_floquet", dp.ref, _ptr(out), C.c_int64(out.stride(0)), _ptr(dp.ev_work),
+         C.c_size_t(dp.ev_work.numel()), _stream(stream))
     return out
 
 
@@ -115,10 +119,12 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def eigh(At, prec: int = MMF_C128, w=None, work=None, info=None, stream=None):
+def eigh(At, prec: int = MMF_C128, w=None, work=None, info=None, stream=None, limits=None):
     """In-place eigendecomposition of the Hermitian matrix held (column-major)
     in At.  Returns (w, At, info): eigenvalues ascending; At's row a is the
-    eigenvector of w[a]; info a device int32 (0 = converged)."""
+    eigenvector of w[a]; info a device int32 (0 = converged).  `limits`, a
+    dict with any of refine_max_iters / secular_max_iters / leaf_max_iters,
+    selects mmf_eigh_ex with those iteration limits."""
     torch = _torch()
     M = At.shape[0]
     dev = At.device
@@ -128,8 +134,13 @@ def eigh(At, prec: int = MMF_C128, w=None, work=None, info=None, stream=None):
         work = _workspace(eigh_workspace_bytes(M, prec), dev)
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=dev)
-    call("mmf_eigh", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), _ptr(w), C.c_int(prec),
-         _ptr(work), C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    if limits is None:
+        call("mmf_eigh", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), _ptr(w), C.c_int(prec),
+             _ptr(work), C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    else:
+        opts = MMFEighOpts(**{k: int(v) for k, v in limits.items()})
+        call("mmf_eigh_ex", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), _ptr(w), C.c_int(prec),
+             C.byref(opts), _ptr(work), C.c_size_t(work.numel()), _ptr(info), _stream(stream))
     return w, At, info
 
 
@@ -369,18 +380,23 @@ def dressed_evolution(problem, dressing_axes, t, t0: float = 0.0, prec: int = MM
             "info": info, "selection_info": minfo}
 
 
-def avg_prob(dp: DeviceProblem, Pt, work=None, stream=None):
-    """Averaged transition probabilities P[i, j] (i final, j initial)."""
+def avg_prob(dp: DeviceProblem, Pt, w, work=None, status=None, stream=None):
+    """Averaged transition probabilities P[i, j] (i final, j initial) from
+    the eigenvectors (rows of Pt) and their ascending eigenvalues w.  Returns
+    (P, status): status is a device int32, MMF_ERR_DEGENERATE when degenerate
+    quasienergies share weight (P then depends on the eigenvector basis)."""
     torch = _torch()
     D = dp.D
     P = torch.empty((D, D), dtype=torch.float64, device=Pt.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=Pt.device)
     if work is None:
         b = C.c_size_t(0)
         call("mmf_avg_prob_workspace", dp.ref, C.byref(b))
         work = _workspace(b.value, Pt.device)
-    call("mmf_avg_prob", dp.ref, _ptr(Pt), C.c_int64(Pt.stride(0)), _ptr(P), _ptr(work),
-         C.c_size_t(work.numel()), _stream(stream))
-    return P.T
+    call("mmf_avg_prob", dp.ref, _ptr(Pt), C.c_int64(Pt.stride(0)), _ptr(w), _ptr(P), _ptr(status),
+         _ptr(work), C.c_size_t(work.numel()), _stream(stream))
+    return P.T, status
 
 
 def solve(problem, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda"):
@@ -392,8 +408,8 @@ def solve(problem, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda"):
     HF = build_floquet(dp)
     w, Pt, info = eigh(HF, prec)
     U = evolve(dp, Pt, w, t0, tt)
-    P = avg_prob(dp, Pt)
-    return {"w": w, "Pt": Pt, "U": U, "P": P, "info": info, "dp": dp}
+    P, pstat = avg_prob(dp, Pt, w)
+    return {"w": w, "Pt": Pt, "U": U, "P": P, "P_status": pstat, "info": info, "dp": dp}
 
 
 def solve_batched(problems, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda", stream=None):
@@ -414,6 +430,6 @@ def solve_batched(problems, t, t0: float = 0.0, prec: int = MMF_C128, device="cu
         out = []
         for k, (dp, w, Pt) in enumerate(zip(dps, ws, Pts)):
             U = evolve(dp, Pt, w, t0, tt, stream=stream)
-            P = avg_prob(dp, Pt, stream=stream)
-            out.append({"w": w, "Pt": Pt, "U": U, "P": P, "info": info[k:k + 1], "dp": dp})
+            P, pstat = avg_prob(dp, Pt, w, stream=stream)
+            out.append({"w": w, "Pt": Pt, "U": U, "P": P, "P_status": pstat, "info": info[k:k + 1], "dp": dp})
     return out

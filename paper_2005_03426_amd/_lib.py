@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libmmf.so")
 
 MMF_C128, MMF_C64_REFINED, MMF_C64_RAW = 0, 1, 2
 MMF_OK, MMF_ERR_HIP, MMF_ERR_WORKSPACE, MMF_ERR_NOT_IMPLEMENTED = 0, 1, 2, 3
-MMF_ERR_NO_CONVERGENCE, MMF_ERR_SELECTION, MMF_ERR_TOO_LARGE = 4, 5, 6
+MMF_ERR_NO_CONVERGENCE, MMF_ERR_SELECTION, MMF_ERR_TOO_LARGE, MMF_ERR_DEGENERATE = 4, 5, 6, 7
 
 
 class MMFProblem(C.Structure):
@@ -24,6 +24,11 @@ class MMFProblem(C.Structure):
         ("omega", C.c_void_p), ("N", C.c_void_p), ("axis", C.c_void_p), ("harm", C.c_void_p),
         ("E", C.c_void_p), ("V", C.c_void_p),
     ]
+
+
+class MMFEighOpts(C.Structure):
+    _fields_ = [("refine_max_iters", C.c_int32), ("secular_max_iters", C.c_int32),
+                ("leaf_max_iters", C.c_int32)]
 
 
 class MMFError(RuntimeError):
@@ -37,10 +42,13 @@ _lib = None
 _SIGS = {
     "mmf_strerror": (C.c_char_p, [C.c_int]),
     "mmf_floquet_dim": (C.c_int, [C.c_void_p, C.c_void_p]),
-    "mmf_build_floquet": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "mmf_build_floquet_workspace": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mmf_build_floquet": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mmf_eigh_workspace": (C.c_int, [C.c_int64, C.c_int, C.c_void_p]),
     "mmf_eigh": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p,
                            C.c_size_t, C.c_void_p, C.c_void_p]),
+    "mmf_eigh_ex": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                              C.c_size_t, C.c_void_p, C.c_void_p]),
     "mmf_eigh_batched_workspace": (C.c_int, [C.c_int64, C.c_void_p, C.c_int, C.c_void_p]),
     "mmf_eigh_batched": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
@@ -66,8 +74,8 @@ _SIGS = {
     "mmf_dressed_evolution": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     "mmf_avg_prob_workspace": (C.c_int, [C.c_void_p, C.c_void_p]),
-    "mmf_avg_prob": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
-                               C.c_size_t, C.c_void_p]),
+    "mmf_avg_prob": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_size_t, C.c_void_p]),
     "mmf_eigh_two_stage_min": (C.c_int64, []),
     "mmf_ktimer_arm": (C.c_int, [C.c_char_p]),
     "mmf_ktimer_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

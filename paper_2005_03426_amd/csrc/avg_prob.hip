@@ -1,5 +1,5 @@
 // Time- and drive-phase-averaged transition probabilities (the
-// MULTIMODETRANSITIONAVG task of the paper, Sec. 5; average of |U_ij|^2 over
+// multimodetransitionavg task of the Python-wrapper example; average of |U_ij|^2 over
 // the eigen expansion of Eqs. 3-5 with a nondegenerate spectrum):
 //   P[i, j] = sum_a W[i,a] Z[j,a],   W[i,a] = sum_n |Phi[(i,n),a]|^2,
 //                                    Z[j,a] = |Phi[(j,0),a]|^2.
@@ -8,6 +8,14 @@
 // multiple of D so every thread accumulates a single level i; bins are
 // folded by a strided tree in LDS.  Per-workgroup D x D partials are summed
 // by a second kernel in fixed workgroup order (deterministic result).
+//
+// Degenerate quasienergies: the time average keeps the cross terms of every
+// pair a != b with w_a = w_b, of size up to sqrt(z_a z_b) with
+// z_a = sum_j |Phi[(j,0),a]|^2, and their value depends on the basis chosen
+// inside the degenerate subspace.  The workgroup that owns column a scans the
+// columns b > a with w_b - w_a <= 1e-8 max(1, |w_0|, |w_{M-1}|) (w ascending)
+// and counts the pairs with z_a z_b > 1e-20; a third kernel turns the counts
+// into the status word.
 #include "common.h"
 #include "problem.h"
 
@@ -16,12 +24,17 @@ namespace mmf {
 constexpr int AP_THREADS = 256;
 constexpr int AP_MAX_WG = 2048;
 
+constexpr double AP_CLUSTER_REL = 1e-8;     // quasienergies closer than this (relative) are degenerate
+constexpr double AP_SHARED_WEIGHT = 1e-20;  // z_a z_b above this: the pair's cross terms matter
+
 __global__ void __launch_bounds__(AP_THREADS)
 avgprob_partial(int64_t M, int D, int64_t s0, const mmf_z *__restrict__ Phi, int64_t ld,
-                double *__restrict__ part, int G) {
+                const double *__restrict__ w, double *__restrict__ part, int32_t *__restrict__ flags, int G) {
   __shared__ double red[AP_THREADS];
   __shared__ double wz[2 * MAX_D];
   const int tid = threadIdx.x;
+  const double delta = AP_CLUSTER_REL * fmax(1.0, fmax(fabs(w[0]), fabs(w[M - 1])));
+  int32_t nflag = 0;                    // wavefront 0's count of degenerate pairs with shared weight
   int P = 1;
   while (D * P * 2 <= AP_THREADS) P *= 2;
   const int Tp = D * P;                 // active threads, multiple of D
@@ -58,8 +71,17 @@ avgprob_partial(int64_t M, int D, int64_t s0, const mmf_z *__restrict__ Phi, int
       const int i = e % D, j = e / D;
       acc[q] += wz[i] * wz[MAX_D + j];
     }
+    if (tid < 64) {                     // cluster check of column a (wavefront 0, lane = level j)
+      const double za = wave_sum(tid < D ? wz[MAX_D + tid] : 0.0);
+      const double wa = w[a];
+      for (int64_t b = a + 1; b < M && w[b] - wa <= delta; ++b) {
+        const double zb = wave_sum(tid < D ? cabs2(ldz(Phi + b * ld + tid + (int64_t)D * s0)) : 0.0);
+        nflag += (za * zb > AP_SHARED_WEIGHT) ? 1 : 0;
+      }
+    }
     __syncthreads();
   }
+  if (tid == 0) flags[blockIdx.x] = nflag;
   for (int q = 0; q < 16; ++q) {
     const int e = tid + AP_THREADS * q;
     if (e >= DD) break;
@@ -85,7 +107,44 @@ __global__ void __launch_bounds__(AP_THREADS) avgprob_reduce(int DD, int G, cons
   if (tid == 0) P[e] = red[0];
 }
 
+// status <- MMF_ERR_DEGENERATE if any workgroup counted a degenerate pair, else 0.
+__global__ void __launch_bounds__(AP_THREADS) avgprob_status(int G, const int32_t *__restrict__ flags,
+                                                            int32_t *__restrict__ status) {
+  __shared__ int32_t any[AP_THREADS / 64];
+  int32_t f = 0;
+  for (int g = threadIdx.x; g < G; g += AP_THREADS) f |= (flags[g] != 0);
+  f = __any(f) ? 1 : 0;
+  if ((threadIdx.x & 63) == 0) any[threadIdx.x >> 6] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int q = 0; q < AP_THREADS / 64; ++q) t |= any[q];
+    *status = t ? MMF_ERR_DEGENERATE : 0;
+  }
+}
+
 inline int avgprob_groups(int64_t M) { return (int)(M < AP_MAX_WG ? M : AP_MAX_WG); }
+
+// workspace: G x D x D partials, then G flag counts
+inline size_t avgprob_ws_bytes(int G, int D) {
+  return (size_t)G * D * D * sizeof(double) + (size_t)G * sizeof(int32_t);
+}
+
+// The three launches shared by mmf_avg_prob and its variants.
+inline int avgprob_launch(const FloqParams &fp, const mmf_z *Phi, int64_t ld, const double *w, double *P,
+                          int32_t *status, int G, void *work, hipStream_t st) {
+  double *part = (double *)work;
+  int32_t *flags = (int32_t *)(part + (size_t)G * fp.D * fp.D);
+  hipLaunchKernelGGL(avgprob_partial, dim3(G), dim3(AP_THREADS), 0, st, fp.M, fp.D, fp.s0, Phi, ld, w,
+                     part, flags, G);
+  MMF_LAUNCH_CHECK();
+  const int DD = fp.D * fp.D;
+  hipLaunchKernelGGL(avgprob_reduce, dim3((unsigned)DD), dim3(AP_THREADS), 0, st, DD, G, part, P);
+  MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(avgprob_status, dim3(1), dim3(AP_THREADS), 0, st, G, flags, status);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
 
 }  // namespace mmf
 
@@ -96,29 +155,22 @@ extern "C" int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes) {
   const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (!bytes) return -2;
-  *bytes = (size_t)avgprob_groups(fp.M) * fp.D * fp.D * sizeof(double) + 256;
+  *bytes = avgprob_ws_bytes(avgprob_groups(fp.M), fp.D);
   return MMF_OK;
 }
 
-extern "C" int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, double *P,
-                            void *work, size_t work_bytes, void *stream) {
+extern "C" int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w, double *P,
+                            int32_t *dev_status, void *work, size_t work_bytes, void *stream) {
   FloqParams fp;
   const int rc = problem_params_small_d(p, 1, &fp);
   if (rc) return rc;
   if (!Phi) return -2;
   if (ld < fp.M) return -3;
-  if (!P) return -4;
+  if (!w) return -4;
+  if (!P) return -5;
+  if (!dev_status) return -6;
   const int G = avgprob_groups(fp.M);
-  const size_t need = (size_t)G * fp.D * fp.D * sizeof(double);
-  if (!work) return -5;
-  if (work_bytes < need) return -6;
-  hipStream_t st = (hipStream_t)stream;
-  double *part = (double *)work;
-  hipLaunchKernelGGL(avgprob_partial, dim3(G), dim3(AP_THREADS), 0, st, fp.M, fp.D, fp.s0, Phi, ld,
-                     part, G);
-  MMF_LAUNCH_CHECK();
-  const int DD = fp.D * fp.D;
-  hipLaunchKernelGGL(avgprob_reduce, dim3((unsigned)DD), dim3(AP_THREADS), 0, st, DD, G, part, P);
-  MMF_LAUNCH_CHECK();
-  return MMF_OK;
+  if (!work) return -7;
+  if (work_bytes < avgprob_ws_bytes(G, fp.D)) return -8;
+  return avgprob_launch(fp, Phi, ld, w, P, dev_status, G, work, (hipStream_t)stream);
 }

@@ -112,15 +112,38 @@ extern "C" int mmf_floquet_dim(const mmf_problem *p, int64_t *M) {
   return MMF_OK;
 }
 
-extern "C" int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *stream) {
+static size_t build_ws_bytes(const FloqParams &fp) {
+  return (size_t)(1 + fp.K) * (size_t)fp.D * (size_t)fp.D * sizeof(mmf_z);
+}
+
+extern "C" int mmf_build_floquet_workspace(const mmf_problem *p, size_t *bytes) {
   FloqParams fp;
   const int rc = problem_params(p, 1, &fp);
   if (rc) return rc;
+  if (!bytes) return -2;
+  *bytes = build_ws_bytes(fp);
+  return MMF_OK;
+}
+
+extern "C" int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *work, size_t work_bytes,
+                                 void *stream) {
+  FloqParams fp;
+  const int rc = problem_params(p, 1, &fp);
+  if (rc) return rc;
+  if (!problem_hermitian(p)) return -1;
   if (!HF) return -2;
   if (ldh < fp.M) return -3;
+  if (!work) return -4;
+  if (work_bytes < build_ws_bytes(fp)) return -5;
+  hipStream_t st = (hipStream_t)stream;
+  // device copies of E and V (V_k at offset (1 + k) D^2)
+  mmf_z *Ed = (mmf_z *)work;
+  mmf_z *Vd = Ed + (size_t)fp.D * fp.D;
+  const size_t dd = (size_t)fp.D * fp.D * sizeof(mmf_z);
+  MMF_HIP_TRY(hipMemcpyAsync(Ed, p->E, dd, hipMemcpyHostToDevice, st));
+  if (fp.K > 0) MMF_HIP_TRY(hipMemcpyAsync(Vd, p->V, dd * fp.K, hipMemcpyHostToDevice, st));
   dim3 grid(cdiv(fp.M, ASM_ROWS), cdiv(fp.M, ASM_COLS));
-  hipLaunchKernelGGL(assemble_kernel, grid, dim3(ASM_ROWS), 0, (hipStream_t)stream, fp, p->E,
-                     p->V, HF, ldh);
+  hipLaunchKernelGGL(assemble_kernel, grid, dim3(ASM_ROWS), 0, st, fp, Ed, Vd, HF, ldh);
   MMF_LAUNCH_CHECK();
   return MMF_OK;
 }
@@ -135,6 +158,8 @@ extern "C" const char *mmf_strerror(int code) {
     case MMF_ERR_NO_CONVERGENCE: return "iteration did not converge";
     case MMF_ERR_SELECTION: return "micromotion: not exactly D orbit representatives";
     case MMF_ERR_TOO_LARGE: return "problem too large";
+    case MMF_ERR_DEGENERATE:
+      return "averaged probabilities: degenerate quasienergies share weight (P depends on the eigenvector basis)";
     default: return "unknown error";
   }
 }

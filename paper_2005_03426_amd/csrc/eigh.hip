@@ -133,17 +133,18 @@ inline Eigh2Ws eigh2_ws(int64_t M, int64_t nc, bool window, void *base) {
 // Band reduction, bulge chase and divide and conquer: eigenvalues in w,
 // tridiagonal eigenvectors in ws.Z, stage-1 reflectors in A.
 inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh2Ws &ws, int32_t *dev_info,
-                         hipStream_t st) {
+                         hipStream_t st, const EighLimits &lim = EighLimits()) {
   int rc = he2hb_run(M, A, lda, ws.tau1, ws.AB, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;
   rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, st);
   if (rc) return rc;
-  return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st);
+  return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
 }
 
-inline int eigh2_run(int64_t M, mmf_z *A, int64_t lda, double *w, void *work, int32_t *dev_info, hipStream_t st) {
+inline int eigh2_run(int64_t M, mmf_z *A, int64_t lda, double *w, void *work, int32_t *dev_info, hipStream_t st,
+                     const EighLimits &lim) {
   const Eigh2Ws ws = eigh2_ws(M, M, false, work);
-  int rc = eigh2_tridiag(M, A, lda, w, ws, dev_info, st);
+  int rc = eigh2_tridiag(M, A, lda, w, ws, dev_info, st, lim);
   if (rc) return rc;
   char *bt1 = (char *)ws.rest;
   // copy the stage-1 reflectors out of A, then Phi = Q2 Z over A, then Phi <- Q1 Phi
@@ -176,8 +177,27 @@ extern "C" int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes) {
   return MMF_OK;
 }
 
-extern "C" int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, void *work,
-                        size_t work_bytes, int32_t *dev_info, void *stream) {
+static int eigh_dispatch(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, void *work, size_t work_bytes,
+                         int32_t *dev_info, hipStream_t st, const EighLimits &lim) {
+  if (prec != MMF_C128) {
+    if (work_bytes < eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED)) return -7;
+    return eigh_c64_run(M, A, lda, w, prec == MMF_C64_REFINED, work, work_bytes, dev_info, st, lim);
+  }
+  if (M > 0 && M >= two_stage_min()) {
+    if (work_bytes < eigh2_ws(M, M, false, nullptr).bytes) return -7;
+    return eigh2_run(M, A, lda, w, work, dev_info, st, lim);
+  }
+  EighWs ws = eigh_ws(M, work, work_bytes);
+  if (work_bytes < ws.bytes) return -7;
+  if (M == 0) return MMF_OK;
+  int rc = hetrd_run(M, A, lda, w, ws.e, ws.tau, ws.rest, ws.rest_bytes, st);
+  if (rc) return rc;
+  rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
+  if (rc) return rc;
+  return unmtr_run(M, A, lda, ws.tau, ws.Z, M, A, lda, ws.rest, ws.rest_bytes, st);
+}
+
+static int eigh_check_args(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, void *work, int32_t *dev_info) {
   if (M < 0) return -1;
   if (!A && M > 0) return -2;
   if (lda < M || lda < 1) return -3;
@@ -185,23 +205,31 @@ extern "C" int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, v
   if (prec != MMF_C128 && prec != MMF_C64_REFINED && prec != MMF_C64_RAW) return -5;
   if (!work) return -6;
   if (!dev_info) return -8;
-  hipStream_t st = (hipStream_t)stream;
-  if (prec != MMF_C128) {
-    if (work_bytes < eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED)) return -7;
-    return eigh_c64_run(M, A, lda, w, prec == MMF_C64_REFINED, work, work_bytes, dev_info, st);
-  }
-  if (M > 0 && M >= two_stage_min()) {
-    if (work_bytes < eigh2_ws(M, M, false, nullptr).bytes) return -7;
-    return eigh2_run(M, A, lda, w, work, dev_info, st);
-  }
-  EighWs ws = eigh_ws(M, work, work_bytes);
-  if (work_bytes < ws.bytes) return -7;
-  if (M == 0) return MMF_OK;
-  int rc = hetrd_run(M, A, lda, w, ws.e, ws.tau, ws.rest, ws.rest_bytes, st);
+  return 0;
+}
+
+extern "C" int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, void *work,
+                        size_t work_bytes, int32_t *dev_info, void *stream) {
+  const int rc = eigh_check_args(M, A, lda, w, prec, work, dev_info);
   if (rc) return rc;
-  rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st);
-  if (rc) return rc;
-  return unmtr_run(M, A, lda, ws.tau, ws.Z, M, A, lda, ws.rest, ws.rest_bytes, st);
+  return eigh_dispatch(M, A, lda, w, prec, work, work_bytes, dev_info, (hipStream_t)stream, EighLimits());
+}
+
+extern "C" int mmf_eigh_ex(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, const mmf_eigh_opts *opts,
+                           void *work, size_t work_bytes, int32_t *dev_info, void *stream) {
+  int rc = eigh_check_args(M, A, lda, w, prec, work, dev_info);
+  if (rc) return rc > -6 ? rc : rc - 1;            // work and dev_info sit one position later
+  EighLimits lim;
+  if (opts) {
+    if (opts->refine_max_iters < 0 || opts->refine_max_iters > 64) return -6;
+    if (opts->secular_max_iters < 0 || opts->secular_max_iters > 100000) return -6;
+    if (opts->leaf_max_iters < 0 || opts->leaf_max_iters > 100000) return -6;
+    if (opts->refine_max_iters) lim.refine_iters = opts->refine_max_iters;
+    if (opts->secular_max_iters) lim.secular_iters = opts->secular_max_iters;
+    if (opts->leaf_max_iters) lim.leaf_iters = opts->leaf_max_iters;
+  }
+  rc = eigh_dispatch(M, A, lda, w, prec, work, work_bytes, dev_info, (hipStream_t)stream, lim);
+  return rc == -7 ? -8 : rc;
 }
 
 extern "C" int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t *bytes) {

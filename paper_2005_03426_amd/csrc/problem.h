@@ -59,6 +59,27 @@ inline int problem_params(const mmf_problem *p, int argpos, FloqParams *fp) {
   return 0;
 }
 
+// E (host, D x D column-major) must be Hermitian: a real diagonal and
+// |E_ij - conj(E_ji)| <= 1e-14 max(1, max |E|) off the diagonal.
+inline bool problem_hermitian(const mmf_problem *p) {
+  const int64_t D = p->D;
+  double emax = 1.0;
+  for (int64_t k = 0; k < D * D; ++k) {
+    const double a = hypot(p->E[k].re, p->E[k].im);
+    if (!(a <= 1e300)) return false;        // NaN or infinite
+    if (a > emax) emax = a;
+  }
+  const double tol = 1e-14 * emax;
+  for (int64_t j = 0; j < D; ++j) {
+    if (p->E[j + D * j].im != 0.0) return false;
+    for (int64_t i = j + 1; i < D; ++i) {
+      const mmf_z a = p->E[i + D * j], b = p->E[j + D * i];
+      if (hypot(a.re - b.re, a.im + b.im) > tol) return false;
+    }
+  }
+  return true;
+}
+
 // As problem_params, for the calls that keep D x D blocks on chip (U(t),
 // micromotion, P): D above MAX_D is MMF_ERR_TOO_LARGE.
 inline int problem_params_small_d(const mmf_problem *p, int argpos, FloqParams *fp) {

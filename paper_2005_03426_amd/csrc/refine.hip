@@ -16,7 +16,12 @@
 //   cluster to the rest use the Ritz values of its rotated vectors.
 // Clusters are runs of consecutive eigenvalues closer than
 //   delta = CL_FACTOR * max_{i!=j} |s_ij - lam_j g_ij|,
-// so that every first-order correction outside a cluster is below 1/CL_FACTOR:
+// so that every first-order correction outside a cluster is below 1/CL_FACTOR.
+// Every pair inside one run takes r_ij / 2, whatever the run's length; the
+// Rayleigh-Ritz rotation works on chunks of at most CL_MAX consecutive members
+// of a run, and the chunk boundaries of runs longer than that move by CL_MAX/2
+// from one iteration to the next, so that couplings across a boundary are
+// rotated in the following iteration (a block-Jacobi sweep over the run).
 // from complex64 eigenvectors (error ~ eps32 ||A|| / gap) a pair closer than
 // that cannot be separated by the first-order step and is rotated inside its
 // cluster instead; the threshold shrinks with the residual (on dense
@@ -29,13 +34,14 @@
 #include "common.h"
 #include "stages.h"
 #include "gemm_core.h"
+#include "jacobi_lds.h"
 
 namespace mmf {
 
-constexpr int REF_ITERS = 6;      // upper bound; converged iterations are skipped on the device
 constexpr double CONV_TOL = 1e-13; // stop once max |s_ij - lam_j g_ij| <= CONV_TOL max(1, max|lam|)
 constexpr double CL_FACTOR = 100.0;
-constexpr int CL_MAX = 32;          // clusters are split into chunks of at most CL_MAX
+constexpr int CL_MAX = JAC_NMAX;    // Rayleigh-Ritz chunks of a run hold at most CL_MAX members
+constexpr int CL_GRID = 1024;       // workgroups of the per-chunk kernels (they loop over the chunks)
 // Predictive stop: once the corrections are small (off-cluster max |e_ij|
 // <= REF_QUAD, second-order regime), the next measured residual is about
 // ms * max|e_ij|; when REF_SAFETY times that is already below the
@@ -116,8 +122,10 @@ __global__ void rf_zero_u64(unsigned long long *p) { if (threadIdx.x == 0) *p = 
 // stop_next <- 1 when the next iteration is predicted converged (msml: this
 // iteration's max |s_ij - lam_j g_ij|, max(1, max |lam|), max |g_ij - delta_ij|).
 __global__ void rf_predict(const unsigned long long *emax_bits, const double *msml, int32_t *stop_next,
-                           const int32_t *skip) {
-  if (threadIdx.x != 0 || *skip) return;
+                           const int32_t *skip, const int32_t *longrun) {
+  // a run longer than one rotation chunk keeps couplings that the
+  // corrections do not remove: then only a measurement can stop
+  if (threadIdx.x != 0 || *skip || *longrun) return;
   const double e = __longlong_as_double((long long)*emax_bits);
   // after X <- X (I + E): residual ~ ms * max|e|, loss of orthogonality ~ r^2 + max|e|^2
   if (e <= REF_QUAD && REF_SAFETY * msml[0] * e <= CONV_TOL * msml[1] &&
@@ -136,16 +144,22 @@ __global__ void __launch_bounds__(256) rf_lambda(int64_t n, const cd *S, const c
   const int64_t j = blockIdx.x;
   const double lj = S[j + j * n].re / G[j + j * n].re;
   double ms = 0.0, mr = 0.0;
+  // fmax drops a NaN operand: a non-finite entry anywhere in the column (or
+  // its Rayleigh quotient) is carried on as +infinity instead
+  bool bad = !isfinite(lj);
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     const cd gij = G[i + j * n];
     if (i == j) {
       mr = fmax(mr, sqrt((gij.re - 1.0) * (gij.re - 1.0) + gij.im * gij.im));
+      bad |= !isfinite(gij.re + gij.im);
       continue;
     }
     mr = fmax(mr, sqrt(cabs2(gij)));
     const cd v = csub(S[i + j * n], cscale(gij, lj));
     ms = fmax(ms, sqrt(cabs2(v)));
+    bad |= !isfinite(v.re + v.im + gij.re + gij.im);
   }
+  if (__any(bad)) ms = mr = INFINITY;
   ms = wave_max(ms);
   mr = wave_max(mr);
   if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ms; sh[1][threadIdx.x >> 6] = mr; }
@@ -157,17 +171,31 @@ __global__ void __launch_bounds__(256) rf_lambda(int64_t n, const cd *S, const c
   }
 }
 
-// Cluster scan (one thread): cid[i] = first index of i's cluster chunk;
-// clist holds (start, size) of every chunk with size >= 2; ncl its count.
+// Cluster scan (one thread): cid[i] = first index of i's run (consecutive
+// eigenvalues closer than delta); clist holds (start, size, offset of its Q
+// block) of every chunk of size >= 2 for the Rayleigh-Ritz rotation (runs cut
+// at start + off + k CL_MAX); ncl its count; *longrun = 1 when some run is
+// longer than a chunk (then pairs of one run are not all rotated together).
+// A non-finite residual, orthogonality or eigenvalue sets *bad and stops the
+// iteration.
 __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, int32_t *cid,
                             int32_t *clist, int32_t *ncl, double *delta_out, double *msml,
-                            const int32_t *skip, int32_t *stop_next) {
+                            const int32_t *skip, int32_t *stop_next, int32_t *bad, int32_t *longrun, int off) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || *skip) return;
   double ms = 0.0, ml = 1.0, mr = 0.0;
+  bool finite = true;
   for (int64_t j = 0; j < n; ++j) {
+    finite = finite && isfinite(colmax[j]) && isfinite(colmax[n + j]) && isfinite(lam[j]);
     ms = fmax(ms, colmax[j]);
     mr = fmax(mr, colmax[n + j]);
     ml = fmax(ml, fabs(lam[j]));
+  }
+  *longrun = 0;
+  if (!finite) {
+    *bad = 1;
+    *stop_next = 1;
+    *ncl = 0;
+    return;
   }
   if (ms <= CONV_TOL * ml && mr <= CONV_TOL_R) *stop_next = 1;     // this iteration's update is the last one
   msml[0] = ms;
@@ -175,21 +203,32 @@ __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, 
   msml[2] = mr;
   const double delta = CL_FACTOR * ms;
   *delta_out = delta;
-  int32_t nc = 0;
+  int32_t nc = 0, qoff = 0, lr = 0;
   int64_t start = 0;
   for (int64_t i = 1; i <= n; ++i) {
-    const bool brk = (i == n) || (fabs(lam[i] - lam[i - 1]) > delta) || (i - start >= CL_MAX);
-    if (brk) {
-      for (int64_t q = start; q < i; ++q) cid[q] = (int32_t)start;
-      if (i - start >= 2) {
-        clist[2 * nc] = (int32_t)start;
-        clist[2 * nc + 1] = (int32_t)(i - start);
+    if (i < n && fabs(lam[i] - lam[i - 1]) <= delta) continue;
+    // run [start, i): cid for the r_ij / 2 rule, chunks for the rotation
+    for (int64_t q = start; q < i; ++q) cid[q] = (int32_t)start;
+    if (i - start > CL_MAX) lr = 1;
+    int64_t c0 = start;
+    int64_t cut = (i - start > CL_MAX && off > 0) ? start + off : start + CL_MAX;
+    while (c0 < i) {
+      const int64_t c1 = cut < i ? cut : i;
+      const int32_t sz = (int32_t)(c1 - c0);
+      if (sz >= 2) {
+        clist[3 * nc] = (int32_t)c0;
+        clist[3 * nc + 1] = sz;
+        clist[3 * nc + 2] = qoff;
+        qoff += sz * sz;
         ++nc;
       }
-      start = i;
+      c0 = c1;
+      cut = c1 + CL_MAX;
     }
+    start = i;
   }
   *ncl = nc;
+  *longrun = lr;
 }
 
 // F = I + E, written over S; emax_bits collects max |e_ij| outside clusters
@@ -207,13 +246,15 @@ __global__ void __launch_bounds__(256) rf_build_f(int64_t n, cd *S, const cd *G,
     cd f;
     if (i == j) {
       f = cmake(1.0 + 0.5 * (1.0 - g.re), 0.0);
-    } else if (cid[i] == cid[j]) {
-      f = cscale(g, -0.5);                         // r_ij / 2
     } else {
       const double den = lam[j] - lam[i];
-      // (s_ij + lam_j r_ij) / (lam_j - lam_i), r_ij = -g_ij
-      f = cscale(csub(s, cscale(g, lam[j])), 1.0 / den);
-      e = sqrt(cabs2(f));
+      if (cid[i] == cid[j] || den == 0.0) {
+        f = cscale(g, -0.5);                       // r_ij / 2 (same run, or no separating gap at all)
+      } else {
+        // (s_ij + lam_j r_ij) / (lam_j - lam_i), r_ij = -g_ij
+        f = cscale(csub(s, cscale(g, lam[j])), 1.0 / den);
+        e = sqrt(cabs2(f));
+      }
     }
     S[i + j * n] = f;
   }
@@ -226,124 +267,124 @@ __global__ void __launch_bounds__(256) rf_build_f(int64_t n, cd *S, const cd *G,
   }
 }
 
-// Cluster blocks: T = S_CC - (R S + S R)/2 with R = I - G (first order),
-// Jacobi-diagonalised by one thread per cluster; Q (size x size) and the
-// Ritz values are stored for the rotation kernel.
-__global__ void rf_cluster_rr(int64_t n, const cd *S, const cd *G, const int32_t *clist,
-                              const int32_t *ncl, cd *Qbuf, double *lam, const int32_t *skip) {
-  __shared__ cd T[CL_MAX][CL_MAX], Q[CL_MAX][CL_MAX];
-  const int c = blockIdx.x;
-  if (*skip || c >= *ncl || threadIdx.x != 0) return;
-  const int st = clist[2 * c], sz = clist[2 * c + 1];
-  for (int a = 0; a < sz; ++a)
-    for (int b = 0; b < sz; ++b) {
-      cd acc = S[(st + a) + (int64_t)(st + b) * n];
-      for (int k = 0; k < sz; ++k) {
-        const cd rak = cmake((a == k ? 1.0 : 0.0) - G[(st + a) + (int64_t)(st + k) * n].re,
-                             -G[(st + a) + (int64_t)(st + k) * n].im);
-        const cd rkb = cmake((k == b ? 1.0 : 0.0) - G[(st + k) + (int64_t)(st + b) * n].re,
-                             -G[(st + k) + (int64_t)(st + b) * n].im);
-        acc = csub(acc, cscale(cadd(cmul(rak, S[(st + k) + (int64_t)(st + b) * n]),
-                                    cmul(S[(st + a) + (int64_t)(st + k) * n], rkb)), 0.5));
-      }
-      T[a][b] = acc;
-      Q[a][b] = cmake(a == b ? 1.0 : 0.0, 0.0);
+// Cluster blocks: T = S_CC - (R S + S R)/2 with R = I - G (first order,
+// sums over the chunk's members), diagonalised by one workgroup per chunk
+// with the parallel Jacobi method in LDS; Q (size x size, column-major at the
+// chunk's offset in Qbuf) and the Ritz values are stored for the rotations.
+__global__ void __launch_bounds__(256) rf_cluster_rr(int64_t n, const cd *S, const cd *G, const int32_t *clist,
+                                                    const int32_t *ncl, cd *Qbuf, double *lam,
+                                                    const int32_t *skip) {
+  __shared__ JacobiLds L;
+  if (*skip) return;
+  const int tid = threadIdx.x;
+  const int nc = *ncl;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int st = clist[3 * c], sz = clist[3 * c + 1], qoff = clist[3 * c + 2];
+    __syncthreads();
+    for (int e = tid; e < sz * sz; e += 256) {
+      const int a = e % sz, b = e / sz;
+      L.T[a * JAC_LD + b] = S[(st + a) + (int64_t)(st + b) * n];          // S_ab
+      const cd g = G[(st + a) + (int64_t)(st + b) * n];
+      L.Q[a * JAC_LD + b] = cmake((a == b ? 1.0 : 0.0) - g.re, -g.im);   // R_ab
     }
-  // make T exactly Hermitian
-  for (int a = 0; a < sz; ++a) {
-    T[a][a].im = 0.0;
-    for (int b = a + 1; b < sz; ++b) {
-      const cd h = cscale(cadd(T[a][b], cconj(T[b][a])), 0.5);
-      T[a][b] = h;
-      T[b][a] = cconj(h);
+    __syncthreads();
+    cd acc[CL_MAX * CL_MAX / 256];
+    for (int q = 0; q < CL_MAX * CL_MAX / 256; ++q) {
+      const int e = tid + 256 * q;
+      if (e >= sz * sz) break;
+      const int a = e % sz, b = e / sz;
+      cd sum = cmake(0.0, 0.0);
+      for (int k = 0; k < sz; ++k)
+        sum = cadd(sum, cadd(cmul(L.Q[a * JAC_LD + k], L.T[k * JAC_LD + b]),
+                             cmul(L.T[a * JAC_LD + k], L.Q[k * JAC_LD + b])));
+      acc[q] = csub(L.T[a * JAC_LD + b], cscale(sum, 0.5));
     }
-  }
-  // cyclic complex Jacobi
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int a = 0; a < sz; ++a)
-      for (int b = 0; b < sz; ++b) {
-        const double v = cabs2(T[a][b]);
-        tot += v;
-        if (a != b) off += v;
+    __syncthreads();
+    for (int q = 0; q < CL_MAX * CL_MAX / 256; ++q) {
+      const int e = tid + 256 * q;
+      if (e >= sz * sz) break;
+      L.T[(e % sz) * JAC_LD + e / sz] = acc[q];
+    }
+    __syncthreads();
+    // exactly Hermitian, and Q = I
+    for (int e = tid; e < sz * sz; e += 256) {
+      const int a = e % sz, b = e / sz;
+      if (a < b) {
+        const cd h = cscale(cadd(L.T[a * JAC_LD + b], cconj(L.T[b * JAC_LD + a])), 0.5);
+        L.T[a * JAC_LD + b] = h;
+        L.T[b * JAC_LD + a] = cconj(h);
+      } else if (a == b) {
+        L.T[a * JAC_LD + a].im = 0.0;
       }
-    if (off <= 1e-32 * tot || off == 0.0) break;
-    for (int p = 0; p < sz - 1; ++p)
-      for (int q = p + 1; q < sz; ++q) {
-        const double r = sqrt(cabs2(T[p][q]));
-        if (r == 0.0) continue;
-        const cd ph = cscale(T[p][q], 1.0 / r);     // a_pq = r e^{i phi}
-        const double theta = (T[q][q].re - T[p][p].re) / (2.0 * r);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-        // J = [[c, s], [-s conj(ph), c conj(ph)]] on columns p, q
-        const cd j00 = cmake(cs, 0.0), j01 = cmake(sn, 0.0);
-        const cd j10 = cscale(cconj(ph), -sn), j11 = cscale(cconj(ph), cs);
-        for (int k = 0; k < sz; ++k) {               // T <- T J
-          const cd tp = T[k][p], tq = T[k][q];
-          T[k][p] = cadd(cmul(tp, j00), cmul(tq, j10));
-          T[k][q] = cadd(cmul(tp, j01), cmul(tq, j11));
-        }
-        for (int k = 0; k < sz; ++k) {               // T <- J^H T
-          const cd tp = T[p][k], tq = T[q][k];
-          T[p][k] = cadd(cmulc(j00, tp), cmulc(j10, tq));
-          T[q][k] = cadd(cmulc(j01, tp), cmulc(j11, tq));
-        }
-        T[p][q] = cmake(0.0, 0.0);
-        T[q][p] = cmake(0.0, 0.0);
-        for (int k = 0; k < sz; ++k) {               // Q <- Q J
-          const cd qp = Q[k][p], qq = Q[k][q];
-          Q[k][p] = cadd(cmul(qp, j00), cmul(qq, j10));
-          Q[k][q] = cadd(cmul(qp, j01), cmul(qq, j11));
-        }
-      }
-  }
-  cd *Qo = Qbuf + (int64_t)c * CL_MAX * CL_MAX;
-  for (int a = 0; a < sz; ++a) {
-    lam[st + a] = T[a][a].re;
-    for (int b = 0; b < sz; ++b) Qo[a + b * CL_MAX] = Q[a][b];
+      L.Q[a * JAC_LD + b] = cmake(a == b ? 1.0 : 0.0, 0.0);
+    }
+    jacobi_herm_lds<256>(L, sz, 30);
+    __syncthreads();
+    for (int e = tid; e < sz * sz; e += 256) {
+      const int a = e % sz, b = e / sz;
+      Qbuf[qoff + e] = L.Q[a * JAC_LD + b];
+      if (b == 0) lam[st + a] = L.T[a * JAC_LD + a].re;
+    }
   }
 }
 
-// F[:, C] <- F[:, C] Q_C for every cluster chunk C (thread = row).
-__global__ void rf_cluster_rotate(int64_t n, cd *F, const int32_t *clist, const int32_t *ncl,
-                                  const cd *Qbuf, const int32_t *skip) {
-  const int c = blockIdx.y;
-  if (*skip || c >= *ncl) return;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const int st = clist[2 * c], sz = clist[2 * c + 1];
-  const cd *Q = Qbuf + (int64_t)c * CL_MAX * CL_MAX;
-  cd row[CL_MAX];
-#pragma unroll
-  for (int a = 0; a < CL_MAX; ++a) row[a] = (a < sz) ? F[r + (int64_t)(st + a) * n] : cmake(0.0, 0.0);
-  for (int b = 0; b < sz; ++b) {
-    cd s = cmake(0.0, 0.0);
-#pragma unroll
-    for (int a = 0; a < CL_MAX; ++a)
-      if (a < sz) s = cadd(s, cmul(row[a], Q[a + b * CL_MAX]));
-    F[r + (int64_t)(st + b) * n] = s;
+// F[:, C] <- F[:, C] Q_C for every chunk C: work items (64-row tile, chunk),
+// the tile and Q_C staged in LDS.
+__global__ void __launch_bounds__(256) rf_cluster_rotate(int64_t n, cd *F, const int32_t *clist,
+                                                        const int32_t *ncl, const cd *Qbuf, const int32_t *skip) {
+  __shared__ cd Ft[64][CL_MAX + 1];
+  __shared__ cd Qs[CL_MAX][CL_MAX + 1];
+  if (*skip) return;
+  const int tid = threadIdx.x;
+  const int64_t ntile = (n + 63) / 64;
+  const int64_t items = (int64_t)(*ncl) * ntile;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int c = (int)(it / ntile);
+    const int64_t r0 = (it % ntile) * 64;
+    const int st = clist[3 * c], sz = clist[3 * c + 1], qoff = clist[3 * c + 2];
+    __syncthreads();
+    for (int e = tid; e < 64 * sz; e += 256) {
+      const int r = e % 64, a = e / 64;
+      Ft[r][a] = (r0 + r < n) ? F[(r0 + r) + (int64_t)(st + a) * n] : cmake(0.0, 0.0);
+    }
+    for (int e = tid; e < sz * sz; e += 256) Qs[e % sz][e / sz] = Qbuf[qoff + e];
+    __syncthreads();
+    const int r = tid % 64;
+    for (int b = tid / 64; b < sz; b += 4) {
+      cd s = cmake(0.0, 0.0);
+      for (int a = 0; a < sz; ++a) s = cadd(s, cmul(Ft[r][a], Qs[a][b]));
+      if (r0 + r < n) F[(r0 + r) + (int64_t)(st + b) * n] = s;
+    }
   }
 }
 
-// S[C, :] <- Q_C^H S[C, :] for every cluster chunk C (thread = column).
-__global__ void rf_cluster_rotate_rows(int64_t n, cd *S, const int32_t *clist, const int32_t *ncl,
-                                       const cd *Qbuf, const int32_t *skip) {
-  const int c = blockIdx.y;
-  if (*skip || c >= *ncl) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int st = clist[2 * c], sz = clist[2 * c + 1];
-  const cd *Q = Qbuf + (int64_t)c * CL_MAX * CL_MAX;
-  cd col[CL_MAX];
-#pragma unroll
-  for (int a = 0; a < CL_MAX; ++a) col[a] = (a < sz) ? S[(st + a) + j * n] : cmake(0.0, 0.0);
-  for (int b = 0; b < sz; ++b) {
-    cd s = cmake(0.0, 0.0);
-#pragma unroll
-    for (int a = 0; a < CL_MAX; ++a)
-      if (a < sz) s = cadd(s, cmulc(Q[a + b * CL_MAX], col[a]));     // (Q^H)_{ba} = conj(Q_ab)
-    S[(st + b) + j * n] = s;
+// S[C, :] <- Q_C^H S[C, :] for every chunk C: work items (64-column tile, chunk).
+__global__ void __launch_bounds__(256) rf_cluster_rotate_rows(int64_t n, cd *S, const int32_t *clist,
+                                                             const int32_t *ncl, const cd *Qbuf,
+                                                             const int32_t *skip) {
+  __shared__ cd St[CL_MAX][64 + 1];
+  __shared__ cd Qs[CL_MAX][CL_MAX + 1];
+  if (*skip) return;
+  const int tid = threadIdx.x;
+  const int64_t ntile = (n + 63) / 64;
+  const int64_t items = (int64_t)(*ncl) * ntile;
+  for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int c = (int)(it / ntile);
+    const int64_t c0 = (it % ntile) * 64;
+    const int st = clist[3 * c], sz = clist[3 * c + 1], qoff = clist[3 * c + 2];
+    __syncthreads();
+    for (int e = tid; e < 64 * sz; e += 256) {
+      const int a = e % sz, k = e / sz;
+      St[a][k] = (c0 + k < n) ? S[(st + a) + (c0 + k) * n] : cmake(0.0, 0.0);
+    }
+    for (int e = tid; e < sz * sz; e += 256) Qs[e % sz][e / sz] = Qbuf[qoff + e];
+    __syncthreads();
+    const int k = tid % 64;
+    for (int b = tid / 64; b < sz; b += 4) {
+      cd s = cmake(0.0, 0.0);
+      for (int a = 0; a < sz; ++a) s = cadd(s, cmulc(Qs[a][b], St[a][k]));     // (Q^H)_{ba} = conj(Q_ab)
+      if (c0 + k < n) S[(st + b) + (c0 + k) * n] = s;
+    }
   }
 }
 
@@ -356,8 +397,8 @@ __global__ void rf_carry(int64_t n, const cd *X, cd *Xo, const int32_t *skip) {
   Xo[r + c * n] = X[r + c * n];
 }
 
-__global__ void rf_flag_unconverged(const int32_t *stop, int32_t *info) {
-  if (threadIdx.x == 0 && *stop == 0 && *info == 0) *info = MMF_ERR_NO_CONVERGENCE;
+__global__ void rf_flag_unconverged(const int32_t *stop, const int32_t *bad, int32_t *info) {
+  if (threadIdx.x == 0 && (*stop == 0 || *bad != 0) && *info == 0) *info = MMF_ERR_NO_CONVERGENCE;
 }
 
 // Final eigenvalues: Rayleigh quotients of the refined vectors,
@@ -414,7 +455,7 @@ struct RefWs {
   size_t stage_bytes;
   cd *X, *B1, *B2;
   double *lam, *colmax, *delta;
-  int32_t *cid, *clist, *ncl, *band, *dest, *skip, *stop;
+  int32_t *cid, *clist, *ncl, *band, *dest, *skip, *stop, *bad, *longrun;
   unsigned long long *emax;
   double *msml;
   int32_t *noskip;        // a flag that stays zero (final products run unconditionally)
@@ -447,16 +488,18 @@ inline RefWs ref_ws(int64_t M, bool refine, void *base) {
   w.colmax = cv.take<double>(2 * n);
   w.delta = cv.take<double>(1);
   w.cid = cv.take<int32_t>(n);
-  w.clist = cv.take<int32_t>(2 * n);
+  w.clist = cv.take<int32_t>(3 * n);
   w.ncl = cv.take<int32_t>(1);
   w.band = cv.take<int32_t>(1);
   w.dest = cv.take<int32_t>(n);
   w.skip = cv.take<int32_t>(1);
   w.stop = cv.take<int32_t>(1);
+  w.bad = cv.take<int32_t>(1);
+  w.longrun = cv.take<int32_t>(1);
   w.emax = cv.take<unsigned long long>(1);
   w.msml = cv.take<double>(3);
   w.noskip = cv.take<int32_t>(1);
-  w.Qbuf = cv.take<cd>((n / 2 + 1) * CL_MAX * CL_MAX);
+  w.Qbuf = cv.take<cd>(n * CL_MAX);             // sum of size^2 over the chunks <= CL_MAX n
   w.bytes = cv.used();
   return w;
 }
@@ -466,7 +509,7 @@ size_t eigh_c64_ws_bytes(int64_t M, bool refine) { return ref_ws(M, refine, null
 // After the complex64 eigensolve (eigenvectors in ws.Ac): widen them into A
 // (raw), or refine them in FP64 against A and write the refined pairs.
 static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, const RefWs &ws, int32_t *info,
-                      hipStream_t st) {
+                      int iters, hipStream_t st) {
   const dim3 g2(cdiv(n, 256), (unsigned)n);
   int rc = MMF_OK;
   if (!refine) {
@@ -482,6 +525,8 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
   MMF_LAUNCH_CHECK();
   hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.stop);
   MMF_LAUNCH_CHECK();
+  hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.bad);
+  MMF_LAUNCH_CHECK();
   // X alternates between two buffers; a skipped iteration must not swap, so
   // the product X F is always written and read back through fixed roles:
   // iteration it reads Xin = bufs[it % 2] and writes Xout = bufs[(it+1) % 2];
@@ -489,7 +534,7 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
   cd *bufs[2] = {ws.X, ws.B1};
   cd *B2 = ws.B2, *B3 = nullptr;
   (void)B3;
-  for (int it = 0; it < REF_ITERS; ++it) {
+  for (int it = 0; it < iters; ++it) {
     cd *X = bufs[it % 2], *Xo = bufs[(it + 1) % 2];
     hipLaunchKernelGGL(rf_latch, dim3(1), dim3(64), 0, st, ws.skip, ws.stop);
     MMF_LAUNCH_CHECK();
@@ -518,25 +563,24 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, S, G, ws.lam, ws.colmax, ws.skip);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_clusters, dim3(1), dim3(64), 0, st, n, ws.lam, ws.colmax, ws.cid, ws.clist,
-                       ws.ncl, ws.delta, ws.msml, ws.skip, ws.stop);
+                       ws.ncl, ws.delta, ws.msml, ws.skip, ws.stop, ws.bad, ws.longrun,
+                       (it & 1) ? CL_MAX / 2 : 0);
     MMF_LAUNCH_CHECK();
-    const unsigned maxcl = (unsigned)(n / 2 + 1);
-    hipLaunchKernelGGL(rf_cluster_rr, dim3(maxcl), dim3(64), 0, st, n, S, G, ws.clist, ws.ncl, ws.Qbuf,
+    hipLaunchKernelGGL(rf_cluster_rr, dim3(CL_GRID), dim3(256), 0, st, n, S, G, ws.clist, ws.ncl, ws.Qbuf,
                        ws.lam, ws.skip);
     MMF_LAUNCH_CHECK();
     // move X, S and G into the Rayleigh-Ritz basis of every cluster:
     // X <- X Q, S <- Q^H S Q, G <- Q^H G Q (Q block diagonal, identity outside clusters)
-    const dim3 gcl(cdiv(n, 256), maxcl);
-    hipLaunchKernelGGL(rf_cluster_rotate, gcl, dim3(256), 0, st, n, X, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
+    hipLaunchKernelGGL(rf_cluster_rotate, dim3(CL_GRID), dim3(256), 0, st, n, X, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_cluster_rotate, gcl, dim3(256), 0, st, n, S, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
+    hipLaunchKernelGGL(rf_cluster_rotate, dim3(CL_GRID), dim3(256), 0, st, n, S, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_cluster_rotate_rows, gcl, dim3(256), 0, st, n, S, ws.clist, ws.ncl, ws.Qbuf,
+    hipLaunchKernelGGL(rf_cluster_rotate_rows, dim3(CL_GRID), dim3(256), 0, st, n, S, ws.clist, ws.ncl, ws.Qbuf,
                        ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_cluster_rotate, gcl, dim3(256), 0, st, n, G, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
+    hipLaunchKernelGGL(rf_cluster_rotate, dim3(CL_GRID), dim3(256), 0, st, n, G, ws.clist, ws.ncl, ws.Qbuf, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_cluster_rotate_rows, gcl, dim3(256), 0, st, n, G, ws.clist, ws.ncl, ws.Qbuf,
+    hipLaunchKernelGGL(rf_cluster_rotate_rows, dim3(CL_GRID), dim3(256), 0, st, n, G, ws.clist, ws.ncl, ws.Qbuf,
                        ws.skip);
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_lambda, dim3((unsigned)n), dim3(256), 0, st, n, S, G, ws.lam, ws.colmax, ws.skip);
@@ -545,7 +589,7 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     MMF_LAUNCH_CHECK();
     hipLaunchKernelGGL(rf_build_f, g2, dim3(256), 0, st, n, S, G, ws.lam, ws.cid, ws.emax, ws.skip);
     MMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(rf_predict, dim3(1), dim3(64), 0, st, ws.emax, ws.msml, ws.stop, ws.skip);
+    hipLaunchKernelGGL(rf_predict, dim3(1), dim3(64), 0, st, ws.emax, ws.msml, ws.stop, ws.skip, ws.longrun);
     MMF_LAUNCH_CHECK();
     // Xo = X F  (G in Xo is no longer needed); a skipped iteration copies X into Xo
     GemmArgs gf = gemm_args(n, n, n, X, n, S, n, Xo, n, 1.0, 0.0, 0.0, 0.0);
@@ -556,9 +600,9 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
     MMF_LAUNCH_CHECK();
   }
   // the iteration cap was reached without the convergence test passing
-  hipLaunchKernelGGL(rf_flag_unconverged, dim3(1), dim3(64), 0, st, ws.stop, info);
+  hipLaunchKernelGGL(rf_flag_unconverged, dim3(1), dim3(64), 0, st, ws.stop, ws.bad, info);
   MMF_LAUNCH_CHECK();
-  cd *X = bufs[REF_ITERS % 2], *Y = bufs[(REF_ITERS + 1) % 2];
+  cd *X = bufs[iters % 2], *Y = bufs[(iters + 1) % 2];
   // eigenvalues as Rayleigh quotients of the final vectors: Y = A X (banded), then per column
   hipLaunchKernelGGL(rf_zero_int, dim3(1), dim3(64), 0, st, ws.noskip);
   MMF_LAUNCH_CHECK();
@@ -580,7 +624,7 @@ static int c64_finish(int64_t n, cd *A, int64_t lda, double *w, bool refine, con
 }
 
 int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void *work, size_t bytes,
-                 int32_t *info, hipStream_t st) {
+                 int32_t *info, hipStream_t st, const EighLimits &lim) {
   if (M <= 0) return MMF_OK;
   RefWs ws = ref_ws(M, refine, work);
   if (bytes < ws.bytes) return MMF_ERR_WORKSPACE;
@@ -591,11 +635,11 @@ int eigh_c64_run(int64_t M, mmf_z *Az, int64_t lda, double *w, bool refine, void
   MMF_LAUNCH_CHECK();
   int rc = hetrd_run_c64(n, ws.Ac, n, w, ws.e, ws.tauc, ws.stage, ws.stage_bytes, st);
   if (rc) return rc;
-  rc = stedc_run(n, w, ws.e, ws.Z, n, ws.stage, ws.stage_bytes, info, st);
+  rc = stedc_run(n, w, ws.e, ws.Z, n, ws.stage, ws.stage_bytes, info, st, lim);
   if (rc) return rc;
   rc = unmtr_run_c64(n, ws.Ac, n, ws.tauc, ws.Z, n, ws.Ac, n, ws.stage, ws.stage_bytes, st);
   if (rc) return rc;
-  return c64_finish(n, A, lda, w, refine, ws, info, st);
+  return c64_finish(n, A, lda, w, refine, ws, info, lim.refine_iters, st);
 }
 
 int eigh_c64_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda, double *const *w,
@@ -620,7 +664,8 @@ int eigh_c64_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int
                          st);
   if (rc) return rc;
   for (int64_t c = 0; c < count; ++c) {
-    rc = c64_finish(n[c], reinterpret_cast<cd *>(A[c]), lda[c], w[c], refine, ws[c], info[c], st);
+    rc = c64_finish(n[c], reinterpret_cast<cd *>(A[c]), lda[c], w[c], refine, ws[c], info[c],
+                    EighLimits().refine_iters, st);
     if (rc) return rc;
   }
   return MMF_OK;

@@ -9,13 +9,21 @@ constexpr int HT_NB = 32;        // Householder panel width of the reduction
 constexpr int BT_NB = 128;       // reflectors per block of the back-transformation (two halves of 64)
 constexpr size_t STAGE_TABLE_BYTES = 512;   // device bytes per problem of a stage's batch table
 
+// Iteration limits of the eigensolver's iterative parts (mmf_eigh_opts; the
+// defaults are what every other entry point uses).
+struct EighLimits {
+  int32_t refine_iters = 6;     // Ogita-Aishima refinement iterations (precision layer)
+  int32_t secular_iters = 200;  // secular-equation steps per root (divide and conquer)
+  int32_t leaf_iters = 60;      // implicit-QL steps per eigenvalue in the D&C leaves
+};
+
 size_t hetrd_ws_bytes(int64_t n);
 int hetrd_run(int64_t n, mmf_z *A, int64_t lda, double *d, double *e, mmf_z *tau, void *work,
               size_t bytes, hipStream_t st);
 
 size_t stedc_ws_bytes(int64_t n);
 int stedc_run(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *work,
-              size_t bytes, int32_t *info, hipStream_t st);
+              size_t bytes, int32_t *info, hipStream_t st, const EighLimits &lim = EighLimits());
 
 size_t unmtr_ws_bytes(int64_t n);
 // Phi may alias V (the reflectors are copied to the workspace first).
@@ -44,7 +52,7 @@ int hetrd_batched_c64(int64_t count, const int64_t *n, void *const *A, const int
                       double *const *e, void *const *tau, void *const *stage, void *table, hipStream_t st);
 int stedc_batched(int64_t count, const int64_t *n, double *const *d, double *const *e, double *const *Z,
                   const int64_t *ldz, void *const *stage, int32_t *const *info, void *table,
-                  hipStream_t st);
+                  hipStream_t st, const EighLimits &lim = EighLimits());
 int unmtr_batched(int64_t count, const int64_t *n, const mmf_z *const *V, const int64_t *ldv,
                   const mmf_z *const *tau, const double *const *Z, const int64_t *ldz, mmf_z *const *Phi,
                   const int64_t *ldphi, void *const *stage, void *table, hipStream_t st);
@@ -55,7 +63,7 @@ int unmtr_batched_c64(int64_t count, const int64_t *n, const void *const *V, con
 // whole eigensolve of the precision layer (complex64 + optional FP64 refinement)
 size_t eigh_c64_ws_bytes(int64_t M, bool refine);
 int eigh_c64_run(int64_t M, mmf_z *A, int64_t lda, double *w, bool refine, void *work, size_t bytes,
-                 int32_t *info, hipStream_t st);
+                 int32_t *info, hipStream_t st, const EighLimits &lim = EighLimits());
 // batch of the same: problem c (order n[c] >= 1) uses workspace base[c] of
 // eigh_c64_ws_bytes(n[c], refine) bytes; `table` as for the batched stages
 int eigh_c64_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda, double *const *w,

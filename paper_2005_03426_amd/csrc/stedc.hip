@@ -84,6 +84,7 @@ size_t stedc_ws_bytes(int64_t n) { return stedc_ws(n, nullptr).bytes + 512; }
 struct DcProb {
   int64_t n, ldz, L;
   int32_t h;
+  int32_t sec_max, leaf_max;     // iteration caps: secular steps per root, QL steps per eigenvalue
   double *d;
   const double *e;
   double *Z;
@@ -135,8 +136,11 @@ __global__ void dc_tear(const DcProb *pr) {
 }
 
 // ------------------------------------------------------------------ leaves
-// One wavefront per leaf: implicit QL with Wilkinson shifts; every lane runs
-// the scalar recurrence (identical values) and rotates its own row of Z.
+// One wavefront per leaf: implicit QL with Wilkinson shifts (the textbook
+// symmetric tridiagonal QL iteration: Bowdler, Martin, Reinsch and Wilkinson,
+// Numer. Math. 11 (1968), the tql2 procedure; Golub and Van Loan, Sec. 8.3);
+// every lane runs the scalar recurrence (identical values) and rotates its
+// own row of Z.
 __global__ void __launch_bounds__(64) dc_leaf(const DcProb *pr) {
   __shared__ double dd[DC_LEAF], ee[DC_LEAF];
   __shared__ double Zl[DC_LEAF * DC_LEAF];
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(64) dc_leaf(const DcProb *pr) {
         ++mm;
       }
       if (mm == l) break;
-      if (++iter > 60) { fail = true; break; }
+      if (++iter > q.leaf_max) { fail = true; break; }
       double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
       double rr = hypot(g, 1.0);
       g = dd[mm] - dd[l] + ee[l] / (g + copysign(rr, g));
@@ -528,7 +532,7 @@ __global__ void __launch_bounds__(256) dc_secular(const DcProb *pr, int lev) {
   double tau = 0.5 * (lo + hi);
   double lastw = hi - lo;
   bool conv = false;
-  for (int it = 0; it < 200; ++it) {
+  for (int it = 0; it < P.sec_max; ++it) {
     double ps = 0.0, ph = 0.0, dps = 0.0, dph = 0.0;
     for (int i = lane; i < K; i += 64) {
       const double den = (d[i] - dorg) - tau;
@@ -820,9 +824,11 @@ int stedc_grouped(const DcProb *pr, const int64_t *nh, int64_t count, hipStream_
 }
 
 inline DcProb dc_prob(int64_t n, double *d, const double *e, double *Z, int64_t ldz, int32_t *info,
-                      const DcWs &w) {
+                      const DcWs &w, const EighLimits &lim) {
   DcProb q;
   q.n = n; q.ldz = ldz;
+  q.sec_max = lim.secular_iters;
+  q.leaf_max = lim.leaf_iters;
   q.h = dc_depth(n);
   q.L = (int64_t)1 << q.h;
   q.d = d; q.e = e; q.Z = Z; q.info = info;
@@ -831,11 +837,12 @@ inline DcProb dc_prob(int64_t n, double *d, const double *e, double *Z, int64_t 
 }
 
 int stedc_batched(int64_t count, const int64_t *n, double *const *d, double *const *e, double *const *Z,
-                  const int64_t *ldz, void *const *stage, int32_t *const *info, void *table, hipStream_t st) {
+                  const int64_t *ldz, void *const *stage, int32_t *const *info, void *table, hipStream_t st,
+                  const EighLimits &lim) {
   static_assert(sizeof(DcProb) <= STAGE_TABLE_BYTES, "table entry");
   std::vector<DcProb> h((size_t)count);
   for (int64_t c = 0; c < count; ++c)
-    h[c] = dc_prob(n[c], d[c], e[c], Z[c], ldz[c], info[c], stedc_ws(n[c], (char *)stage[c] + 512));
+    h[c] = dc_prob(n[c], d[c], e[c], Z[c], ldz[c], info[c], stedc_ws(n[c], (char *)stage[c] + 512), lim);
   DcProb *pr = reinterpret_cast<DcProb *>(table);
   const int rc = table_write(pr, h.data(), count, st);
   if (rc) return rc;
@@ -843,13 +850,13 @@ int stedc_batched(int64_t count, const int64_t *n, double *const *d, double *con
 }
 
 int stedc_run(int64_t n, double *d, const double *e, double *Z, int64_t ldz, void *work, size_t bytes,
-              int32_t *info, hipStream_t st) {
+              int32_t *info, hipStream_t st, const EighLimits &lim) {
   if (n <= 0) return MMF_OK;
   static_assert(sizeof(DcProb) <= 512, "table entry");
   DcWs w = stedc_ws(n, (char *)work + 512);
   if (bytes < w.bytes + 512) return MMF_ERR_WORKSPACE;
   DcProb *pr = reinterpret_cast<DcProb *>(work);
-  const DcProb q = dc_prob(n, d, e, Z, ldz, info, w);
+  const DcProb q = dc_prob(n, d, e, Z, ldz, info, w, lim);
   const int rc = table_write(pr, &q, 1, st);
   if (rc) return rc;
   return stedc_grouped(pr, &n, 1, st);

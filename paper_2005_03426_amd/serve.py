@@ -57,7 +57,7 @@ class Request:
 
 class Executor:
     def __init__(self, slots: int = 4, hbm_budget: int | None = None, device: str = "cuda",
-                 keep_eigenvectors: bool = False, max_batch: int = 64):
+                 max_batch: int = 64):
         import torch
         self.torch = torch
         self.device = device
@@ -67,7 +67,6 @@ class Executor:
             free, _total = torch.cuda.mem_get_info()
             hbm_budget = int(0.8 * free)
         self.budget = hbm_budget
-        self.keep_vectors = keep_eigenvectors
         self._lock = threading.Condition()
         self._in_use = 0
         self._pending: list[Request] = []
@@ -98,11 +97,9 @@ class Executor:
             for r, dp, w, Pt, inf in zip(reqs, dps, ws, Pts, infos):
                 tt = torch.as_tensor(np.asarray(r.times, dtype=np.float64), device=self.device)
                 U = evolve(dp, Pt, w, r.t0, tt, stream=stream)
-                P = avg_prob(dp, Pt, stream=stream)
-                res = {"w": w, "U": U, "P": P, "info": inf, "M": dp.M}
-                if self.keep_vectors:
-                    res["Pt"] = Pt
-                out.append(res)
+                P, pstat = avg_prob(dp, Pt, w, stream=stream)
+                # results keep no M x M buffer, so a finished request frees its whole footprint
+                out.append({"w": w, "U": U, "P": P, "P_status": pstat, "info": inf, "M": dp.M})
         stream.synchronize()
         return out
 

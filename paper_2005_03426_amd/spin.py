@@ -1,4 +1,4 @@
-"""Problem builders for spin systems (Sec. 3.3 of the paper: the spin
+"""Problem builders for spin systems (Sec. 3.4 of the paper: the spin
 couplings of Eq. 7 and the two-spin dipole system).
 
 These build the *inputs* of a Floquet problem -- the D x D matrices E and

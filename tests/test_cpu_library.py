@@ -181,3 +181,56 @@ def test_eigh_window_argument_checks_host_only():
     assert call(work=None) == -11
     assert call(nb=16) == -12
     assert call(info=None) == -13
+
+
+def test_build_floquet_rejects_non_hermitian_E_host_only():
+    """E is host memory in the problem statement and is validated before
+    anything is enqueued: an imaginary diagonal entry or an off-diagonal pair
+    that is not conjugate makes the problem invalid (-1)."""
+    import paper_2005_03426_amd as mmf
+    from paper_2005_03426_amd._lib import MMFProblem
+    L = mmf.lib()
+    omega = np.array([1.1]); N = np.array([2], np.int32)
+    axis = np.array([0], np.int32); harm = np.array([1], np.int32)
+    V = np.zeros((1, 2, 2), np.complex128)
+    d = C.c_void_p(16)                          # never dereferenced on these paths
+
+    def rc(E):
+        Ec = np.ascontiguousarray(E.T.astype(np.complex128))
+        p = MMFProblem(2, 1, 1, omega.ctypes.data, N.ctypes.data, axis.ctypes.data, harm.ctypes.data,
+                       Ec.ctypes.data, V.ctypes.data)
+        b = C.c_size_t(0)
+        assert L.mmf_build_floquet_workspace(C.byref(p), C.byref(b)) == 0 and b.value == 2 * 4 * 16
+        return L.mmf_build_floquet(C.byref(p), d, C.c_int64(10), d, C.c_size_t(b.value), None)
+    assert rc(np.array([[0.5, 0.1 + 0.2j], [0.1 - 0.2j, -0.5]])) != -1      # Hermitian: passes the check
+    assert rc(np.array([[0.5 + 1e-9j, 0.0], [0.0, -0.5]])) == -1           # complex diagonal
+    assert rc(np.array([[0.5, 0.1 + 0.2j], [0.1 + 0.2j, -0.5]])) == -1     # not conjugate
+    assert rc(np.array([[0.5, 0.1], [0.1 + 1e-12, -0.5]])) == -1           # asymmetric beyond 1e-14
+    assert rc(np.array([[0.5, 0.1], [0.1 + 1e-16, -0.5]])) != -1           # within 1e-14 max|E|
+    assert rc(np.array([[np.nan, 0.0], [0.0, -0.5]])) == -1
+
+
+def test_avg_prob_argument_checks_host_only():
+    import paper_2005_03426_amd as mmf
+    from paper_2005_03426_amd._lib import MMFProblem
+    L = mmf.lib()
+    omega = np.array([1.1]); N = np.array([3], np.int32)
+    axis = np.array([0], np.int32); harm = np.array([1], np.int32)
+    E = np.eye(2, dtype=np.complex128); V = np.zeros((1, 2, 2), np.complex128)
+    p = MMFProblem(2, 1, 1, omega.ctypes.data, N.ctypes.data, axis.ctypes.data, harm.ctypes.data,
+                   E.ctypes.data, V.ctypes.data)
+    b = C.c_size_t(0)
+    assert L.mmf_avg_prob_workspace(C.byref(p), C.byref(b)) == 0 and b.value >= 14 * 4 * 8
+    d = C.c_void_p(16)
+
+    def call(Phi=d, ld=14, w=d, P=d, st=d, work=d, nb=None):
+        return L.mmf_avg_prob(C.byref(p), Phi, C.c_int64(ld), w, P, st, work,
+                              C.c_size_t(b.value if nb is None else nb), None)
+    assert call(Phi=None) == -2
+    assert call(ld=13) == -3
+    assert call(w=None) == -4
+    assert call(P=None) == -5
+    assert call(st=None) == -6
+    assert call(work=None) == -7
+    assert call(nb=b.value - 1) == -8
+    assert L.mmf_strerror(7).decode().startswith("averaged probabilities")

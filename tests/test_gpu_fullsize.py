@@ -22,7 +22,7 @@ def _solve(mmf, torch, dp, tt, t0, prec):
     HF = mmf.build_floquet(dp)
     w, Pt, info = mmf.eigh(HF, prec)
     U = mmf.evolve(dp, Pt, w, t0, tt)
-    P = mmf.avg_prob(dp, Pt)
+    P, _ = mmf.avg_prob(dp, Pt, w)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
     return w, Pt, U, P

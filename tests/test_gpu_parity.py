@@ -72,8 +72,48 @@ def test_avg_prob_on_oracle_eigenvectors(mk):
     p = mk()
     H, w, Phi = _oracle_solve(p)
     dp = mmf.DeviceProblem(p)
-    P = mmf.avg_prob(dp, to_dev_cm(torch, Phi))
+    P, st = mmf.avg_prob(dp, to_dev_cm(torch, Phi), torch.as_tensor(w, device="cuda"))
     torch.cuda.synchronize()
+    assert int(st.item()) == 0 and not oracle.avg_prob_degenerate(p, Phi, w)
+    np.testing.assert_allclose(P.cpu().numpy(), oracle.avg_prob(p, Phi), rtol=0, atol=1e-13)
+
+
+def _rot(Phi, a, b, theta=0.6):
+    R = Phi.copy()
+    c, s = math.cos(theta), math.sin(theta)
+    R[:, a] = c * Phi[:, a] + s * Phi[:, b]
+    R[:, b] = -s * Phi[:, a] + c * Phi[:, b]
+    return R
+
+
+@pytest.mark.parametrize("case", ["same_site", "same_site_rotated", "cross_site", "cross_site_rotated"])
+def test_avg_prob_degenerate_flag_matches_oracle(case):
+    """The device status of mmf_avg_prob against the oracle's degeneracy rule
+    on static problems with exactly degenerate quasienergies, in the pure
+    eigenbasis and with a degenerate pair mixed; P itself matches the oracle
+    on the same (flagged or not) eigenvectors."""
+    torch, mmf = require_gpu()
+    if case.startswith("same_site"):
+        p = Problem(E=np.diag([0.3, 0.3, -0.5]).astype(np.complex128), omega=[1.1], N=[2], axis=[0], harm=[1],
+                    V=[np.zeros((3, 3))])
+    else:
+        p = Problem(E=np.diag([0.0, 1.0]).astype(np.complex128), omega=[1.0], N=[3], axis=[0], harm=[1],
+                    V=[np.zeros((2, 2))])
+    H, w, Phi = _oracle_solve(p)
+    if case.endswith("rotated"):
+        D, s0 = p.D, oracle.zero_site(p.N)
+        row = np.argmax(np.abs(Phi) ** 2, axis=0)
+        # a degenerate pair whose second member sits on the zero site
+        b = int(np.nonzero(row == D * s0 + (0 if case.startswith("same") else 1))[0][0])
+        a = [k for k in range(len(w)) if k != b and abs(w[k] - w[b]) < 1e-12][0]
+        Phi = _rot(Phi, a, b)
+    expect = oracle.avg_prob_degenerate(p, Phi, w)
+    assert expect == (case != "cross_site")
+    dp = mmf.DeviceProblem(p)
+    P, st = mmf.avg_prob(dp, to_dev_cm(torch, Phi), torch.as_tensor(w, device="cuda"))
+    torch.cuda.synchronize()
+    log(f"avg_prob degeneracy {case}: status {int(st.item())}")
+    assert int(st.item()) == (mmf.MMF_ERR_DEGENERATE if expect else 0)
     np.testing.assert_allclose(P.cpu().numpy(), oracle.avg_prob(p, Phi), rtol=0, atol=1e-13)
 
 
@@ -300,8 +340,13 @@ def test_argument_errors():
     p = cfg1_tls()[0]
     dp = mmf.DeviceProblem(p)
     buf = torch.empty((dp.M, dp.M), dtype=torch.complex128, device="cuda")
-    assert L.mmf_build_floquet(dp.ref, C.c_void_p(buf.data_ptr()), C.c_int64(dp.M - 1), None) == -3
-    assert L.mmf_build_floquet(dp.ref, None, C.c_int64(dp.M), None) == -2
+    ev = C.c_void_p(dp.ev_work.data_ptr())
+    evn = C.c_size_t(dp.ev_work.numel())
+    assert L.mmf_build_floquet(dp.ref, C.c_void_p(buf.data_ptr()), C.c_int64(dp.M - 1), ev, evn, None) == -3
+    assert L.mmf_build_floquet(dp.ref, None, C.c_int64(dp.M), ev, evn, None) == -2
+    assert L.mmf_build_floquet(dp.ref, C.c_void_p(buf.data_ptr()), C.c_int64(dp.M), None, evn, None) == -4
+    assert L.mmf_build_floquet(dp.ref, C.c_void_p(buf.data_ptr()), C.c_int64(dp.M), ev, C.c_size_t(16),
+                               None) == -5
     w = torch.empty(dp.M, dtype=torch.float64, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     small = torch.empty(16, dtype=torch.uint8, device="cuda")

@@ -1,4 +1,4 @@
-"""GPU checks of the spin front end (Sec. 3.3).
+"""GPU checks of the spin front end (Sec. 3.4).
 
 * spin 1 and 3/2 in a circularly polarised drive: the Floquet states from the
   GPU window solve match the rotating-frame closed form m Omega_R (+ w/2 for

@@ -1,4 +1,4 @@
-"""Oracle pins for the driven-lattice quasienergy scan (Sec. 4.2, Eq. 8).
+"""Oracle pins for the driven-lattice quasienergy scan (Sec. 4.2, the unnumbered lattice Hamiltonian).
 
 The open chain's hopping phases t exp(i cos(2 pi m / D)) are a pure gauge
 (a diagonal unitary removes them bond by bond), so the static spectrum is

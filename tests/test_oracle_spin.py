@@ -1,4 +1,4 @@
-"""Oracle pins for the spin front end (Sec. 3.3: Eq. 7 and the two-spin
+"""Oracle pins for the spin front end (Sec. 3.4: Eq. 7 and the two-spin
 dipole system) and parity of the library's host-side builders with it.
 
 * angular-momentum algebra: [S_x, S_y] = i S_z (and cyclic), S^2 = s(s+1),

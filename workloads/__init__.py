@@ -117,7 +117,7 @@ def dressed_qubit(omega_P: float, Omega_X: float = 0.025, omega_D: float = 1.0, 
 
 def lattice_problem(omega: float, D: int = 256, V0: float = 0.25, t: float = 0.125, V: float = 0.0625,
                     phi: float = 0.0, N: int = 10) -> Problem:
-    """Driven 1-D lattice of Sec. 4.2 (Eq. 8): D sites (D/2 two-site cells)
+    """Driven 1-D lattice of Sec. 4.2 (its unnumbered lattice Hamiltonian): D sites (D/2 two-site cells)
     with on-site energies (-1)^m V0 (m = 1..D), static hopping
     t exp(i cos(2 pi m / D)) from site m+1 to site m, and a uniform hopping
     modulation V cos(omega t + phi) on every bond.  The drive's Fourier
