@@ -17,7 +17,8 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (lib, call, check, MMFProblem, MMFEighOpts, MMFError, EXPORTED, LIB_PATH, MMF_ERR_DEGENERATE,
-                   MMF_C128, MMF_C64_REFINED, MMF_C64_RAW)
+                   MMF_C128, MMF_C64_REFINED, MMF_C64_RAW, MMF_OK, MMF_ERR_HIP, MMF_ERR_WORKSPACE,
+                   MMF_ERR_NOT_IMPLEMENTED, MMF_ERR_NO_CONVERGENCE, MMF_ERR_SELECTION, MMF_ERR_TOO_LARGE)
 
 __all__ = [
     "DeviceProblem", "floquet_dim", "build_floquet", "eigh", "eigh_workspace_bytes", "hetrd",

@@ -15,8 +15,10 @@
 //   X <- X Q, S <- Q^H S Q, G <- Q^H G Q, so that the corrections coupling a
 //   cluster to the rest use the Ritz values of its rotated vectors.
 // Clusters are runs of consecutive eigenvalues closer than
-//   delta = CL_FACTOR * max_{i!=j} |s_ij - lam_j g_ij|,
-// so that every first-order correction outside a cluster is below 1/CL_FACTOR.
+//   delta = max(CL_FACTOR * max_{i!=j} |s_ij - lam_j g_ij|, 1e7 eps max|lam| sqrt(n)),
+// so that every first-order correction outside a cluster is below 1/CL_FACTOR
+// and the rounding error of S, amplified by a small gap, cannot spoil the
+// orthogonality (second term).
 // Every pair inside one run takes r_ij / 2, whatever the run's length; the
 // Rayleigh-Ritz rotation works on chunks of at most CL_MAX consecutive members
 // of a run, and the chunk boundaries of runs longer than that move by CL_MAX/2
@@ -201,7 +203,13 @@ __global__ void rf_clusters(int64_t n, const double *lam, const double *colmax, 
   msml[0] = ms;
   msml[1] = ml;
   msml[2] = mr;
-  const double delta = CL_FACTOR * ms;
+  // A first-order correction e_ij = (s_ij - lam_j g_ij) / (lam_j - lam_i)
+  // carries the rounding error of s_ij, eta ~ eps max|lam| sqrt(n), divided
+  // by the gap, and X (I + E) leaves |e|^2 in the orthogonality: pairs
+  // closer than eta sqrt(REF_SAFETY / CONV_TOL_R) are kept in a cluster
+  // (Rayleigh-Ritz rotation) so that this term stays below the tolerance.
+  const double eta = DBL_EPSILON * ml * sqrt((double)n);
+  const double delta = fmax(CL_FACTOR * ms, eta * sqrt(REF_SAFETY / CONV_TOL_R));
   *delta_out = delta;
   int32_t nc = 0, qoff = 0, lr = 0;
   int64_t start = 0;
