@@ -314,6 +314,22 @@ int mmf_avg_prob_workspace(const mmf_problem *p, size_t *bytes);
 int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w, double *P,
                  int32_t *dev_status, void *work, size_t work_bytes, void *stream);
 
+/* mmf_avg_prob without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  The partial sums and flags live in a 32 MiB array
+ * inside the library (one per GPU, allocated when the library's code is
+ * loaded on that GPU and held until the process ends); the call allocates and
+ * frees nothing.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.  Partials: min(2048, M) workgroups as in
+ * mmf_avg_prob when they fit in the array (D <= 45: results bitwise equal to
+ * mmf_avg_prob's), else 32 MiB / (8 D^2 + 4) of them (equal up to rounding).
+ * Arguments and status as mmf_avg_prob without work/work_bytes.
+ * Errors: -1 problem, -2 Phi, -3 ld, -4 w, -5 P, -6 dev_status NULL,
+ * MMF_ERR_TOO_LARGE if the partials cannot fit, MMF_ERR_HIP. */
+int mmf_avg_prob_noalloc(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w, double *P,
+                         int32_t *dev_status, void *stream);
+
 /* Benchmark instrumentation (not needed for computation).  mmf_ktimer_arm
  * starts recording HIP events around every launch of one kernel class on
  * the stream it is launched on, together with the algorithmic work of each

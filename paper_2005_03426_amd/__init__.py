@@ -400,6 +400,21 @@ def avg_prob(dp: DeviceProblem, Pt, w, work=None, status=None, stream=None):
     return P.T, status
 
 
+def avg_prob_noalloc(dp: DeviceProblem, Pt, w, P=None, status=None, stream=None):
+    """avg_prob through the entry point that allocates nothing (the
+    library's own fixed device array holds the partial sums).  P and status
+    may be passed in so that the call itself allocates nothing either."""
+    torch = _torch()
+    D = dp.D
+    if P is None:
+        P = torch.empty((D, D), dtype=torch.float64, device=Pt.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=Pt.device)
+    call("mmf_avg_prob_noalloc", dp.ref, _ptr(Pt), C.c_int64(Pt.stride(0)), _ptr(w), _ptr(P), _ptr(status),
+         _stream(stream))
+    return P.T, status
+
+
 def solve(problem, t, t0: float = 0.0, prec: int = MMF_C128, device="cuda"):
     """One Floquet solve: assemble -> eigh -> U at times t -> averaged P.
     Returns a dict of device tensors (w, Pt, U, P, info)."""

@@ -76,6 +76,8 @@ _SIGS = {
     "mmf_avg_prob_workspace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mmf_avg_prob": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_size_t, C.c_void_p]),
+    "mmf_avg_prob_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
     "mmf_eigh_two_stage_min": (C.c_int64, []),
     "mmf_ktimer_arm": (C.c_int, [C.c_char_p]),
     "mmf_ktimer_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -16,6 +16,7 @@
 // columns b > a with w_b - w_a <= 1e-8 max(1, |w_0|, |w_{M-1}|) (w ascending)
 // and counts the pairs with z_a z_b > 1e-20; a third kernel turns the counts
 // into the status word.
+#include <mutex>
 #include "common.h"
 #include "problem.h"
 
@@ -173,4 +174,58 @@ extern "C" int mmf_avg_prob(const mmf_problem *p, const mmf_z *Phi, int64_t ld, 
   if (!work) return -7;
   if (work_bytes < avgprob_ws_bytes(G, fp.D)) return -8;
   return avgprob_launch(fp, Phi, ld, w, P, dev_status, G, work, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Variant for callers that cannot allocate: the partials and flags live in a
+// fixed device array of this file (one copy per GPU, held until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address is looked up once per device and cached.
+namespace mmf {
+
+constexpr size_t AP_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[AP_SCRATCH_BYTES];
+
+constexpr int AP_MAX_DEVICES = 64;
+static std::mutex ap_scratch_mu;
+static void *ap_scratch_ptr[AP_MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on each device).  Returns MMF_OK or MMF_ERR_HIP.
+static int ap_scratch(void **out) {
+  int dev = 0;
+  MMF_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= AP_MAX_DEVICES) return MMF_ERR_HIP;
+  std::lock_guard<std::mutex> lock(ap_scratch_mu);
+  if (!ap_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    MMF_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return MMF_ERR_HIP;
+    ap_scratch_ptr[dev] = ptr;
+  }
+  *out = ap_scratch_ptr[dev];
+  return MMF_OK;
+}
+
+}  // namespace mmf
+
+extern "C" int mmf_avg_prob_noalloc(const mmf_problem *p, const mmf_z *Phi, int64_t ld, const double *w,
+                                    double *P, int32_t *dev_status, void *stream) {
+  FloqParams fp;
+  const int rc = problem_params_small_d(p, 1, &fp);
+  if (rc) return rc;
+  if (!Phi) return -2;
+  if (ld < fp.M) return -3;
+  if (!w) return -4;
+  if (!P) return -5;
+  if (!dev_status) return -6;
+  // as many partials as the workspace form uses when they fit, fewer otherwise
+  const size_t per_group = avgprob_ws_bytes(1, fp.D);
+  int64_t G = avgprob_groups(fp.M);
+  if ((size_t)G * per_group > AP_SCRATCH_BYTES) G = (int64_t)(AP_SCRATCH_BYTES / per_group);
+  if (G < 1 || avgprob_ws_bytes((int)G, fp.D) > AP_SCRATCH_BYTES) return MMF_ERR_TOO_LARGE;
+  void *buf = nullptr;
+  const int src = ap_scratch(&buf);
+  if (src) return src;
+  return avgprob_launch(fp, Phi, ld, w, P, dev_status, (int)G, buf, (hipStream_t)stream);
 }
