@@ -29,6 +29,33 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
+# (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors a 1 GiB device
+# copy gives), with the sha256 prefixes of the sources that define the kernel
+# when they were taken: a changed kernel reports null.
+TRAFFIC = {
+    ("bt2", "ladder20808"): {
+        "bytes_per_launch": 2.0932e9 + 2.1287e9,
+        "sources": {"paper_2005_03426_amd/csrc/hb2st.hip": "566d8a4c05dd07b3",
+                    "paper_2005_03426_amd/csrc/twostage.h": "70bb0d4372819a69"},
+        "profile": "profiles/hbm_bytes_ladder20808_counters.md",
+    },
+}
+
+
+def counter_traffic(kernel, workload_name):
+    """Counter-measured HBM bytes per launch, or None if none were taken for
+    this (kernel, workload) or a defining source changed since."""
+    import hashlib
+    rec = TRAFFIC.get((kernel, workload_name))
+    if rec is None:
+        return None
+    for path, h in rec["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != h:
+                return None
+    return rec["bytes_per_launch"]
+
 
 def workload(name):
     from workloads import cfg1_tls, cfg2_large
@@ -532,7 +559,8 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
         tfs = per_launch_flops / (avg_ms / 1e3) / 1e12
         out["roofline"] = {
             "bound": "mfma", "achieved": tfs, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": tfs / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+            "frac": tfs / FP64_MFMA_PEAK_TFLOPS, "traffic": counter_traffic("bt2", name),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "kernel": "bt2_apply (back-transformation by the bulge-chasing reflectors: compact-WY groups "
                       "of 16 on the FP64 matrix cores; achieved counts the algorithmic flops, the kernel "
                       "executes 1.25 times as many)",
@@ -577,6 +605,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-ktimer", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--sync-every", type=int, default=0,
+                    help="profiling aid: the library waits for the device after every n launches")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--requests", type=int, default=200)
@@ -593,6 +623,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.sync_every:
+        mmf.call("mmf_profile_sync_every", C.c_int64(args.sync_every))
     if args.workload == "precision41616":
         run_precision(args, torch, mmf)
         return

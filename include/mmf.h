@@ -345,6 +345,14 @@ int mmf_avg_prob_noalloc(const mmf_problem *p, const mmf_z *Phi, int64_t ld, con
 int mmf_ktimer_arm(const char *kernel);
 int mmf_ktimer_read(int64_t *launches, double *total_ms, double *work);
 
+/* Profiling aid (not needed for computation): with n > 0 the library waits
+ * for the whole device (hipDeviceSynchronize) after every n of its kernel
+ * launches, so that at most n of its dispatches are pending at once -- for
+ * hardware-counter collection tools that cannot hold the tens of thousands
+ * of pending dispatches one eigensolve enqueues.  n <= 0 turns it off (the
+ * default).  Process-wide; never fails. */
+int mmf_profile_sync_every(int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ _SIGS = {
     "mmf_eigh_two_stage_min": (C.c_int64, []),
     "mmf_ktimer_arm": (C.c_int, [C.c_char_p]),
     "mmf_ktimer_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mmf_profile_sync_every": (C.c_int, [C.c_int64]),
 }
 
 EXPORTED = tuple(_SIGS.keys())

@@ -11,11 +11,21 @@
     if (_e != hipSuccess) return MMF_ERR_HIP;               \
   } while (0)
 
-#define MMF_LAUNCH_CHECK() MMF_HIP_TRY(hipGetLastError())
+namespace mmf {
+// After every kernel launch: nonzero if the launch failed.  With the opt-in
+// profiling throttle (mmf_profile_sync_every) it also waits for the device
+// every n launches.
+int launch_check();
+}  // namespace mmf
+
+#define MMF_LAUNCH_CHECK()                                  \
+  do {                                                      \
+    if (mmf::launch_check() != 0) return MMF_ERR_HIP;       \
+  } while (0)
 // the same with a clean-up statement before the error return
 #define MMF_LAUNCH_CHECK_OR(cleanup)                        \
   do {                                                      \
-    if (hipGetLastError() != hipSuccess) {                  \
+    if (mmf::launch_check() != 0) {                         \
       cleanup;                                              \
       return MMF_ERR_HIP;                                   \
     }                                                       \

@@ -1,5 +1,6 @@
 // Opt-in kernel timer (see ktimer.h) and its C-ABI controls.
 #include <string.h>
+#include <atomic>
 #include <vector>
 #include "ktimer.h"
 
@@ -16,6 +17,18 @@ struct Timer {
 Timer g_timer;
 constexpr size_t KT_MAX = 1 << 17;
 }  // namespace
+
+// profiling throttle: wait for the device after every g_sync_every launches
+std::atomic<int64_t> g_sync_every{0};
+std::atomic<int64_t> g_launches{0};
+
+int launch_check() {
+  if (hipGetLastError() != hipSuccess) return 1;
+  const int64_t every = g_sync_every.load(std::memory_order_relaxed);
+  if (every > 0 && (g_launches.fetch_add(1, std::memory_order_relaxed) + 1) % every == 0)
+    if (hipDeviceSynchronize() != hipSuccess) return 1;
+  return 0;
+}
 
 bool ktimer_armed(const char *name) { return g_timer.armed && strcmp(g_timer.name, name) == 0; }
 
@@ -71,5 +84,13 @@ extern "C" int mmf_ktimer_read(int64_t *launches, double *total_ms, double *work
   *launches = (int64_t)g_timer.used;
   *total_ms = t;
   *work = wsum;
+  return MMF_OK;
+}
+
+// Profiling aid: wait for the device after every n library launches (n <= 0
+// turns it off).
+extern "C" int mmf_profile_sync_every(int64_t n) {
+  g_sync_every.store(n > 0 ? n : 0);
+  g_launches.store(0);
   return MMF_OK;
 }
