@@ -236,6 +236,56 @@ def run_grouped_batch(args, torch, mmf):
     print(json.dumps(out), flush=True)
 
 
+def run_plan_bench(args, torch, mmf):
+    """A batch of solves as one BatchPlan: all device state resident, the
+    whole launch sequence recorded once as a graph and replayed per step.
+    Compared on the same GPU with the same plan launched eagerly and with the
+    small orders sent to the grouped path (tile table of zeros)."""
+    from paper_2005_03426_amd.batch import BatchPlan
+    from paper_2005_03426_amd import autotune
+    from workloads import cfg3_batch, cfg3_uniform_sweep
+    items = cfg3_uniform_sweep() if args.workload == "sweep512" else cfg3_batch()
+    probs = [p for p, _, _ in items]
+    times = [ts for _, ts, _ in items]
+    t0 = items[0][2]
+    tuned = autotune.load_table()
+    variants = [("graph_tuned", tuned, True), ("eager_tuned", tuned, False), ("graph_grouped_only", [0] * 8, True)]
+    runs = {}
+    sizes = None
+    for name, tiles, graph in variants:
+        plan = BatchPlan(probs, times, t0, tiles=tiles, graph=graph, group_max=args.group_max)
+        sizes = plan.sizes
+        for _ in range(args.warmup):
+            plan.run()
+        plan.synchronize()
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for _ in range(args.steps):
+            plan.run()
+        plan.synchronize()
+        wall = time.perf_counter() - t_a
+        bad = int(plan.info().ne(0).sum().item())
+        flops = sum((40.0 / 3.0) * float(m) ** 3 for m in sizes)
+        runs[name] = {"solves_per_s": len(probs) * args.steps / wall, "ms_per_batch": wall * 1e3 / args.steps,
+                      "eigh_tflops_nominal_over_batch": flops * args.steps / wall / 1e12, "failed": bad,
+                      "tiles": list(tiles) if tiles is not None else "library rule"}
+        print(f"[bench] {args.workload} {name}: {runs[name]}", file=sys.stderr, flush=True)
+        del plan
+        torch.cuda.empty_cache()
+    main_run = runs["graph_tuned"]
+    out = {
+        "metric": "Floquet eigensolves/s", "value": main_run["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_batch"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": args.workload, "requests": len(probs), "dims": f"{min(sizes)}..{max(sizes)}",
+                   "times": len(times[0]), "mode": "BatchPlan (recorded graph)"},
+        "runs": runs,
+        "graph_gain_vs_eager": runs["graph_tuned"]["solves_per_s"] / runs["eager_tuned"]["solves_per_s"],
+        "small_solver_gain_vs_grouped": runs["graph_tuned"]["solves_per_s"] / runs["graph_grouped_only"]["solves_per_s"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_lattice_sweep(args, torch, mmf):
     """Quasienergy scan of the driven lattice (D = 256, +-10, M = 5376) over
     64 drive frequencies in [0.2, 1]: every H_F assembled, then one grouped
@@ -609,9 +659,10 @@ def main():
                     help="profiling aid: the library waits for the device after every n launches")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--group-max", type=int, default=64, help="problems per grouped eigensolver call (BatchPlan)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--prec-only", default="")
-    ap.add_argument("--batch-mode", default="executor", choices=["grouped", "executor"])
+    ap.add_argument("--batch-mode", default="executor", choices=["grouped", "executor", "plan"])
     ap.add_argument("--prec", default="c128", choices=["c128", "c64_refined", "c64_raw"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -633,6 +684,9 @@ def main():
         return
     if args.workload == "lattice_sweep":
         run_lattice_sweep(args, torch, mmf)
+        return
+    if args.workload == "sweep512" or (args.workload == "batch512" and args.batch_mode == "plan"):
+        run_plan_bench(args, torch, mmf)
         return
     if args.workload == "batch512" and args.batch_mode == "grouped":
         run_grouped_batch(args, torch, mmf)

@@ -125,6 +125,47 @@ int mmf_build_floquet_workspace(const mmf_problem *p, size_t *bytes);
 int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, void *work, size_t work_bytes,
                       void *stream);
 
+/* mmf_build_floquet with E and V already on the device, laid out as its
+ * workspace holds them after a call (E, then V_k at offset (1 + k) D^2,
+ * column-major): no host copy is made, the call is one kernel launch (so it
+ * can be recorded in a HIP graph).  p is validated as by mmf_build_floquet,
+ * its host E included; EV is taken to hold the same matrices.
+ * Errors: -1 bad problem, -2 EV NULL, -3 HF NULL, -4 ldh < M, MMF_ERR_HIP. */
+int mmf_build_floquet_dev(const mmf_problem *p, const mmf_z *EV, mmf_z *HF, int64_t ldh, void *stream);
+
+/* Batches of small problems (parameter sweeps): the assembly, U(t, t0) and
+ * the averaged probabilities of `count` problems in a fixed number of launches
+ * whatever the count (a device table of the problems, written per call with
+ * kernel-argument launches of 14 entries each).  Problems: D <= 64, at most 4
+ * fundamentals and 8 couplings (MMF_ERR_TOO_LARGE otherwise).  Results equal
+ * the single calls' to rounding (other reduction order), not bitwise.
+ *
+ * Workspace bytes for both calls below (count problems, T times). */
+int mmf_batched_workspace(int64_t count, const mmf_problem *p, int32_t T, size_t *bytes);
+
+/* H_F of every problem c (Sec. 2, Eq. 6; as mmf_build_floquet_dev): p[c]
+ * host problem statements (E validated), EV[c] device copies of E and V in
+ * mmf_build_floquet's workspace layout, HF[c] dev M_c x M_c (ldh[c] >= M_c);
+ * EV, HF, ldh are host arrays [count].  work: at least count * 272 bytes of
+ * the mmf_batched_workspace size.
+ * Errors: -1 count < 0, -2 a bad problem, -3 EV, -4 HF, -5 ldh, -6/-7
+ * workspace NULL or too small, MMF_ERR_TOO_LARGE, MMF_ERR_HIP. */
+int mmf_build_floquet_batched(int64_t count, const mmf_problem *p, const mmf_z *const *EV, mmf_z *const *HF,
+                              const int64_t *ldh, void *work, size_t work_bytes, void *stream);
+
+/* U(t_q, t0) at T times per problem and the averaged transition
+ * probabilities (Eqs. 3-5; as mmf_evolve and mmf_avg_prob) for every problem
+ * c: Phi[c] eigenvectors (ld[c]), w[c] ascending eigenvalues, t[c] dev [T]
+ * times, U[c] dev [T][D*D], P[c] dev [D*D], dev_status [count] (0 or
+ * MMF_ERR_DEGENERATE, as mmf_avg_prob).  Host arrays of device pointers.
+ * D * T <= 2048.  work: mmf_batched_workspace(count, p, T) bytes.
+ * Errors: -1 count, -2 problem, -3 Phi, -4 ld, -5 w, -7 T < 1, -8 t, -9 U,
+ * -10 P, -11 dev_status, -12/-13 workspace, MMF_ERR_TOO_LARGE, MMF_ERR_HIP. */
+int mmf_observables_batched(int64_t count, const mmf_problem *p, const mmf_z *const *Phi, const int64_t *ld,
+                            const double *const *w, double t0, int32_t T, const double *const *t,
+                            mmf_z *const *U, double *const *P, int32_t *dev_status, void *work,
+                            size_t work_bytes, void *stream);
+
 /* Workspace bytes that mmf_eigh needs for an M x M problem at precision prec. */
 int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
 
@@ -135,7 +176,9 @@ int mmf_eigh_workspace(int64_t M, int prec, size_t *bytes);
  * w:   dev [M], eigenvalues in ascending order.
  * work/work_bytes: dev scratch of at least mmf_eigh_workspace() bytes.
  * dev_info: dev int32, set to 0 or to MMF_ERR_NO_CONVERGENCE by the kernels.
- * Method: Householder reduction to a real symmetric tridiagonal matrix,
+ * Method: order <= 64: one workgroup holding the matrix and its
+ * eigenvectors in LDS, parallel cyclic Jacobi (complex128).  Above that:
+ * Householder reduction to a real symmetric tridiagonal matrix,
  * Cuppen divide and conquer with Gu-Eisenstat eigenvector recomputation,
  * back-transformation.  Below order mmf_eigh_two_stage_min() the reduction is
  * one-stage (blocked, trailing updates and back-transformation on the FP64
@@ -195,6 +238,31 @@ int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t
 int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
                      double *const *w, int prec, void *work, size_t work_bytes,
                      int32_t *dev_info, void *stream);
+
+/* Tile table of the batched eigensolver, per order bucket b = (n - 1) / 8
+ * (orders 1-8, 9-16, ..., 57-64): the workgroup size (64, 128, 256 or 512
+ * threads) of the one-workgroup solver that keeps the whole matrix and its
+ * eigenvectors in LDS (parallel cyclic Jacobi), or 0 to send the bucket to
+ * the grouped Householder / divide-and-conquer path.  Written by the
+ * project's autotuner from measurements (paper_2005_03426_amd/autotune.py);
+ * without one the library uses 64 threads up to order 16, 128 up to 32 and
+ * 256 up to 64 (the same rule mmf_eigh applies to a single matrix of order
+ * <= 64). */
+typedef struct {
+  int32_t small_threads[8];
+} mmf_batch_opts;
+
+/* mmf_eigh_batched with a tile table (opts NULL: the built-in rule).
+ * complex128 problems whose bucket has a nonzero entry are solved by one
+ * persistent launch per workgroup size: its workgroups take problems from a
+ * device work queue (largest first), each with its matrix in LDS.  The
+ * eigenpairs agree with the other path's to rounding (not bitwise).
+ * Arguments as for mmf_eigh_batched with opts inserted after prec.
+ * Errors: as mmf_eigh_batched, with -7 an invalid table entry and the
+ * workspace, size and dev_info positions moved to -8, -9 and -10. */
+int mmf_eigh_batched_ex(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                        double *const *w, int prec, const mmf_batch_opts *opts, void *work, size_t work_bytes,
+                        int32_t *dev_info, void *stream);
 
 /* Workspace bytes of mmf_eigh_window for order M and at most kmax vectors. */
 int mmf_eigh_window_workspace(int64_t M, int64_t kmax, size_t *bytes);

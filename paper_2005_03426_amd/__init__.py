@@ -16,7 +16,7 @@ from __future__ import annotations
 import ctypes as C
 import numpy as np
 
-from ._lib import (lib, call, check, MMFProblem, MMFEighOpts, MMFError, EXPORTED, LIB_PATH, MMF_ERR_DEGENERATE,
+from ._lib import (lib, call, check, MMFProblem, MMFEighOpts, MMFBatchOpts, MMFError, EXPORTED, LIB_PATH, MMF_ERR_DEGENERATE,
                    MMF_C128, MMF_C64_REFINED, MMF_C64_RAW, MMF_OK, MMF_ERR_HIP, MMF_ERR_WORKSPACE,
                    MMF_ERR_NOT_IMPLEMENTED, MMF_ERR_NO_CONVERGENCE, MMF_ERR_SELECTION, MMF_ERR_TOO_LARGE)
 
@@ -75,6 +75,11 @@ class DeviceProblem:
         b = C.c_size_t(0)
         call("mmf_build_floquet_workspace", self.ref, C.byref(b))
         self.ev_work = _workspace(b.value, device)
+        # the device copy of E and V in the workspace's layout (E, then each
+        # V_k, column-major), for mmf_build_floquet_dev
+        ev = [self.E.ravel()] + ([self.V.ravel()] if self.K else [])
+        ev = np.ascontiguousarray(np.concatenate(ev)).view(np.uint8)
+        self.ev_work[:ev.size].copy_(torch.from_numpy(ev))
         S = self.M // self.D
         s0, stride = 0, 1
         for n in self.N:
@@ -101,6 +106,14 @@ def build_floquet(dp: DeviceProblem, out=None, stream=None):
         out = torch.empty((M, M), dtype=torch.complex128, device=dp.device)
     call("mmf_build_floquet", dp.ref, _ptr(out), C.c_int64(out.stride(0)), _ptr(dp.ev_work),
          C.c_size_t(dp.ev_work.numel()), _stream(stream))
+    return out
+
+
+def build_floquet_dev(dp: DeviceProblem, out, stream=None):
+    """H_F from the device copy of E and V held by dp (one kernel launch, no
+    host copy: usable under stream capture).  out: preallocated (M, M)
+    complex128 tensor, H_F = out.T."""
+    call("mmf_build_floquet_dev", dp.ref, _ptr(dp.ev_work), _ptr(out), C.c_int64(out.stride(0)), _stream(stream))
     return out
 
 
@@ -152,11 +165,14 @@ def eigh_batched_workspace_bytes(sizes, prec: int = MMF_C128) -> int:
     return int(b.value)
 
 
-def eigh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stream=None):
+def eigh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stream=None, tiles=None):
     """In-place eigendecomposition of every Hermitian matrix of the list
     `mats` (column-major like eigh's argument) in one grouped call.  Returns
     (ws, mats, info): eigenvalue tensors, the matrices now holding the
-    eigenvectors (row a = eigenvector a), and a device int32 [count]."""
+    eigenvectors (row a = eigenvector a), and a device int32 [count].
+    `tiles`: the 8-entry tile table of mmf_batch_opts (workgroup size of the
+    one-workgroup solver per order bucket, 0 = grouped path), e.g. from
+    autotune.load_table(); None keeps the library's built-in rule."""
     torch = _torch()
     count = len(mats)
     if count == 0:
@@ -173,8 +189,13 @@ def eigh_batched(mats, prec: int = MMF_C128, ws=None, work=None, info=None, stre
     ld = (C.c_int64 * count)(*[int(A.stride(0)) if m else 1 for A, m in zip(mats, sizes)])
     Ap = (C.c_void_p * count)(*[A.data_ptr() for A in mats])
     wp = (C.c_void_p * count)(*[w.data_ptr() for w in ws])
-    call("mmf_eigh_batched", C.c_int64(count), n, Ap, ld, wp, C.c_int(prec), _ptr(work),
-         C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    if tiles is None:
+        call("mmf_eigh_batched", C.c_int64(count), n, Ap, ld, wp, C.c_int(prec), _ptr(work),
+             C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    else:
+        opts = MMFBatchOpts((C.c_int32 * 8)(*[int(x) for x in tiles]))
+        call("mmf_eigh_batched_ex", C.c_int64(count), n, Ap, ld, wp, C.c_int(prec), C.byref(opts), _ptr(work),
+             C.c_size_t(work.numel()), _ptr(info), _stream(stream))
     return ws, mats, info
 
 
@@ -293,12 +314,14 @@ def unmtr(Vt, tau, Zt, out=None, work=None, stream=None):
     return out
 
 
-def evolve(dp: DeviceProblem, Pt, w, t0: float, t, work=None, stream=None):
-    """U(t, t0) for every time in t (device float64).  Returns U[tau, i, j]."""
+def evolve(dp: DeviceProblem, Pt, w, t0: float, t, work=None, stream=None, out=None):
+    """U(t, t0) for every time in t (device float64).  Returns U[tau, i, j]
+    (a transposed view of `out`, a preallocated (T, D, D) complex128 tensor
+    if given)."""
     torch = _torch()
     T = int(t.shape[0])
     D = dp.D
-    U = torch.empty((T, D, D), dtype=torch.complex128, device=Pt.device)
+    U = out if out is not None else torch.empty((T, D, D), dtype=torch.complex128, device=Pt.device)
     if work is None:
         b = C.c_size_t(0)
         call("mmf_evolve_workspace", dp.ref, C.c_int32(T), C.byref(b))
@@ -381,14 +404,15 @@ def dressed_evolution(problem, dressing_axes, t, t0: float = 0.0, prec: int = MM
             "info": info, "selection_info": minfo}
 
 
-def avg_prob(dp: DeviceProblem, Pt, w, work=None, status=None, stream=None):
+def avg_prob(dp: DeviceProblem, Pt, w, work=None, status=None, stream=None, out=None):
     """Averaged transition probabilities P[i, j] (i final, j initial) from
     the eigenvectors (rows of Pt) and their ascending eigenvalues w.  Returns
     (P, status): status is a device int32, MMF_ERR_DEGENERATE when degenerate
-    quasienergies share weight (P then depends on the eigenvector basis)."""
+    quasienergies share weight (P then depends on the eigenvector basis).
+    out: optional preallocated (D, D) float64 tensor (P is its transpose)."""
     torch = _torch()
     D = dp.D
-    P = torch.empty((D, D), dtype=torch.float64, device=Pt.device)
+    P = out if out is not None else torch.empty((D, D), dtype=torch.float64, device=Pt.device)
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=Pt.device)
     if work is None:

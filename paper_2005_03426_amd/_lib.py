@@ -31,6 +31,10 @@ class MMFEighOpts(C.Structure):
                 ("leaf_max_iters", C.c_int32)]
 
 
+class MMFBatchOpts(C.Structure):
+    _fields_ = [("small_threads", C.c_int32 * 8)]
+
+
 class MMFError(RuntimeError):
     def __init__(self, fn, code, msg):
         super().__init__(f"{fn} returned {code}: {msg}")
@@ -44,6 +48,13 @@ _SIGS = {
     "mmf_floquet_dim": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mmf_build_floquet_workspace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mmf_build_floquet": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "mmf_build_floquet_dev": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "mmf_batched_workspace": (C.c_int, [C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    "mmf_build_floquet_batched": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_size_t, C.c_void_p]),
+    "mmf_observables_batched": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_size_t, C.c_void_p]),
     "mmf_eigh_workspace": (C.c_int, [C.c_int64, C.c_int, C.c_void_p]),
     "mmf_eigh": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p,
                            C.c_size_t, C.c_void_p, C.c_void_p]),
@@ -52,6 +63,8 @@ _SIGS = {
     "mmf_eigh_batched_workspace": (C.c_int, [C.c_int64, C.c_void_p, C.c_int, C.c_void_p]),
     "mmf_eigh_batched": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                    C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "mmf_eigh_batched_ex": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "mmf_eigh_window_workspace": (C.c_int, [C.c_int64, C.c_int64, C.c_void_p]),
     "mmf_eigh_window": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,

@@ -12,13 +12,19 @@
 // across the workgroup, so its mixed-radix digits are scalar work.
 #include "common.h"
 #include "problem.h"
+#include "batch.h"
 
 namespace mmf {
 
 constexpr int ASM_ROWS = 256;    // rows per workgroup
 constexpr int ASM_COLS = 32;     // columns per workgroup
 
-__device__ inline void decode_site(const FloqParams &fp, int64_t s, int32_t *n) {
+// The routines below read the problem's sizes, truncations, frequencies and
+// coupling table through any parameter block PT with the fields of
+// FloqParams (D, F, K, M, N[], radix[], omega[], axis[], harm[]), so the
+// single and the batched assembly share one body.
+template <class PT>
+__device__ inline void decode_site(const PT &fp, int64_t s, int32_t *n) {
   for (int l = 0; l < MAX_F; ++l) {
     if (l >= fp.F) break;
     const int64_t q = s % fp.radix[l];
@@ -32,7 +38,8 @@ __device__ inline void decode_site(const FloqParams &fp, int64_t s, int32_t *n) 
 // unfused also where the function is inlined), in the same order as the CPU
 // definition.  (Inlined: a call would take the address of the by-value
 // parameter block and make every thread copy it to scratch memory.)
-__device__ inline double diag_shift(double e, const FloqParams &fp, const int32_t *n) {
+template <class PT>
+__device__ inline double diag_shift(double e, const PT &fp, const int32_t *n) {
 #pragma clang fp contract(off)
   double x = e;
   for (int l = 0; l < MAX_F; ++l) {
@@ -43,12 +50,10 @@ __device__ inline double diag_shift(double e, const FloqParams &fp, const int32_
   return x;
 }
 
-__global__ void __launch_bounds__(ASM_ROWS)
-assemble_kernel(FloqParams fp, const mmf_z *__restrict__ E, const mmf_z *__restrict__ V,
-                mmf_z *__restrict__ HF, int64_t ldh) {
-  const int64_t r = (int64_t)blockIdx.x * ASM_ROWS + threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * ASM_COLS;
-  if (r >= fp.M) return;
+// Row r, columns c0 .. c0 + ASM_COLS - 1 of H_F (r < M, c0 < M).
+template <class PT>
+__device__ inline void assemble_strip(const PT &fp, const mmf_z *__restrict__ E, const mmf_z *__restrict__ V,
+                                      mmf_z *__restrict__ HF, int64_t ldh, int64_t r, int64_t c0) {
   const int D = fp.D;
   const int i = (int)(r % D);
   const int64_t sr = r / D;
@@ -99,6 +104,36 @@ assemble_kernel(FloqParams fp, const mmf_z *__restrict__ E, const mmf_z *__restr
   }
 }
 
+__global__ void __launch_bounds__(ASM_ROWS)
+assemble_kernel(FloqParams fp, const mmf_z *__restrict__ E, const mmf_z *__restrict__ V,
+                mmf_z *__restrict__ HF, int64_t ldh) {
+  const int64_t r = (int64_t)blockIdx.x * ASM_ROWS + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * ASM_COLS;
+  if (r >= fp.M) return;
+  assemble_strip(fp, E, V, HF, ldh, r, c0);
+}
+
+// Batched assembly: problem blockIdx.z from the device table (its E and V
+// from the staged copy EV: E, then V_k at offset (1 + k) D^2).
+__global__ void __launch_bounds__(ASM_ROWS) assemble_batched(const BEnt *__restrict__ tab) {
+  const BEnt &fp = tab[blockIdx.z];
+  const int64_t r = (int64_t)blockIdx.x * ASM_ROWS + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * ASM_COLS;
+  if (r >= fp.M || c0 >= fp.M) return;
+  const mmf_z *E = reinterpret_cast<const mmf_z *>(fp.EV);
+  assemble_strip(fp, E, E + (int64_t)fp.D * fp.D, reinterpret_cast<mmf_z *>(fp.HF), fp.ld, r, c0);
+}
+
+int assemble_batched_launch(const BEnt *tab, int64_t count, int64_t Mmax, hipStream_t st) {
+  for (int64_t z0 = 0; z0 < count; z0 += 65535) {
+    const int64_t zc = count - z0 < 65535 ? count - z0 : 65535;
+    hipLaunchKernelGGL(assemble_batched, dim3(cdiv(Mmax, ASM_ROWS), cdiv(Mmax, ASM_COLS), (unsigned)zc),
+                       dim3(ASM_ROWS), 0, st, tab + z0);
+    MMF_LAUNCH_CHECK();
+  }
+  return MMF_OK;
+}
+
 }  // namespace mmf
 
 using namespace mmf;
@@ -144,6 +179,21 @@ extern "C" int mmf_build_floquet(const mmf_problem *p, mmf_z *HF, int64_t ldh, v
   if (fp.K > 0) MMF_HIP_TRY(hipMemcpyAsync(Vd, p->V, dd * fp.K, hipMemcpyHostToDevice, st));
   dim3 grid(cdiv(fp.M, ASM_ROWS), cdiv(fp.M, ASM_COLS));
   hipLaunchKernelGGL(assemble_kernel, grid, dim3(ASM_ROWS), 0, st, fp, Ed, Vd, HF, ldh);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+extern "C" int mmf_build_floquet_dev(const mmf_problem *p, const mmf_z *EV, mmf_z *HF, int64_t ldh, void *stream) {
+  FloqParams fp;
+  const int rc = problem_params(p, 1, &fp);
+  if (rc) return rc;
+  if (!problem_hermitian(p)) return -1;
+  if (!EV) return -2;
+  if (!HF) return -3;
+  if (ldh < fp.M) return -4;
+  dim3 grid(cdiv(fp.M, ASM_ROWS), cdiv(fp.M, ASM_COLS));
+  hipLaunchKernelGGL(assemble_kernel, grid, dim3(ASM_ROWS), 0, (hipStream_t)stream, fp, EV,
+                     EV + (size_t)fp.D * fp.D, HF, ldh);
   MMF_LAUNCH_CHECK();
   return MMF_OK;
 }

@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <vector>
 #include "common.h"
+#include "small.h"
 #include "stages.h"
 #include "twostage.h"
 
@@ -190,6 +191,12 @@ static int eigh_dispatch(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, 
   EighWs ws = eigh_ws(M, work, work_bytes);
   if (work_bytes < ws.bytes) return -7;
   if (M == 0) return MMF_OK;
+  if (M <= SMALL_NMAX && ws.rest_bytes >= small_table_bytes(1)) {
+    // one workgroup with the matrix in LDS (Jacobi)
+    const SmallProb pr = {M, lda, A, w, dev_info};
+    const int32_t th = small_default_threads(M);
+    return eigh_small_batched(1, &pr, &th, ws.rest, st);
+  }
   int rc = hetrd_run(M, A, lda, w, ws.e, ws.tau, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;
   rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
@@ -247,9 +254,39 @@ extern "C" int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int p
   return MMF_OK;
 }
 
+// threads of the one-workgroup solver for order n (0: grouped path)
+static int32_t small_threads_for(int64_t n, const mmf_batch_opts *opts) {
+  if (n < 1 || n > SMALL_NMAX) return 0;
+  if (!opts) return small_default_threads(n);
+  return opts->small_threads[(n - 1) / 8];
+}
+
+static int eigh_batched_run(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                            double *const *w, int prec, const mmf_batch_opts *opts, void *work, size_t work_bytes,
+                            int32_t *dev_info, void *stream);
+
 extern "C" int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
                                 double *const *w, int prec, void *work, size_t work_bytes, int32_t *dev_info,
                                 void *stream) {
+  return eigh_batched_run(count, n, A, lda, w, prec, nullptr, work, work_bytes, dev_info, stream);
+}
+
+extern "C" int mmf_eigh_batched_ex(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                                   double *const *w, int prec, const mmf_batch_opts *opts, void *work,
+                                   size_t work_bytes, int32_t *dev_info, void *stream) {
+  if (opts) {
+    for (int b = 0; b < 8; ++b) {
+      const int32_t t = opts->small_threads[b];
+      if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512) return -7;
+    }
+  }
+  const int rc = eigh_batched_run(count, n, A, lda, w, prec, opts, work, work_bytes, dev_info, stream);
+  return rc <= -7 ? rc - 1 : rc;                  // work, work_bytes and dev_info sit one position later
+}
+
+static int eigh_batched_run(int64_t count, const int64_t *n, mmf_z *const *A, const int64_t *lda,
+                            double *const *w, int prec, const mmf_batch_opts *opts, void *work, size_t work_bytes,
+                            int32_t *dev_info, void *stream) {
   if (count < 0) return -1;
   if (count == 0) return MMF_OK;
   if (!n) return -2;
@@ -280,8 +317,18 @@ extern "C" int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A
   std::vector<double *> wv;
   std::vector<void *> base;
   std::vector<int32_t *> info;
+  std::vector<SmallProb> small;
+  std::vector<int32_t> small_th;
   for (int64_t c = 0; c < count; ++c) {
     if (n[c] == 0) continue;
+    const int32_t th = prec == MMF_C128 ? small_threads_for(n[c], opts) : 0;
+    if (th) {
+      // one workgroup in LDS; its slot of the workspace stays unused
+      small.push_back(SmallProb{n[c], lda[c], A[c], w[c], dev_info + c});
+      small_th.push_back(th);
+      cur += align256(eigh_one_bytes(n[c], prec));
+      continue;
+    }
     nn.push_back(n[c]);
     ld.push_back(lda[c]);
     Av.push_back(A[c]);
@@ -289,6 +336,10 @@ extern "C" int mmf_eigh_batched(int64_t count, const int64_t *n, mmf_z *const *A
     base.push_back(cur);
     info.push_back(dev_info + c);
     cur += align256(eigh_one_bytes(n[c], prec));
+  }
+  if (!small.empty()) {
+    const int rc = eigh_small_batched((int64_t)small.size(), small.data(), small_th.data(), table, st);
+    if (rc) return rc;
   }
   const int64_t live = (int64_t)nn.size();
   for (int64_t g0 = 0; g0 < live; g0 += EIGH_GROUP_MAX) {

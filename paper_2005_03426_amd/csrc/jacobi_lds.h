@@ -11,15 +11,34 @@
 namespace mmf {
 
 constexpr int JAC_NMAX = 64;            // largest order (T and Q: 2 x 64 x 65 complex = 130 KiB of LDS)
-constexpr int JAC_LD = JAC_NMAX + 1;    // row stride of T and Q in LDS (padding against bank conflicts)
+constexpr int JAC_LD = JAC_NMAX + 1;    // row stride of T and Q for the largest order
 
-struct JacobiLds {
-  cd T[JAC_NMAX * JAC_LD];              // T[r * JAC_LD + c]
-  cd Q[JAC_NMAX * JAC_LD];
-  double rot[JAC_NMAX / 2][4];          // per pair: c, s, Re ph, Im ph
-  int pair[JAC_NMAX / 2][2];
-  double red[2][16];
+// LDS of one solve: T and Q (n x n, row r at r * ld, ld >= n + 1 against bank
+// conflicts), the rotations of one step and a reduction scratch.
+struct JacView {
+  cd *T, *Q;
+  int ld;
+  double (*rot)[4];                     // per pair: c, s, Re ph, Im ph
+  int (*pair)[2];
+  double (*red)[16];                    // [2][16]
 };
+
+// Bytes of LDS a JacView of order n takes (laid out by jac_view).
+__host__ __device__ constexpr size_t jac_lds_bytes(int n) {
+  return 2 * (size_t)n * (size_t)(n + 1) * sizeof(cd) + (size_t)(n / 2 + 1) * (4 * sizeof(double) + 2 * sizeof(int)) +
+         32 * sizeof(double) + 64;
+}
+
+__device__ inline JacView jac_view(char *lds, int nmax) {
+  JacView v;
+  v.ld = nmax + 1;
+  v.T = reinterpret_cast<cd *>(lds);
+  v.Q = v.T + (size_t)nmax * v.ld;
+  v.rot = reinterpret_cast<double (*)[4]>(v.Q + (size_t)nmax * v.ld);
+  v.red = reinterpret_cast<double (*)[16]>(&v.rot[nmax / 2 + 1][0]);
+  v.pair = reinterpret_cast<int (*)[2]>(&v.red[2][0]);
+  return v;
+}
 
 // Position j of the round-robin schedule at step r for m players (m even):
 // player 0 stays, the others rotate.
@@ -27,7 +46,7 @@ __device__ inline int jac_player(int j, int r, int m) { return j == 0 ? 0 : ((j 
 
 // Sum over the workgroup of two doubles (result valid in every thread).
 template <int NT>
-__device__ inline void jac_sum2(JacobiLds &L, double &a, double &b) {
+__device__ inline void jac_sum2(const JacView &L, double &a, double &b) {
   a = wave_sum(a);
   b = wave_sum(b);
   const int w = threadIdx.x >> 6;
@@ -42,26 +61,31 @@ __device__ inline void jac_sum2(JacobiLds &L, double &a, double &b) {
 
 // Diagonalises the Hermitian n x n matrix in L.T (n <= JAC_NMAX) and
 // accumulates the rotations into L.Q (which the caller initialises, e.g. to
-// the identity): on return T = Q0^H-rotated to diagonal, eigenvalues on the
-// diagonal of T (unsorted), eigenvectors in the columns of Q.  Stops when the
-// off-diagonal Frobenius norm is below 1e-16 of the total (or after
-// max_sweeps sweeps).  Every thread of the NT-thread workgroup calls it.
+// the identity): on return the eigenvalues are on the diagonal of T
+// (unsorted) and the eigenvectors in the columns of Q.  Sweeps until the
+// off-diagonal Frobenius norm is below 1e-16 of the total, at most max_sweeps
+// of them; returns whether it ended below (n eps)^2 of the total in squares
+// (eigenvalues then within about n eps ||T||).  Every thread of the NT-thread
+// workgroup calls it.
 template <int NT>
-__device__ void jacobi_herm_lds(JacobiLds &L, int n, int max_sweeps) {
+__device__ bool jacobi_herm_lds(const JacView &L, int n, int max_sweeps) {
   const int tid = threadIdx.x;
+  const int ld = L.ld;
   const int m = n + (n & 1);            // players; an odd n gets a dummy index n (skipped)
   const int np = m / 2;
+  double off = 0.0, tot = 0.0;
   __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, tot = 0.0;
+  for (int sweep = 0;; ++sweep) {
+    off = 0.0;
+    tot = 0.0;
     for (int e = tid; e < n * n; e += NT) {
       const int r = e / n, c = e % n;
-      const double v = cabs2(L.T[r * JAC_LD + c]);
+      const double v = cabs2(L.T[r * ld + c]);
       tot += v;
       if (r != c) off += v;
     }
     jac_sum2<NT>(L, off, tot);
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    if (off <= 1e-32 * tot || off == 0.0 || sweep == max_sweeps) break;
     for (int step = 0; step < m - 1; ++step) {
       // rotation of every pair of this step
       if (tid < np) {
@@ -69,12 +93,12 @@ __device__ void jacobi_herm_lds(JacobiLds &L, int n, int max_sweeps) {
         if (p > q) { const int t = p; p = q; q = t; }
         double cs = 1.0, sn = 0.0, phr = 1.0, phi = 0.0;
         if (q < n) {
-          const cd tpq = L.T[p * JAC_LD + q];
+          const cd tpq = L.T[p * ld + q];
           const double r = sqrt(cabs2(tpq));
           if (r > 0.0) {
             phr = tpq.re / r;
             phi = tpq.im / r;
-            const double theta = (L.T[q * JAC_LD + q].re - L.T[p * JAC_LD + p].re) / (2.0 * r);
+            const double theta = (L.T[q * ld + q].re - L.T[p * ld + p].re) / (2.0 * r);
             const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             cs = 1.0 / sqrt(t * t + 1.0);
             sn = t * cs;
@@ -97,14 +121,14 @@ __device__ void jacobi_herm_lds(JacobiLds &L, int n, int max_sweeps) {
         const cd phc = cmake(L.rot[j][2], -L.rot[j][3]);
         const cd j10 = cscale(phc, -sn), j11 = cscale(phc, cs);
         {
-          const cd tp = L.T[k * JAC_LD + p], tq = L.T[k * JAC_LD + q];
-          L.T[k * JAC_LD + p] = cadd(cscale(tp, cs), cmul(tq, j10));
-          L.T[k * JAC_LD + q] = cadd(cscale(tp, sn), cmul(tq, j11));
+          const cd tp = L.T[k * ld + p], tq = L.T[k * ld + q];
+          L.T[k * ld + p] = cadd(cscale(tp, cs), cmul(tq, j10));
+          L.T[k * ld + q] = cadd(cscale(tp, sn), cmul(tq, j11));
         }
         {
-          const cd qp = L.Q[k * JAC_LD + p], qq = L.Q[k * JAC_LD + q];
-          L.Q[k * JAC_LD + p] = cadd(cscale(qp, cs), cmul(qq, j10));
-          L.Q[k * JAC_LD + q] = cadd(cscale(qp, sn), cmul(qq, j11));
+          const cd qp = L.Q[k * ld + p], qq = L.Q[k * ld + q];
+          L.Q[k * ld + p] = cadd(cscale(qp, cs), cmul(qq, j10));
+          L.Q[k * ld + q] = cadd(cscale(qp, sn), cmul(qq, j11));
         }
       }
       __syncthreads();
@@ -115,21 +139,23 @@ __device__ void jacobi_herm_lds(JacobiLds &L, int n, int max_sweeps) {
         if (q >= n) continue;
         const double cs = L.rot[j][0], sn = L.rot[j][1];
         const cd ph = cmake(L.rot[j][2], L.rot[j][3]);
-        const cd tp = L.T[p * JAC_LD + k], tq = L.T[q * JAC_LD + k];
-        L.T[p * JAC_LD + k] = csub(cscale(tp, cs), cmul(cscale(ph, sn), tq));
-        L.T[q * JAC_LD + k] = cadd(cscale(tp, sn), cmul(cscale(ph, cs), tq));
+        const cd tp = L.T[p * ld + k], tq = L.T[q * ld + k];
+        L.T[p * ld + k] = csub(cscale(tp, cs), cmul(cscale(ph, sn), tq));
+        L.T[q * ld + k] = cadd(cscale(tp, sn), cmul(cscale(ph, cs), tq));
       }
       __syncthreads();
       if (tid < np) {
         const int p = L.pair[tid][0], q = L.pair[tid][1];
         if (q < n) {
-          L.T[p * JAC_LD + q] = cmake(0.0, 0.0);
-          L.T[q * JAC_LD + p] = cmake(0.0, 0.0);
+          L.T[p * ld + q] = cmake(0.0, 0.0);
+          L.T[q * ld + p] = cmake(0.0, 0.0);
         }
       }
       __syncthreads();
     }
   }
+  const double tol = (double)n * 2.220446049250313e-16;
+  return off <= tol * tol * tot;
 }
 
 }  // namespace mmf

@@ -282,7 +282,8 @@ __global__ void __launch_bounds__(256) rf_build_f(int64_t n, cd *S, const cd *G,
 __global__ void __launch_bounds__(256) rf_cluster_rr(int64_t n, const cd *S, const cd *G, const int32_t *clist,
                                                     const int32_t *ncl, cd *Qbuf, double *lam,
                                                     const int32_t *skip) {
-  __shared__ JacobiLds L;
+  __shared__ __align__(16) char lds[jac_lds_bytes(JAC_NMAX)];
+  const JacView L = jac_view(lds, JAC_NMAX);
   if (*skip) return;
   const int tid = threadIdx.x;
   const int nc = *ncl;

@@ -21,11 +21,12 @@ __global__ void table_set(T *dst, TableChunk<T, K> c) {
   if ((int)threadIdx.x < c.count) dst[threadIdx.x] = c.v[threadIdx.x];
 }
 
-// Writes host entries [0, count) into the device table, K entries per launch
-// (kernel arguments kept under 1 KiB).
-template <class T>
+// Writes host entries [0, count) into the device table, as many entries per
+// launch as fit in ARG_BYTES of kernel arguments (under 1 KiB by default;
+// large per-problem tables take up to 3840 bytes, below the 4 KiB limit).
+template <class T, int ARG_BYTES = 960>
 inline int table_write(T *dev, const T *host, int64_t count, hipStream_t st) {
-  constexpr int K = (960 / (int)sizeof(T)) > 0 ? (960 / (int)sizeof(T)) : 1;
+  constexpr int K = (ARG_BYTES / (int)sizeof(T)) > 0 ? (ARG_BYTES / (int)sizeof(T)) : 1;
   for (int64_t base = 0; base < count; base += K) {
     TableChunk<T, K> c;
     c.count = (int32_t)((count - base < K) ? count - base : K);
