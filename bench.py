@@ -121,7 +121,7 @@ def run_executor_bench(args, torch, mmf):
         items = [(0.0, p, ts, t0) for p, ts, t0 in cfg3_batch()]
         cfg = {"workload": "batch512", "requests": len(items), "dims": "22..1995", "times": 32}
     else:
-        items = cfg5_serving(R=args.requests)
+        items = cfg5_serving(R=args.requests or 2000)
         cfg = {"workload": "serve", "requests": len(items), "rate_per_s": 200.0, "dims": "50..12000",
                "times": 32}
     out_runs = {}
@@ -294,7 +294,7 @@ def run_lattice_sweep(args, torch, mmf):
     dev = "cuda"
     prec = {"c128": mmf.MMF_C128, "c64_raw": mmf.MMF_C64_RAW}.get(args.prec)
     assert prec is not None, "the eigenvalue-only scan runs in c128 or c64_raw"
-    probs = lattice_sweep(count=args.requests if args.requests != 200 else 64)
+    probs = lattice_sweep(count=args.requests or 64)
     dps = [mmf.DeviceProblem(p, dev) for p in probs]
     M = dps[0].M
     sizes = [dp.M for dp in dps]
@@ -660,7 +660,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--group-max", type=int, default=64, help="problems per grouped eigensolver call (BatchPlan)")
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=0, help="serve: requests (default 2000); lattice: frequencies (64)")
     ap.add_argument("--prec-only", default="")
     ap.add_argument("--batch-mode", default="executor", choices=["grouped", "executor", "plan"])
     ap.add_argument("--prec", default="c128", choices=["c128", "c64_refined", "c64_raw"])
