@@ -133,16 +133,27 @@ def run_executor_bench(args, torch, mmf):
             ex.run([serve.Request(rid=-1, arrival=0.0, problem=items[0][1], times=items[0][2], prec=prec)])
         reqs = [serve.Request(rid=k, arrival=a, problem=p, times=ts, t0=t0, prec=prec)
                 for k, (a, p, ts, t0) in enumerate(items)]
-        ex = serve.Executor(slots=args.slots, max_batch=args.max_batch)
+        step = max(1, len(reqs) // 20)
+        marks = {"next": step}
+
+        def progress(done, name=prec_name, total=len(reqs)):
+            # printed as batches of requests complete
+            if done >= marks["next"]:
+                marks["next"] = (done // step + 1) * step
+                print(f"[bench] {args.workload} {name}: {done}/{total} requests done", file=sys.stderr, flush=True)
+        ex = serve.Executor(slots=args.slots, max_batch=args.max_batch, progress=progress)
         torch.cuda.synchronize()
         t_a = time.perf_counter()
         done = ex.run(reqs)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_a
         st = serve.latency_stats(done)
-        bad = sum(int(r.result["info"].item()) != 0 for r in done)
+        failed = [(r.rid, int(r.result["M"]), int(r.problem.D), len(r.problem.N), int(r.result["info"].item()))
+                  for r in done if int(r.result["info"].item()) != 0]
+        bad = len(failed)
         flops = sum((40.0 / 3.0) * float(r.result["M"]) ** 3 for r in done)
         st.update({"wall_s": wall, "eigh_tflops": flops / wall / 1e12, "failed": bad,
+                   "failed_rid_M_D_F_info": failed[:64],
                    "rejected": len(ex.rejected), "batches": len(ex.batches),
                    "mean_batch": float(np.mean(ex.batches)) if ex.batches else 0.0})
         print(f"[bench] {args.workload} {prec_name}: {st}", file=sys.stderr, flush=True)
@@ -576,7 +587,10 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
         check["trace_rel"] = float(abs(w.sum().item() - torch.diagonal(Hm).real.sum().item()) / hn)
         check["colsum_P_max_dev"] = float((P.sum(dim=0) - 1.0).abs().max().item())
         Ud = U.conj().transpose(1, 2) @ U - torch.eye(D, dtype=U.dtype, device=dev)
-        check["unitarity_U_max_dev"] = float(Ud.abs().max().item())
+        # a truncation diagnostic, not a numerical error: U of a finite Fourier
+        # box is unitary only as the truncation converges (the oracle on the
+        # same ladder: 0.27, 0.10, 0.032, 0.012 at truncation 6, 8, 10, 12)
+        check["truncation_unitarity_defect_U"] = float(Ud.abs().max().item())
         del H, R, G
 
     value = steps / elapsed

@@ -43,6 +43,7 @@ __all__ = [
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
     "zero_site", "tridiag_eigh", "quasienergies", "restrict_modes", "dressed_evolution",
     "spin_ops", "spin_drive", "avg_prob_degenerate", "evolve_expm_sparse",
+    "build_floquet_sparse", "quasienergies_near",
 ]
 
 
@@ -187,6 +188,79 @@ def build_floquet(p) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Dense Hermitian eigensolve (the paper delegates it to LAPACK, Sec. 3.2)
 # ---------------------------------------------------------------------------
+def build_floquet_sparse(p):
+    """The same truncated H_F (Eq. 6 / App. A) as a SciPy CSR matrix, for
+    orders whose dense form would not fit the host comfortably.  The same
+    row-site loop as `build_floquet`: each row site's nonzero column sites
+    are itself (block E + n.w) and its neighbours at the couplings' offsets
+    +-h e_l (blocks V, V^H); every stored block entry is kept, zeros
+    included, so the values equal the dense form's entry for entry."""
+    from scipy.sparse import csr_matrix
+    n = sites(p.N)
+    S, F, D = n.shape[0], n.shape[1], p.D
+    M = D * S
+    index = {tuple(v): s for s, v in enumerate(n.tolist())}
+    offsets = [tuple([0] * F)]
+    for k in range(p.K):
+        for sgn in (+1, -1):
+            o = [0] * F
+            o[int(p.axis[k])] = sgn * int(p.harm[k])
+            if tuple(o) not in offsets:
+                offsets.append(tuple(o))
+    blocks = {o: _offset_block(p, o) for o in offsets}
+    ii = np.repeat(np.arange(D), D)
+    jj = np.tile(np.arange(D), D)
+    rows, cols, vals = [], [], []
+    for sr in range(S):
+        for o in offsets:
+            m = tuple(int(a) - b for a, b in zip(n[sr], o))   # delta = n - m = o
+            sc = index.get(m)
+            blk = blocks[o]
+            if sc is None or blk is None:
+                continue
+            blk = blk.copy()
+            if all(x == 0 for x in o):
+                for i in range(D):
+                    blk[i, i] = complex(_diag_shift(blk[i, i].real, n[sr], p.omega), blk[i, i].imag)
+            rows.append(D * sr + ii)
+            cols.append(D * sc + jj)
+            vals.append(blk.reshape(-1))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals).astype(np.complex128)
+    return csr_matrix((v, (r, c)), shape=(M, M))
+
+
+def quasienergies_near(H, sigma: float, k: int) -> np.ndarray:
+    """The k eigenvalues of the Hermitian (sparse) H_F closest to sigma,
+    ascending, for spot checks of spectra too large for a full
+    diagonalisation: shift-invert Arnoldi through SciPy's ARPACK interface,
+    the inverse of H_F - sigma I applied by LAPACK's banded LU (H_F is
+    banded: its nonzero blocks sit at most one coupling offset from the
+    diagonal in the site order)."""
+    from scipy.linalg import lapack
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    A = coo_matrix(H)
+    M = A.shape[0]
+    kl = int(max(0, (A.row - A.col).max()))
+    ku = int(max(0, (A.col - A.row).max()))
+    ab = np.zeros((2 * kl + ku + 1, M), dtype=np.complex128)
+    ab[kl + ku + A.row - A.col, A.col] = A.data
+    ab[kl + ku, :] -= sigma
+    lu, piv, info = lapack.zgbtrf(ab, kl, ku)
+    if info != 0:
+        raise ValueError(f"shift {sigma} is an eigenvalue to working precision (zgbtrf info {info})")
+
+    def solve(x):
+        y, inf = lapack.zgbtrs(lu, kl, ku, np.asarray(x, dtype=np.complex128).reshape(M, -1), piv)
+        return y
+
+    op = LinearOperator((M, M), matvec=solve, dtype=np.complex128)
+    w = eigsh(A.tocsr(), k=k, sigma=sigma, which="LM", OPinv=op, return_eigenvectors=False, tol=0.0)
+    return np.sort(np.asarray(w).real.astype(np.float64))
+
+
 def eigh(H: np.ndarray):
     """Eigenvalues (ascending) and orthonormal eigenvectors (columns) of the
     Hermitian H_F: LAPACK zheevd through NumPy, the library routine the

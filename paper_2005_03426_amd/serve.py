@@ -57,12 +57,13 @@ class Request:
 
 class Executor:
     def __init__(self, slots: int = 4, hbm_budget: int | None = None, device: str = "cuda",
-                 max_batch: int = 64):
+                 max_batch: int = 64, progress=None):
         import torch
         self.torch = torch
         self.device = device
         self.slots = slots
         self.max_batch = max(1, int(max_batch))
+        self.progress = progress          # optional callable(done_count), called as batches finish
         if hbm_budget is None:
             free, _total = torch.cuda.mem_get_info()
             hbm_budget = int(0.8 * free)
@@ -166,7 +167,10 @@ class Executor:
                         r.done = t_done
                         self._in_use -= r._fp
                         self._finished.append(r)
+                    done = len(self._finished)
                     self._lock.notify_all()
+                if self.progress is not None:
+                    self.progress(done)
 
     def _now(self) -> float:
         return time.perf_counter() - self._t0

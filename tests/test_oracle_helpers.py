@@ -220,3 +220,52 @@ def test_evolve_expm_sparse_matches_eigen_and_dense_routes():
     assert np.abs(Us - Ud).max() < 1e-12
     # U(t0, t0) is the identity exactly up to rounding
     np.testing.assert_allclose(Us[0], np.eye(3), atol=1e-14)
+
+
+# ------------------------------------------------ sparse assembly, spot spectra
+@pytest.mark.parametrize("case", ["one_axis", "two_axes", "three_axes_harmonic", "duplicate_coupling"])
+def test_build_floquet_sparse_equals_dense_definition(case):
+    """The sparse assembly stores exactly the dense assembly's entries (which
+    the Appendix-A layout and the closed forms pin), including a second
+    harmonic and two couplings on the same (axis, h), summed."""
+    from workloads import random_problem
+    if case == "one_axis":
+        p = random_problem(3, (7,), seed=21)
+    elif case == "two_axes":
+        p = random_problem(4, (3, 2), seed=22)
+    elif case == "three_axes_harmonic":
+        p = random_problem(2, (2, 3, 1), seed=23, harmonics=[(0, 1), (1, 1), (2, 1), (0, 2)])
+    else:
+        p = random_problem(3, (4, 2), seed=24, harmonics=[(0, 1), (1, 1), (0, 1)])
+    Hs = oracle.build_floquet_sparse(p)
+    assert Hs.shape == (oracle.floquet_dim(p),) * 2
+    assert np.array_equal(Hs.toarray(), oracle.build_floquet(p))
+
+
+def test_quasienergies_near_static_closed_form():
+    """Undriven problem: the quasienergies are E_i + n . w exactly, so the k
+    closest to a shift are known in closed form."""
+    E = np.diag([0.0, 0.37, 1.3]).astype(np.complex128)
+    w = np.array([1.0, math.sqrt(2.0)])
+    N = [6, 5]
+    p = Problem(E=E, omega=w, N=N, axis=[0, 1], harm=[1, 1], V=[np.zeros((3, 3)), np.zeros((3, 3))])
+    Hs = oracle.build_floquet_sparse(p)
+    n0, n1 = np.meshgrid(np.arange(-6, 7), np.arange(-5, 6), indexing="ij")
+    all_eps = np.sort((np.diag(E).real[:, None] + (n0 * w[0] + n1 * w[1]).reshape(1, -1)).reshape(-1))
+    for sigma in (0.11, -2.9, 4.05):
+        got = oracle.quasienergies_near(Hs, sigma, 6)
+        ref = np.sort(all_eps[np.argsort(np.abs(all_eps - sigma))[:6]])
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+
+
+def test_quasienergies_near_driven_against_lapack():
+    """Driven problem with non-Hermitian V: the shift-invert values equal the
+    k eigenvalues of LAPACK's full solve closest to the shift."""
+    from workloads import random_problem
+    p = random_problem(3, (6, 4), seed=11)
+    wl = np.linalg.eigvalsh(oracle.build_floquet(p))
+    Hs = oracle.build_floquet_sparse(p)
+    for sigma in (0.37, 2.2, -1.75):
+        got = oracle.quasienergies_near(Hs, sigma, 7)
+        ref = np.sort(wl[np.argsort(np.abs(wl - sigma))[:7]])
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
