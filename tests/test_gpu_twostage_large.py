@@ -7,10 +7,15 @@ The oracle's full eigendecomposition of this matrix takes minutes on the host,
 so the comparison uses the oracle's cheaper routes to the same quantities:
 every quasienergy against LAPACK's eigenvalue-only solver (1e-10 normwise),
 U(t, t0) at three times against the sparse action of exp(-i H_F t) on the zero
-Fourier block (no eigendecomposition at all, 1e-10), and for the averaged
-probabilities the identities that hold for any orthonormal eigenvector set
-(column sums 1 to 1e-12, entries in [0, 1]).
+Fourier block (no eigendecomposition at all, 1e-10), and the averaged
+probabilities against the oracle's table stored by
+tests/golden/make_ladder8712_pbar.py (1e-10; the oracle found no
+near-degenerate quasienergies sharing weight, so the table is unique), plus
+the identities that hold for any orthonormal eigenvector set (column sums 1
+to 1e-12, entries in [0, 1]).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -50,3 +55,11 @@ def test_two_stage_ladder_8712_against_oracle():
     assert err_u < 1e-10
     assert np.abs(P.sum(axis=0) - 1.0).max() < 1e-12
     assert P.min() >= -1e-14 and P.max() <= 1.0 + 1e-12
+    golden = os.path.join(os.path.dirname(__file__), "golden", "ladder8712_pbar.txt")
+    with open(golden) as f:
+        assert "degenerate_clusters_share_weight 0" in f.read()
+    Po = np.loadtxt(golden)
+    assert int(out["P_status"].item()) == 0
+    err_p = np.abs(P - Po).max()
+    log(f"  P against the stored oracle table: {err_p:.2e}")
+    assert err_p < 1e-10
