@@ -6,10 +6,15 @@ transition probabilities, with every input already resident in HBM.
 
 Default workload: 8-level ladder under two incommensurate drives
 (w = 1, golden ratio), truncation +-25 on both axes, Floquet dimension
-M = 20808 (complex128), U at 256 times.  Prints one JSON line.
+M = 20808 (complex128), U at 256 times; the default run also solves the
+16-level spectrum at M = 41616 once and times the CPU oracle on a bounded
+sample.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload ladder20808|tls82]
-                  [--no-cpu-baseline] [--profile-stage]
+  python bench.py [--steps K] [--warmup W] [--no-large] [--no-cpu-baseline]
+                  [--workload ladder20808|spec41616|tls82|ladder_N<n>|precision41616|
+                              sweep512|batch512|serve|lattice_sweep|window_lattice]
+                  [--batch-mode executor|grouped|plan] [--prec c128|c64_refined|c64_raw]
+                  [--sync-every N]   (launch throttle for rocprofv3 counter runs)
 """
 from __future__ import annotations
 
@@ -627,7 +632,8 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "kernel": "bt2_apply (back-transformation by the bulge-chasing reflectors: compact-WY groups "
                       "of 16 on the FP64 matrix cores; achieved counts the algorithmic flops, the kernel "
-                      "executes 1.25 times as many)",
+                      "executes 1.25 times as many in the usual count, forming each complex product from "
+                      "three real ones)",
             "launches": kt["launches"], "avg_launch_us": avg_ms * 1e3,
             "algorithmic_flops_per_launch": per_launch_flops,
             "share_of_step": kt["total_ms"] / (elapsed * 1e3),
@@ -644,9 +650,12 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
             "algorithmic_bytes_per_launch": per_launch_bytes,
             "share_of_step": kt["total_ms"] / (elapsed * 1e3),
         }
-    # the two-stage path executes (16/3 + 10 + 8) M^3 real flops (band reduction,
-    # stage-2 back-transformation with its zero triangles, stage-1
-    # back-transformation); the one-stage path the nominal (40/3) M^3
+    # the two-stage path executes (16/3 + 10 + 8) M^3 real flops in the usual
+    # count of four real products per complex one (band reduction, stage-2
+    # back-transformation with its zero triangles, stage-1 back-transformation;
+    # its GEMMs and the stage-2 kernel form each complex product from three
+    # real ones, which this count does not discount); the one-stage path the
+    # nominal (40/3) M^3
     exec_flops = (16.0 / 3.0 + 10.0 + 8.0) * M ** 3 if two_stage else eigh_flops
     out["eigh_executed_tflops"] = exec_flops / t_eigh / 1e12
     out["eigh_executed_frac_fp64_peak"] = out["eigh_executed_tflops"] / FP64_MFMA_PEAK_TFLOPS

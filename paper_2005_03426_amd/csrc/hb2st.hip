@@ -427,8 +427,10 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
   // V and V T of the four groups, zeros included, row rho / column i at
   // [g][rho][i ^ (rho % 16)]: both operand reads (16 consecutive columns of
   // one row, 16 consecutive rows of one column) then touch 16 distinct banks
-  __shared__ cd vg[BT2_NG][BT2_VR][BT2_NB];
-  __shared__ cd vt[BT2_NG][BT2_VR][BT2_NB];
+  // (one array, group-major: a group's V and V T lie within 40 KiB of each
+  // other, so that every operand read of a group is one address register
+  // plus an immediate offset)
+  __shared__ cd vv[BT2_NG][2][BT2_VR][BT2_NB];
   // this workgroup's share of the launch's (block, column tile) pairs, pair
   // b ntile + ct, split evenly over the workgroups: one segment per block it
   // reaches (at most two)
@@ -510,15 +512,18 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
 #pragma unroll
       for (int m = 0; m < NV; ++m) {
         const int f = tid + BT2_THREADS * m, j = f / BW, e = f % BW, g = j / BT2_NB, i = j % BT2_NB, rho = e + i;
-        vg[g][rho][i ^ (rho & 15)] = (s0 + j <= smax) ? vbuf[m] : cmake(0.0, 0.0);
+        vv[g][0][rho][i ^ (rho & 15)] = (s0 + j <= smax) ? vbuf[m] : cmake(0.0, 0.0);
       }
 #pragma unroll
-      for (int m = 0; m < NT; ++m) (&vt[0][0][0])[tid + BT2_THREADS * m] = tbuf[m];
+      for (int m = 0; m < NT; ++m) {
+        const int f = tid + BT2_THREADS * m, g = f / (BT2_VR * BT2_NB);
+        (&vv[g][1][0][0])[f % (BT2_VR * BT2_NB)] = tbuf[m];
+      }
     }
     for (int f = tid; f < BT2_NG * BT2_NB * BT2_NB; f += BT2_THREADS) {
       const int g = f / (BT2_NB * BT2_NB), i = (f / BT2_NB) % BT2_NB, m = f % BT2_NB;
       const int rho = m < i ? m : BW + m;         // the i slots above, 16 - i below
-      vg[g][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
+      vv[g][0][rho][i ^ (rho & 15)] = cmake(0.0, 0.0);
     }
     // the first window
     int64_t ct = ctb;
@@ -571,50 +576,93 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
         // fixes them.
         // W = V^H X: A operand of lane (q, li) = conj V[16 t + 4 r + q][li]
         // (tiles t = 2, 3, 4 first: in the first group of a column tile the
-        // others arrive last)
-        v4d wr = {0.0, 0.0, 0.0, 0.0}, wi = wr;
+        // others arrive last).  With V = a + i b and X = c + i d, three real
+        // products give both parts (Gauss's trick):
+        //   k1 = a^T (c + d),  k2 = (a - b)^T d,  k3 = (a + b)^T c,
+        //   Re W = a^T c + b^T d = k1 - k2,   Im W = a^T d - b^T c = k1 - k3.
+        // operand reads: group g's V at vq[gq + 16 rho + col], its V T 1280
+        // entries further (gq behind an empty asm statement, so that the
+        // compiler forms the group's addresses here instead of keeping all
+        // groups' addresses in registers across the loop)
+        int gq = g * (2 * BT2_VR * BT2_NB);
+        asm volatile("" : "+s"(gq));
+        const cd *vq = &vv[0][0][0][0];
+        v4d k1 = {0.0, 0.0, 0.0, 0.0}, k2 = k1, k3 = k1;
 #pragma unroll
         for (int tt = 0; tt < 5; ++tt) {
           const int t = (tt + 2) % 5;
+          double a[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int rho = 16 * t + 4 * r + q;
-            const cd v = vg[g][rho][li ^ (rho & 15)];
-            wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xr[g + t][r], wr, 0, 0, 0);
-            wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xi[g + t][r], wr, 0, 0, 0);
+            a[r] = vq[gq + 16 * rho + (li ^ (rho & 15))].re;
           }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            k1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], xr[g + t][r] + xi[g + t][r], k1, 0, 0, 0);
         }
-        asm volatile("" : "+v"(wr), "+v"(wi));
+        asm volatile("" : "+v"(k1), "+v"(k2) : : "memory");
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
+          cd v[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int rho = 16 * t + 4 * r + q;
-            const cd v = vg[g][rho][li ^ (rho & 15)];
-            wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.re, xi[g + t][r], wi, 0, 0, 0);
-            wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.im, xr[g + t][r], wi, 0, 0, MFMA_NEG_A);
+            v[r] = vq[gq + 16 * rho + (li ^ (rho & 15))];
           }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            k2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re - v[r].im, xi[g + t][r], k2, 0, 0, 0);
         }
-        asm volatile("" : "+v"(wi), "+v"(xr[g]));
+        asm volatile("" : "+v"(k2), "+v"(k3) : : "memory");
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          cd v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rho = 16 * t + 4 * r + q;
+            v[r] = vq[gq + 16 * rho + (li ^ (rho & 15))];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            k3 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re + v[r].im, xr[g + t][r], k3, 0, 0, 0);
+        }
+        asm volatile("" : "+v"(k3), "+v"(xr[g]) : : "memory");
         // X <- X - (V T) W: A operand of lane (q, li) = (V T)[16 t + li][4 r + q]
+        // = e + i f, B operand W = c + i d (c = k1 - k2, d = k1 - k3), again
+        // three real products per tile:
+        //   m1 = (e + f) c,  m2 = e (d - c),  m3 = f (c + d),
+        //   Re = m1 - m3,  Im = m1 + m2:  Xr += m3 - m1,  Xi -= m1 + m2.
+        // Two passes over the window: m1 (into a temporary) and m3 first, m2
+        // after, so that only two of c, c + d, d - c are live at a time.
+        v4d wc = k1 - k2, wcd = (k1 - k2) + (k1 - k3);
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
           const int u = g + t, rho = 16 * t + li;
           cd v[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = vt[g][rho][(4 * r + q) ^ li];
+          for (int r = 0; r < 4; ++r) v[r] = vq[gq + BT2_VR * BT2_NB + 16 * rho + ((4 * r + q) ^ li)];
+          v4d m1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wr[r], xr[u], 0, 0, MFMA_NEG_A);
-            xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wi[r], xr[u], 0, 0, 0);
-          }
-          asm volatile("" : "+v"(xr[u]), "+v"(xi[u]));
+          for (int r = 0; r < 4; ++r) m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re + v[r].im, wc[r], m1, 0, 0, 0);
+          asm volatile("" : "+v"(m1), "+v"(xr[u]));
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].re, wi[r], xi[u], 0, 0, MFMA_NEG_A);
-            xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wr[r], xi[u], 0, 0, MFMA_NEG_A);
-          }
-          if (t < 4) asm volatile("" : "+v"(xi[u]), "+v"(xr[u + 1]));
+          for (int r = 0; r < 4; ++r) xr[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[r].im, wcd[r], xr[u], 0, 0, 0);
+          xr[u] -= m1;
+          xi[u] -= m1;
+          if (t < 4) asm volatile("" : "+v"(xr[u]), "+v"(xr[u + 1]));
+        }
+        const v4d wdc = wcd - (wc + wc);
+        asm volatile("" : "+v"(xr[g + 4]), "+v"(xi[g]));
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const int u = g + t, rho = 16 * t + li;
+          double e[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) e[r] = vq[gq + BT2_VR * BT2_NB + 16 * rho + ((4 * r + q) ^ li)].re;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xi[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(e[r], wdc[r], xi[u], 0, 0, MFMA_NEG_A);
+          if (t < 4) asm volatile("" : "+v"(xi[u]), "+v"(xi[u + 1]));
         }
       }
       Pprev = P;
