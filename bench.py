@@ -157,8 +157,11 @@ def run_executor_bench(args, torch, mmf):
                   for r in done if int(r.result["info"].item()) != 0]
         bad = len(failed)
         flops = sum((40.0 / 3.0) * float(r.result["M"]) ** 3 for r in done)
+        retried = [(r.rid, int(r.result["M"]), int(r.problem.D), len(r.problem.N))
+                   for r in done if r.result.get("retried_c128")]
         st.update({"wall_s": wall, "eigh_tflops": flops / wall / 1e12, "failed": bad,
-                   "failed_rid_M_D_F_info": failed[:64],
+                   "failed_rid_M_D_F_info": failed[:64], "retried_c128": len(retried),
+                   "retried_rid_M_D_F": retried[:64],
                    "rejected": len(ex.rejected), "batches": len(ex.batches),
                    "mean_batch": float(np.mean(ex.batches)) if ex.batches else 0.0})
         print(f"[bench] {args.workload} {prec_name}: {st}", file=sys.stderr, flush=True)

@@ -12,7 +12,12 @@ solved with one grouped eigensolve (each kernel launch advances every matrix
 of the batch), then U(t) and the averaged P per request, all on the slot's
 stream; batches of different slots overlap on the GPU.  A request's result
 does not depend on the batch it joined (the grouped kernels do the same
-arithmetic per matrix as a single solve).  Results stay on the device until
+arithmetic per matrix as a single solve).  A request whose mixed-precision
+eigensolve reports non-convergence is solved again in complex128 on the
+same stream (its result then says `retried_c128`), unless the executor was
+made with retry_c128=False.  A batch whose workspace the caching allocator
+cannot place (fragmented free blocks) is solved one request at a time after
+the cache is returned.  Results stay on the device until
 the caller reads them.  Latency runs from a request's arrival to the moment
 its batch's stream has finished.  Every step runs in the library's kernels
 (libmmf.so); this module only schedules.
@@ -31,10 +36,14 @@ from . import (DeviceProblem, build_floquet, eigh, eigh_batched, evolve, avg_pro
 
 
 def footprint_bytes(M: int, D: int, T: int, prec: int = MMF_C128) -> int:
-    """HBM bytes a solve holds while in flight (matrix + workspaces + outputs)."""
+    """HBM bytes a solve holds while in flight (matrix + workspaces + outputs;
+    for a mixed-precision request also what its complex128 retry needs)."""
     S = M // D
     ev = T * S * 16 + T * D * M * 16 + ((M + 2047) // 2048) * T * D * D * 16
-    return 16 * M * M + eigh_workspace_bytes(M, prec) + ev + 8 * M + 16 * T * D * D + 4096
+    ws = eigh_workspace_bytes(M, prec)
+    if prec != MMF_C128:
+        ws = max(ws, eigh_workspace_bytes(M, MMF_C128))
+    return 16 * M * M + ws + ev + 8 * M + 16 * T * D * D + 4096
 
 
 @dataclass
@@ -57,9 +66,21 @@ class Request:
 
 class Executor:
     def __init__(self, slots: int = 4, hbm_budget: int | None = None, device: str = "cuda",
-                 max_batch: int = 64, progress=None):
+                 max_batch: int = 64, progress=None, retry_c128: bool = True, limits: dict | None = None):
+        """slots: streams (and worker threads); hbm_budget: bytes of admitted
+        footprints at once (default 0.8 of the free HBM); max_batch: requests
+        per grouped eigensolve; progress: callable(done_count) called as
+        batches finish; retry_c128: solve a mixed-precision request again in
+        complex128 when its eigensolve reports non-convergence; limits:
+        iteration limits of mmf_eigh_ex (e.g. {"refine_max_iters": 1}) to
+        force the failure handling from the host; with limits every request
+        is solved alone (the grouped eigensolver takes none)."""
         import torch
         self.torch = torch
+        self.retry_c128 = retry_c128
+        self.limits = limits
+        if limits is not None:
+            max_batch = 1
         self.device = device
         self.slots = slots
         self.max_batch = max(1, int(max_batch))
@@ -89,7 +110,7 @@ class Executor:
             dps = [DeviceProblem(r.problem, self.device) for r in reqs]
             HFs = [build_floquet(dp, stream=stream) for dp in dps]
             if len(reqs) == 1:
-                w, Pt, info = eigh(HFs[0], prec=reqs[0].prec, stream=stream)
+                w, Pt, info = eigh(HFs[0], prec=reqs[0].prec, stream=stream, limits=self.limits)
                 ws, Pts, infos = [w], [Pt], [info]
             else:
                 ws, Pts, info = eigh_batched(HFs, prec=reqs[0].prec, stream=stream)
@@ -101,7 +122,22 @@ class Executor:
                 P, pstat = avg_prob(dp, Pt, w, stream=stream)
                 # results keep no M x M buffer, so a finished request frees its whole footprint
                 out.append({"w": w, "U": U, "P": P, "P_status": pstat, "info": inf, "M": dp.M})
+            HFs = Pts = Pt = None         # the M x M buffers go before any retry allocates its own
         stream.synchronize()
+        if self.retry_c128 and reqs[0].prec != MMF_C128:
+            for k, (r, dp) in enumerate(zip(reqs, dps)):
+                if int(out[k]["info"].item()) == 0:
+                    continue
+                with torch.cuda.stream(stream):
+                    HF = build_floquet(dp, stream=stream)
+                    w, Pt, inf = eigh(HF, prec=MMF_C128, stream=stream)
+                    tt = torch.as_tensor(np.asarray(r.times, dtype=np.float64), device=self.device)
+                    U = evolve(dp, Pt, w, r.t0, tt, stream=stream)
+                    P, pstat = avg_prob(dp, Pt, w, stream=stream)
+                    out[k] = {"w": w, "U": U, "P": P, "P_status": pstat, "info": inf, "M": dp.M,
+                              "retried_c128": True}
+                    del HF, Pt
+                stream.synchronize()
         return out
 
     def _take(self, now: float) -> list[Request]:
@@ -152,7 +188,18 @@ class Executor:
                     r.admitted = t_adm
                 self.batches.append(len(reqs))
             try:
-                results = self._solve(reqs, stream)
+                results = None
+                try:
+                    results = self._solve(reqs, stream)
+                except torch.OutOfMemoryError:
+                    pass                          # (leaves the handler, so the failed frame's buffers go)
+                if results is None:
+                    # the admitted footprints fit the budget, but the caching
+                    # allocator's free blocks may be too fragmented for one
+                    # batch workspace: return them and solve one at a time
+                    stream.synchronize()
+                    torch.cuda.empty_cache()
+                    results = [self._solve([r], stream)[0] for r in reqs]
                 for r, res in zip(reqs, results):
                     r.result = res
             except BaseException as exc:          # surfaced by run()

@@ -57,3 +57,22 @@ def test_admission_rejects_oversized_and_respects_budget():
     assert len(done) == 3 and len(ex.rejected) == 1 and ex.rejected[0].problem is big
     for r in done:
         assert int(r.result["info"].item()) == 0
+
+
+def test_refined_non_convergence_is_solved_again_in_complex128():
+    """A mixed-precision request whose eigensolve reports non-convergence
+    (forced from the host: one refinement iteration) is solved again in
+    complex128: its result is then the plain complex128 result, bit for bit;
+    without the retry the status is reported as it is."""
+    torch, mmf = require_gpu()
+    from paper_2005_03426_amd import serve
+    p = [random_problem(3, (6, 2), seed=7)]
+    ex = serve.Executor(slots=1, limits={"refine_max_iters": 1}, retry_c128=False)
+    r0 = ex.run(_reqs(serve, p, [0.0], mmf.MMF_C64_REFINED))[0].result
+    assert int(r0["info"].item()) == mmf.MMF_ERR_NO_CONVERGENCE and "retried_c128" not in r0
+    ex = serve.Executor(slots=1, limits={"refine_max_iters": 1})
+    r1 = ex.run(_reqs(serve, p, [0.0], mmf.MMF_C64_REFINED))[0].result
+    assert r1.get("retried_c128") and int(r1["info"].item()) == 0
+    ref = serve.Executor(slots=1).run(_reqs(serve, p, [0.0], mmf.MMF_C128))[0].result
+    for k in ("w", "U", "P", "P_status"):
+        assert torch.equal(ref[k], r1[k]), k
