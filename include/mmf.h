@@ -79,7 +79,7 @@ enum {
   MMF_C64_REFINED = 1,   /* complex64 reduction/back-transform + FP64 refinement          */
   MMF_C64_RAW = 2        /* complex64 reduction/back-transform, no refinement             */
 };
-/* MMF_C64_REFINED iterates (at most six times) until max |s_ij - lam_j g_ij|
+/* MMF_C64_REFINED iterates (at most twelve times) until max |s_ij - lam_j g_ij|
  * <= 1e-13 max(1, max |lam|) and max |g_ij - delta_ij| <= 1e-12 for
  * S = X^H A X, G = X^H X; otherwise dev_info is set to MMF_ERR_NO_CONVERGENCE
  * and the last iterate is returned. */
@@ -195,7 +195,7 @@ int mmf_eigh(int64_t M, mmf_z *A, int64_t lda, double *w, int prec,
  * callers that need a different budget, and for testing the failure report:
  * a limit that is reached sets dev_info to MMF_ERR_NO_CONVERGENCE. */
 typedef struct {
-  int32_t refine_max_iters;   /* MMF_C64_REFINED refinement iterations, default 6, at most 64  */
+  int32_t refine_max_iters;   /* MMF_C64_REFINED refinement iterations, default 12, at most 64 */
   int32_t secular_max_iters;  /* divide and conquer: steps per secular-equation root, default
                                  200, at most 100000                                            */
   int32_t leaf_max_iters;     /* divide and conquer: implicit-QL steps per eigenvalue of a leaf,

@@ -12,7 +12,7 @@ constexpr size_t STAGE_TABLE_BYTES = 512;   // device bytes per problem of a sta
 // Iteration limits of the eigensolver's iterative parts (mmf_eigh_opts; the
 // defaults are what every other entry point uses).
 struct EighLimits {
-  int32_t refine_iters = 6;     // Ogita-Aishima refinement iterations (precision layer)
+  int32_t refine_iters = 12;    // Ogita-Aishima refinement iterations (precision layer)
   int32_t secular_iters = 200;  // secular-equation steps per root (divide and conquer)
   int32_t leaf_iters = 60;      // implicit-QL steps per eigenvalue in the D&C leaves
 };
