@@ -415,12 +415,20 @@ __global__ void __launch_bounds__(256) bt2_tgen(int64_t n, const cd *V2, const c
 //   W = V^H X    (16 x 16, k-step r of tile t contracts the rows 4 r .. 4 r + 3,
 //                 i.e. element r of the window's registers is the B operand),
 //   X <- X - (V T) W  (element r of W is again the B operand),
-// complex products as four real MFMAs.  Tile g + 4 is then final (no later
+// complex products as three real MFMAs (below).  Tile g + 4 is then final (no later
 // group reaches it) and goes to HBM at the start of group g - 1, when tile
 // g - 2 is read for the group after.  The last group also reads tiles 5 .. 7
 // of the next column tile; the tiles 0 .. 4 left at the end go to HBM at the
 // start of the next column tile, whose tiles 3 and 4 are read then (its first
 // group contracts tiles 5 .. 7 first).
+// RM: Phi is stored row-major (element (r, c) at r ldphi + c) instead of
+// column-major.  A lane's reads are the same rows of its column either way,
+// but row-major the workgroup's 128 columns of one row are 2 KiB of
+// consecutive memory, where column-major each of them is a separate 256-byte
+// piece of a column (columns 16 ldphi bytes apart): measured without the
+// matrix-core work, the tile traffic of one launch takes 786 instead of
+// 1056 us at order 20808.
+template <bool RM>
 __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t nc, const cd *V2, const cd *Tws, cd *Phi,
                                                           int64_t ldphi, int64_t Gmax, int64_t step, int64_t Gb,
                                                           int64_t cnt, int64_t ntile, cd *sink) {
@@ -459,7 +467,7 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
     auto colp = [&](int64_t ct, bool &ok) {
       const int64_t col = ct * BT2_TILE + wave * 16 + li;
       ok = col < nc;
-      return Phi + R0 + (ok ? col : 0) * ldphi;
+      return RM ? Phi + R0 * ldphi + (ok ? col : 0) : Phi + R0 + (ok ? col : 0) * ldphi;
     };
 
     // Rows past the block's end (row >= Lr) and the columns of idle lanes are
@@ -472,6 +480,8 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
     // are then formed where they are used instead of being kept in registers
     // across the loop)
     int Lv = Lr;
+    int ldv = (int)ldphi;                             // row stride when RM (< 2^23, so row offsets fit
+                                                      // 32 bits), laundered like Lv
     v4d xr[8], xi[8];
     auto load_tile = [&](const cd *P, int u) {
 #pragma unroll
@@ -480,15 +490,20 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
         const int ir = 2 * (row < Lv ? row : Lv - 1);
         int ii = ir + 1;
         asm volatile("" : "+v"(ii));                 // keep the two loads apart
-        xr[u][r] = reinterpret_cast<const double *>(P)[ir];
-        xi[u][r] = reinterpret_cast<const double *>(P)[ii];
+        if (RM) {
+          xr[u][r] = reinterpret_cast<const double *>(P)[ir * ldv];
+          xi[u][r] = reinterpret_cast<const double *>(P)[ir * ldv + 1];
+        } else {
+          xr[u][r] = reinterpret_cast<const double *>(P)[ir];
+          xi[u][r] = reinterpret_cast<const double *>(P)[ii];
+        }
       }
     };
     auto store_tile = [&](cd *P, bool ok, int u) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * u + 4 * r + q;
-        *((ok && row < Lv) ? P + row : sink) = cmake(xr[u][r], xi[u][r]);
+        *((ok && row < Lv) ? P + (RM ? row * ldv : row) : sink) = cmake(xr[u][r], xi[u][r]);
       }
     };
 
@@ -536,7 +551,7 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
     cd *Pprev = P;
     bool okprev = ok;
     for (bool first = true;; first = false) {
-      asm volatile("" : "+s"(Lv));
+      asm volatile("" : "+s"(Lv), "+s"(ldv));
       const int64_t ctn = ct + 1;
       const bool more = ctn < cte;                   // uniform
       bool okn;
@@ -678,6 +693,51 @@ __global__ void __launch_bounds__(BT2_THREADS, 1) bt2_apply(int64_t n, int64_t n
   }
 }
 
+// Phi = Z stored row-major (Phi[r ldphi + c] = Z[r + c ldz]), through 32 x 32
+// tiles in LDS so that both the reads of Z and the writes of Phi are whole
+// rows of the tile.
+__global__ void __launch_bounds__(256) bt2_init_rm(int64_t n, const double *Z, int64_t ldz, cd *Phi, int64_t ldphi) {
+  __shared__ double t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + tx, c = c0 + j;
+    t[j][tx] = (r < n && c < n) ? Z[r + c * ldz] : 0.0;          // t[c][r]
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < n && c < n) Phi[r * ldphi + c] = cmake(t[tx][i], 0.0);
+  }
+}
+
+// In-place transpose of the n x n complex matrix at Phi (ld ldphi): workgroup
+// (I, J) with I <= J exchanges the 32 x 32 tiles (I, J) and (J, I) through
+// LDS (a diagonal tile is transposed onto itself); workgroups with I > J do
+// nothing, so every element is moved by exactly one workgroup.
+__global__ void __launch_bounds__(256) bt2_transpose(int64_t n, cd *Phi, int64_t ldphi) {
+  __shared__ cd a[32][33], b[32][33];
+  const int64_t I = blockIdx.x, J = blockIdx.y;
+  if (I > J) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t ri = I * 32, cj = J * 32;
+  for (int k = ty; k < 32; k += 8) {
+    // a = tile (I, J) read along its columns' rows: element (ri + tx, cj + k)
+    const int64_t r = ri + tx, c = cj + k;
+    a[k][tx] = (r < n && c < n) ? Phi[r + c * ldphi] : cmake(0.0, 0.0);
+    const int64_t r2 = cj + tx, c2 = ri + k;                  // b = tile (J, I)
+    b[k][tx] = (r2 < n && c2 < n) ? Phi[r2 + c2 * ldphi] : cmake(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    // tile (I, J) <- tile (J, I)^T: element (ri + tx, cj + k) = old (cj + k, ri + tx) = b[tx][k]
+    const int64_t r = ri + tx, c = cj + k;
+    if (r < n && c < n) Phi[r + c * ldphi] = b[tx][k];
+    const int64_t r2 = cj + tx, c2 = ri + k;
+    if (I != J && r2 < n && c2 < n) Phi[r2 + c2 * ldphi] = a[tx][k];
+  }
+}
+
 __global__ void bt2_init(int64_t n, int64_t nc, const double *Z, int64_t ldz, cd *Phi, int64_t ldphi) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -695,7 +755,13 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
   const cd *V2 = reinterpret_cast<const cd *>(V2z);
   const cd *tau2 = reinterpret_cast<const cd *>(tau2z);
   cd *Phi = reinterpret_cast<cd *>(Phiz);
-  if (Z) {
+  // the whole square back-transformation runs on a row-major copy (set from Z,
+  // transposed back in place at the end); a column window stays column-major
+  const bool rm = Z != nullptr && nc == n && n >= 2 && ldphi < (1 << 23);
+  if (rm) {
+    hipLaunchKernelGGL(bt2_init_rm, dim3(cdiv(n, 32), cdiv(n, 32)), dim3(256), 0, st, n, Z, ldz, Phi, ldphi);
+    MMF_LAUNCH_CHECK();
+  } else if (Z) {
     hipLaunchKernelGGL(bt2_init, dim3(cdiv(n, 256), cdiv(nc, 64)), dim3(256), 0, st, n, nc, Z, ldz, Phi, ldphi);
     MMF_LAUNCH_CHECK();
   }
@@ -719,8 +785,12 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
       // cnt * ntile (block, column tile) pairs spread evenly over them
       const int64_t pairs = cnt * (int64_t)ntile;
       const unsigned nwg = (unsigned)(pairs < BT2_SLOTS ? pairs : BT2_SLOTS);
-      hipLaunchKernelGGL(bt2_apply, dim3(nwg), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi, Gmax, step,
-                         Gb, cnt, (int64_t)ntile, sink);
+      if (rm)
+        hipLaunchKernelGGL(bt2_apply<true>, dim3(nwg), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi, Gmax,
+                           step, Gb, cnt, (int64_t)ntile, sink);
+      else
+        hipLaunchKernelGGL(bt2_apply<false>, dim3(nwg), dim3(BT2_THREADS), 0, st, n, nc, V2, Tws, Phi, ldphi, Gmax,
+                           step, Gb, cnt, (int64_t)ntile, sink);
       MMF_LAUNCH_CHECK();
       if (ks >= 0) {
         // algorithmic flops: v^H x and x -= v f, 8 real flops per complex
@@ -737,6 +807,11 @@ int bt2_run(int64_t n, int64_t nc, const mmf_z *V2z, const mmf_z *tau2z, const d
         ktimer_end(ks, st, fl);
       }
     }
+  }
+  if (rm) {
+    const unsigned nt = cdiv(n, 32);
+    hipLaunchKernelGGL(bt2_transpose, dim3(nt, nt), dim3(256), 0, st, n, Phi, ldphi);
+    MMF_LAUNCH_CHECK();
   }
   return MMF_OK;
 }
