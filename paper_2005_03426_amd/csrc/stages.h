@@ -6,7 +6,7 @@
 namespace mmf {
 
 constexpr int HT_NB = 32;        // Householder panel width of the reduction
-constexpr int BT_NB = 128;       // reflectors per block of the back-transformation (two halves of 64)
+constexpr int BT_NB = 128;       // reflectors per block of the back-transformation (two quarters of 64)
 constexpr size_t STAGE_TABLE_BYTES = 512;   // device bytes per problem of a stage's batch table
 
 // Iteration limits of the eigensolver's iterative parts (mmf_eigh_opts; the
