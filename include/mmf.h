@@ -210,7 +210,7 @@ int mmf_eigh_ex(int64_t M, mmf_z *A, int64_t lda, double *w, int prec, const mmf
                 void *work, size_t work_bytes, int32_t *dev_info, void *stream);
 
 /* Order from which mmf_eigh and mmf_eigh_window take the two-stage reduction
- * (default 6400, the measured crossover; the environment variable
+ * (default 5888, the measured crossover; the environment variable
  * MMF_EIGH_TWO_STAGE_MIN, read at every call, overrides it and also the
  * eigenvalue-only thresholds of mmf_eigvalsh_batched).  Query the workspace
  * size and call the solver under the same setting.  Host-only, never fails. */

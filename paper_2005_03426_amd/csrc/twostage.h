@@ -15,10 +15,10 @@ constexpr int BT2_G = 64;         // sweeps per block of the second back-transfo
 // column, the two-stage one runs almost all of its reduction flops on the
 // matrix cores but adds 2 n sequential chase steps and (with eigenvectors) a
 // second back-transformation.  Measured crossovers on MI355X: full
-// eigensolve ~6.3k; eigenvalues only ~4.6k for one matrix, ~1.2k for a batch
+// eigensolve ~5.9k; eigenvalues only ~4.6k for one matrix, ~1.2k for a batch
 // of 8 (the chase steps of all problems share each launch).  The environment
 // variable MMF_EIGH_TWO_STAGE_MIN overrides every default.
-constexpr int64_t TWO_STAGE_MIN_DEFAULT = 6400;
+constexpr int64_t TWO_STAGE_MIN_DEFAULT = 5888;
 constexpr int64_t EV_TWO_STAGE_MIN_ONE = 4608;     // eigenvalues only, few problems
 constexpr int64_t EV_TWO_STAGE_MIN_BATCH = 1280;   // eigenvalues only, >= EV_TWO_STAGE_BATCH such problems
 constexpr int64_t EV_TWO_STAGE_BATCH = 8;

@@ -1,7 +1,7 @@
 """GPU parity of the two-stage eigensolver (dense -> band -> real tridiagonal
 by bulge chasing, then the two back-transformations) against the oracle.
 
-mmf_eigh takes this path from order MMF_EIGH_TWO_STAGE_MIN up (default 6400);
+mmf_eigh takes this path from order MMF_EIGH_TWO_STAGE_MIN up (default 5888);
 the tests lower the threshold to 0 so that small orders, which the oracle
 solves in milliseconds, exercise every edge of the band reduction: partial
 last panels, sweeps shorter than the bandwidth, single-element reflectors,
