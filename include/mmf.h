@@ -225,7 +225,10 @@ int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t
  * Floquet matrices of a parameter scan.  Problem c is exactly the mmf_eigh
  * problem (n[c], A[c], lda[c], w[c]) and gets the same result; the stages
  * run grouped, so each kernel launch advances every matrix of the batch
- * (sizes may differ; launches cover the largest).
+ * (sizes may differ; launches cover the largest).  Every problem takes the
+ * grouped one-stage path, also from mmf_eigh_two_stage_min() up (where the
+ * single call takes the two-stage path; the results then agree to rounding,
+ * not bit for bit).
  * n, lda: host arrays [count]; A, w: host arrays [count] of device pointers
  *   (A[c] n[c] x n[c] column-major, lower triangle read, eigenvectors on
  *   exit; w[c] eigenvalues ascending).  Problems with n[c] = 0 are skipped.

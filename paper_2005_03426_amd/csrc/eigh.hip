@@ -39,8 +39,21 @@ inline EighWs eigh_ws(int64_t M, void *base, size_t have) {
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// bytes of the two-stage full eigensolve's workspace (defined below)
+size_t eigh2_full_ws_bytes(int64_t M);
+
+// Batched calls could solve their complex128 problems from the two-stage
+// order up one by one on the two-stage path (as single calls do).  This is
+// switched off: the serving benchmark with it enabled ended in a GPU fault
+// whose cause has not been found; batched problems of every order take the
+// grouped one-stage path.
+constexpr bool BATCHED_TWO_STAGE = false;
+
+// one problem's slot in a batched call
 inline size_t eigh_one_bytes(int64_t M, int prec) {
-  return prec == MMF_C128 ? eigh_ws(M, nullptr, 0).bytes : eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED);
+  if (prec == MMF_C128)
+    return (BATCHED_TWO_STAGE && M >= two_stage_min()) ? eigh2_full_ws_bytes(M) : eigh_ws(M, nullptr, 0).bytes;
+  return eigh_c64_ws_bytes(M, prec == MMF_C64_REFINED);
 }
 
 // largest number of problems one grouped launch takes (grid z dimension)
@@ -141,6 +154,8 @@ inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh
   if (rc) return rc;
   return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
 }
+
+size_t eigh2_full_ws_bytes(int64_t M) { return eigh2_ws(M, M, false, nullptr).bytes; }
 
 inline int eigh2_run(int64_t M, mmf_z *A, int64_t lda, double *w, void *work, int32_t *dev_info, hipStream_t st,
                      const EighLimits &lim) {
@@ -319,8 +334,19 @@ static int eigh_batched_run(int64_t count, const int64_t *n, mmf_z *const *A, co
   std::vector<int32_t *> info;
   std::vector<SmallProb> small;
   std::vector<int32_t> small_th;
+  std::vector<int64_t> big;                           // complex128 problems for the two-stage path
+  std::vector<char *> big_base;
+  const int64_t ts_min = two_stage_min();
   for (int64_t c = 0; c < count; ++c) {
     if (n[c] == 0) continue;
+    if (BATCHED_TWO_STAGE && prec == MMF_C128 && n[c] >= ts_min) {
+      // solved alone by the two-stage path (each already fills the GPU; the
+      // single call takes the same path, so the results agree bit for bit)
+      big.push_back(c);
+      big_base.push_back(cur);
+      cur += align256(eigh_one_bytes(n[c], prec));
+      continue;
+    }
     const int32_t th = prec == MMF_C128 ? small_threads_for(n[c], opts) : 0;
     if (th) {
       // one workgroup in LDS; its slot of the workspace stays unused
@@ -339,6 +365,11 @@ static int eigh_batched_run(int64_t count, const int64_t *n, mmf_z *const *A, co
   }
   if (!small.empty()) {
     const int rc = eigh_small_batched((int64_t)small.size(), small.data(), small_th.data(), table, st);
+    if (rc) return rc;
+  }
+  for (size_t k = 0; k < big.size(); ++k) {
+    const int64_t c = big[k];
+    const int rc = eigh2_run(n[c], A[c], lda[c], w[c], big_base[k], dev_info + c, st, EighLimits());
     if (rc) return rc;
   }
   const int64_t live = (int64_t)nn.size();

@@ -99,3 +99,33 @@ def test_solve_batched_floquet_against_oracle():
         assert np.abs(out["U"].cpu().numpy() - Uo).max() < 1e-10
         Po = oracle.avg_prob(p, Phio)
         assert np.abs(out["P"].cpu().numpy() - Po).max() < 1e-10
+
+
+@pytest.mark.skip(reason="the batched two-stage path is switched off (BATCHED_TWO_STAGE in csrc/eigh.hip): the "
+                         "serving benchmark with it ended in a GPU fault whose cause has not been found")
+def test_batched_routes_large_orders_to_the_two_stage_path(monkeypatch):
+    """With the two-stage threshold lowered to 100, the batch's problems of
+    order >= 100 are solved one by one by the two-stage path inside the
+    batched call: bitwise equal to single calls under the same setting (which
+    take the two-stage path too), and against the oracle; the rest stay on
+    the grouped and one-workgroup paths."""
+    torch, mmf = require_gpu()
+    monkeypatch.setenv("MMF_EIGH_TWO_STAGE_MIN", "100")
+    assert mmf.eigh_two_stage_min() == 100
+    sizes = [40, 150, 99, 100, 257, 7]
+    Hs = [_hermitian(n, 900 + k) for k, n in enumerate(sizes)]
+    ws, Pts, info = mmf.eigh_batched([to_dev_cm(torch, H) for H in Hs])
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0] * len(sizes)
+    for H, w, Pt in zip(Hs, ws, Pts):
+        w1, P1, info1 = mmf.eigh(to_dev_cm(torch, H))
+        torch.cuda.synchronize()
+        assert int(info1.item()) == 0
+        assert torch.equal(w1, w) and torch.equal(P1, Pt)
+        wo, _ = oracle.eigh(H)
+        n = H.shape[0]
+        Phi = from_dev_cm(Pt)
+        assert np.abs(w.cpu().numpy() - wo).max() <= 1e-10 * max(1.0, np.abs(wo).max())
+        assert np.linalg.norm(H @ Phi - Phi * w.cpu().numpy()) <= 1e-12 * max(1.0, np.linalg.norm(H)) * n
+        assert np.abs(Phi.conj().T @ Phi - np.eye(n)).max() < 1e-12 * max(1, n)
+    log("batched: orders >= 100 through the two-stage path, bitwise equal to single calls")
