@@ -16,8 +16,8 @@ arithmetic per matrix as a single solve).  A request whose mixed-precision
 eigensolve reports non-convergence is solved again in complex128 on the
 same stream (its result then says `retried_c128`), unless the executor was
 made with retry_c128=False.  A batch whose workspace the caching allocator
-cannot place (fragmented free blocks) is solved one request at a time after
-the cache is returned.  Results stay on the device until
+cannot place (fragmented free blocks) is solved one request at a time.
+Results stay on the device until
 the caller reads them.  Latency runs from a request's arrival to the moment
 its batch's stream has finished.  Every step runs in the library's kernels
 (libmmf.so); this module only schedules.
@@ -122,8 +122,8 @@ class Executor:
                 P, pstat = avg_prob(dp, Pt, w, stream=stream)
                 # results keep no M x M buffer, so a finished request frees its whole footprint
                 out.append({"w": w, "U": U, "P": P, "P_status": pstat, "info": inf, "M": dp.M})
-            HFs = Pts = Pt = None         # the M x M buffers go before any retry allocates its own
         stream.synchronize()
+        HFs = Pts = Pt = None             # the M x M buffers go before any retry allocates its own
         if self.retry_c128 and reqs[0].prec != MMF_C128:
             for k, (r, dp) in enumerate(zip(reqs, dps)):
                 if int(out[k]["info"].item()) == 0:
@@ -196,9 +196,11 @@ class Executor:
                 if results is None:
                     # the admitted footprints fit the budget, but the caching
                     # allocator's free blocks may be too fragmented for one
-                    # batch workspace: return them and solve one at a time
+                    # batch workspace: solve one at a time (smaller pieces).
+                    # The cache is not returned to the driver here: other
+                    # slots' streams may still be using blocks that their
+                    # threads have already released to it.
                     stream.synchronize()
-                    torch.cuda.empty_cache()
                     results = [self._solve([r], stream)[0] for r in reqs]
                 for r, res in zip(reqs, results):
                     r.result = res
