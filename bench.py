@@ -692,7 +692,7 @@ def main():
     ap.add_argument("--prec", default="c128", choices=["c128", "c64_refined", "c64_raw"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
 
     import torch

@@ -89,7 +89,7 @@ enum {
   MMF_OK = 0,
   MMF_ERR_HIP = 1,             /* a HIP runtime call failed                               */
   MMF_ERR_WORKSPACE = 2,       /* workspace smaller than the size query returned         */
-  MMF_ERR_NOT_IMPLEMENTED = 3, /* option not available in this build                     */
+  MMF_ERR_NOT_IMPLEMENTED = 3, /* option not available in this library                   */
   MMF_ERR_NO_CONVERGENCE = 4,  /* device status: an iteration did not converge           */
   MMF_ERR_SELECTION = 5,       /* micromotion: not exactly D orbit representatives found */
   MMF_ERR_TOO_LARGE = 6,       /* size beyond what the library supports                   */
