@@ -31,7 +31,24 @@ int launch_check();
     }                                                       \
   } while (0)
 
+// Global-memory pointer.  A pointer read from a device table is generic to the
+// compiler, and a generic (FLAT) access counts against the same wait counter as
+// LDS and scalar loads, so every wait for an LDS read would also wait for the
+// HBM loads and stores still in flight.  Kernels view such pointers through
+// this qualifier (all device buffers of the library are global memory).  The
+// host pass, which also reads device code, takes it as a plain pointer.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MMF_GLOBAL __attribute__((address_space(1)))
+#else
+#define MMF_GLOBAL
+#endif
+
 namespace mmf {
+
+// Value behind a global pointer (the operands of a conditional expression
+// cannot mix address spaces).
+template <typename T>
+__device__ __forceinline__ T gload(const MMF_GLOBAL T *p) { return *p; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));

@@ -113,6 +113,7 @@ struct Eigh2Ws {
   mmf_z *AB, *V2, *tau2;
   double *wall, *Zk;          // window path only
   void *table;                // one-entry table of the chase
+  int32_t *sync;              // the persistent chase's ticket, status and progress words
   void *rest;
   size_t rest_bytes, bt1_bytes;
   size_t bytes;
@@ -133,6 +134,7 @@ inline Eigh2Ws eigh2_ws(int64_t M, int64_t nc, bool window, void *base) {
   w.wall = window ? cv.take<double>(n) : nullptr;
   w.Zk = window ? cv.take<double>(n * (size_t)(nc > 0 ? nc : 1)) : nullptr;
   w.table = cv.take<char>(STAGE_TABLE_BYTES);
+  w.sync = cv.take<int32_t>((size_t)hb_sync_ints(M));
   w.bt1_bytes = (unmtr_band_ws_bytes(M, nc) + 255) & ~(size_t)255;
   size_t stage = he2hb_ws_bytes(M);
   const size_t s2 = stedc_ws_bytes(M), s3 = w.bt1_bytes + bt2_ws_bytes(M, nc);
@@ -150,9 +152,11 @@ inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh
                          hipStream_t st, const EighLimits &lim = EighLimits()) {
   int rc = he2hb_run(M, A, lda, ws.tau1, ws.AB, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;
-  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, st);
+  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, ws.sync, st);
   if (rc) return rc;
-  return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
+  rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
+  if (rc) return rc;
+  return hb2st_status(ws.sync, dev_info, st);
 }
 
 size_t eigh2_full_ws_bytes(int64_t M) { return eigh2_ws(M, M, false, nullptr).bytes; }

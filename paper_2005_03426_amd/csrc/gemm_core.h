@@ -79,10 +79,10 @@ template <> struct MfmaT<float> {
 template <typename R, bool CPLX>
 __device__ inline void ld_elem(const void *base, int64_t off, bool conj, R &re, R &im) {
   if (CPLX) {
-    const cx<R> v = reinterpret_cast<const cx<R> *>(base)[off];
+    const cx<R> v = ((const MMF_GLOBAL cx<R> *)base)[off];
     re = v.re; im = conj ? -v.im : v.im;
   } else {
-    re = reinterpret_cast<const R *>(base)[off];
+    re = ((const MMF_GLOBAL R *)base)[off];
     im = R(0);
   }
 }
@@ -186,7 +186,7 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
 
   // K range of this tile (band clipping keeps slices aligned to GT_K from kbeg)
   int64_t kbeg = 0, kend = g.K;
-  const int64_t band = g.band_ptr ? (int64_t)(*g.band_ptr) : g.band;
+  const int64_t band = g.band_ptr ? (int64_t)gload((const MMF_GLOBAL int32_t *)g.band_ptr) : g.band;
   if (band >= 0) {
     kbeg = m0 - band;
     if (kbeg < 0) kbeg = 0;
@@ -287,7 +287,7 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
   for (int q = 0; q < 16; ++q) {
     const int64_t n = n0 + (tid >> 6) + 4 * q;
     ok[q] = n < g.N && !(g.lower && m < n);
-    const int64_t cn = ok[q] ? (g.colmap ? (int64_t)g.colmap[n] : n) : 0;
+    const int64_t cn = ok[q] ? (g.colmap ? (int64_t)((const MMF_GLOBAL int32_t *)g.colmap)[n] : n) : 0;
     off[q] = m + cn * g.ldc;
   }
   R cr[16], ci[16];
@@ -295,11 +295,11 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       if (CPLX) {
-        const cx<R> c = reinterpret_cast<const cx<R> *>(g.C)[off[q]];
+        const cx<R> c = ((const MMF_GLOBAL cx<R> *)g.C)[off[q]];
         cr[q] = c.re;
         ci[q] = c.im;
       } else {
-        cr[q] = reinterpret_cast<const R *>(g.C)[off[q]];
+        cr[q] = ((const MMF_GLOBAL R *)g.C)[off[q]];
         ci[q] = R(0);
       }
     }
@@ -317,11 +317,11 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
         rr += ber * cr[q] - bei * ci[q];
         ri += ber * ci[q] + bei * cr[q];
       }
-      reinterpret_cast<cx<R> *>(g.C)[off[q]] = cmk<R>(rr, ri);
+      ((MMF_GLOBAL cx<R> *)g.C)[off[q]] = cmk<R>(rr, ri);
     } else {
       R rr = alr * vr;
       if (usebeta) rr += ber * cr[q];
-      reinterpret_cast<R *>(g.C)[off[q]] = rr;
+      ((MMF_GLOBAL R *)g.C)[off[q]] = rr;
     }
   }
 }
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) gemm_kernel_t(GemmArgs g) {
   const int64_t m0 = (int64_t)blockIdx.x * GT_M;
   const int64_t n0 = (int64_t)blockIdx.y * GT_N;
   if (g.lower && m0 + GT_M <= n0) return;     // tile entirely above the diagonal
-  if (g.skip && *g.skip) return;
+  if (g.skip && gload((const MMF_GLOBAL int32_t *)g.skip)) return;
   gemm_tile_t<R, CPLX, OA, OB>(g, m0, n0, lds);
 }
 

@@ -77,26 +77,61 @@ __host__ __device__ inline void hb_step_range(int64_t n, int64_t t, int64_t &smi
   smin = num > 0 ? (num + den - 1) / den : 0;
 }
 
-// One step of the pipelined chase: task (s, k = t - 2 s) for s = smin + blockIdx.x
-// of problem blockIdx.z.  Thread (i, q) = (tid % 64, tid / 64); the scalar work
-// (reflectors, sums over 64 entries) stays in wavefront 0.  With compact
-// storage only the current reflector of each sweep is kept (slot s).
-__global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t t) {
-  __shared__ cd D[BW][BW + 1];
-  __shared__ cd E[BW][BW + 1];
-  __shared__ cd vs[BW], v2[BW], wv[BW], zz[BW], red[CH_Q][BW], red2[CH_Q][BW];
-  __shared__ cd tsh[2];
-  __shared__ double bsh[2];
-  const HsProb &P = pr[blockIdx.z];
+// LDS of one chase task (the blocks D_k, E_k and the reflector vectors).
+struct ChaseSh {
+  cd D[BW][BW + 1];
+  cd E[BW][BW + 1];
+  cd vs[BW], v2[BW], wv[BW], zz[BW], red[CH_Q][BW], red2[CH_Q][BW];
+  cd tsh[2];
+  double bsh[2];
+};
+
+constexpr int CH_NE = BW * BW / CH_THREADS;   // block entries per thread
+
+// Global loads of the lower band of D_k and of the block E_k (task (s, k))
+// into registers: thread tid holds entries tid + CH_THREADS q2 (row entry % 64,
+// column entry / 64, so wavefront w holds columns w + 8 q2).  part: 0 every
+// entry, 1 all but the block's last column (wavefront 7, q2 = CH_NE - 1),
+// 2 only that column.
+__device__ __forceinline__ void chase_load(const HsProb &P, int64_t s, int64_t k, cd (&dreg)[CH_NE],
+                                           cd (&ereg)[CH_NE], int part) {
   const int64_t n = P.n;
-  int64_t smin, smax;
-  hb_step_range(n, t, smin, smax);
-  const int64_t s = smin + blockIdx.x;
-  if (s > smax) return;
-  const int64_t k = t - 2 * s;
   const int64_t r0 = s + 1 + k * BW;
-  if (k < 0 || r0 > n - 1) return;
-  cd *AB = P.AB, *V2 = P.V2, *tau2 = P.tau2;
+  const MMF_GLOBAL cd *AB = (const MMF_GLOBAL cd *)P.AB;
+  const int L = (int)((n - r0 < BW) ? n - r0 : BW);
+  const int64_t e0 = r0 + L;
+  const bool hasE = e0 <= n - 1;
+  const int Le = hasE ? (int)((n - e0 < BW) ? n - e0 : BW) : 0;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q2 = 0; q2 < CH_NE; ++q2) {
+    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
+    const bool last = jj == BW - 1;                 // uniform in the wavefront
+    if ((part == 1 && last) || (part == 2 && !last)) continue;
+    dreg[q2] = (ii >= jj && ii < L) ? gload(AB + (ii - jj) + (r0 + jj) * (int64_t)LDAB) : cmake(0.0, 0.0);
+    ereg[q2] = (hasE && ii < Le) ? gload(AB + (BW + ii - jj) + (r0 + jj) * (int64_t)LDAB) : cmake(0.0, 0.0);
+  }
+}
+
+// Task (s, k) of the chase of problem P, run by the whole workgroup.  Thread
+// (i, q) = (tid % 64, tid / 64); the scalar work (reflectors, sums over 64
+// entries) stays in wavefront 0.  With compact storage only the current
+// reflector of each sweep is kept (slot s).  With carry (k >= 1), H_{s,k} is
+// taken from sh.v2 / sh.tsh[1], where task (s, k - 1) of the same workgroup
+// left it, instead of from V2 / tau2.  part: the chase_load part still to be
+// loaded here (0: all of D_k and E_k; 2: the caller has loaded the rest).
+__device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k, ChaseSh &sh, bool carry,
+                                           cd (&dreg)[CH_NE], cd (&ereg)[CH_NE], int part) {
+  cd (&D)[BW][BW + 1] = sh.D;
+  cd (&E)[BW][BW + 1] = sh.E;
+  cd *vs = sh.vs, *v2 = sh.v2, *wv = sh.wv, *zz = sh.zz;
+  cd (&red)[CH_Q][BW] = sh.red;
+  cd (&red2)[CH_Q][BW] = sh.red2;
+  cd *tsh = sh.tsh;
+  double *bsh = sh.bsh;
+  const int64_t n = P.n;
+  const int64_t r0 = s + 1 + k * BW;
+  MMF_GLOBAL cd *AB = (MMF_GLOBAL cd *)P.AB, *V2 = (MMF_GLOBAL cd *)P.V2, *tau2 = (MMF_GLOBAL cd *)P.tau2;
   const int L = (int)((n - r0 < BW) ? n - r0 : BW);
   const int tid = threadIdx.x, i = tid & 63, q = tid >> 6;
   const int64_t voff = P.compact ? s * BW : hb_voff(n, k) + s * BW;
@@ -107,21 +142,11 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
 
   // ---- all global loads first: column s or the current reflector, the lower
   // band of D_k, the block E_k
-  cd *col = AB + s * (int64_t)LDAB;
+  MMF_GLOBAL cd *col = AB + s * (int64_t)LDAB;
   cd xi = cmake(0.0, 0.0);
-  if (q == 0) xi = (k == 0) ? ((i < L) ? col[1 + i] : cmake(0.0, 0.0)) : V2[voff + i];
-  constexpr int NE = BW * BW / CH_THREADS;
-  cd dreg[NE], ereg[NE];
-#pragma unroll
-  for (int q2 = 0; q2 < NE; ++q2) {
-    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
-    dreg[q2] = (ii >= jj && ii < L) ? AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
-  }
-#pragma unroll
-  for (int q2 = 0; q2 < NE; ++q2) {
-    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
-    ereg[q2] = (hasE && ii < Le) ? AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] : cmake(0.0, 0.0);
-  }
+  if (q == 0) xi = (k == 0) ? ((i < L) ? gload(col + 1 + i) : cmake(0.0, 0.0)) : (carry ? v2[i] : gload(V2 + voff + i));
+  constexpr int NE = CH_NE;
+  chase_load(P, s, k, dreg, ereg, part);
   // ---- current reflector H = H_{s,k} (wavefront 0)
   if (q == 0) {
     if (k == 0) {
@@ -134,7 +159,7 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
       if (i == 0) { tau2[toff] = tau; tsh[0] = tau; }
     } else {
       vs[i] = xi;
-      if (i == 0) tsh[0] = tau2[toff];
+      if (i == 0) tsh[0] = carry ? tsh[1] : tau2[toff];
     }
   }
   // D is kept as the full Hermitian block (the upper triangle mirrored, the
@@ -240,6 +265,110 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
   if (tid == 0) tau2[toff1] = tau1;
 }
 
+// One step of the pipelined chase: task (s, k = t - 2 s) for s = smin + blockIdx.x
+// of problem blockIdx.z.
+__global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t t) {
+  __shared__ ChaseSh sh;
+  const HsProb &P = pr[blockIdx.z];
+  const int64_t n = P.n;
+  int64_t smin, smax;
+  hb_step_range(n, t, smin, smax);
+  const int64_t s = smin + blockIdx.x;
+  if (s > smax) return;
+  const int64_t k = t - 2 * s;
+  if (k < 0 || s + 1 + k * BW > n - 1) return;
+  cd dreg[CH_NE], ereg[CH_NE];
+  chase_task(P, s, k, sh, false, dreg, ereg, 0);
+}
+
+// Longest wait of the persistent chase for the sweep before (1 s of the
+// 100 MHz real-time counter): far beyond any legitimate wait, which is bounded
+// by a few thousand task times.
+constexpr uint64_t CH_WAIT_TICKS = 100000000ull;
+constexpr int64_t CH_PERSIST_WG = 256;
+
+// The whole chase of problem pr[0] in one launch.  Workgroups take sweeps in
+// increasing order from a ticket counter and run each sweep's tasks in order;
+// task (s, k) starts once sweep s - 1 has finished its tasks 0 .. k + 1 (all
+// of them when it has fewer).  By induction every earlier task whose band
+// columns meet those of (s, k) (sweep s - d, positions up to k + 1 + d / BW)
+// is then finished, and no later task touching them has started, so the
+// order of operations on every band entry is that of the step-by-step
+// launches.  The sweep before is always held by a running workgroup (tickets
+// are taken in order), so the waits end however many workgroups are
+// resident; each is bounded nonetheless: past CH_WAIT_TICKS the workgroup
+// sets the status word and leaves, and the others leave at their next wait.
+// sync (zeroed before the launch): [0] ticket, [1] status, [2 + s] tasks
+// finished in sweep s.  Band data is published with device-scope release /
+// acquire fences around relaxed atomics on the progress words.
+__global__ void __launch_bounds__(CH_THREADS) hb_chase_persist(const HsProb *pr, int32_t *sync) {
+  __shared__ ChaseSh sh;
+  __shared__ int64_t s_sh;
+  __shared__ int stop_sh;
+  const HsProb &P = pr[0];
+  const int64_t n = P.n;
+  const int tid = threadIdx.x;
+  int32_t *ticket = sync, *status = sync + 1, *prog = sync + 2;
+  for (;;) {
+    if (tid == 0) s_sh = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t s = s_sh;
+    if (s > n - 2) return;                                  // uniform: no sweep left
+    const int64_t K = (n - 2 - s) / BW + 1;                 // tasks of sweep s
+    const int64_t K1 = s >= 1 ? (n - 1 - s) / BW + 1 : 0;   // tasks of sweep s - 1
+    for (int64_t k = 0; k < K; ++k) {
+      // everything task (s, k) reads except its last band column was final
+      // once sweep s - 1 finished task k (the previous wait): load it now,
+      // the column shared with task (s - 1, k + 1) after the wait
+      cd dreg[CH_NE], ereg[CH_NE];
+      if (k >= 1) chase_load(P, s, k, dreg, ereg, 1);
+      if (tid == 0) {
+        int stop = 0;
+        if (s >= 1) {
+          const int32_t need = (int32_t)(k + 2 < K1 ? k + 2 : K1);
+          const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+          while (__hip_atomic_load(prog + (s - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              stop = 1;
+              break;
+            }
+            if (__builtin_amdgcn_s_memrealtime() - t0 > CH_WAIT_TICKS) {
+              __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              stop = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+          }
+        }
+        stop_sh = stop;
+      }
+      if (tid < 64) {                                       // one wavefront invalidates the CU's and XCD's caches
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
+      __syncthreads();
+      if (stop_sh) return;                                  // uniform
+      chase_task(P, s, k, sh, true, dreg, ereg, k >= 1 ? 2 : 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");     // every wavefront's stores have reached L2
+      __syncthreads();
+      if (tid == 0) {                                       // one write-back of the XCD's L2, then publish
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(prog + s, (int32_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+__global__ void hb_sync_clear(int32_t *sync, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) sync[i] = 0;
+}
+
+// A persistent chase that gave up marks the solve as failed.
+__global__ void hb_chase_status(const int32_t *sync, int32_t *dev_info) {
+  if (sync[1] != 0) *dev_info = MMF_ERR_NO_CONVERGENCE;
+}
+
 __global__ void hb_extract(const HsProb *pr) {
   const HsProb &P = pr[blockIdx.z];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -281,7 +410,8 @@ int hb2st_grouped(const HsProb *pr, const int64_t *nh, int64_t count, hipStream_
   return MMF_OK;
 }
 
-int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, hipStream_t st) {
+int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, int32_t *sync,
+              hipStream_t st) {
   if (n <= 0) return MMF_OK;
   static_assert(sizeof(HsProb) <= STAGE_TABLE_BYTES, "table entry");
   HsProb q;
@@ -290,7 +420,25 @@ int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e
   HsProb *pr = reinterpret_cast<HsProb *>(table);
   const int rc = table_write(pr, &q, 1, st);
   if (rc) return rc;
-  return hb2st_grouped(pr, &n, 1, st);
+  const int64_t ns = hb_sync_ints(n);
+  hipLaunchKernelGGL(hb_sync_clear, dim3(cdiv(ns, 256)), dim3(256), 0, st, sync, ns);
+  MMF_LAUNCH_CHECK();
+  if (n >= 2) {                          // sweeps 0 .. n - 2 (n = 2: the phase of the one off-diagonal)
+    // one workgroup per CU at most (the task's LDS); more than the ~n / (2 BW)
+    // sweeps that run at once would only wait
+    const int64_t G = (n - 1 < CH_PERSIST_WG) ? n - 1 : CH_PERSIST_WG;
+    hipLaunchKernelGGL(hb_chase_persist, dim3((unsigned)G), dim3(CH_THREADS), 0, st, pr, sync);
+    MMF_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(hb_extract, dim3(cdiv(n, 256), 1, 1), dim3(256), 0, st, pr);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
+int hb2st_status(const int32_t *sync, int32_t *dev_info, hipStream_t st) {
+  hipLaunchKernelGGL(hb_chase_status, dim3(1), dim3(1), 0, st, sync, dev_info);
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
 }
 
 // Batch (eigenvalues only): compact reflector storage, V2[c] holds n[c] x BW

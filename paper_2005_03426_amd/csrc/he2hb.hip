@@ -140,13 +140,14 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
   if ((int64_t)blockIdx.x >= nwg) return;
   const int64_t n = P.n, lda = P.lda, q0 = pp.q0;
   const int bw = pp.bw, nr = pp.nr;
-  cd *A = P.A;
+  MMF_GLOBAL cd *A = (MMF_GLOBAL cd *)P.A;
   const HbWs &ws = P.ws;
   const int tid = threadIdx.x;
   const int64_t r = q0 + (int64_t)blockIdx.x * QR_ROWS + tid;
   const int wr = j & 1, rd = wr ^ 1;
-  cd *gw = ws.gpart + (int64_t)wr * ws.nwg * BW, *gr = ws.gpart + (int64_t)rd * ws.nwg * BW;
-  cd *pw = ws.prow + wr * BW, *prd = ws.prow + rd * BW;
+  MMF_GLOBAL cd *gw = (MMF_GLOBAL cd *)ws.gpart + (int64_t)wr * ws.nwg * BW;
+  MMF_GLOBAL cd *gr = (MMF_GLOBAL cd *)ws.gpart + (int64_t)rd * ws.nwg * BW;
+  MMF_GLOBAL cd *pw = (MMF_GLOBAL cd *)ws.prow + wr * BW, *prd = (MMF_GLOBAL cd *)ws.prow + rd * BW;
   cd vown = cmake(0.0, 0.0);                // this row's entry of v_{j-1}
   if (j >= 1) {
     // ---- reflector jp = j - 1 from the previous launch's sums
@@ -182,8 +183,8 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
       d[tid] = (tid >= j && tid < bw) ? cmulc(tj, cadd(prd[tid], cmulc(sc, gs[tid]))) : cmake(0.0, 0.0);
     }
     if (blockIdx.x == 0 && tid == 0) {
-      P.tau[c0 + jp] = tj;
-      ws.beta[jp] = beta;
+      ((MMF_GLOBAL cd *)P.tau)[c0 + jp] = tj;
+      ((MMF_GLOBAL double *)ws.beta)[jp] = beta;
     }
     __syncthreads();
     if (r < n && r >= rjp) {
@@ -192,8 +193,9 @@ __global__ void __launch_bounds__(QR_ROWS) hb_qr_step(const HbProb *pr, int64_t 
         v = cmul(A[r + (c0 + jp) * lda], sc);
         A[r + (c0 + jp) * lda] = v;
       }
-      hb_p3(P, c0)[r + (int64_t)jp * n] = v;
-      hb_p3(P, c0)[r + (int64_t)(2 * BW + jp) * n] = v;
+      MMF_GLOBAL cd *p3 = (MMF_GLOBAL cd *)hb_p3(P, c0);
+      p3[r + (int64_t)jp * n] = v;
+      p3[r + (int64_t)(2 * BW + jp) * n] = v;
       vown = v;
     }
   }

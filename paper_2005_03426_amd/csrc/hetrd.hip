@@ -208,10 +208,10 @@ template <> struct NtVec<float> { typedef float v __attribute__((ext_vector_type
 template <typename R>
 __device__ void ht_dots_wave(const HtProb<R> &pq, int64_t i, int k, int g, int qq) {
   const int64_t n = pq.n;
-  const cx<R> *P3 = pq.P3;
+  const MMF_GLOBAL cx<R> *P3 = (const MMF_GLOBAL cx<R> *)pq.P3;
   const int q = qq % k, which = qq / k;
-  const cx<R> *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
-  const cx<R> *v = P3 + (int64_t)k * n;
+  const MMF_GLOBAL cx<R> *X = P3 + (int64_t)(which == 0 ? HT_NB + q : q) * n;
+  const MMF_GLOBAL cx<R> *v = P3 + (int64_t)k * n;
   const int lane = threadIdx.x & 63;
   const int64_t r0 = i + 1 + (int64_t)g * DOT_ROWS;
   cx<R> s = cmk<R>(0, 0);
@@ -223,7 +223,7 @@ __device__ void ht_dots_wave(const HtProb<R> &pq, int64_t i, int k, int g, int q
   R re = s.re, im = s.im;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) { re += __shfl_xor(re, o, 64); im += __shfl_xor(im, o, 64); }
-  if (lane == 0) pq.dots[(int64_t)g * 2 * HT_NB + which * HT_NB + q] = cmk<R>(re, im);
+  if (lane == 0) ((MMF_GLOBAL cx<R> *)pq.dots)[(int64_t)g * 2 * HT_NB + which * HT_NB + q] = cmk<R>(re, im);
 }
 
 // u = A_trail v over the lower triangle of the trailing matrix
@@ -268,14 +268,14 @@ __global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i
   }
   const int64_t first = bj + 1 + (slot - 1) * HV_CH;   // interior chunk's first block row
   if (slot > 0 && first >= nfull) return;
-  const C *A = q.A;
-  const C *v = q.P3 + (int64_t)k * n;               // v[row], zero outside [i+1, n)
-  C *pdir = q.pdir, *ptrn = q.ptrn;
+  const MMF_GLOBAL C *A = (const MMF_GLOBAL C *)q.A;
+  const MMF_GLOBAL C *v = (const MMF_GLOBAL C *)q.P3 + (int64_t)k * n;   // v[row], zero outside [i+1, n)
+  MMF_GLOBAL C *pdir = (MMF_GLOBAL C *)q.pdir, *ptrn = (MMF_GLOBAL C *)q.ptrn;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   if (tid < HV_T) {
     const int64_t gc = bj * HV_T + tid;
-    vcol[tid] = (gc > i && gc < n) ? v[gc] : cmk<R>(0, 0);
+    vcol[tid] = (gc > i && gc < n) ? gload(v + gc) : cmk<R>(0, 0);
   }
   __syncthreads();
   if (slot == 0) {
@@ -288,13 +288,13 @@ __global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i
       const int64_t bi = (tt == 0) ? bj : nb - 1;
       const int64_t row = bi * HV_T + lane;
       const bool rok = row > i && row < n;
-      const C vr = rok ? v[row] : cmk<R>(0, 0);
+      const C vr = rok ? gload(v + row) : cmk<R>(0, 0);
       C d = cmk<R>(0, 0);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int64_t col = bj * HV_T + 16 * wave + j;
         const bool ok = rok && col > i && row >= col;     // col < n follows from row < n
-        C a = ok ? A[row + col * lda] : cmk<R>(0, 0);
+        C a = ok ? gload(A + row + col * lda) : cmk<R>(0, 0);
         const bool dg = (row == col);
         if (dg) a.im = R(0);
         d = cadd(d, cmul(a, vcol[16 * wave + j]));
@@ -324,15 +324,15 @@ __global__ void __launch_bounds__(256, 2) ht_hemv(const HtProb<R> *pr, int64_t i
   C vc[4], tacc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) { vc[j] = vcol[cb + j]; tacc[j] = cmk<R>(0, 0); }
-  const C *colp = A + (bj * HV_T + cb) * lda + rg;
+  const MMF_GLOBAL C *colp = A + (bj * HV_T + cb) * lda + rg;
   C b0t[4][4], b1t[4][4];
   auto load = [&](C (&b)[4][4], int64_t bi) {
-    const C *p = colp + bi * HV_T;
+    const MMF_GLOBAL C *p = colp + bi * HV_T;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        const nv x = __builtin_nontemporal_load(reinterpret_cast<const nv *>(p + 16 * qq + (int64_t)j * lda));
+        const nv x = __builtin_nontemporal_load(reinterpret_cast<const MMF_GLOBAL nv *>(p + 16 * qq + (int64_t)j * lda));
         b[j][qq] = cmk<R>(x[0], x[1]);
       }
   };
