@@ -152,7 +152,7 @@ inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh
                          hipStream_t st, const EighLimits &lim = EighLimits()) {
   int rc = he2hb_run(M, A, lda, ws.tau1, ws.AB, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;
-  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, ws.sync, st);
+  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, ws.sync, lim.chase_wait_us, st);
   if (rc) return rc;
   rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
   if (rc) return rc;
@@ -250,9 +250,11 @@ extern "C" int mmf_eigh_ex(int64_t M, mmf_z *A, int64_t lda, double *w, int prec
     if (opts->refine_max_iters < 0 || opts->refine_max_iters > 64) return -6;
     if (opts->secular_max_iters < 0 || opts->secular_max_iters > 100000) return -6;
     if (opts->leaf_max_iters < 0 || opts->leaf_max_iters > 100000) return -6;
+    if (opts->chase_wait_us < 0 || opts->chase_wait_us > 60000000) return -6;
     if (opts->refine_max_iters) lim.refine_iters = opts->refine_max_iters;
     if (opts->secular_max_iters) lim.secular_iters = opts->secular_max_iters;
     if (opts->leaf_max_iters) lim.leaf_iters = opts->leaf_max_iters;
+    if (opts->chase_wait_us) lim.chase_wait_us = opts->chase_wait_us;
   }
   rc = eigh_dispatch(M, A, lda, w, prec, work, work_bytes, dev_info, (hipStream_t)stream, lim);
   return rc == -7 ? -8 : rc;

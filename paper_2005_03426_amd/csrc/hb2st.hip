@@ -205,16 +205,26 @@ __device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k
     zz[i] = cmul(tau, z);
   }
   __syncthreads();
-  // ---- D <- D - w v^H - v w^H (lower band to AB); E <- E - (tau z) v^H
+  // ---- D <- D - w v^H - v w^H (lower band to AB); E <- E - (tau z) v^H.
+  // The thread's entries of D_k and E_k are still in dreg / ereg (the LDS
+  // copy of D differs only in the imaginary part of the diagonal, which the
+  // update drops), its row is ii = i for every q2.
+  {
+    const cd wvi = wv[i], vsi = vs[i], zzi = zz[i];
 #pragma unroll
-  for (int q2 = 0; q2 < NE; ++q2) {
-    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
-    if (ii >= jj && ii < L) {
-      cd d = csub(D[ii][jj], cadd(cmul(wv[ii], cconj(vs[jj])), cmul(vs[ii], cconj(wv[jj]))));
-      if (ii == jj) d.im = 0.0;
-      AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB] = d;
+    for (int q2 = 0; q2 < NE; ++q2) {
+      const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
+      const cd vj = vs[jj];
+      if (ii >= jj && ii < L) {
+        cd d = csub(dreg[q2], cadd(cmul(wvi, cconj(vj)), cmul(vsi, cconj(wv[jj]))));
+        if (ii == jj) d.im = 0.0;
+        AB[(ii - jj) + (r0 + jj) * (int64_t)LDAB] = d;
+      }
+      if (hasE) {
+        ereg[q2] = csub(ereg[q2], cmul(zzi, cconj(vj)));
+        E[ii][jj] = ereg[q2];
+      }
     }
-    if (hasE) E[ii][jj] = csub(E[ii][jj], cmul(zz[ii], cconj(vs[jj])));
   }
   if (!hasE) return;                      // uniform: no block below
   __syncthreads();
@@ -247,16 +257,19 @@ __device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k
     }
     __syncthreads();
   }
+  {
+    const cd v2i = v2[i];
 #pragma unroll
-  for (int q2 = 0; q2 < NE; ++q2) {
-    const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
-    if (ii < Le) {
-      cd x = E[ii][jj];
-      if (active) {
-        if (jj == 0) x = (ii == 0) ? cmake(beta1, 0.0) : cmake(0.0, 0.0);
-        else x = csub(x, cmul(v2[ii], wv[jj]));
+    for (int q2 = 0; q2 < NE; ++q2) {
+      const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
+      if (ii < Le) {
+        cd x = ereg[q2];
+        if (active) {
+          if (jj == 0) x = (ii == 0) ? cmake(beta1, 0.0) : cmake(0.0, 0.0);
+          else x = csub(x, cmul(v2i, wv[jj]));
+        }
+        AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] = x;
       }
-      AB[(BW + ii - jj) + (r0 + jj) * (int64_t)LDAB] = x;
     }
   }
   const int64_t voff1 = P.compact ? s * BW : hb_voff(n, k + 1) + s * BW;
@@ -281,11 +294,8 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
   chase_task(P, s, k, sh, false, dreg, ereg, 0);
 }
 
-// Longest wait of the persistent chase for the sweep before (1 s of the
-// 100 MHz real-time counter): far beyond any legitimate wait, which is bounded
-// by a few thousand task times.
-constexpr uint64_t CH_WAIT_TICKS = 100000000ull;
 constexpr int64_t CH_PERSIST_WG = 256;
+constexpr uint64_t CH_TICKS_PER_US = 100;   // the real-time counter runs at 100 MHz
 
 // The whole chase of problem pr[0] in one launch.  Workgroups take sweeps in
 // increasing order from a ticket counter and run each sweep's tasks in order;
@@ -296,12 +306,14 @@ constexpr int64_t CH_PERSIST_WG = 256;
 // order of operations on every band entry is that of the step-by-step
 // launches.  The sweep before is always held by a running workgroup (tickets
 // are taken in order), so the waits end however many workgroups are
-// resident; each is bounded nonetheless: past CH_WAIT_TICKS the workgroup
-// sets the status word and leaves, and the others leave at their next wait.
+// resident; each is bounded nonetheless (by wait_ticks of the 100 MHz
+// real-time counter, 1 s by default: far beyond any legitimate wait, which
+// lasts a few thousand task times at most): past it the workgroup sets the
+// status word and leaves, and the others leave at their next wait.
 // sync (zeroed before the launch): [0] ticket, [1] status, [2 + s] tasks
 // finished in sweep s.  Band data is published with device-scope release /
 // acquire fences around relaxed atomics on the progress words.
-__global__ void __launch_bounds__(CH_THREADS) hb_chase_persist(const HsProb *pr, int32_t *sync) {
+__global__ void __launch_bounds__(CH_THREADS) hb_chase_persist(const HsProb *pr, int32_t *sync, uint64_t wait_ticks) {
   __shared__ ChaseSh sh;
   __shared__ int64_t s_sh;
   __shared__ int stop_sh;
@@ -332,7 +344,7 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase_persist(const HsProb *pr,
               stop = 1;
               break;
             }
-            if (__builtin_amdgcn_s_memrealtime() - t0 > CH_WAIT_TICKS) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) {
               __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               stop = 1;
               break;
@@ -411,7 +423,7 @@ int hb2st_grouped(const HsProb *pr, const int64_t *nh, int64_t count, hipStream_
 }
 
 int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, int32_t *sync,
-              hipStream_t st) {
+              int32_t wait_us, hipStream_t st) {
   if (n <= 0) return MMF_OK;
   static_assert(sizeof(HsProb) <= STAGE_TABLE_BYTES, "table entry");
   HsProb q;
@@ -427,7 +439,8 @@ int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e
     // one workgroup per CU at most (the task's LDS); more than the ~n / (2 BW)
     // sweeps that run at once would only wait
     const int64_t G = (n - 1 < CH_PERSIST_WG) ? n - 1 : CH_PERSIST_WG;
-    hipLaunchKernelGGL(hb_chase_persist, dim3((unsigned)G), dim3(CH_THREADS), 0, st, pr, sync);
+    const uint64_t wait_ticks = (uint64_t)(wait_us > 0 ? wait_us : 1) * CH_TICKS_PER_US;
+    hipLaunchKernelGGL(hb_chase_persist, dim3((unsigned)G), dim3(CH_THREADS), 0, st, pr, sync, wait_ticks);
     MMF_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(hb_extract, dim3(cdiv(n, 256), 1, 1), dim3(256), 0, st, pr);
