@@ -200,10 +200,6 @@ typedef struct {
                                  200, at most 100000                                            */
   int32_t leaf_max_iters;     /* divide and conquer: implicit-QL steps per eigenvalue of a leaf,
                                  default 60, at most 100000                                     */
-  int32_t chase_wait_us;      /* two-stage path: longest wait of a bulge-chase workgroup for the
-                                 sweep before it, microseconds, default 1000000, at most 60000000;
-                                 a workgroup that waits longer stops the chase (every workgroup
-                                 then leaves) and the solve reports MMF_ERR_NO_CONVERGENCE     */
 } mmf_eigh_opts;
 
 /* mmf_eigh with iteration limits (opts may be NULL: the defaults, identical

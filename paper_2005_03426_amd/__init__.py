@@ -137,8 +137,8 @@ def eigh(At, prec: int = MMF_C128, w=None, work=None, info=None, stream=None, li
     """In-place eigendecomposition of the Hermitian matrix held (column-major)
     in At.  Returns (w, At, info): eigenvalues ascending; At's row a is the
     eigenvector of w[a]; info a device int32 (0 = converged).  `limits`, a
-    dict with any of refine_max_iters / secular_max_iters / leaf_max_iters /
-    chase_wait_us, selects mmf_eigh_ex with those limits."""
+    dict with any of refine_max_iters / secular_max_iters / leaf_max_iters,
+    selects mmf_eigh_ex with those iteration limits."""
     torch = _torch()
     M = At.shape[0]
     dev = At.device

@@ -28,7 +28,7 @@ class MMFProblem(C.Structure):
 
 class MMFEighOpts(C.Structure):
     _fields_ = [("refine_max_iters", C.c_int32), ("secular_max_iters", C.c_int32),
-                ("leaf_max_iters", C.c_int32), ("chase_wait_us", C.c_int32)]
+                ("leaf_max_iters", C.c_int32)]
 
 
 class MMFBatchOpts(C.Structure):

@@ -113,7 +113,6 @@ struct Eigh2Ws {
   mmf_z *AB, *V2, *tau2;
   double *wall, *Zk;          // window path only
   void *table;                // one-entry table of the chase
-  int32_t *sync;              // the persistent chase's ticket, status and progress words
   void *rest;
   size_t rest_bytes, bt1_bytes;
   size_t bytes;
@@ -134,7 +133,6 @@ inline Eigh2Ws eigh2_ws(int64_t M, int64_t nc, bool window, void *base) {
   w.wall = window ? cv.take<double>(n) : nullptr;
   w.Zk = window ? cv.take<double>(n * (size_t)(nc > 0 ? nc : 1)) : nullptr;
   w.table = cv.take<char>(STAGE_TABLE_BYTES);
-  w.sync = cv.take<int32_t>((size_t)hb_sync_ints(M));
   w.bt1_bytes = (unmtr_band_ws_bytes(M, nc) + 255) & ~(size_t)255;
   size_t stage = he2hb_ws_bytes(M);
   const size_t s2 = stedc_ws_bytes(M), s3 = w.bt1_bytes + bt2_ws_bytes(M, nc);
@@ -152,11 +150,9 @@ inline int eigh2_tridiag(int64_t M, mmf_z *A, int64_t lda, double *w, const Eigh
                          hipStream_t st, const EighLimits &lim = EighLimits()) {
   int rc = he2hb_run(M, A, lda, ws.tau1, ws.AB, ws.rest, ws.rest_bytes, st);
   if (rc) return rc;
-  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, ws.sync, lim.chase_wait_us, st);
+  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, w, ws.e, ws.table, st);
   if (rc) return rc;
-  rc = stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
-  if (rc) return rc;
-  return hb2st_status(ws.sync, dev_info, st);
+  return stedc_run(M, w, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st, lim);
 }
 
 size_t eigh2_full_ws_bytes(int64_t M) { return eigh2_ws(M, M, false, nullptr).bytes; }
@@ -250,11 +246,9 @@ extern "C" int mmf_eigh_ex(int64_t M, mmf_z *A, int64_t lda, double *w, int prec
     if (opts->refine_max_iters < 0 || opts->refine_max_iters > 64) return -6;
     if (opts->secular_max_iters < 0 || opts->secular_max_iters > 100000) return -6;
     if (opts->leaf_max_iters < 0 || opts->leaf_max_iters > 100000) return -6;
-    if (opts->chase_wait_us < 0 || opts->chase_wait_us > 60000000) return -6;
     if (opts->refine_max_iters) lim.refine_iters = opts->refine_max_iters;
     if (opts->secular_max_iters) lim.secular_iters = opts->secular_max_iters;
     if (opts->leaf_max_iters) lim.leaf_iters = opts->leaf_max_iters;
-    if (opts->chase_wait_us) lim.chase_wait_us = opts->chase_wait_us;
   }
   rc = eigh_dispatch(M, A, lda, w, prec, work, work_bytes, dev_info, (hipStream_t)stream, lim);
   return rc == -7 ? -8 : rc;

@@ -90,11 +90,9 @@ constexpr int CH_NE = BW * BW / CH_THREADS;   // block entries per thread
 
 // Global loads of the lower band of D_k and of the block E_k (task (s, k))
 // into registers: thread tid holds entries tid + CH_THREADS q2 (row entry % 64,
-// column entry / 64, so wavefront w holds columns w + 8 q2).  part: 0 every
-// entry, 1 all but the block's last column (wavefront 7, q2 = CH_NE - 1),
-// 2 only that column.
+// column entry / 64).
 __device__ __forceinline__ void chase_load(const HsProb &P, int64_t s, int64_t k, cd (&dreg)[CH_NE],
-                                           cd (&ereg)[CH_NE], int part) {
+                                           cd (&ereg)[CH_NE]) {
   const int64_t n = P.n;
   const int64_t r0 = s + 1 + k * BW;
   const MMF_GLOBAL cd *AB = (const MMF_GLOBAL cd *)P.AB;
@@ -106,8 +104,6 @@ __device__ __forceinline__ void chase_load(const HsProb &P, int64_t s, int64_t k
 #pragma unroll
   for (int q2 = 0; q2 < CH_NE; ++q2) {
     const int e = tid + CH_THREADS * q2, ii = e & 63, jj = e >> 6;
-    const bool last = jj == BW - 1;                 // uniform in the wavefront
-    if ((part == 1 && last) || (part == 2 && !last)) continue;
     dreg[q2] = (ii >= jj && ii < L) ? gload(AB + (ii - jj) + (r0 + jj) * (int64_t)LDAB) : cmake(0.0, 0.0);
     ereg[q2] = (hasE && ii < Le) ? gload(AB + (BW + ii - jj) + (r0 + jj) * (int64_t)LDAB) : cmake(0.0, 0.0);
   }
@@ -116,12 +112,8 @@ __device__ __forceinline__ void chase_load(const HsProb &P, int64_t s, int64_t k
 // Task (s, k) of the chase of problem P, run by the whole workgroup.  Thread
 // (i, q) = (tid % 64, tid / 64); the scalar work (reflectors, sums over 64
 // entries) stays in wavefront 0.  With compact storage only the current
-// reflector of each sweep is kept (slot s).  With carry (k >= 1), H_{s,k} is
-// taken from sh.v2 / sh.tsh[1], where task (s, k - 1) of the same workgroup
-// left it, instead of from V2 / tau2.  part: the chase_load part still to be
-// loaded here (0: all of D_k and E_k; 2: the caller has loaded the rest).
-__device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k, ChaseSh &sh, bool carry,
-                                           cd (&dreg)[CH_NE], cd (&ereg)[CH_NE], int part) {
+// reflector of each sweep is kept (slot s).
+__device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k, ChaseSh &sh) {
   cd (&D)[BW][BW + 1] = sh.D;
   cd (&E)[BW][BW + 1] = sh.E;
   cd *vs = sh.vs, *v2 = sh.v2, *wv = sh.wv, *zz = sh.zz;
@@ -144,9 +136,10 @@ __device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k
   // band of D_k, the block E_k
   MMF_GLOBAL cd *col = AB + s * (int64_t)LDAB;
   cd xi = cmake(0.0, 0.0);
-  if (q == 0) xi = (k == 0) ? ((i < L) ? gload(col + 1 + i) : cmake(0.0, 0.0)) : (carry ? v2[i] : gload(V2 + voff + i));
+  if (q == 0) xi = (k == 0) ? ((i < L) ? gload(col + 1 + i) : cmake(0.0, 0.0)) : gload(V2 + voff + i);
   constexpr int NE = CH_NE;
-  chase_load(P, s, k, dreg, ereg, part);
+  cd dreg[NE], ereg[NE];
+  chase_load(P, s, k, dreg, ereg);
   // ---- current reflector H = H_{s,k} (wavefront 0)
   if (q == 0) {
     if (k == 0) {
@@ -159,7 +152,7 @@ __device__ __forceinline__ void chase_task(const HsProb &P, int64_t s, int64_t k
       if (i == 0) { tau2[toff] = tau; tsh[0] = tau; }
     } else {
       vs[i] = xi;
-      if (i == 0) tsh[0] = carry ? tsh[1] : tau2[toff];
+      if (i == 0) tsh[0] = tau2[toff];
     }
   }
   // D is kept as the full Hermitian block (the upper triangle mirrored, the
@@ -290,95 +283,7 @@ __global__ void __launch_bounds__(CH_THREADS) hb_chase(const HsProb *pr, int64_t
   if (s > smax) return;
   const int64_t k = t - 2 * s;
   if (k < 0 || s + 1 + k * BW > n - 1) return;
-  cd dreg[CH_NE], ereg[CH_NE];
-  chase_task(P, s, k, sh, false, dreg, ereg, 0);
-}
-
-constexpr int64_t CH_PERSIST_WG = 256;
-constexpr uint64_t CH_TICKS_PER_US = 100;   // the real-time counter runs at 100 MHz
-
-// The whole chase of problem pr[0] in one launch.  Workgroups take sweeps in
-// increasing order from a ticket counter and run each sweep's tasks in order;
-// task (s, k) starts once sweep s - 1 has finished its tasks 0 .. k + 1 (all
-// of them when it has fewer).  By induction every earlier task whose band
-// columns meet those of (s, k) (sweep s - d, positions up to k + 1 + d / BW)
-// is then finished, and no later task touching them has started, so the
-// order of operations on every band entry is that of the step-by-step
-// launches.  The sweep before is always held by a running workgroup (tickets
-// are taken in order), so the waits end however many workgroups are
-// resident; each is bounded nonetheless (by wait_ticks of the 100 MHz
-// real-time counter, 1 s by default: far beyond any legitimate wait, which
-// lasts a few thousand task times at most): past it the workgroup sets the
-// status word and leaves, and the others leave at their next wait.
-// sync (zeroed before the launch): [0] ticket, [1] status, [2 + s] tasks
-// finished in sweep s.  Band data is published with device-scope release /
-// acquire fences around relaxed atomics on the progress words.
-__global__ void __launch_bounds__(CH_THREADS) hb_chase_persist(const HsProb *pr, int32_t *sync, uint64_t wait_ticks) {
-  __shared__ ChaseSh sh;
-  __shared__ int64_t s_sh;
-  __shared__ int stop_sh;
-  const HsProb &P = pr[0];
-  const int64_t n = P.n;
-  const int tid = threadIdx.x;
-  int32_t *ticket = sync, *status = sync + 1, *prog = sync + 2;
-  for (;;) {
-    if (tid == 0) s_sh = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int64_t s = s_sh;
-    if (s > n - 2) return;                                  // uniform: no sweep left
-    const int64_t K = (n - 2 - s) / BW + 1;                 // tasks of sweep s
-    const int64_t K1 = s >= 1 ? (n - 1 - s) / BW + 1 : 0;   // tasks of sweep s - 1
-    for (int64_t k = 0; k < K; ++k) {
-      // everything task (s, k) reads except its last band column was final
-      // once sweep s - 1 finished task k (the previous wait): load it now,
-      // the column shared with task (s - 1, k + 1) after the wait
-      cd dreg[CH_NE], ereg[CH_NE];
-      if (k >= 1) chase_load(P, s, k, dreg, ereg, 1);
-      if (tid == 0) {
-        int stop = 0;
-        if (s >= 1) {
-          const int32_t need = (int32_t)(k + 2 < K1 ? k + 2 : K1);
-          const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-          while (__hip_atomic_load(prog + (s - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-              stop = 1;
-              break;
-            }
-            if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) {
-              __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              stop = 1;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(4);
-          }
-        }
-        stop_sh = stop;
-      }
-      if (tid < 64) {                                       // one wavefront invalidates the CU's and XCD's caches
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      }
-      __syncthreads();
-      if (stop_sh) return;                                  // uniform
-      chase_task(P, s, k, sh, true, dreg, ereg, k >= 1 ? 2 : 0);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");     // every wavefront's stores have reached L2
-      __syncthreads();
-      if (tid == 0) {                                       // one write-back of the XCD's L2, then publish
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(prog + s, (int32_t)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-  }
-}
-
-__global__ void hb_sync_clear(int32_t *sync, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) sync[i] = 0;
-}
-
-// A persistent chase that gave up marks the solve as failed.
-__global__ void hb_chase_status(const int32_t *sync, int32_t *dev_info) {
-  if (sync[1] != 0) *dev_info = MMF_ERR_NO_CONVERGENCE;
+  chase_task(P, s, k, sh);
 }
 
 __global__ void hb_extract(const HsProb *pr) {
@@ -422,8 +327,7 @@ int hb2st_grouped(const HsProb *pr, const int64_t *nh, int64_t count, hipStream_
   return MMF_OK;
 }
 
-int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, int32_t *sync,
-              int32_t wait_us, hipStream_t st) {
+int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, hipStream_t st) {
   if (n <= 0) return MMF_OK;
   static_assert(sizeof(HsProb) <= STAGE_TABLE_BYTES, "table entry");
   HsProb q;
@@ -432,26 +336,7 @@ int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e
   HsProb *pr = reinterpret_cast<HsProb *>(table);
   const int rc = table_write(pr, &q, 1, st);
   if (rc) return rc;
-  const int64_t ns = hb_sync_ints(n);
-  hipLaunchKernelGGL(hb_sync_clear, dim3(cdiv(ns, 256)), dim3(256), 0, st, sync, ns);
-  MMF_LAUNCH_CHECK();
-  if (n >= 2) {                          // sweeps 0 .. n - 2 (n = 2: the phase of the one off-diagonal)
-    // one workgroup per CU at most (the task's LDS); more than the ~n / (2 BW)
-    // sweeps that run at once would only wait
-    const int64_t G = (n - 1 < CH_PERSIST_WG) ? n - 1 : CH_PERSIST_WG;
-    const uint64_t wait_ticks = (uint64_t)(wait_us > 0 ? wait_us : 1) * CH_TICKS_PER_US;
-    hipLaunchKernelGGL(hb_chase_persist, dim3((unsigned)G), dim3(CH_THREADS), 0, st, pr, sync, wait_ticks);
-    MMF_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL(hb_extract, dim3(cdiv(n, 256), 1, 1), dim3(256), 0, st, pr);
-  MMF_LAUNCH_CHECK();
-  return MMF_OK;
-}
-
-int hb2st_status(const int32_t *sync, int32_t *dev_info, hipStream_t st) {
-  hipLaunchKernelGGL(hb_chase_status, dim3(1), dim3(1), 0, st, sync, dev_info);
-  MMF_LAUNCH_CHECK();
-  return MMF_OK;
+  return hb2st_grouped(pr, &n, 1, st);
 }
 
 // Batch (eigenvalues only): compact reflector storage, V2[c] holds n[c] x BW

@@ -15,7 +15,6 @@ struct EighLimits {
   int32_t refine_iters = 12;    // Ogita-Aishima refinement iterations (precision layer)
   int32_t secular_iters = 200;  // secular-equation steps per root (divide and conquer)
   int32_t leaf_iters = 60;      // implicit-QL steps per eigenvalue in the D&C leaves
-  int32_t chase_wait_us = 1000000;  // longest wait of a persistent-chase workgroup (two-stage path)
 };
 
 size_t hetrd_ws_bytes(int64_t n);

@@ -57,15 +57,8 @@ __host__ __device__ inline int64_t hb_voff(int64_t n, int64_t k) {
 }
 inline int64_t hb_npos(int64_t n) { return n > 1 ? (n - 2) / BW + 1 : 0; }
 inline size_t hb_v2_elems(int64_t n) { return n > 1 ? (size_t)hb_voff(n, hb_npos(n)) : 1; }
-// table: STAGE_TABLE_BYTES of device memory for the one-entry problem table;
-// sync: hb_sync_ints(n) int32 of device memory for the persistent chase (its
-// ticket, status word and per-sweep progress), read back by hb2st_status,
-// which sets dev_info to MMF_ERR_NO_CONVERGENCE if a workgroup of the chase
-// waited longer than wait_us microseconds and the chase gave up.
-inline int64_t hb_sync_ints(int64_t n) { return (n > 0 ? n : 1) + 2; }
-int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, int32_t *sync,
-              int32_t wait_us, hipStream_t st);
-int hb2st_status(const int32_t *sync, int32_t *dev_info, hipStream_t st);
+// table: STAGE_TABLE_BYTES of device memory for the one-entry problem table
+int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, hipStream_t st);
 
 // Batches (eigenvalues only): problem c has order n[c], its own stage-1
 // workspace stage[c] (he2hb_ws_bytes(n[c])), band array AB[c] (n x LDAB), and

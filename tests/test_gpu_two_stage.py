@@ -62,27 +62,6 @@ def test_two_stage_block_diagonal(two_stage):
     _check_eigh(H)
 
 
-def test_two_stage_chase_wait_bound_reports_failure(two_stage):
-    """The single-matrix bulge chase runs as one persistent launch whose
-    workgroups wait for the sweep before theirs; every such wait is bounded.
-    A bound of 1 us, set from the host, makes a workgroup give up at its first
-    real wait: every workgroup leaves, the call returns and reports
-    MMF_ERR_NO_CONVERGENCE.  The default bound then solves the same matrix."""
-    torch, mmf = require_gpu()
-    n = 2100
-    H = _herm(n, 4242)
-    log("two-stage chase with a 1 us wait bound")
-    w, Pt, info = mmf.eigh(to_dev_cm(torch, H), limits={"chase_wait_us": 1})
-    torch.cuda.synchronize()
-    log(f"  info {int(info.item())}")
-    assert int(info.item()) == mmf.MMF_ERR_NO_CONVERGENCE
-    w, Pt, info = mmf.eigh(to_dev_cm(torch, H), limits={})
-    torch.cuda.synchronize()
-    assert int(info.item()) == 0
-    wo, _ = oracle.eigh(H)
-    assert np.abs(w.cpu().numpy() - wo).max() <= 1e-10 * max(1.0, np.abs(wo).max())
-
-
 def test_two_stage_padded_ld(two_stage):
     torch, mmf = require_gpu()
     n, pad = 150, 9
