@@ -11,8 +11,10 @@ M = 20808 (complex128), U at 256 times; the default run also solves the
 sample.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--no-large] [--no-cpu-baseline]
-                  [--workload ladder20808|spec41616|tls82|ladder_N<n>|precision41616|
+                  [--workload ladder20808|spec41616|tls82|ladder_N<n>|band20816|precision41616|
                               sweep512|batch512|serve|lattice_sweep|window_lattice]
+                  [--band]   (band20816 and the other single solves: mmf_eigh_band at the
+                              workload's Floquet half-bandwidth)
                   [--batch-mode executor|grouped|plan] [--prec c128|c64_refined|c64_raw]
                   [--sync-every N]   (launch throttle for rocprofv3 counter runs)
 """
@@ -74,6 +76,9 @@ def workload(name):
     elif name.startswith("ladder_N"):
         n = int(name[len("ladder_N"):])
         p, ts, t0 = cfg2_large(N=(n, n))
+    elif name == "band20816":
+        from workloads import one_drive_band
+        p, ts, t0 = one_drive_band()
     else:
         raise SystemExit(f"unknown workload {name}")
     return p, ts, t0
@@ -511,7 +516,13 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
     HF = torch.empty((M, M), dtype=torch.complex128, device=dev)
     w = torch.empty(M, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
-    ework = torch.empty(mmf.eigh_workspace_bytes(M, prec), dtype=torch.uint8, device=dev)
+    band = getattr(args, "band", False) and prec == mmf.MMF_C128
+    bw = mmf.floquet_half_bandwidth(p)
+    if band:
+        print(f"[bench] band path: half-bandwidth {bw}", file=sys.stderr, flush=True)
+        ework = torch.empty(mmf.eigh_band_workspace_bytes(M, bw), dtype=torch.uint8, device=dev)
+    else:
+        ework = torch.empty(mmf.eigh_workspace_bytes(M, prec), dtype=torch.uint8, device=dev)
 
     b = C.c_size_t(0)
     mmf.call("mmf_evolve_workspace", dp.ref, C.c_int32(T), C.byref(b))
@@ -526,7 +537,10 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
         if ev: ev[0].record()
         mmf.build_floquet(dp, out=HF)
         if ev: ev[1].record()
-        mmf.eigh(HF, prec=prec, w=w, work=ework, info=info)
+        if band:
+            mmf.eigh_band(HF, bw, w=w, work=ework, info=info)
+        else:
+            mmf.eigh(HF, prec=prec, w=w, work=ework, info=info)
         if ev: ev[2].record()
         U = mmf.evolve(dp, HF, w, t0, tt, work=uwork)
         if ev: ev[3].record()
@@ -552,7 +566,7 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
     torch.cuda.synchronize()
     # dominant kernel: the HEMV of the one-stage reduction, or the
     # back-transformation by the bulge-chasing reflectors of the two-stage one
-    two_stage = prec == mmf.MMF_C128 and M >= mmf.eigh_two_stage_min()
+    two_stage = prec == mmf.MMF_C128 and (M >= mmf.eigh_two_stage_min() or (band and bw <= 64))
     if ktimer:
         mmf.call("mmf_ktimer_arm", b"bt2" if two_stage else b"hemv")
     t_start = time.perf_counter()
@@ -617,7 +631,8 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
         "data": "synthetic",
         "config": {"workload": name, "precision": args.prec, "D": D, "M": M, "times": T,
                    "drives": [float(x) for x in p.omega], "truncation": [int(x) for x in p.N],
-                   "reduction": "two-stage" if two_stage else "one-stage"},
+                   "reduction": (f"band (chase from the native half-bandwidth {bw})" if band
+                                 else "two-stage" if two_stage else "one-stage")},
         "eigh_tflops": eigh_tflops,
         "eigh_frac_fp64_peak": eigh_tflops / FP64_MFMA_PEAK_TFLOPS,
         "stage_ms": med,
@@ -659,7 +674,8 @@ def run_single(args, torch, mmf, name, steps, warmup, prec, ktimer=True, check_e
     # its GEMMs and the stage-2 kernel form each complex product from three
     # real ones, which this count does not discount); the one-stage path the
     # nominal (40/3) M^3
-    exec_flops = (16.0 / 3.0 + 10.0 + 8.0) * M ** 3 if two_stage else eigh_flops
+    # (the band path: only the stage-2 back-transformation's 10 M^3)
+    exec_flops = (10.0 * M ** 3 if band else (16.0 / 3.0 + 10.0 + 8.0) * M ** 3 if two_stage else eigh_flops)
     out["eigh_executed_tflops"] = exec_flops / t_eigh / 1e12
     out["eigh_executed_frac_fp64_peak"] = out["eigh_executed_tflops"] / FP64_MFMA_PEAK_TFLOPS
     out["eigh_roofline"] = {
@@ -680,6 +696,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the one-solve M = 41616 measurement")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-ktimer", action="store_true")
+    ap.add_argument("--band", action="store_true",
+                    help="solve with mmf_eigh_band at the workload's Floquet half-bandwidth")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--sync-every", type=int, default=0,
                     help="profiling aid: the library waits for the device after every n launches")

@@ -287,6 +287,26 @@ int mmf_eigh_window(int64_t M, mmf_z *A, int64_t lda, double vl, double vu, int6
                     double *w, mmf_z *Z, int64_t ldz, int32_t *count, void *work,
                     size_t work_bytes, int32_t *dev_info, void *stream);
 
+/* Workspace bytes of mmf_eigh_band for order M and half-bandwidth b.
+ * Errors: -1 M < 0, -2 b < 0, -3 bytes NULL. */
+int mmf_eigh_band_workspace(int64_t M, int64_t b, size_t *bytes);
+
+/* Band-aware eigendecomposition (Sec. 3.2; the band half of the paper's sparse
+ * path): mmf_eigh (complex128) for a Hermitian A whose entries vanish below
+ * its b-th subdiagonal, b stated by the caller (entries beyond it are not
+ * read).  A Floquet matrix of one drive with harmonics up to h is banded with
+ * b = D h + D - 1 (Eq. 6 in the block order of App. A).  With b <= 64 and
+ * M > 64 the band goes straight to the bulge chase of the two-stage solver: no dense ->
+ * band stage and no first back-transformation, so the eigensolve costs the
+ * chase, divide and conquer and the 8 M^3 of the second back-transformation.
+ * Otherwise the call is mmf_eigh with prec MMF_C128.  A: dev M x M (lda),
+ * lower band read; on exit column a holds the eigenvector of w[a].
+ * w: dev [M] ascending.  dev_info as for mmf_eigh.
+ * Errors: -1 M < 0, -2 A NULL, -3 lda < M, -4 b < 0, -5 w NULL, -6/-7
+ * workspace NULL or too small, -8 dev_info NULL, MMF_ERR_HIP. */
+int mmf_eigh_band(int64_t M, mmf_z *A, int64_t lda, int64_t b, double *w, void *work, size_t work_bytes,
+                  int32_t *dev_info, void *stream);
+
 /* Workspace bytes that mmf_eigvalsh_batched needs (count, n as for
  * mmf_eigh_batched_workspace; prec MMF_C128 or MMF_C64_RAW).
  * Errors: -1 count < 0, -2 n NULL or an n[c] < 0, -3 prec unsupported, -4 bytes NULL. */

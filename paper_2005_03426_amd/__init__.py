@@ -222,7 +222,47 @@ def eigh_window(At, vl: float, vu: float, kmax: int, work=None, stream=None):
     return w[:kmax], Zt[:kmax], count, info
 
 
-def eigvalsh_batched_workspace_bytes(sizes, prec: int = MMF_C128) -> int:
+def eigh_band_workspace_bytes(M: int, b: int) -> int:
+    nb = C.c_size_t(0)
+    call("mmf_eigh_band_workspace", C.c_int64(M), C.c_int64(b), C.byref(nb))
+    return int(nb.value)
+
+
+def eigh_band(At, b: int, w=None, work=None, info=None, stream=None):
+    """In-place eigendecomposition (complex128) of the Hermitian matrix held
+    column-major in At whose entries vanish below its b-th subdiagonal (see
+    mmf_eigh_band; b = D h_max for a one-drive Floquet matrix).  Returns
+    (w, At, info) as eigh."""
+    torch = _torch()
+    M = At.shape[0]
+    dev = At.device
+    if w is None:
+        w = torch.empty(M, dtype=torch.float64, device=dev)
+    if work is None:
+        work = _workspace(eigh_band_workspace_bytes(M, b), dev)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+    call("mmf_eigh_band", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), C.c_int64(b), _ptr(w),
+         _ptr(work), C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return w, At, info
+
+
+def floquet_half_bandwidth(p) -> int:
+    """Half-bandwidth of the Floquet matrix of a problem statement (workloads.
+    Problem) in the block order of App. A: a coupling of harmonic h on axis l
+    sits h * prod_{l' < l} (2 N_l' + 1) blocks of D rows off the diagonal (none
+    when h > 2 N_l), so the farthest entry is D - 1 rows beyond that block
+    offset times D."""
+    import numpy as np
+    D = int(np.asarray(p.E).shape[0])
+    stride = [1]
+    for n in p.N:
+        stride.append(stride[-1] * (2 * int(n) + 1))
+    far = 0
+    for ax, h in zip(p.axis, p.harm):
+        if int(h) <= 2 * int(p.N[ax]):
+            far = max(far, int(h) * stride[ax])
+    return D * far + (D - 1)
     n = (C.c_int64 * max(len(sizes), 1))(*[int(m) for m in sizes])
     b = C.c_size_t(0)
     call("mmf_eigvalsh_batched_workspace", C.c_int64(len(sizes)), n, C.c_int(prec), C.byref(b))

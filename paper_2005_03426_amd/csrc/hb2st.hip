@@ -339,6 +339,30 @@ int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e
   return hb2st_grouped(pr, &n, 1, st);
 }
 
+// Band array of a matrix that is already banded: AB[o + c LDAB] = A[c + o, c]
+// for offsets o <= b (b <= BW; the diagonal's imaginary part dropped), zero
+// for the other offsets (the bulge rows included).  Entries of A beyond the
+// b-th subdiagonal are not read.
+__global__ void hb_band_from_dense(int64_t n, const cd *A, int64_t lda, int64_t b, cd *AB) {
+  const int64_t c = blockIdx.x;
+  if (c >= n) return;
+  const int o = threadIdx.x;                        // 0 .. LDAB - 1
+  const int64_t r = c + o;
+  cd v = cmake(0.0, 0.0);
+  if (o <= b && r < n) v = A[r + c * lda];
+  if (o == 0) v.im = 0.0;
+  AB[o + c * (int64_t)LDAB] = v;
+}
+
+int hb_band_from_dense_run(int64_t n, const mmf_z *A, int64_t lda, int64_t b, mmf_z *AB, hipStream_t st) {
+  if (n <= 0) return MMF_OK;
+  if (b < 0 || b > BW) return MMF_ERR_NOT_IMPLEMENTED;
+  hipLaunchKernelGGL(hb_band_from_dense, dim3((unsigned)n), dim3(LDAB), 0, st, n, reinterpret_cast<const cd *>(A),
+                     lda, b, reinterpret_cast<cd *>(AB));
+  MMF_LAUNCH_CHECK();
+  return MMF_OK;
+}
+
 // Batch (eigenvalues only): compact reflector storage, V2[c] holds n[c] x BW
 // and tau2[c] n[c] entries.
 int hb2st_batched(int64_t count, const int64_t *n, mmf_z *const *AB, mmf_z *const *V2, mmf_z *const *tau2,

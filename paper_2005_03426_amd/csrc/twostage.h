@@ -59,6 +59,9 @@ inline int64_t hb_npos(int64_t n) { return n > 1 ? (n - 2) / BW + 1 : 0; }
 inline size_t hb_v2_elems(int64_t n) { return n > 1 ? (size_t)hb_voff(n, hb_npos(n)) : 1; }
 // table: STAGE_TABLE_BYTES of device memory for the one-entry problem table
 int hb2st_run(int64_t n, mmf_z *AB, mmf_z *V2, mmf_z *tau2, double *d, double *e, void *table, hipStream_t st);
+// The band array of a matrix A whose entries vanish below its b-th
+// subdiagonal (b <= BW), for the chase without the dense -> band stage.
+int hb_band_from_dense_run(int64_t n, const mmf_z *A, int64_t lda, int64_t b, mmf_z *AB, hipStream_t st);
 
 // Batches (eigenvalues only): problem c has order n[c], its own stage-1
 // workspace stage[c] (he2hb_ws_bytes(n[c])), band array AB[c] (n x LDAB), and

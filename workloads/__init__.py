@@ -187,6 +187,21 @@ def cfg4_precision(seed: int = 4, N=(25, 25), T: int = 256) -> tuple[Problem, np
     return p, time_grid(20.0 * math.pi / w[0], T), 0.0
 
 
+def one_drive_band(seed: int = 6, D: int = 16, N: int = 650, T: int = 256) -> tuple[Problem, np.ndarray, float]:
+    """16-level random spectrum in [0,20) under one strong drive w = 1 with a
+    coupling C = GUE(16, 2.0) (V = C/2) and its second harmonic C2 = GUE(16,
+    0.5) (V2 = C2/2), truncation +-650 (strong driving needs many photon
+    blocks): dimension 16*1301 = 20816, a banded Floquet matrix of half-width
+    16*2 + 15 = 47 in the block order of App. A.  256 times in [0, 20 pi]."""
+    rng = np.random.default_rng(seed)
+    E = _ladder(rng, D, 20.0)
+    C1 = gue(rng, D, 2.0)
+    C2 = gue(rng, D, 0.5)
+    p = Problem(E=E, omega=np.array([1.0]), N=[N, ], axis=[0, 0], harm=[1, 2],
+                V=[C1 / 2.0, C2 / 2.0], name=f"spec{D}_1drive_N{N}")
+    return p, time_grid(20.0 * math.pi, T), 0.0
+
+
 def _scaled_gue(rng, D, a):
     G = gue(rng, D, 1.0)
     return a * G / np.linalg.norm(G, 2)
