@@ -50,7 +50,7 @@ def _check(H, b):
     assert np.abs(Phi.conj().T @ Phi - np.eye(n)).max() < 1e-12 * max(1.0, n / 100)
 
 
-@pytest.mark.parametrize("n,b", [(2, 1), (5, 10), (64, 3), (65, 0), (65, 1), (65, 64), (66, 70 - 10), (129, 64),
+@pytest.mark.parametrize("n,b", [(2, 1), (5, 10), (64, 3), (65, 0), (65, 1), (65, 64), (66, 60), (129, 64),
                                  (130, 17), (200, 64), (300, 1), (300, 40), (1100, 31), (1100, 64)])
 def test_band_random(n, b):
     log(f"band eigh random n={n} b={b}")
