@@ -263,6 +263,9 @@ def floquet_half_bandwidth(p) -> int:
         if int(h) <= 2 * int(p.N[ax]):
             far = max(far, int(h) * stride[ax])
     return D * far + (D - 1)
+
+
+def eigvalsh_batched_workspace_bytes(sizes, prec: int = MMF_C128) -> int:
     n = (C.c_int64 * max(len(sizes), 1))(*[int(m) for m in sizes])
     b = C.c_size_t(0)
     call("mmf_eigvalsh_batched_workspace", C.c_int64(len(sizes)), n, C.c_int(prec), C.byref(b))
