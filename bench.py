@@ -167,6 +167,7 @@ def run_executor_bench(args, torch, mmf):
         st.update({"wall_s": wall, "eigh_tflops": flops / wall / 1e12, "failed": bad,
                    "failed_rid_M_D_F_info": failed[:64], "retried_c128": len(retried),
                    "retried_rid_M_D_F": retried[:64],
+                   "band_path": sum(1 for r in done if getattr(r, "_band", None) is not None),
                    "rejected": len(ex.rejected), "batches": len(ex.batches),
                    "mean_batch": float(np.mean(ex.batches)) if ex.batches else 0.0})
         print(f"[bench] {args.workload} {prec_name}: {st}", file=sys.stderr, flush=True)

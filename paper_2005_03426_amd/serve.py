@@ -15,7 +15,12 @@ does not depend on the batch it joined (the grouped kernels do the same
 arithmetic per matrix as a single solve).  A request whose mixed-precision
 eigensolve reports non-convergence is solved again in complex128 on the
 same stream (its result then says `retried_c128`), unless the executor was
-made with retry_c128=False.  A batch whose workspace the caching allocator
+made with retry_c128=False.  With `band_min` set, a complex128 request whose
+Floquet matrix is banded within its 64th subdiagonal (one drive with
+D h + D - 1 <= 64) and of order at least band_min is solved alone through the
+band-aware eigensolver (mmf_eigh_band: no dense -> band stage).  That routing
+is off by default: the 2000-request serving benchmark with it ended in a GPU
+memory fault whose cause has not been found.  A batch whose workspace the caching allocator
 cannot place (fragmented free blocks) is solved one request at a time.
 Results stay on the device until
 the caller reads them.  Latency runs from a request's arrival to the moment
@@ -31,16 +36,19 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (DeviceProblem, build_floquet, eigh, eigh_batched, evolve, avg_prob, eigh_workspace_bytes,
-               call, MMF_C128)
+from . import (DeviceProblem, build_floquet, eigh, eigh_band, eigh_batched, evolve, avg_prob, eigh_workspace_bytes,
+               eigh_band_workspace_bytes, floquet_half_bandwidth, call, MMF_C128)
+
+BAND_MAX = 64          # widest native half-bandwidth the band-aware eigensolver takes
 
 
-def footprint_bytes(M: int, D: int, T: int, prec: int = MMF_C128) -> int:
+def footprint_bytes(M: int, D: int, T: int, prec: int = MMF_C128, band: int | None = None) -> int:
     """HBM bytes a solve holds while in flight (matrix + workspaces + outputs;
-    for a mixed-precision request also what its complex128 retry needs)."""
+    for a mixed-precision request also what its complex128 retry needs; with
+    `band`, the band-aware eigensolver's workspace)."""
     S = M // D
     ev = T * S * 16 + T * D * M * 16 + ((M + 2047) // 2048) * T * D * D * 16
-    ws = eigh_workspace_bytes(M, prec)
+    ws = eigh_band_workspace_bytes(M, band) if band is not None else eigh_workspace_bytes(M, prec)
     if prec != MMF_C128:
         ws = max(ws, eigh_workspace_bytes(M, MMF_C128))
     return 16 * M * M + ws + ev + 8 * M + 16 * T * D * D + 4096
@@ -66,7 +74,8 @@ class Request:
 
 class Executor:
     def __init__(self, slots: int = 4, hbm_budget: int | None = None, device: str = "cuda",
-                 max_batch: int = 64, progress=None, retry_c128: bool = True, limits: dict | None = None):
+                 max_batch: int = 64, progress=None, retry_c128: bool = True, limits: dict | None = None,
+                 band_min: int | None = None):
         """slots: streams (and worker threads); hbm_budget: bytes of admitted
         footprints at once (default 0.8 of the free HBM); max_batch: requests
         per grouped eigensolve; progress: callable(done_count) called as
@@ -74,11 +83,15 @@ class Executor:
         complex128 when its eigensolve reports non-convergence; limits:
         iteration limits of mmf_eigh_ex (e.g. {"refine_max_iters": 1}) to
         force the failure handling from the host; with limits every request
-        is solved alone (the grouped eigensolver takes none)."""
+        is solved alone (the grouped eigensolver takes none); band_min: order
+        from which narrow-band complex128 requests take the band-aware
+        eigensolver (None, the default: never; the serving benchmark with
+        band_min = 1024 ended in a GPU fault whose cause is not known)."""
         import torch
         self.torch = torch
         self.retry_c128 = retry_c128
         self.limits = limits
+        self.band_min = band_min if limits is None else None
         if limits is not None:
             max_batch = 1
         self.device = device
@@ -109,7 +122,10 @@ class Executor:
         with torch.cuda.stream(stream):
             dps = [DeviceProblem(r.problem, self.device) for r in reqs]
             HFs = [build_floquet(dp, stream=stream) for dp in dps]
-            if len(reqs) == 1:
+            if len(reqs) == 1 and reqs[0]._band is not None:
+                w, Pt, info = eigh_band(HFs[0], reqs[0]._band, stream=stream)
+                ws, Pts, infos = [w], [Pt], [info]
+            elif len(reqs) == 1:
                 w, Pt, info = eigh(HFs[0], prec=reqs[0].prec, stream=stream, limits=self.limits)
                 ws, Pts, infos = [w], [Pt], [info]
             else:
@@ -234,8 +250,12 @@ class Executor:
             M = D
             for n in r.problem.N:
                 M *= 2 * int(n) + 1
-            r._fp = footprint_bytes(M, D, len(r.times), r.prec)
-            r._cls = int(M).bit_length()                 # octave of M
+            b = floquet_half_bandwidth(r.problem)
+            r._band = (b if self.band_min is not None and r.prec == MMF_C128 and b <= BAND_MAX
+                       and M >= self.band_min else None)
+            r._fp = footprint_bytes(M, D, len(r.times), r.prec, r._band)
+            # octave of M; a band-aware request is a class of its own (solved alone)
+            r._cls = int(M).bit_length() if r._band is None else ("band", id(r))
             if r._fp > self.budget:
                 self.rejected.append(r)
         reqs = [r for r in reqs if r._fp <= self.budget]

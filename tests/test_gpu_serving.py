@@ -46,6 +46,44 @@ def test_result_same_alone_and_in_mix(prec, burst):
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
 
 
+@pytest.mark.skip(reason="the executor's band routing (band_min) is switched off: the 2000-request serving "
+                         "benchmark with it ended in a GPU memory fault whose cause has not been found")
+@pytest.mark.parametrize("burst", [False, True])
+def test_band_requests_take_the_band_solver_alone_and_in_mix(burst):
+    """A complex128 request whose Floquet matrix is banded within 64 (one
+    drive, D h + D - 1 <= 64) and of order >= band_min is solved alone through
+    mmf_eigh_band: its result equals the direct band solve bit for bit, alone
+    and among two-drive requests of its size class."""
+    torch, mmf = require_gpu()
+    from paper_2005_03426_amd import serve
+    band = [random_problem(4, (128,), seed=31), random_problem(5, (110,), seed=32)]     # M = 1028, 1105
+    wide = [random_problem(4, (12, 10), seed=40 + s) for s in range(4)]               # M = 2100, b = 103
+    for p in band:
+        assert mmf.floquet_half_bandwidth(p) <= 64
+    for p in wide:
+        assert mmf.floquet_half_bandwidth(p) > 64
+    direct = []
+    for p in band:
+        dp = mmf.DeviceProblem(p)
+        w, Pt, info = mmf.eigh_band(mmf.build_floquet(dp), mmf.floquet_half_bandwidth(p))
+        torch.cuda.synchronize()
+        assert int(info.item()) == 0
+        direct.append(w)
+    mix = band + wide
+    arrivals = np.zeros(len(mix)) if burst else np.linspace(0.0, 0.02, len(mix))
+    ex = serve.Executor(slots=4, band_min=1024)
+    done = ex.run(_reqs(serve, mix, arrivals))
+    by_problem = {id(r.problem): r for r in done}
+    for p, w in zip(band, direct):
+        r = by_problem[id(p)]
+        assert r._band is not None
+        assert torch.equal(r.result["w"], w)
+        assert int(r.result["info"].item()) == 0
+    for p in wide:
+        assert by_problem[id(p)]._band is None
+    log(f"band requests burst={burst}: batches {ex.batches}")
+
+
 def test_admission_rejects_oversized_and_respects_budget():
     torch, mmf = require_gpu()
     from paper_2005_03426_amd import serve
