@@ -12,7 +12,7 @@ sample.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--no-large] [--no-cpu-baseline]
                   [--workload ladder20808|spec41616|tls82|ladder_N<n>|band20816|precision41616|
-                              sweep512|batch512|serve|lattice_sweep|window_lattice]
+                              sweep512|batch512|serve|lattice_sweep|window_lattice|band_window20816]
                   [--band]   (band20816 and the other single solves: mmf_eigh_band at the
                               workload's Floquet half-bandwidth)
                   [--batch-mode executor|grouped|plan] [--prec c128|c64_refined|c64_raw]
@@ -436,6 +436,58 @@ def run_window(args, torch, mmf):
     print(json.dumps(out), flush=True)
 
 
+def run_band_window(args, torch, mmf):
+    """Floquet states of the one-drive workload (16 levels, harmonics 1 and 2,
+    +-650, M = 20816, half-bandwidth 47): the window [-omega/2, omega/2)
+    through the band-aware partial-spectrum solver, against the band-aware
+    full solve and the dense partial-spectrum solver on the same matrix."""
+    from workloads import one_drive_band
+    dev = "cuda"
+    p, ts, t0 = one_drive_band()
+    dp = mmf.DeviceProblem(p, dev)
+    M = dp.M
+    b = mmf.floquet_half_bandwidth(p)
+    HF = torch.empty((M, M), dtype=torch.complex128, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def one(kind):
+        mmf.build_floquet(dp, out=HF)
+        ev[0].record()
+        if kind == "band_window":
+            out = mmf.eigh_band_window(HF, b, -0.5, 0.5, 64)
+        elif kind == "band_full":
+            out = mmf.eigh_band(HF, b)
+        else:
+            out = mmf.eigh_window(HF, -0.5, 0.5, 64)
+        ev[1].record()
+        return out
+
+    res = {}
+    for kind in ("band_window", "band_full", "dense_window"):
+        for _ in range(args.warmup):
+            one(kind)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.steps):
+            out = one(kind)
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        res[kind] = float(np.median(ms))
+        if kind == "band_window":
+            res["count"] = int(out[2].item())
+        print(f"[bench] band window: {kind} {res[kind]:.1f} ms", file=sys.stderr, flush=True)
+    out = {
+        "metric": "Floquet eigensolves/s", "value": 1e3 / res["band_window"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["band_window"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "band_window20816", "D": dp.D, "M": M, "half_bandwidth": b, "window": [-0.5, 0.5],
+                   "states": res["count"]},
+        "band_window_ms": res["band_window"], "band_full_ms": res["band_full"],
+        "dense_window_ms": res["dense_window"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_precision(args, torch, mmf):
     """16-level spectrum under two drives, M = 41616: the complex64 paths
     (raw, and refined in FP64) against the plain complex128 solve on the same
@@ -723,6 +775,9 @@ def main():
         mmf.call("mmf_profile_sync_every", C.c_int64(args.sync_every))
     if args.workload == "precision41616":
         run_precision(args, torch, mmf)
+        return
+    if args.workload == "band_window20816":
+        run_band_window(args, torch, mmf)
         return
     if args.workload == "window_lattice":
         run_window(args, torch, mmf)

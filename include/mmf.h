@@ -307,6 +307,24 @@ int mmf_eigh_band_workspace(int64_t M, int64_t b, size_t *bytes);
 int mmf_eigh_band(int64_t M, mmf_z *A, int64_t lda, int64_t b, double *w, void *work, size_t work_bytes,
                   int32_t *dev_info, void *stream);
 
+/* Workspace bytes of mmf_eigh_band_window for order M, half-bandwidth b and at
+ * most kmax vectors.  Errors: -1 M < 0, -2 b < 0, -3 kmax < 0, -4 bytes NULL. */
+int mmf_eigh_band_window_workspace(int64_t M, int64_t b, int64_t kmax, size_t *bytes);
+
+/* Partial spectrum of a banded Hermitian matrix (Sec. 3.2: both halves of the
+ * paper's sparse path): mmf_eigh_window for an A whose entries vanish below
+ * its b-th subdiagonal.  With b <= 64 and M > 64 the band goes straight to the
+ * bulge chase and only the window's k eigenvectors are back-transformed by the
+ * chase reflectors (8 M^2 k flops, nothing else of order M^3), and A is only
+ * read; otherwise the call is mmf_eigh_window (which destroys A).  Arguments
+ * as for mmf_eigh_window with b after lda.
+ * Errors: -1 M < 0, -2 A NULL, -3 lda, -4 b < 0, -5 not vl < vu, -7 kmax < 0,
+ *   -8 w NULL, -9 Z NULL, -10 ldz < M, -11 count NULL, -12/-13 workspace,
+ *   -14 dev_info NULL. */
+int mmf_eigh_band_window(int64_t M, const mmf_z *A, int64_t lda, int64_t b, double vl, double vu, int64_t kmax,
+                         double *w, mmf_z *Z, int64_t ldz, int32_t *count, void *work, size_t work_bytes,
+                         int32_t *dev_info, void *stream);
+
 /* Workspace bytes that mmf_eigvalsh_batched needs (count, n as for
  * mmf_eigh_batched_workspace; prec MMF_C128 or MMF_C64_RAW).
  * Errors: -1 count < 0, -2 n NULL or an n[c] < 0, -3 prec unsupported, -4 bytes NULL. */

@@ -43,7 +43,7 @@ __all__ = [
     "hamiltonian_at", "rk4_evolve", "jacobi_eigh", "householder_tridiag_apply",
     "zero_site", "tridiag_eigh", "quasienergies", "restrict_modes", "dressed_evolution",
     "spin_ops", "spin_drive", "avg_prob_degenerate", "evolve_expm_sparse",
-    "build_floquet_sparse", "quasienergies_near",
+    "build_floquet_sparse", "quasienergies_near", "eigvalsh",
 ]
 
 
@@ -269,11 +269,17 @@ def eigh(H: np.ndarray):
     return w, Phi
 
 
-def quasienergies(p) -> np.ndarray:
-    """All eigenvalues (ascending) of the truncated H_F, without eigenvectors:
+def eigvalsh(H: np.ndarray) -> np.ndarray:
+    """All eigenvalues (ascending) of a Hermitian matrix, without eigenvectors:
     LAPACK's eigenvalue-only Hermitian solver through NumPy (the paper's
-    LAPACK_FULLEIGENVALUES call on the Floquet matrix, Sec. 4.2)."""
-    return np.linalg.eigvalsh(build_floquet(p))
+    LAPACK_FULLEIGENVALUES call, Sec. 3.2)."""
+    return np.linalg.eigvalsh(H)
+
+
+def quasienergies(p) -> np.ndarray:
+    """All eigenvalues (ascending) of the truncated H_F, without eigenvectors
+    (the paper's LAPACK_FULLEIGENVALUES call on the Floquet matrix, Sec. 4.2)."""
+    return eigvalsh(build_floquet(p))
 
 
 def jacobi_eigh(H: np.ndarray, sweeps: int = 30, tol: float = 1e-15):

@@ -247,6 +247,28 @@ def eigh_band(At, b: int, w=None, work=None, info=None, stream=None):
     return w, At, info
 
 
+def eigh_band_window(At, b: int, vl: float, vu: float, kmax: int, work=None, stream=None):
+    """Eigenpairs with eigenvalue in [vl, vu) of the banded Hermitian matrix
+    in At (column-major, half-bandwidth b; kept when b <= 64, see
+    mmf_eigh_band_window).  Returns (w, Zt, count, info) as eigh_window."""
+    torch = _torch()
+    M = At.shape[0]
+    dev = At.device
+    kmax = int(min(kmax, M))
+    w = torch.zeros(max(kmax, 1), dtype=torch.float64, device=dev)
+    Zt = torch.zeros((max(kmax, 1), M), dtype=torch.complex128, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    if work is None:
+        nb = C.c_size_t(0)
+        call("mmf_eigh_band_window_workspace", C.c_int64(M), C.c_int64(b), C.c_int64(kmax), C.byref(nb))
+        work = _workspace(nb.value, dev)
+    call("mmf_eigh_band_window", C.c_int64(M), _ptr(At), C.c_int64(At.stride(0) if M else 1), C.c_int64(b),
+         C.c_double(vl), C.c_double(vu), C.c_int64(kmax), _ptr(w), _ptr(Zt), C.c_int64(max(M, 1)), _ptr(count),
+         _ptr(work), C.c_size_t(work.numel()), _ptr(info), _stream(stream))
+    return w[:kmax], Zt[:kmax], count, info
+
+
 def floquet_half_bandwidth(p) -> int:
     """Half-bandwidth of the Floquet matrix of a problem statement (workloads.
     Problem) in the block order of App. A: a coupling of harmonic h on axis l

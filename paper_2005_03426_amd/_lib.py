@@ -69,6 +69,10 @@ _SIGS = {
     "mmf_eigh_band_workspace": (C.c_int, [C.c_int64, C.c_int64, C.c_void_p]),
     "mmf_eigh_band": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                 C.c_size_t, C.c_void_p, C.c_void_p]),
+    "mmf_eigh_band_window_workspace": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_void_p]),
+    "mmf_eigh_band_window": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                                       C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_size_t, C.c_void_p, C.c_void_p]),
     "mmf_eigh_window": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,
                                   C.c_void_p, C.c_void_p]),

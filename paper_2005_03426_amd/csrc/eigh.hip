@@ -299,6 +299,54 @@ extern "C" int mmf_eigh_band(int64_t M, mmf_z *A, int64_t lda, int64_t b, double
   return eigh_band_run(M, A, lda, b, w, work, dev_info, (hipStream_t)stream);
 }
 
+extern "C" int mmf_eigh_band_window_workspace(int64_t M, int64_t b, int64_t kmax, size_t *bytes) {
+  if (M < 0) return -1;
+  if (b < 0) return -2;
+  if (kmax < 0) return -3;
+  if (!bytes) return -4;
+  if (!band_path(M, b)) return mmf_eigh_window_workspace(M, kmax, bytes);
+  *bytes = eigh2_ws(M, kmax < M ? kmax : M, true, nullptr).bytes;
+  return MMF_OK;
+}
+
+extern "C" int mmf_eigh_band_window(int64_t M, const mmf_z *A, int64_t lda, int64_t b, double vl, double vu,
+                                    int64_t kmax, double *w, mmf_z *Z, int64_t ldz, int32_t *count, void *work,
+                                    size_t work_bytes, int32_t *dev_info, void *stream) {
+  if (M < 0) return -1;
+  if (!A && M > 0) return -2;
+  if (lda < M || lda < 1) return -3;
+  if (b < 0) return -4;
+  if (!(vl < vu)) return -5;
+  if (kmax < 0) return -7;
+  if (!w && kmax > 0) return -8;
+  if (!Z && kmax > 0) return -9;
+  if (ldz < M || ldz < 1) return -10;
+  if (!count) return -11;
+  if (!work) return -12;
+  if (!dev_info) return -14;
+  if (!band_path(M, b)) {
+    // the dense window path (it destroys A, which this entry point promises to keep)
+    const int rc = mmf_eigh_window(M, const_cast<mmf_z *>(A), lda, vl, vu, kmax, w, Z, ldz, count, work, work_bytes,
+                                   dev_info, stream);
+    return rc == -12 ? -13 : rc;
+  }
+  const int64_t kk = kmax < M ? kmax : M;
+  if (work_bytes < eigh2_ws(M, kk, true, nullptr).bytes) return -13;
+  hipStream_t st = (hipStream_t)stream;
+  const Eigh2Ws ws = eigh2_ws(M, kk, true, work);
+  int rc = hb_band_from_dense_run(M, A, lda, b, ws.AB, st);
+  if (rc) return rc;
+  rc = hb2st_run(M, ws.AB, ws.V2, ws.tau2, ws.wall, ws.e, ws.table, st);
+  if (rc) return rc;
+  rc = stedc_run(M, ws.wall, ws.e, ws.Z, M, ws.rest, ws.rest_bytes, dev_info, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(eigh_window_gather, dim3(kk > 0 ? cdiv(M, 256) : 1, kk > 0 ? (unsigned)kk : 1),
+                     dim3(kk > 0 ? 256 : 1), 0, st, M, ws.wall, ws.Z, vl, vu, kk, w, ws.Zk, count);
+  MMF_LAUNCH_CHECK();
+  if (kk == 0) return MMF_OK;
+  return bt2_run(M, kk, ws.V2, ws.tau2, ws.Zk, M, Z, ldz, ws.rest, ws.rest_bytes, st);
+}
+
 extern "C" int mmf_eigh_batched_workspace(int64_t count, const int64_t *n, int prec, size_t *bytes) {
   if (count < 0) return -1;
   if (count > 0 && !n) return -2;

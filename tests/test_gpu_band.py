@@ -150,3 +150,134 @@ def test_band_full_size_spot_checks_against_oracle():
         err = np.abs(inside - wo).max() / scale
         log(f"  quasienergies near {sigma}: {err:.2e} normwise")
         assert err < 1e-10
+
+
+# ------------------------------------------------------------ partial spectrum
+def _check_window(H, vl, vu, kmax, w, Zt, count, info):
+    wo, _ = oracle.eigh(H)
+    sel = np.nonzero((wo >= vl) & (wo < vu))[0]
+    assert int(info.item()) == 0
+    assert int(count.item()) == len(sel)
+    k = min(len(sel), kmax)
+    wg = w.cpu().numpy()[:k]
+    Z = Zt.cpu().numpy()[:k].T                      # columns = eigenvectors
+    scale = max(1.0, np.abs(wo).max())
+    assert np.abs(wg - wo[sel[:k]]).max(initial=0.0) <= 1e-10 * scale
+    if k:
+        assert np.linalg.norm(H @ Z - Z * wg) / max(1.0, np.linalg.norm(H)) < 1e-12
+        assert np.abs(Z.conj().T @ Z - np.eye(k)).max() < 1e-12
+    return k
+
+
+@pytest.mark.parametrize("n,b,vl,vu,kmax", [(300, 17, -0.5, 0.7, 300), (300, 17, -0.5, 0.7, 10),
+                                            (1100, 64, -1.0, 1.0, 1100), (129, 3, 50.0, 60.0, 5),
+                                            (65, 0, -100.0, 100.0, 65), (200, 40, -3.0, 3.0, 0)])
+def test_band_window_random(n, b, vl, vu, kmax):
+    torch, mmf = require_gpu()
+    H = _banded(n, b, 900 + n + b)
+    At = to_dev_cm(torch, H)
+    A0 = At.clone()
+    log(f"band window n={n} b={b} [{vl},{vu}) kmax={kmax}")
+    out = mmf.eigh_band_window(At, b, vl, vu, kmax)
+    torch.cuda.synchronize()
+    _check_window(H, vl, vu, kmax, *out)
+    assert torch.equal(At, A0)                      # the band path only reads A
+
+
+def test_band_window_floquet_states_match_the_full_band_solve():
+    torch, mmf = require_gpu()
+    p = one_drive_band(N=40)[0]
+    b = mmf.floquet_half_bandwidth(p)
+    dp = mmf.DeviceProblem(p)
+    H = oracle.build_floquet(p)
+    log(f"band window floquet: M={dp.M} b={b}")
+    out = mmf.eigh_band_window(mmf.build_floquet(dp), b, -0.5, 0.5, 64)
+    wf, _, info = mmf.eigh_band(mmf.build_floquet(dp), b)
+    torch.cuda.synchronize()
+    k = _check_window(H, -0.5, 0.5, 64, *out)
+    assert k > 0 and int(info.item()) == 0
+    sel = (wf >= -0.5) & (wf < 0.5)
+    assert torch.equal(out[0][:k], wf[sel])          # the same tridiagonal and divide and conquer
+
+
+def test_band_window_wider_than_64_is_the_dense_window():
+    torch, mmf = require_gpu()
+    H = _banded(300, 100, 19)
+    log("band window b=100 against mmf_eigh_window")
+    w1, Z1, c1, i1 = mmf.eigh_band_window(to_dev_cm(torch, H), 100, -2.0, 2.0, 300)
+    w2, Z2, c2, i2 = mmf.eigh_window(to_dev_cm(torch, H), -2.0, 2.0, 300)
+    torch.cuda.synchronize()
+    assert int(i1.item()) == 0 and int(c1.item()) == int(c2.item())
+    assert torch.equal(w1, w2) and torch.equal(Z1, Z2)
+
+
+def test_band_window_argument_errors():
+    torch, mmf = require_gpu()
+    import ctypes as C
+    L = mmf.lib()
+    n, kmax = 80, 8
+    A = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    w = torch.empty(kmax, dtype=torch.float64, device="cuda")
+    Z = torch.empty((kmax, n), dtype=torch.complex128, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nb = C.c_size_t(0)
+    assert L.mmf_eigh_band_window_workspace(C.c_int64(n), C.c_int64(3), C.c_int64(kmax), C.byref(nb)) == 0
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    ptr = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+
+    def call(M=n, a=A, lda=n, b=3, vl=-1.0, vu=1.0, km=kmax, ww=w, zz=Z, ldz=n, c=cnt, wk=work,
+             nbytes=nb.value, inf=info):
+        return L.mmf_eigh_band_window(C.c_int64(M), ptr(a), C.c_int64(lda), C.c_int64(b), C.c_double(vl),
+                                      C.c_double(vu), C.c_int64(km), ptr(ww), ptr(zz), C.c_int64(ldz), ptr(c),
+                                      ptr(wk), C.c_size_t(nbytes), ptr(inf), None)
+    assert call(M=-1) == -1
+    assert call(a=None) == -2
+    assert call(lda=n - 1) == -3
+    assert call(b=-1) == -4
+    assert call(vl=1.0, vu=1.0) == -5
+    assert call(km=-1) == -7
+    assert call(ww=None) == -8
+    assert call(zz=None) == -9
+    assert call(ldz=n - 1) == -10
+    assert call(c=None) == -11
+    assert call(wk=None) == -12
+    assert call(nbytes=16) == -13
+    assert call(inf=None) == -14
+    assert call() == 0
+    out = C.c_size_t(0)
+    assert L.mmf_eigh_band_window_workspace(C.c_int64(-1), C.c_int64(3), C.c_int64(1), C.byref(out)) == -1
+    assert L.mmf_eigh_band_window_workspace(C.c_int64(n), C.c_int64(-1), C.c_int64(1), C.byref(out)) == -2
+    assert L.mmf_eigh_band_window_workspace(C.c_int64(n), C.c_int64(3), C.c_int64(-1), C.byref(out)) == -3
+    assert L.mmf_eigh_band_window_workspace(C.c_int64(n), C.c_int64(3), C.c_int64(1), None) == -4
+    torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(600)
+def test_band_window_full_size_against_oracle():
+    torch, mmf = require_gpu()
+    p, ts, t0 = one_drive_band()
+    dp = mmf.DeviceProblem(p)
+    M = dp.M
+    b = mmf.floquet_half_bandwidth(p)
+    log("one-drive band window M=20816: oracle sparse H_F")
+    Hs = oracle.build_floquet_sparse(p)
+    log("one-drive band window M=20816: GPU window [-0.5, 0.5)")
+    w, Zt, count, info = mmf.eigh_band_window(mmf.build_floquet(dp), b, -0.5, 0.5, 64)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    k = int(count.item())
+    assert 0 < k <= 64
+    w = w.cpu().numpy()[:k]
+    Z = Zt.cpu().numpy()[:k].T
+    hn = float(abs(Hs).sum(axis=0).max())
+    res = np.abs(Hs @ Z - Z * w[None, :]).max() / hn
+    log(f"  {k} states, residual against the oracle's H_F {res:.2e}")
+    assert res < 1e-12
+    assert np.abs(Z.conj().T @ Z - np.eye(k)).max() < 1e-12
+    wo = oracle.quasienergies_near(Hs, 0.0, k + 8)
+    wo = wo[(wo >= -0.5) & (wo < 0.5)]
+    assert wo.shape[0] == k
+    err = np.abs(w - wo).max() / max(1.0, np.abs(w).max())
+    log(f"  quasienergies against the oracle's shift-invert solver {err:.2e}")
+    assert err < 1e-10

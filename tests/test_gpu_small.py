@@ -70,7 +70,7 @@ def test_small_structured(kind):
     torch.cuda.synchronize()
     assert int(info.item()) == 0
     w, Phi = w.cpu().numpy(), from_dev_cm(Pt)
-    wo = np.linalg.eigvalsh(H)
+    wo = oracle.eigvalsh(H)
     scale = max(1.0, np.abs(wo).max())
     log(f"small {kind}: eig err {np.abs(w - wo).max() / scale:.2e}")
     assert np.abs(w - wo).max() <= 1e-12 * scale

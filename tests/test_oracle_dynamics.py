@@ -37,6 +37,17 @@ def test_jacobi_agrees_with_lapack():
         assert np.abs(P1 - P2).max() < 1e-10
 
 
+def test_eigvalsh_agrees_with_jacobi():
+    """The eigenvalue-only library route against the oracle's own Jacobi
+    method (an independent algorithm), on a Floquet matrix with a cluster."""
+    p = random_problem(3, (5, 1), seed=12)        # M = 3*11*3 = 99
+    H = oracle.build_floquet(p)
+    wj, _ = oracle.jacobi_eigh(H)
+    w = oracle.eigvalsh(H)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - wj).max() <= 1e-12 * max(1.0, np.abs(wj).max())
+
+
 def test_eigh_residual_and_orthogonality():
     p = random_problem(3, (3, 3), seed=4)
     H, w, Phi = _solve(p)
