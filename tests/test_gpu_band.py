@@ -281,3 +281,40 @@ def test_band_window_full_size_against_oracle():
     err = np.abs(w - wo).max() / max(1.0, np.abs(w).max())
     log(f"  quasienergies against the oracle's shift-invert solver {err:.2e}")
     assert err < 1e-10
+
+
+def test_band_padded_leading_dimensions():
+    """A and Z inside larger buffers (lda, ldz > M)."""
+    torch, mmf = require_gpu()
+    import ctypes as C
+    n, b, pad = 150, 20, 9
+    H = _banded(n, b, 77)
+    buf = torch.zeros((n, n + pad), dtype=torch.complex128, device="cuda")
+    buf[:, :n] = to_dev_cm(torch, H)
+    log("band eigh padded ld")
+    w, Pt, info = mmf.eigh_band(buf[:, :n], b)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Phi = from_dev_cm(Pt[:, :n])
+    wo, _ = oracle.eigh(H)
+    assert np.abs(w.cpu().numpy() - wo).max() <= 1e-10 * max(1.0, np.abs(wo).max())
+    assert np.linalg.norm(H @ Phi - Phi * w.cpu().numpy()) / np.linalg.norm(H) < 1e-12
+    assert float(buf[:, n:].abs().max()) == 0.0                  # the padding is not written
+    log("band window padded ld and ldz")
+    A = torch.zeros((n, n + pad), dtype=torch.complex128, device="cuda")
+    A[:, :n] = to_dev_cm(torch, H)
+    kmax = 40
+    wv = torch.zeros(kmax, dtype=torch.float64, device="cuda")
+    Zb = torch.zeros((kmax, n + 5), dtype=torch.complex128, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    inf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nb = C.c_size_t(0)
+    mmf.call("mmf_eigh_band_window_workspace", C.c_int64(n), C.c_int64(b), C.c_int64(kmax), C.byref(nb))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    mmf.call("mmf_eigh_band_window", C.c_int64(n), C.c_void_p(A.data_ptr()), C.c_int64(n + pad), C.c_int64(b),
+             C.c_double(-1.0), C.c_double(1.0), C.c_int64(kmax), C.c_void_p(wv.data_ptr()),
+             C.c_void_p(Zb.data_ptr()), C.c_int64(n + 5), C.c_void_p(cnt.data_ptr()), C.c_void_p(work.data_ptr()),
+             C.c_size_t(work.numel()), C.c_void_p(inf.data_ptr()), None)
+    torch.cuda.synchronize()
+    _check_window(H, -1.0, 1.0, kmax, wv, Zb[:, :n], cnt, inf)
+    assert float(Zb[:, n:].abs().max()) == 0.0
