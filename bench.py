@@ -43,8 +43,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     ("bt2", "ladder20808"): {
         "bytes_per_launch": 1.9180e9 + 1.8857e9,
-        "sources": {"paper_2005_03426_amd/csrc/hb2st.hip": "e7695152a8004277",
-                    "paper_2005_03426_amd/csrc/twostage.h": "1186fddf0f06eba8"},
+        "sources": {"paper_2005_03426_amd/csrc/hb2st.hip": "14affd338dc97d86",
+                    "paper_2005_03426_amd/csrc/twostage.h": "a20ae151221be86a"},
         "profile": "profiles/hbm_bytes_ladder20808_counters.md",
     },
 }

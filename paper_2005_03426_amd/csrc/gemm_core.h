@@ -15,8 +15,8 @@
 // transformations need.  Complex FP32 products (the complex64 stages of the
 // precision layer) keep four MFMAs (re += ar*br - ai*bi, im += ar*bi +
 // ai*br): there the larger 3M constant leaves starting vectors that the FP64
-// refinement needs more iterations to fix.  K advances in slices of 16 with a
-// register prefetch of the next slice while the current one is multiplied.
+// refinement needs more iterations to fix.  K advances in slices of 16 with
+// register prefetches two slices ahead (two register sets).
 // The epilogue stages the tile through LDS so that every wavefront writes 64
 // consecutive rows of one column (coalesced).
 //
@@ -89,34 +89,37 @@ __device__ inline void ld_elem(const void *base, int64_t off, bool conj, R &re, 
 
 template <typename R, bool CPLX, int OA>
 __device__ inline void load_a(const GemmArgs &g, int64_t m0, int64_t k0, int64_t kend, int tid,
-                              R (&re)[4], R (&im)[4]) {
+                              R (&re)[4], R (&im)[4], unsigned &msk) {
+  msk = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + GEMM_THREADS * q;
     int mm, kk;
     if (OA != A_C) { mm = e & 63; kk = e >> 6; } else { mm = e >> 4; kk = e & 15; }
     const int64_t m = m0 + mm, k = k0 + kk;
-    R r = R(0), i = R(0);
-    if (m < g.M && k < kend) {
-      int64_t off;
-      if (OA == A_N) off = m + k * g.lda;
-      else if (OA == A_C) off = k + m * g.lda;
-      else off = (m % g.grp) + k * g.grp + (m / g.grp) * g.lda;
-      ld_elem<R, CPLX>(g.A, off, OA == A_C, r, i);
-    }
-    re[q] = r; im[q] = i;
+    // elements outside the operand read its first element and are replaced
+    // by zero when stored to LDS (no branch around the load and no use of it
+    // before then, so the compiler can count the loads in flight exactly)
+    const bool ok = m < g.M && k < kend;
+    msk |= ok ? 1u << q : 0u;
+    int64_t off;
+    if (OA == A_N) off = m + k * g.lda;
+    else if (OA == A_C) off = k + m * g.lda;
+    else off = (m % g.grp) + k * g.grp + (m / g.grp) * g.lda;
+    ld_elem<R, CPLX>(g.A, ok ? off : 0, OA == A_C, re[q], im[q]);
   }
 }
 
 template <typename R, bool CPLX, int OA>
-__device__ inline void store_a(R *As_re, R *As_im, int tid, const R (&re)[4], const R (&im)[4]) {
+__device__ inline void store_a(R *As_re, R *As_im, int tid, const R (&re)[4], const R (&im)[4], unsigned msk) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + GEMM_THREADS * q;
     int mm, kk;
     if (OA != A_C) { mm = e & 63; kk = e >> 6; } else { mm = e >> 4; kk = e & 15; }
-    As_re[kk * GT_LD + mm] = re[q];
-    if (CPLX) As_im[kk * GT_LD + mm] = im[q];
+    const bool ok = (msk >> q) & 1u;
+    As_re[kk * GT_LD + mm] = ok ? re[q] : R(0);
+    if (CPLX) As_im[kk * GT_LD + mm] = ok ? im[q] : R(0);
   }
 }
 
@@ -127,34 +130,34 @@ __device__ inline void b_coords(int e, int &kk, int &nn) {
 
 template <typename R, bool CPLX, int OB>
 __device__ inline void load_b(const GemmArgs &g, int64_t k0, int64_t kend, int64_t n0, int tid,
-                              R (&re)[4], R (&im)[4]) {
+                              R (&re)[4], R (&im)[4], unsigned &msk) {
+  msk = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + GEMM_THREADS * q;
     int kk, nn;
     b_coords<OB>(e, kk, nn);
     const int64_t k = k0 + kk, n = n0 + nn;
-    R r = R(0), i = R(0);
-    if (k < kend && n < g.N) {
-      int64_t off;
-      if (OB == B_N) off = k + n * g.ldb;
-      else if (OB == B_C) off = n + k * g.ldb;
-      else off = (n % g.grp) + k * g.grp + (n / g.grp) * g.ldb;
-      ld_elem<R, CPLX>(g.B, off, OB == B_C, r, i);
-    }
-    re[q] = r; im[q] = i;
+    const bool ok = k < kend && n < g.N;
+    msk |= ok ? 1u << q : 0u;
+    int64_t off;
+    if (OB == B_N) off = k + n * g.ldb;
+    else if (OB == B_C) off = n + k * g.ldb;
+    else off = (n % g.grp) + k * g.grp + (n / g.grp) * g.ldb;
+    ld_elem<R, CPLX>(g.B, ok ? off : 0, OB == B_C, re[q], im[q]);
   }
 }
 
 template <typename R, bool CPLX, int OB>
-__device__ inline void store_b(R *Bs_re, R *Bs_im, int tid, const R (&re)[4], const R (&im)[4]) {
+__device__ inline void store_b(R *Bs_re, R *Bs_im, int tid, const R (&re)[4], const R (&im)[4], unsigned msk) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + GEMM_THREADS * q;
     int kk, nn;
     b_coords<OB>(e, kk, nn);
-    Bs_re[kk * GT_LD + nn] = re[q];
-    if (CPLX) Bs_im[kk * GT_LD + nn] = im[q];
+    const bool ok = (msk >> q) & 1u;
+    Bs_re[kk * GT_LD + nn] = ok ? re[q] : R(0);
+    if (CPLX) Bs_im[kk * GT_LD + nn] = ok ? im[q] : R(0);
   }
 }
 
@@ -194,41 +197,50 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
     const int64_t ke = m0 + GT_M + band;
     if (ke < kend) kend = ke;
   }
-  R ar[4], ai[4], br[4], bi[4];
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + GT_K - 1) / GT_K : 0;
+  // Two register sets of operands: slice t + 2 is read from memory while
+  // slice t is multiplied and slice t + 1 (read during slice t - 1) goes to
+  // LDS at its end, so each read has two slices of matrix-core work to
+  // arrive in.  Reads past the last slice are masked element by element
+  // (k >= kend) and touch no memory.
+  R ar[2][4], ai[2][4], br[2][4], bi[2][4];
+  unsigned ma[2], mb[2];
   if (nk > 0) {
-    load_a<R, CPLX, OA>(g, m0, kbeg, kend, tid, ar, ai);
-    load_b<R, CPLX, OB>(g, kbeg, kend, n0, tid, br, bi);
-    store_a<R, CPLX, OA>(plane(0, 0), plane(0, 1), tid, ar, ai);
-    store_b<R, CPLX, OB>(plane(0, 2), plane(0, 3), tid, br, bi);
+    load_a<R, CPLX, OA>(g, m0, kbeg, kend, tid, ar[0], ai[0], ma[0]);
+    load_b<R, CPLX, OB>(g, kbeg, kend, n0, tid, br[0], bi[0], mb[0]);
+    load_a<R, CPLX, OA>(g, m0, kbeg + GT_K, kend, tid, ar[1], ai[1], ma[1]);
+    load_b<R, CPLX, OB>(g, kbeg + GT_K, kend, n0, tid, br[1], bi[1], mb[1]);
+    store_a<R, CPLX, OA>(plane(0, 0), plane(0, 1), tid, ar[0], ai[0], ma[0]);
+    store_b<R, CPLX, OB>(plane(0, 2), plane(0, 3), tid, br[0], bi[0], mb[0]);
   }
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int s = (int)(kt & 1);
-    const bool more = (kt + 1 < nk);
-    if (more) {
-      load_a<R, CPLX, OA>(g, m0, kbeg + (kt + 1) * GT_K, kend, tid, ar, ai);
-      load_b<R, CPLX, OB>(g, kbeg + (kt + 1) * GT_K, kend, n0, tid, br, bi);
-    }
+  // slice t from LDS stage t & 1; L: the set that takes slice t + 2, S: the
+  // set holding slice t + 1
+  auto slice = [&](int64_t t, R (&Lar)[4], R (&Lai)[4], R (&Lbr)[4], R (&Lbi)[4], unsigned &Lma, unsigned &Lmb,
+                   const R (&Sar)[4], const R (&Sai)[4], const R (&Sbr)[4], const R (&Sbi)[4], unsigned Sma,
+                   unsigned Smb) {
+    const int s = (int)(t & 1);
+    load_a<R, CPLX, OA>(g, m0, kbeg + (t + 2) * GT_K, kend, tid, Lar, Lai, Lma);
+    load_b<R, CPLX, OB>(g, kbeg + (t + 2) * GT_K, kend, n0, tid, Lbr, Lbi, Lmb);
     const R *Ar = plane(s, 0), *Ai = plane(s, 1), *Br = plane(s, 2), *Bi = plane(s, 3);
 #pragma unroll
     for (int kk = 0; kk < GT_K; kk += 4) {
       R fa_r[2], fa_i[2], fb_r[2], fb_i[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        fa_r[t] = Ar[(kk + lk) * GT_LD + wr + t * 16 + lrow];
-        fb_r[t] = Br[(kk + lk) * GT_LD + wc + t * 16 + lrow];
+      for (int u = 0; u < 2; ++u) {
+        fa_r[u] = Ar[(kk + lk) * GT_LD + wr + u * 16 + lrow];
+        fb_r[u] = Br[(kk + lk) * GT_LD + wc + u * 16 + lrow];
         if (CPLX) {
-          fa_i[t] = Ai[(kk + lk) * GT_LD + wr + t * 16 + lrow];
-          fb_i[t] = Bi[(kk + lk) * GT_LD + wc + t * 16 + lrow];
+          fa_i[u] = Ai[(kk + lk) * GT_LD + wr + u * 16 + lrow];
+          fb_i[u] = Bi[(kk + lk) * GT_LD + wc + u * 16 + lrow];
         }
       }
       R fa_s[2], fb_s[2];
       if (M3) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          fa_s[t] = fa_r[t] + fa_i[t];
-          fb_s[t] = fb_r[t] + fb_i[t];
+        for (int u = 0; u < 2; ++u) {
+          fa_s[u] = fa_r[u] + fa_i[u];
+          fb_s[u] = fb_r[u] + fb_i[u];
         }
       }
 #pragma unroll
@@ -246,11 +258,16 @@ __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {
           }
         }
     }
-    if (more) {
-      store_a<R, CPLX, OA>(plane(s ^ 1, 0), plane(s ^ 1, 1), tid, ar, ai);
-      store_b<R, CPLX, OB>(plane(s ^ 1, 2), plane(s ^ 1, 3), tid, br, bi);
+    if (t + 1 < nk) {
+      store_a<R, CPLX, OA>(plane(s ^ 1, 0), plane(s ^ 1, 1), tid, Sar, Sai, Sma);
+      store_b<R, CPLX, OB>(plane(s ^ 1, 2), plane(s ^ 1, 3), tid, Sbr, Sbi, Smb);
     }
     __syncthreads();
+  };
+  for (int64_t kt = 0; kt < nk; kt += 2) {
+    slice(kt, ar[0], ai[0], br[0], bi[0], ma[0], mb[0], ar[1], ai[1], br[1], bi[1], ma[1], mb[1]);
+    if (kt + 1 < nk)
+      slice(kt + 1, ar[1], ai[1], br[1], bi[1], ma[1], mb[1], ar[0], ai[0], br[0], bi[0], ma[0], mb[0]);
   }
 
   // ---- epilogue: stage the tile through LDS as Cs[col][row] (re, im planes)
