@@ -161,6 +161,25 @@ __device__ inline void store_b(R *Bs_re, R *Bs_im, int tid, const R (&re)[4], co
   }
 }
 
+// Tile (x, y) of workgroup (bx, by) of a gx x gy grid with one z slice.
+// Workgroups are dispatched to the eight XCDs in turn (linear index modulo
+// 8), each XCD with its own L2: here XCD j takes the j-th contiguous eighth of
+// the tiles, in the order of its workgroups, and the tiles are walked in
+// groups of G tile rows, a group's columns one after another, so that while an
+// XCD works through a group the A rows of its G row tiles stay in that XCD's
+// L2 and every B tile is used by G workgroups in a row.
+__device__ inline void xcd_tile(uint32_t bx, uint32_t by, uint32_t gx, uint32_t gy, uint32_t G, uint32_t &x,
+                                uint32_t &y) {
+  const uint32_t total = gx * gy, L = bx + by * gx;
+  const uint32_t j = L & 7u, q = total >> 3, r = total & 7u;
+  const uint32_t t = j * q + (j < r ? j : r) + (L >> 3);
+  const uint32_t grp = t / (G * gy), first = grp * G;
+  const uint32_t gs = (gx - first < G) ? gx - first : G;
+  const uint32_t within = t - first * gy;
+  x = first + within % gs;
+  y = within / gs;
+}
+
 // One 64x64 output tile at (m0, n0).  lds: GEMM_LDS_ELEMS elements of R.
 template <typename R, bool CPLX, int OA, int OB>
 __device__ void gemm_tile_t(const GemmArgs &g, int64_t m0, int64_t n0, R *lds) {

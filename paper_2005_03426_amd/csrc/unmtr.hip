@@ -289,7 +289,10 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) bt_update(const BtProb<R> *pr
   const BtProb<R> &P = pr[blockIdx.z];
   if (b >= P.nblk) return;
   const int64_t n = P.n, p = b * NB, mb = n - p - 1;
-  const int64_t m0 = (int64_t)blockIdx.x * GT_M, n0 = (int64_t)blockIdx.y * GT_N;
+  // one problem: XCD-grouped tile order (eight row tiles of V T per group)
+  uint32_t tx = blockIdx.x, ty = blockIdx.y;
+  if (gridDim.z == 1) xcd_tile(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y, 8, tx, ty);
+  const int64_t m0 = (int64_t)tx * GT_M, n0 = (int64_t)ty * GT_N;
   if (m0 >= mb || n0 >= P.nc) return;
   GemmArgs u = gemm_args(mb, P.nc, NB, P.VT, mb, P.W2, NB, P.Phi + (p + 1), P.ldphi, -1.0, 0.0, 1.0, 0.0);
   gemm_tile_t<R, true, A_N, B_N>(u, m0, n0, lds);
